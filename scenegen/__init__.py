@@ -1,0 +1,202 @@
+"""Seeded synthetic inputs for the textured 2D-Gaussian rasterizer.
+
+This module draws scenes, cameras and output adjoints from fixed seeds. It holds none of
+the renderer's arithmetic: both the FP64 oracle and the HIP path read the arrays it makes,
+and neither is imported here.
+
+A scene is the set of already-activated per-splat parameters of the paper's primitive
+(Sec. 3.1, Eq. 3: center p, tangents t_u and t_v from a rotation, scales s_u and s_v,
+opacity) plus the per-splat N x N RGB colour grid of Sec. 3.2. Tangents come from a random
+unit quaternion as in 2DGS; everything is drawn in float64 and cast to float32 (textures
+optionally rounded to bfloat16, round-to-nearest-even).
+
+Cameras are pinholes with a horizontal field of view, axes x right, y down, z forward,
+pixel centres at (i + 1/2, j + 1/2), principal point at the image centre.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+__all__ = [
+    "Scene", "View", "make_scene", "look_at_view", "frontal_view", "orbit_views",
+    "make_dl_drgb", "to_bf16_bits", "bf16_bits_to_f32", "CONFIGS", "config",
+]
+
+
+@dataclasses.dataclass
+class Scene:
+    """Per-splat parameters, all C-contiguous float32 (textures float32; see ``tex_bf16``)."""
+    means: np.ndarray      # [P,3]
+    tan_u: np.ndarray      # [P,3]
+    tan_v: np.ndarray      # [P,3]
+    scales: np.ndarray     # [P,2]  (s_u, s_v) > 0
+    opacity: np.ndarray    # [P]    in (0, 1)
+    textures: np.ndarray   # [P,N,N,3] indexed [k, i_u, i_v, c]
+
+    @property
+    def P(self) -> int:
+        return int(self.means.shape[0])
+
+    @property
+    def N(self) -> int:
+        return int(self.textures.shape[1])
+
+    def subset(self, idx) -> "Scene":
+        return Scene(*(np.ascontiguousarray(a[idx]) for a in
+                       (self.means, self.tan_u, self.tan_v, self.scales, self.opacity,
+                        self.textures)))
+
+
+@dataclasses.dataclass
+class View:
+    """Pinhole camera: world->camera rotation R (row-major) and translation t."""
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    R: np.ndarray          # [3,3] float32
+    t: np.ndarray          # [3] float32
+    z_near: float = 0.01
+
+
+def _intrinsics(width: int, height: int, fov_deg: float) -> Tuple[float, float, float, float]:
+    f = (width / 2.0) / math.tan(math.radians(fov_deg) / 2.0)
+    return f, f, width / 2.0, height / 2.0
+
+
+def look_at_view(pos, width: int, height: int, fov_deg: float = 60.0,
+                 target=(0.0, 0.0, 0.0), z_near: float = 0.01) -> View:
+    """Camera at ``pos`` looking at ``target``; rows of R are the camera axes in world space."""
+    pos = np.asarray(pos, dtype=np.float64)
+    f = np.asarray(target, dtype=np.float64) - pos
+    f /= np.linalg.norm(f)
+    up = np.array([0.0, 1.0, 0.0])
+    if abs(float(f @ up)) > 0.99:
+        up = np.array([1.0, 0.0, 0.0])
+    r = np.cross(f, up)
+    r /= np.linalg.norm(r)
+    d = np.cross(f, r)
+    R = np.stack([r, d, f])
+    t = -R @ pos
+    fx, fy, cx, cy = _intrinsics(width, height, fov_deg)
+    return View(width, height, fx, fy, cx, cy, R.astype(np.float32), t.astype(np.float32), z_near)
+
+
+def frontal_view(width: int, height: int, fov_deg: float = 60.0, z_near: float = 0.01) -> View:
+    """Identity camera at the origin looking down +z (the image-fitting set-up)."""
+    fx, fy, cx, cy = _intrinsics(width, height, fov_deg)
+    return View(width, height, fx, fy, cx, cy, np.eye(3, dtype=np.float32),
+                np.zeros(3, dtype=np.float32), z_near)
+
+
+def quat_to_tangents(q: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """Unit quaternions (w,x,y,z) -> first two columns of the rotation matrix."""
+    q = q / np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
+    c0 = np.stack([1 - 2 * (y * y + z * z), 2 * (x * y + w * z), 2 * (x * z - w * y)], axis=1)
+    c1 = np.stack([2 * (x * y - w * z), 1 - 2 * (x * x + z * z), 2 * (y * z + w * x)], axis=1)
+    return c0, c1
+
+
+def to_bf16_bits(x: np.ndarray) -> np.ndarray:
+    """float32 -> bfloat16 bit patterns (uint16), round to nearest even. NaN kept quiet."""
+    b = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32)
+    rounding = ((b >> 16) & 1) + np.uint32(0x7FFF)
+    out = ((b + rounding) >> 16).astype(np.uint16)
+    nan = np.isnan(x)
+    if nan.any():
+        out[nan] = np.uint16(0x7FC0)
+    return out
+
+
+def bf16_bits_to_f32(b: np.ndarray) -> np.ndarray:
+    return (np.asarray(b, dtype=np.uint16).astype(np.uint32) << 16).view(np.float32)
+
+
+def make_scene(seed: int, P: int, lo: float, hi: float, s_lo: float, s_hi: float, N: int,
+               tex_bf16: bool = False, op_lo: float = 0.05, op_hi: float = 0.95) -> Scene:
+    """Draw order: means, quaternions, log-scales, opacity, textures (one PCG64 stream).
+
+    With ``tex_bf16`` the texel values are rounded to the nearest bfloat16 and returned as
+    float32 holding those exact values (the GPU receives their bit patterns).
+    """
+    rng = np.random.default_rng(seed)
+    means = rng.uniform(lo, hi, (P, 3))
+    q = rng.standard_normal((P, 4))
+    tu, tv = quat_to_tangents(q)
+    scales = np.exp(rng.uniform(math.log(s_lo), math.log(s_hi), (P, 2)))
+    opacity = rng.uniform(op_lo, op_hi, P)
+    textures = rng.uniform(0.0, 1.0, (P, N, N, 3))
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    tex = f32(textures)
+    if tex_bf16:
+        tex = bf16_bits_to_f32(to_bf16_bits(tex)).reshape(tex.shape)
+    return Scene(f32(means), f32(tu), f32(tv), f32(scales), f32(opacity), tex)
+
+
+def orbit_views(seed: int, n: int, radius: float, resolutions: Sequence[Tuple[int, int]],
+                fov_deg: float = 60.0, pick_resolution: bool = False) -> List[View]:
+    """``n`` cameras on a sphere of ``radius`` looking at the origin (directions N(0,I))."""
+    rng = np.random.default_rng(seed + 1)
+    views = []
+    for _ in range(n):
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        if pick_resolution:
+            w, h = resolutions[int(rng.integers(0, len(resolutions)))]
+        else:
+            w, h = resolutions[0]
+        views.append(look_at_view(radius * d, w, h, fov_deg))
+    return views
+
+
+def make_dl_drgb(seed: int, views: Sequence[View]) -> np.ndarray:
+    """Output adjoint dL/drgb ~ N(0,1), views packed in order, each [H][W][3] (float32)."""
+    total = sum(v.width * v.height for v in views)
+    rng = np.random.default_rng(seed + 2)
+    return np.ascontiguousarray(rng.standard_normal((total, 3)), dtype=np.float32)
+
+
+# ---------------------------------------------------------------------------------------
+# Named workloads. Sizes and distributions follow the benchmark configurations; where a
+# detail is open (orientation of config 2, centres and cameras of config 4) it follows the
+# nearest configuration that states it.
+# ---------------------------------------------------------------------------------------
+CONFIGS = {
+    # 1k splats, 4x4 FP32 textures, one 128x128 view at distance 3, forward only
+    "C1": dict(P=1000, lo=-1.0, hi=1.0, s_lo=0.02, s_hi=0.2, N=4, bf16=False,
+               views=("front", 3.0, [(128, 128)], 1)),
+    # 100k splats, 8x8 FP32 textures, one 800x800 view at distance 5, fwd+bwd
+    "C2": dict(P=100_000, lo=-2.0, hi=2.0, s_lo=0.005, s_hi=0.1, N=8, bf16=False,
+               views=("front", 5.0, [(800, 800)], 1)),
+    # 1M splats, 4x4 FP32 textures, 16 uneven views on a radius-8 sphere
+    "C3": dict(P=1_000_000, lo=-4.0, hi=4.0, s_lo=0.02, s_hi=0.2, N=4, bf16=False,
+               views=("orbit", 8.0, [(640, 480), (1024, 768), (1280, 720), (1600, 1060)], 16)),
+    # 3M splats, 8x8 BF16 textures, 4 views 1920x1080 on a radius-8 sphere
+    "C4": dict(P=3_000_000, lo=-4.0, hi=4.0, s_lo=0.002, s_hi=0.05, N=8, bf16=True,
+               views=("orbit", 8.0, [(1920, 1080)], 4)),
+    # 1M splats, 8x8 textures, one 1920x1080 view at distance 8 (FP32 and BF16 variants)
+    "T0": dict(P=1_000_000, lo=-4.0, hi=4.0, s_lo=0.02, s_hi=0.2, N=8, bf16=False,
+               views=("front", 8.0, [(1920, 1080)], 1)),
+    "T0_BF16": dict(P=1_000_000, lo=-4.0, hi=4.0, s_lo=0.02, s_hi=0.2, N=8, bf16=True,
+                    views=("front", 8.0, [(1920, 1080)], 1)),
+}
+
+
+def config(name: str, seed: int = 0, P: Optional[int] = None) -> Tuple[Scene, List[View]]:
+    """Build the scene and views of a named workload (optionally with fewer splats)."""
+    c = CONFIGS[name]
+    scene = make_scene(seed, P if P is not None else c["P"], c["lo"], c["hi"], c["s_lo"],
+                       c["s_hi"], c["N"], tex_bf16=c["bf16"])
+    kind, dist, res, nv = c["views"]
+    if kind == "front":
+        views = [look_at_view((0.0, 0.0, -dist), res[0][0], res[0][1])]
+    else:
+        views = orbit_views(seed, nv, dist, res, pick_resolution=len(res) > 1)
+    return scene, views

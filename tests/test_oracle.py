@@ -1,0 +1,398 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix (CPU only).
+
+Each test names the passage it pins. None of them re-types the oracle's own formula: they use
+closed forms of special geometries, invariants, symmetries, finite differences and brute force.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+from oracle import gb_oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def one_scene(means, tan_u, tan_v, scales, opacity, textures):
+    f = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.float64), dtype=np.float32)
+    return sg.Scene(f(means), f(tan_u), f(tan_v), f(scales), f(opacity), f(textures))
+
+
+def frontal_splat(X, Y, Z, s=(0.1, 0.1), theta=0.0, o=0.8, tex=None, N=4):
+    tu = [math.cos(theta), math.sin(theta), 0.0]
+    tv = [-math.sin(theta), math.cos(theta), 0.0]
+    if tex is None:
+        tex = np.full((N, N, 3), 0.5)
+    return [X, Y, Z], tu, tv, list(s), o, tex
+
+
+def scene_of(splats):
+    cols = list(zip(*splats))
+    return one_scene(*(np.stack([np.asarray(c, dtype=np.float64) for c in col]) for col in cols))
+
+
+def pixel_to_world(view, x, y, Z):
+    """Identity camera: the point at depth Z seen through pixel position (x, y)."""
+    return (Z * (x - view.cx) / view.fx, Z * (y - view.cy) / view.fy, Z)
+
+
+# --- P1: alpha at the splat centre equals opacity (the benchmark spec) -------------------------
+def test_alpha_at_center_equals_opacity():
+    view = sg.frontal_view(16, 16)
+    X, Y, Z = pixel_to_world(view, 8.5, 7.5, 4.0)
+    col = np.array([0.25, 0.5, 0.75])
+    sc = scene_of([frontal_splat(X, Y, Z, o=0.6, tex=np.broadcast_to(col, (4, 4, 3)))])
+    r = O.render(sc, view, O.Options())
+    o = float(sc.opacity[0])
+    col = sc.textures[0, 0, 0].astype(np.float64)
+    assert r.rgb[7, 8] == pytest.approx(o * col, abs=1e-12)
+    assert r.T_final[7, 8] == pytest.approx(1.0 - o, abs=1e-12)
+
+
+# --- P5: image-fitting geometry (Sec. 4.1: camera along +z, rotation about z only) -------
+def test_uv_closed_form_for_image_plane_splats():
+    rng = np.random.default_rng(1)
+    view = sg.frontal_view(64, 48)
+    for _ in range(20):
+        Z = rng.uniform(1.0, 10.0)
+        X, Y = rng.uniform(-1, 1, 2)
+        th = rng.uniform(-math.pi, math.pi)
+        su, sv = rng.uniform(0.05, 0.5, 2)
+        sc = scene_of([frontal_splat(X, Y, Z, s=(su, sv), theta=th)])
+        M = O.splat_M(sc, view, 0)
+        xs, ys = rng.uniform(0, 64, 50), rng.uniform(0, 48, 50)
+        u, v, valid, *_ = O.ray_splat_uv(M, xs, ys)
+        assert valid.all()
+        # the inputs are float32; use their exact values in the closed form
+        X, Y, Z = (float(c) for c in sc.means[0])
+        c, s = float(sc.tan_u[0, 0]), float(sc.tan_u[0, 1])
+        su, sv = (float(c_) for c_ in sc.scales[0])
+        dx = Z * (xs - view.cx) / view.fx - X
+        dy = Z * (ys - view.cy) / view.fy - Y
+        tvx, tvy = float(sc.tan_v[0, 0]), float(sc.tan_v[0, 1])
+        # tangents of a float32 rotation are only nearly orthonormal: solve the 2x2 system
+        A = np.array([[su * c, sv * tvx], [su * s, sv * tvy]])
+        uv = np.linalg.solve(A, np.stack([dx, dy]))
+        np.testing.assert_allclose(u, uv[0], rtol=1e-9, atol=1e-9)
+        np.testing.assert_allclose(v, uv[1], rtol=1e-9, atol=1e-9)
+
+
+# --- P6 + golden: falloff at the grid border (Sec. 3.2 isolines) -------------------------
+def test_grid_border_isolines_match_paper():
+    with open(os.path.join(GOLDEN, "isolines.json")) as f:
+        gold = json.load(f)
+    view = sg.frontal_view(200, 200)
+    for case in gold["cases"]:
+        sig = case["sigma"]
+        # a big frontal splat; the pixel whose ray hits (u, v) = (sigma, 0)
+        Z, s = 5.0, 2.0
+        X, Y, _ = pixel_to_world(view, 100.5, 100.5, Z)
+        sc = scene_of([frontal_splat(X, Y, Z, s=(s, s), o=0.9,
+                                     tex=np.ones((4, 4, 3)))])
+        Xf, Zf, sf = float(sc.means[0, 0]), float(sc.means[0, 2]), float(sc.scales[0, 0])
+        x_border = view.cx + view.fx * (Xf + sig * sf) / Zf
+        opts = O.Options(sigma=sig)
+        M = O.splat_M(sc, view, 0)
+        u, v, *_ = O.ray_splat_uv(M, [x_border], [100.5])
+        assert u[0] == pytest.approx(sig, rel=1e-9)
+        _, _, _, _, _, G, *_ = O._falloff(M, np.array([x_border]), np.array([100.5]), 0.5)
+        assert G[0] == pytest.approx(math.exp(-sig * sig / 2), rel=1e-9)
+        # "roughly" the quoted isoline: within a factor 1.5 either way
+        assert case["approx_falloff_at_border"] / 1.5 < G[0] < case["approx_falloff_at_border"] * 1.5
+        # the colour at the border is the edge texel column, and it stays so beyond it (clamp)
+        tex = np.zeros((4, 4, 3))
+        tex[3, :, :] = 1.0
+        col = O.bilinear(tex, [sig, sig * 1.7, sig * 0.99], [0.0, 0.0, 0.0], sig)
+        assert col[0] == pytest.approx([1, 1, 1], abs=1e-12)
+        assert col[1] == pytest.approx([1, 1, 1], abs=1e-12)
+        assert col[2][0] < 1.0
+
+
+# --- P4: a linear texel field is reproduced exactly (Alg. 2, pins the floor reading) ------
+@pytest.mark.parametrize("N", [2, 3, 4, 8])
+def test_bilinear_reproduces_linear_fields(N):
+    rng = np.random.default_rng(N)
+    sig = 0.5
+    a, b, c = rng.standard_normal((3, 3))
+    i = np.arange(N)[:, None, None]
+    j = np.arange(N)[None, :, None]
+    C = a + b * i + c * j
+    u = rng.uniform(-0.8, 0.8, 500)
+    v = rng.uniform(-0.8, 0.8, 500)
+    up = np.clip((N - 1) * (u + sig) / (2 * sig), 0, N - 1)
+    vp = np.clip((N - 1) * (v + sig) / (2 * sig), 0, N - 1)
+    want = a + b * up[:, None] + c * vp[:, None]
+    np.testing.assert_allclose(O.bilinear(C, u, v, sig), want, atol=1e-12)
+    # texel centres sit at +-sigma: the corners return the corner texels
+    got = O.bilinear(C, [-sig, sig, -sig, sig], [-sig, -sig, sig, sig], sig)
+    np.testing.assert_allclose(got, [C[0, 0], C[N - 1, 0], C[0, N - 1], C[N - 1, N - 1]], atol=1e-12)
+
+
+def test_bilinear_N1_is_constant():
+    C = np.array([[[0.1, 0.2, 0.3]]])
+    got = O.bilinear(C, [-3, 0, 0.2], [1, 0, -0.4], 0.5)
+    np.testing.assert_allclose(got, np.broadcast_to([0.1, 0.2, 0.3], (3, 3)))
+    dC, du, dv = O.adj_bilinear(C, [0.1, 0.2], [0.0, 0.3], 0.5, np.ones((2, 3)))
+    assert (du == 0).all() and (dv == 0).all()
+    np.testing.assert_allclose(dC[0, 0], [2, 2, 2])
+
+
+# --- P10: adj-bilinear against central differences of bilinear (Alg. 2) -------------------
+@pytest.mark.parametrize("N", [2, 4, 8])
+def test_adj_bilinear_matches_finite_differences(N):
+    rng = np.random.default_rng(10 + N)
+    sig = 0.5
+    C = rng.uniform(0, 1, (N, N, 3))
+    for _ in range(40):
+        u, v = rng.uniform(-0.9, 0.9, 2)
+        dc = rng.standard_normal(3)
+        dC, du, dv = O.adj_bilinear(C, [u], [v], sig, dc[None])
+        h = 1e-7
+        f = lambda uu, vv: float(O.bilinear(C, [uu], [vv], sig)[0] @ dc)
+        grid_u = (N - 1) * (u + sig) / (2 * sig)
+        grid_v = (N - 1) * (v + sig) / (2 * sig)
+        near_kink = lambda g: abs(g - round(g)) < 1e-5
+        if not near_kink(grid_u) and abs(abs(u) - sig) > 1e-5:
+            assert du[0] == pytest.approx((f(u + h, v) - f(u - h, v)) / (2 * h), rel=1e-6, abs=1e-7)
+        if not near_kink(grid_v) and abs(abs(v) - sig) > 1e-5:
+            assert dv[0] == pytest.approx((f(u, v + h) - f(u, v - h)) / (2 * h), rel=1e-6, abs=1e-7)
+        if abs(u) >= sig:
+            assert du[0] == 0.0
+        if abs(v) >= sig:
+            assert dv[0] == 0.0
+        # colour is linear in C: the adjoint is the exact derivative
+        for (i, j, c) in [(0, 0, 0), (N - 1, N - 1, 2), (N // 2, 0, 1)]:
+            Cp = C.copy()
+            Cp[i, j, c] += 1.0
+            assert dC[i, j, c] == pytest.approx(
+                float(O.bilinear(Cp, [u], [v], sig)[0] @ dc) - f(u, v), abs=1e-12)
+
+
+# --- P2: constant texture == plain 2DGS (N = 1, Sec. 4.1 ablation) -----------------------
+def test_constant_texture_equals_plain_2dgs():
+    scene, views = sg.config("C1", P=200)
+    view = sg.look_at_view((0, 0, -3.0), 48, 40)
+    colors = np.random.default_rng(3).uniform(0, 1, (scene.P, 3)).astype(np.float32)
+    tex4 = np.ascontiguousarray(np.broadcast_to(colors[:, None, None, :], (scene.P, 4, 4, 3)))
+    tex1 = np.ascontiguousarray(colors[:, None, None, :])
+    s4 = sg.Scene(scene.means, scene.tan_u, scene.tan_v, scene.scales, scene.opacity, tex4)
+    s1 = sg.Scene(scene.means, scene.tan_u, scene.tan_v, scene.scales, scene.opacity, tex1)
+    r4 = O.render(s4, view, O.Options())
+    r1 = O.render(s1, view, O.Options())
+    np.testing.assert_allclose(r4.rgb, r1.rgb, atol=1e-13)
+    np.testing.assert_array_equal(r4.T_final, r1.T_final)
+    # and the box-filtered (coarsest level) grid of a varying texture is its mean colour
+    C = np.random.default_rng(4).uniform(0, 1, (8, 8, 3))
+    np.testing.assert_allclose(O.box_filter_grid(C, 8)[0, 0], C.mean(axis=(0, 1)))
+
+
+# --- P3: blend weights plus residual transmittance sum to one (Eq. 2 telescopes) ---------
+@pytest.mark.parametrize("t_min", [1e-4, 0.0])
+def test_weights_plus_transmittance_sum_to_one(t_min):
+    scene, _ = sg.config("C1", P=300)
+    view = sg.look_at_view((0, 0, -3.0), 40, 32)
+    white = sg.Scene(scene.means, scene.tan_u, scene.tan_v, scene.scales, scene.opacity,
+                     np.ones_like(scene.textures))
+    r = O.render(white, view, O.Options(t_min=t_min))
+    np.testing.assert_allclose(r.rgb[..., 0] + r.T_final, 1.0, atol=1e-12)
+    rb = O.render(white, view, O.Options(t_min=t_min, bg=(1.0, 1.0, 1.0)))
+    np.testing.assert_allclose(rb.rgb, 1.0, atol=1e-12)
+
+
+# --- P7: symmetries fix the texture axis order ------------------------------------------
+def test_swap_uv_axes_with_transposed_grid():
+    scene, _ = sg.config("C1", P=150)
+    view = sg.look_at_view((0, 0, -3.0), 40, 40)
+    swapped = sg.Scene(scene.means, scene.tan_v, scene.tan_u,
+                       np.ascontiguousarray(scene.scales[:, ::-1]), scene.opacity,
+                       np.ascontiguousarray(scene.textures.transpose(0, 2, 1, 3)))
+    a = O.render(scene, view, O.Options())
+    b = O.render(swapped, view, O.Options())
+    np.testing.assert_allclose(a.rgb, b.rgb, atol=1e-12)
+
+
+def test_flip_u_with_flipped_grid():
+    scene, _ = sg.config("C1", P=150)
+    view = sg.look_at_view((0, 0, -3.0), 40, 40)
+    flipped = sg.Scene(scene.means, np.ascontiguousarray(-scene.tan_u), scene.tan_v,
+                       scene.scales, scene.opacity,
+                       np.ascontiguousarray(scene.textures[:, ::-1, :, :]))
+    a = O.render(scene, view, O.Options())
+    b = O.render(flipped, view, O.Options())
+    np.testing.assert_allclose(a.rgb, b.rgb, atol=1e-12)
+    # flipping the grid along the other axis is not a symmetry
+    wrong = sg.Scene(scene.means, np.ascontiguousarray(-scene.tan_u), scene.tan_v,
+                     scene.scales, scene.opacity,
+                     np.ascontiguousarray(scene.textures[:, :, ::-1, :]))
+    c = O.render(wrong, view, O.Options())
+    assert np.abs(a.rgb - c.rgb).max() > 1e-3
+
+
+# --- P11: stacked layers, transmittance product and early termination --------------------
+def test_stacked_layers_terminate_at_t_min():
+    view = sg.frontal_view(16, 16)
+    cols = np.random.default_rng(5).uniform(0, 1, (6, 3))
+    splats = []
+    for k in range(6):
+        X, Y, Z = pixel_to_world(view, 8.5, 8.5, 2.0 + 0.1 * k)
+        splats.append(frontal_splat(X, Y, Z, s=(1.0, 1.0), o=0.95,
+                                    tex=np.broadcast_to(cols[k], (2, 2, 3)), N=2))
+    sc = scene_of(splats)
+    r = O.render(sc, view, O.Options())
+    # T: 1 -> .05 -> .0025 -> .000125; the 4th would give 6.25e-6 < 1e-4 and ends the pixel
+    o = float(sc.opacity[0])
+    tex = sc.textures[:, 0, 0].astype(np.float64)
+    assert r.n_blended[8, 8] == 3 and r.terminated[8, 8]
+    assert r.T_final[8, 8] == pytest.approx((1 - o) ** 3, rel=1e-12)
+    want = sum(o * (1 - o) ** k * tex[k] for k in range(3))
+    np.testing.assert_allclose(r.rgb[8, 8], want, rtol=1e-12)
+    # without the early stop all six layers blend
+    r0 = O.render(sc, view, O.Options(t_min=0.0))
+    assert r0.n_blended[8, 8] == 6
+    assert r0.T_final[8, 8] == pytest.approx((1 - o) ** 6, rel=1e-12)
+
+
+# --- P12: equal depths are ordered by splat index ---------------------------------------
+def test_equal_depth_orders_by_index():
+    view = sg.frontal_view(16, 16)
+    X, Y, Z = pixel_to_world(view, 8.5, 8.5, 3.0)
+    red, blue = np.array([1.0, 0, 0]), np.array([0, 0, 1.0])
+    sc = scene_of([frontal_splat(X, Y, Z, o=0.5, tex=np.broadcast_to(red, (2, 2, 3)), N=2),
+                   frontal_splat(X, Y, Z, o=0.5, tex=np.broadcast_to(blue, (2, 2, 3)), N=2)])
+    r = O.render(sc, view, O.Options())
+    np.testing.assert_allclose(r.rgb[8, 8], 0.5 * red + 0.25 * blue, atol=1e-12)
+    ks = O.key_stage(sc, view, O.Options())
+    assert list(O.depth_order(ks)) == [0, 1]
+
+
+# --- Key stage: hand-computed rectangle and brute-force conservativeness ------------------
+def test_key_stage_rectangle_of_a_frontal_splat():
+    view = sg.frontal_view(200, 100)
+    sc = scene_of([frontal_splat(0.1, -0.05, 2.0, s=(0.05, 0.02), o=0.5)])
+    ks = O.key_stage(sc, view, O.Options())
+    X, Y, Z = (float(c) for c in sc.means[0])
+    su, sv = (float(c) for c in sc.scales[0])
+    cx, cy = view.cx + view.fx * X / Z, view.cy + view.fy * Y / Z
+    rx, ry = view.fx * 3.33 * su / Z, view.fy * 3.33 * sv / Z
+    xmin, xmax = min(cx - rx, cx - 2.36) - 0.01, max(cx + rx, cx + 2.36) + 0.01
+    ymin, ymax = min(cy - ry, cy - 2.36) - 0.01, max(cy + ry, cy + 2.36) + 0.01
+    want = [math.ceil(xmin - 0.5), math.floor(xmax - 0.5), math.ceil(ymin - 0.5),
+            math.floor(ymax - 0.5)]
+    assert list(ks["rect"][0]) == want
+    assert list(ks["tile_rect"][0]) == [want[0] // 16, want[1] // 16, want[2] // 16, want[3] // 16]
+    assert ks["count"][0] == (want[1] // 16 - want[0] // 16 + 1) * (want[3] // 16 - want[2] // 16 + 1)
+    assert ks["depth"][0] == np.float32(2.0)
+
+
+def test_key_stage_culls():
+    view = sg.frontal_view(64, 64)
+    sc = scene_of([frontal_splat(0, 0, -1.0), frontal_splat(0, 0, 2.0, o=0.003),
+                   frontal_splat(50.0, 0, 2.0), frontal_splat(0, 0, 2.0)])
+    ks = O.key_stage(sc, view, O.Options())
+    assert list(ks["visible"]) == [False, False, False, True]
+    assert list(ks["count"][:3]) == [0, 0, 0]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_key_stage_rect_contains_every_contributing_pixel(seed):
+    """Brute force: evaluate every visible splat at every pixel; alpha >= alpha_min only
+    inside its rectangle (tiny scenes of big and grazing splats)."""
+    rng = np.random.default_rng(100 + seed)
+    P = 12
+    scene = sg.make_scene(seed, P, -0.6, 0.6, 0.05, 0.6, 2)
+    view = sg.look_at_view(rng.standard_normal(3) * 0 + np.array([0.3, -0.2, -2.5]), 40, 30)
+    opts = O.Options()
+    ks = O.key_stage(scene, view, opts)
+    x, y = O._pixel_grid((0, 0, 40, 30))
+    for k in range(P):
+        M = O.splat_M(scene, view, k)
+        *_, G, _, _, _ = O._falloff(M, x, y, opts.lowpass_var)
+        u, v, valid, *_ = O.ray_splat_uv(M, x, y)
+        alpha = np.minimum(opts.alpha_max, float(scene.opacity[k]) * G)
+        hit = valid & (alpha >= opts.alpha_min)
+        if not ks["visible"][k]:
+            continue
+        i0, i1, j0, j1 = ks["rect"][k]
+        ii, jj = (x - 0.5).astype(int), (y - 0.5).astype(int)
+        inside = (ii >= i0) & (ii <= i1) & (jj >= j0) & (jj <= j1)
+        assert not (hit & ~inside).any()
+
+
+def test_tile_pairs_invariants_multi_view():
+    scene, _ = sg.config("C1", P=400)
+    views = [sg.look_at_view((0, 0, -3.0), 70, 50), sg.look_at_view((2.0, 1.0, -2.0), 33, 47)]
+    opts = O.Options()
+    keys, vals, ranges = O.tile_pairs(scene, views, opts)
+    total = 0
+    for v, view in enumerate(views):
+        total += O.key_stage(scene, view, opts)["count"].sum()
+    assert keys.size == total
+    assert (np.diff(keys.astype(np.int64)) >= 0).all()
+    covered = ranges[:, 1] - ranges[:, 0]
+    assert covered.sum() == keys.size
+    for tile in range(ranges.shape[0]):
+        s, e = ranges[tile]
+        if e > s:
+            assert (keys[s:e] == tile).all()
+            rec = vals[s:e].astype(np.int64)
+            view_id = rec // scene.P
+            assert (view_id == view_id[0]).all()
+            ks = O.key_stage(scene, views[view_id[0]], opts)
+            d = ks["depth"][rec % scene.P].view(np.uint32).astype(np.int64)
+            order = np.lexsort((rec, d))
+            assert (order == np.arange(order.size)).all()
+
+
+# --- P8: analytic gradient vs central finite differences (fp64) --------------------------
+def _loss(scene, view, opts, g):
+    r = O.render(scene, view, opts)
+    return float(np.sum(r.rgb.reshape(-1, 3) * g)), r
+
+
+def _decisions(r):
+    return r.n_blended.copy(), r.terminated.copy()
+
+
+@pytest.mark.parametrize("thresholds", ["default", "off"])
+def test_oracle_gradient_matches_central_differences(thresholds):
+    rng = np.random.default_rng(7)
+    P = 4
+    scene = sg.make_scene(21, P, -0.3, 0.3, 0.08, 0.3, 3)
+    view = sg.look_at_view((0.2, -0.1, -2.0), 24, 20)
+    if thresholds == "off":
+        opts = O.Options(alpha_min=0.0, t_min=0.0, alpha_max=1.0, bg=(0.2, 0.3, 0.4))
+    else:
+        opts = O.Options(bg=(0.1, 0.0, 0.5))
+    g = rng.standard_normal((24 * 20, 3))
+    r = O.render(scene, view, opts, keep_saved=True)
+    gr = O.render_backward(scene, view, opts, r, g)
+    fields = ["means", "tan_u", "tan_v", "scales", "opacity", "textures"]
+    checked = 0
+    for name in fields:
+        arr = getattr(scene, name)
+        ana = getattr(gr, name)
+        flat_idx = rng.choice(arr.size, size=min(arr.size, 10), replace=False)
+        for fi in flat_idx:
+            idx = np.unravel_index(fi, arr.shape)
+            base = float(arr[idx])
+            h = 1e-3 * max(1.0, abs(base)) if name == "textures" else 1e-4 * max(0.1, abs(base))
+            vals = []
+            decs = []
+            for sgn in (1, -1):
+                s2 = sg.Scene(*(a.astype(np.float64) for a in
+                                (scene.means, scene.tan_u, scene.tan_v, scene.scales,
+                                 scene.opacity, scene.textures)))
+                getattr(s2, name)[idx] = base + sgn * h
+                L, rr = _loss(s2, view, opts, g)
+                vals.append(L)
+                decs.append(_decisions(rr))
+            if not all((a == b).all() for a, b in zip(decs[0], decs[1])):
+                continue
+            fd = (vals[0] - vals[1]) / (2 * h)
+            a = float(ana[idx])
+            assert a == pytest.approx(fd, rel=2e-5, abs=2e-6 * max(1.0, abs(fd))), (name, idx)
+            checked += 1
+    assert checked >= 40
