@@ -1,0 +1,184 @@
+/*
+ * gbb.h -- C ABI of the MI355X rasterizer for textured 2D Gaussian splats
+ * ("Gaussian Billboards": 2D Gaussian surfels carrying an N x N RGB colour grid).
+ *
+ * What the library computes (Gaussian Billboards, Sec. 3 and the supplementary Alg. 1-2):
+ *   - a splat k has centre p_k, tangents t_u, t_v, scales (s_u, s_v) and opacity o_k; its
+ *     tangent plane is P(u, v) = p_k + s_u t_u u + s_v t_v v (Eq. 3);
+ *   - a pixel ray meets the plane at (u, v); the splat's opacity there is
+ *     alpha = min(alpha_max, o_k * G_hat), G_hat = exp(-min((u^2 + v^2)/2, |x - c2|^2/(2 var_lp)))
+ *     (Eq. 4 with a screen-space low-pass around the projected centre c2);
+ *   - its colour is the bilinear lookup of the N x N grid C_k over [-sigma, sigma]^2 of the
+ *     uv plane, border-clamped (Eq. 5, Alg. 2);
+ *   - splats are composited front to back by centre depth (Eq. 2), skipping alpha < alpha_min
+ *     and stopping a pixel before its transmittance would drop below t_min (Alg. 1);
+ *   - the backward pass returns the gradient of sum(d_rgb * rgb) with respect to every
+ *     splat parameter, including the colour grid (Alg. 1 backward, Alg. 2 adj-bilinear).
+ *
+ * Conventions
+ *   - Every pointer in gb_splats, the rgb/T/d_rgb outputs and gb_grads is a DEVICE pointer
+ *     owned by the caller; float arrays must be 4-byte aligned, the workspace 256-byte
+ *     aligned. The library never allocates device memory in gb_render_fwd/gb_render_bwd.
+ *   - gb_view arrays and option structs are HOST memory, read during the call only.
+ *   - `stream` is a hipStream_t (NULL = the default stream). Every launch is ordered on it and
+ *     no call below synchronises, except gb_count_pairs and gb_read_status, which wait for the
+ *     stream. Nothing throws across the ABI and nothing aborts.
+ *   - Camera: world->camera rotation R (row-major) and translation t, axes x right, y down,
+ *     z forward; pinhole intrinsics fx, fy, cx, cy in pixels; pixel (i, j) has its centre at
+ *     (i + 1/2, j + 1/2). Views are packed in order: view v occupies pixels
+ *     [sum_{u<v} W_u H_u, ... + W_v H_v), row-major.
+ *   - Splat parameters are used as given (already activated): opacity in (0, 1], scales > 0.
+ *     Tangents are not renormalised.
+ *   - Textures are [P][N][N][3] indexed [k][i_u][i_v][c] (i_u follows u), float32 or bfloat16.
+ *     Gradients are always float32.
+ */
+#ifndef GBB_H_
+#define GBB_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GB_OK = 0,
+  GB_ERR_ARG = 1,          /* invalid argument; nothing was launched */
+  GB_ERR_HIP = 2,          /* a HIP runtime call failed */
+  GB_ERR_CAPACITY = 3,     /* the (tile, splat) pair count exceeded the workspace capacity */
+  GB_ERR_UNSUPPORTED = 4   /* valid but not built (e.g. texture side N outside {1,2,4,8}) */
+} gb_status;
+
+typedef enum { GB_F32 = 0, GB_BF16 = 1 } gb_dtype;
+
+#define GB_MAX_VIEWS 256
+
+typedef struct {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  float R[9];    /* world -> camera rotation, row-major */
+  float t[3];    /* world -> camera translation */
+  float z_near;  /* splats whose centre depth is not beyond z_near are culled */
+} gb_view;
+
+typedef struct {
+  int32_t P;               /* number of splats, >= 1 */
+  int32_t N;               /* texture side, one of 1, 2, 4, 8 */
+  int32_t tex_dtype;       /* gb_dtype of `textures` */
+  const float* means;      /* [P][3] */
+  const float* tan_u;      /* [P][3] */
+  const float* tan_v;      /* [P][3] */
+  const float* scales;     /* [P][2] (s_u, s_v) */
+  const float* opacity;    /* [P] */
+  const void* textures;    /* [P][N][N][3], float32 or bfloat16 bit patterns */
+} gb_splats;
+
+typedef struct {
+  float sigma;        /* half extent of the colour grid in uv (paper default 0.5) */
+  float alpha_min;    /* skip threshold; >= 1/255 for the tile bound to hold (below it every
+                         splat covers the whole image) */
+  float alpha_max;    /* opacity clamp, e.g. 0.99; 1 switches it off */
+  float t_min;        /* early-termination transmittance, e.g. 1e-4; 0 switches it off */
+  float lowpass_var;  /* variance of the screen-space low-pass in px^2, e.g. 0.5 */
+  float bg[3];        /* background colour composited with the final transmittance */
+  int32_t tile_w;     /* tile width in px: 8, 16 or 32 */
+  int32_t tile_h;     /* tile height in px: 8, 16 or 32; tile_w * tile_h <= 1024 */
+  int32_t batch;      /* splats staged in LDS per batch: 0 = default, else 8..64 (mult. of 8) */
+} gb_options;
+
+/* Output gradients (device, float32, overwritten -- not accumulated). */
+typedef struct {
+  float* d_means;     /* [P][3] */
+  float* d_tan_u;     /* [P][3] */
+  float* d_tan_v;     /* [P][3] */
+  float* d_scales;    /* [P][2] */
+  float* d_opacity;   /* [P] */
+  float* d_textures;  /* [P][N][N][3] float32 */
+} gb_grads;
+
+/* Byte offsets of the workspace sections that tests and tools may read back. */
+typedef struct {
+  size_t total_bytes;
+  size_t status;      /* uint32[4]: pair count K, pairs sorted, overflow flag, reserved */
+  size_t depth_key;   /* uint32[V*P]: float bits of the centre depth, 0xFFFFFFFF if culled */
+  size_t tile_count;  /* uint32[V*P]: tiles covered by record v*P+k */
+  size_t records;     /* 96-byte record per (view, splat): 19 floats of blend geometry, then
+                         int32 i0 | i1 << 16, int32 j0 | j1 << 16 (inclusive pixel rectangle,
+                         valid if the tile count is > 0), int32 splat, int32 view, pad */
+  size_t order;       /* uint32[V*P]: records sorted by (depth, record index) */
+  size_t pair_keys;   /* uint32[capacity]: sorted global tile index of each pair */
+  size_t pair_vals;   /* uint32[capacity]: record index v*P+k of each pair */
+  size_t ranges;      /* uint32[total tiles][2]: [start, end) of each tile's pairs */
+  size_t n_last;      /* uint32[sum HW]: one past the last pair blended at each pixel */
+  int64_t pair_capacity;
+  int64_t total_tiles;
+} gb_layout;
+
+/* Workspace layout for P splats of texture side N over n_views views with room for
+ * `pair_capacity` (tile, splat) pairs. Pure host computation; no device access.
+ * Returns GB_ERR_ARG on invalid sizes or options. */
+gb_status gb_workspace_layout(int32_t P, int32_t N, const gb_view* views, int32_t n_views,
+                              const gb_options* opts, int64_t pair_capacity, gb_layout* out);
+
+/* Runs the per-splat preprocess (key stage: depth, screen rectangle, tile count) for every
+ * (view, splat) and returns the total pair count K in *K_out. The workspace must be laid out
+ * for the same arguments (any capacity). Synchronises `stream`. */
+gb_status gb_count_pairs(const gb_splats* splats, const gb_view* views, int32_t n_views,
+                         const gb_options* opts, void* workspace, size_t ws_bytes,
+                         int64_t pair_capacity, int64_t* K_out, void* stream);
+
+/* Forward render of all views (Alg. 1 forward):
+ *   rgb     [sum HW][3] float32 (device)  composited colour, background included;
+ *   T_final [sum HW]    float32 (device)  transmittance after the last blended splat.
+ * The workspace keeps what gb_render_bwd needs until the next forward on it. If the pair
+ * count exceeds `pair_capacity`, the overflow flag is set on the device, every later stage of
+ * this call does nothing and the images are background; gb_read_status reports it. */
+gb_status gb_render_fwd(const gb_splats* splats, const gb_view* views, int32_t n_views,
+                        const gb_options* opts, void* workspace, size_t ws_bytes,
+                        int64_t pair_capacity, float* rgb, float* T_final, void* stream);
+
+/* Backward of the last gb_render_fwd on `workspace` with the same splats, views, options and
+ * capacity (Alg. 1 backward, Alg. 2 adj-bilinear). T_final is the forward's output;
+ * d_rgb: [sum HW][3] float32 device adjoint of rgb. Writes every field of *grads (all must be
+ * non-NULL). */
+gb_status gb_render_bwd(const gb_splats* splats, const gb_view* views, int32_t n_views,
+                        const gb_options* opts, void* workspace, size_t ws_bytes,
+                        int64_t pair_capacity, const float* T_final, const float* d_rgb,
+                        const gb_grads* grads, void* stream);
+
+/* Waits for `stream`, then reports the pair count of the last forward and its overflow
+ * flag. */
+gb_status gb_read_status(const void* workspace, int64_t* K_out, int32_t* overflow_out,
+                         void* stream);
+
+/* Work counts of one forward, for measurement: runs gb_render_fwd with counting enabled in the
+ * blend kernel and waits for the stream. counts_out[0] = (pixel, splat) pairs blended,
+ * [1] = pixels stopped by the t_min rule, [2] = (pixel, splat) evaluations performed by the
+ * waves (64 per wave and splat evaluated), [3] = (tile, splat) pairs staged into LDS. */
+gb_status gb_blend_stats(const gb_splats* splats, const gb_view* views, int32_t n_views,
+                         const gb_options* opts, void* workspace, size_t ws_bytes,
+                         int64_t pair_capacity, float* rgb, float* T_final, int64_t* counts_out,
+                         void* stream);
+
+/* Stage timing for measurement. While enabled, gb_render_fwd and gb_render_bwd record a HIP
+ * event on their stream before and after each stage (events are created on first use).
+ * gb_timing_read waits for the events of the last forward and backward and writes the elapsed
+ * milliseconds of up to n stages to ms_out (stage names from gb_timing_stage_name). */
+gb_status gb_timing_enable(int32_t on);
+gb_status gb_timing_read(float* ms_out, int32_t n, int32_t* n_written);
+const char* gb_timing_stage_name(int32_t stage);
+
+/* Fills *out with the default options (sigma 0.5, alpha_min 1/255, alpha_max 0.99,
+ * t_min 1e-4, lowpass_var 0.5, black background, 16 x 16 tiles, default batch). */
+void gb_default_options(gb_options* out);
+
+const char* gb_status_string(gb_status status);
+
+/* Last HIP error text recorded by the library in this process (empty if none). */
+const char* gb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GBB_H_ */

@@ -266,8 +266,9 @@ def adj_bilinear(C, u, v, sigma, dc):
 # Ray-splat intersection (Eq. 3 solved for the pixel ray).
 # ---------------------------------------------------------------------------------------
 def intrinsics(view) -> np.ndarray:
-    return np.array([[view.fx, 0.0, view.cx], [0.0, view.fy, view.cy], [0.0, 0.0, 1.0]],
-                    dtype=np.float64)
+    """Pinhole matrix from the float32 camera values the renderer receives."""
+    fx, fy, cx, cy = (float(F32(c)) for c in (view.fx, view.fy, view.cx, view.cy))
+    return np.array([[fx, 0.0, cx], [0.0, fy, cy], [0.0, 0.0, 1.0]], dtype=np.float64)
 
 
 def splat_frame(scene, view, k: int):
@@ -353,7 +354,10 @@ class RenderResult:
     T_final: np.ndarray        # [h, w]
     n_blended: np.ndarray      # [h, w]   splats blended per pixel
     terminated: np.ndarray     # [h, w]   pixel stopped by the t_min rule
-    margin: np.ndarray         # [h, w]   smallest relative distance of a decision to its threshold
+    alpha_gap: np.ndarray      # [h, w]   min relative distance |alpha - alpha_min| / alpha_min
+    t_gap: np.ndarray          # [h, w]   min relative distance |T(1-alpha) - t_min| / t_min
+    kink_gap: np.ndarray       # [h, w]   min relative distance to a gradient-only kink (alpha_max
+                               #          clamp, tie between the two falloff branches)
     crop: Tuple[int, int, int, int]
     # saved for the backward: per blended splat (index, pixel ids, T before, alpha)
     saved: List[Tuple[int, np.ndarray, np.ndarray, np.ndarray]] = dataclasses.field(repr=False,
@@ -399,7 +403,9 @@ def render(scene, view, opts: Options, crop=None, keep_saved: bool = False) -> R
     acc = np.zeros((npx, 3))
     done = np.zeros(npx, dtype=bool)
     nbl = np.zeros(npx, dtype=np.int64)
-    margin = np.full(npx, np.inf)
+    a_gap = np.full(npx, np.inf)
+    t_gap = np.full(npx, np.inf)
+    k_gap = np.full(npx, np.inf)
     saved = []
     evals = 0
     a_min, a_max, t_min = opts.alpha_min, opts.alpha_max, opts.t_min
@@ -414,13 +420,14 @@ def render(scene, view, opts: Options, crop=None, keep_saved: bool = False) -> R
         alpha = np.minimum(a_max, o * G)
         live = active & valid
         m = _rel_gap(alpha, a_min)
-        m = np.minimum(m, _rel_gap(o * G, a_max))
         contrib = live & (alpha >= a_min)
         Tn = T * (1.0 - alpha)
         m_t = _rel_gap(Tn, t_min)
+        m_c = _rel_gap(o * G, a_max)
         m_b = np.abs(q_uv - q_lp) / np.maximum(np.maximum(q_uv, q_lp), 1e-300)
-        margin = np.where(live, np.minimum(margin, m), margin)
-        margin = np.where(contrib, np.minimum(margin, np.minimum(m_t, m_b)), margin)
+        a_gap = np.where(live, np.minimum(a_gap, m), a_gap)
+        t_gap = np.where(contrib, np.minimum(t_gap, m_t), t_gap)
+        k_gap = np.where(contrib, np.minimum(k_gap, np.minimum(m_c, m_b)), k_gap)
         term = contrib & (Tn < t_min)
         blend = contrib & ~term
         if blend.any():
@@ -437,7 +444,27 @@ def render(scene, view, opts: Options, crop=None, keep_saved: bool = False) -> R
     rgb = acc + T[:, None] * bg[None, :]
     h, w = crop[3], crop[2]
     return RenderResult(rgb.reshape(h, w, 3), T.reshape(h, w), nbl.reshape(h, w),
-                        done.reshape(h, w), margin.reshape(h, w), crop, saved, evals)
+                        done.reshape(h, w), a_gap.reshape(h, w), t_gap.reshape(h, w),
+                        k_gap.reshape(h, w), crop, saved, evals)
+
+
+# Default flag thresholds: a float32 renderer reproduces alpha to ~1e-6 relative and the
+# transmittance after ~100 blends to ~1e-5 relative; decisions closer than these to their
+# threshold may legitimately go either way.
+TAU_ALPHA = 1e-5
+TAU_T = 1e-4
+TAU_KINK = 1e-4
+
+
+def image_flags(r: RenderResult, tau_alpha=TAU_ALPHA, tau_t=TAU_T) -> np.ndarray:
+    """Pixels whose image may differ between exact and float32 arithmetic by a discrete
+    decision (alpha_min skip or t_min stop taken differently)."""
+    return (r.alpha_gap < tau_alpha) | (r.t_gap < tau_t)
+
+
+def grad_flags(r: RenderResult, tau_alpha=TAU_ALPHA, tau_t=TAU_T, tau_kink=TAU_KINK) -> np.ndarray:
+    """Image flags plus pixels near a kink of the gradient (alpha_max clamp, branch tie)."""
+    return image_flags(r, tau_alpha, tau_t) | (r.kink_gap < tau_kink)
 
 
 @dataclasses.dataclass

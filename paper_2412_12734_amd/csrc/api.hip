@@ -1,0 +1,463 @@
+// C ABI of libgbb: argument validation, workspace plan, stream-ordered launch sequence.
+//
+// Forward sequence (all on the caller's stream, no host synchronisation):
+//   views -> preprocess (key stage + records) -> depth sort of records (stable, 32-bit key)
+//   -> exclusive scan of tile counts in depth order (K) -> overflow check
+//   -> duplicate into (tile, record) pairs -> stable sort of pairs by tile
+//   -> per-tile ranges -> blend forward.
+// Backward: clear gradient buffers -> blend backward -> preprocess backward.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "gbb_internal.h"
+
+namespace gbb {
+namespace {
+
+thread_local std::string g_last_error;
+
+gb_status hip_fail(hipError_t e, const char* what) {
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%s: %s", what, hipGetErrorString(e));
+  g_last_error = buf;
+  return GB_ERR_HIP;
+}
+
+gb_status arg_fail(const char* what) {
+  g_last_error = what;
+  return GB_ERR_ARG;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+gb_status validate_options(const gb_options* o) {
+  if (!o) return arg_fail("options is NULL");
+  if (!(o->sigma > 0.f) || !std::isfinite(o->sigma)) return arg_fail("sigma must be > 0");
+  if (!(o->alpha_min >= 0.f && o->alpha_min < 1.f)) return arg_fail("alpha_min outside [0,1)");
+  if (!(o->alpha_max > 0.f && o->alpha_max <= 1.f)) return arg_fail("alpha_max outside (0,1]");
+  if (!(o->t_min >= 0.f && o->t_min < 1.f)) return arg_fail("t_min outside [0,1)");
+  if (!(o->lowpass_var > 0.f) || !std::isfinite(o->lowpass_var))
+    return arg_fail("lowpass_var must be > 0");
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(o->bg[i])) return arg_fail("bg must be finite");
+  const int tw = o->tile_w == 0 ? 16 : o->tile_w, th = o->tile_h == 0 ? 16 : o->tile_h;
+  const bool ok_w = tw == 8 || tw == 16 || tw == 32, ok_h = th == 8 || th == 16 || th == 32;
+  if (!ok_w || !ok_h || tw * th > 256) return arg_fail("tile must be 8/16/32 per side, <= 256 px");
+  if (o->batch != 0 && o->batch != 16 && o->batch != 32 && o->batch != 64)
+    return arg_fail("batch must be 0, 16, 32 or 64");
+  return GB_OK;
+}
+
+gb_status validate_views(const gb_view* views, int32_t n_views) {
+  if (!views) return arg_fail("views is NULL");
+  if (n_views < 1 || n_views > GB_MAX_VIEWS) return arg_fail("n_views outside [1, 256]");
+  for (int i = 0; i < n_views; ++i) {
+    const gb_view& v = views[i];
+    if (v.width < 1 || v.height < 1 || v.width > 32767 || v.height > 32767)
+      return arg_fail("view size outside [1, 32767]");
+    if (!(v.fx > 0.f) || !(v.fy > 0.f) || !std::isfinite(v.fx) || !std::isfinite(v.fy) ||
+        !std::isfinite(v.cx) || !std::isfinite(v.cy))
+      return arg_fail("view intrinsics invalid");
+    if (!(v.z_near >= 0.f) || !std::isfinite(v.z_near)) return arg_fail("z_near must be >= 0");
+    for (int k = 0; k < 9; ++k)
+      if (!std::isfinite(v.R[k])) return arg_fail("view rotation not finite");
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(v.t[k])) return arg_fail("view translation not finite");
+  }
+  return GB_OK;
+}
+
+gb_status validate_splats(const gb_splats* s) {
+  if (!s) return arg_fail("splats is NULL");
+  if (s->P < 1) return arg_fail("P must be >= 1");
+  if (!(s->N == 1 || s->N == 2 || s->N == 4 || s->N == 8)) {
+    g_last_error = "texture side N must be 1, 2, 4 or 8";
+    return GB_ERR_UNSUPPORTED;
+  }
+  if (s->tex_dtype != GB_F32 && s->tex_dtype != GB_BF16) {
+    g_last_error = "tex_dtype must be GB_F32 or GB_BF16";
+    return GB_ERR_UNSUPPORTED;
+  }
+  const void* ptrs[] = {s->means, s->tan_u, s->tan_v, s->scales, s->opacity};
+  for (const void* p : ptrs)
+    if (!p || !aligned(p, 4)) return arg_fail("splat array NULL or not 4-byte aligned");
+  if (!s->textures || !aligned(s->textures, 16)) return arg_fail("textures NULL or not 16-byte aligned");
+  return GB_OK;
+}
+
+gb_status make_plan(int32_t P, int32_t N, const gb_view* views, int32_t n_views,
+                    const gb_options* o, int64_t capacity, Plan* pl) {
+  if (capacity < 0 || capacity > (int64_t)0xFFFFFFF0) return arg_fail("pair_capacity outside [0, 2^32-16]");
+  const int64_t VP = (int64_t)P * n_views;
+  if (VP > ((int64_t)1 << 31)) return arg_fail("P * n_views exceeds 2^31");
+  pl->P = P;
+  pl->N = N;
+  pl->V = n_views;
+  pl->VP = VP;
+  pl->capacity = capacity;
+  pl->tile_w = o->tile_w == 0 ? 16 : o->tile_w;
+  pl->tile_h = o->tile_h == 0 ? 16 : o->tile_h;
+  pl->batch_fwd = o->batch != 0 ? o->batch : (N >= 8 ? 32 : 64);
+  pl->batch_bwd = o->batch != 0 ? (o->batch > 32 ? 32 : (o->batch < 16 ? 16 : o->batch))
+                                : (N >= 8 ? 16 : 32);
+  int64_t tiles = 0, pixels = 0;
+  for (int i = 0; i < n_views; ++i) {
+    tiles += (int64_t)((views[i].width + pl->tile_w - 1) / pl->tile_w) *
+             ((views[i].height + pl->tile_h - 1) / pl->tile_h);
+    pixels += (int64_t)views[i].width * views[i].height;
+  }
+  if (tiles >= ((int64_t)1 << 31)) return arg_fail("too many tiles");
+  pl->total_tiles = tiles;
+  pl->total_pixels = pixels;
+  int bits = 1;
+  while (((int64_t)1 << bits) < tiles) ++bits;
+  pl->tile_bits = bits;
+  pl->nb_vp = (VP + kRadixTile - 1) / kRadixTile;
+  pl->nb_pairs = (capacity + kRadixTile - 1) / kRadixTile;
+  const int64_t nb_max = pl->nb_vp > pl->nb_pairs ? pl->nb_vp : pl->nb_pairs;
+  pl->hist_len = 256 * nb_max;
+  int64_t part = (VP + kScanTile - 1) / kScanTile;
+  const int64_t part_h = (pl->hist_len + kScanTile - 1) / kScanTile;
+  if (part_h > part) part = part_h;
+  pl->partials_len = part + 2;
+
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes, 256);
+    return at;
+  };
+  pl->off_status = take(256);
+  pl->off_views = take(sizeof(ViewDev) * (size_t)n_views);
+  pl->off_depth_key = take(4 * (size_t)VP);
+  pl->off_depth_key_alt = take(4 * (size_t)VP);
+  pl->off_order = take(4 * (size_t)VP);
+  pl->off_order_alt = take(4 * (size_t)VP);
+  pl->off_count = take(4 * (size_t)VP);
+  pl->off_offsets = take(4 * (size_t)VP);
+  pl->off_rec = take(sizeof(SplatRec) * (size_t)VP);
+  pl->off_partials = take(4 * (size_t)pl->partials_len);
+  pl->off_hist = take(4 * (size_t)pl->hist_len);
+  pl->off_pair_keys = take(4 * (size_t)capacity);
+  pl->off_pair_vals = take(4 * (size_t)capacity);
+  pl->off_pair_keys_alt = take(4 * (size_t)capacity);
+  pl->off_pair_vals_alt = take(4 * (size_t)capacity);
+  pl->off_ranges = take(8 * (size_t)tiles);
+  pl->off_n_last = take(4 * (size_t)pixels);
+  pl->off_drec = take(4 * (size_t)kRecGrad * (size_t)VP);
+  pl->off_stats = take(64);
+  pl->total = off;
+  return GB_OK;
+}
+
+gb_status check_common(const gb_splats* s, const gb_view* views, int32_t n_views,
+                       const gb_options* o, void* ws, size_t ws_bytes, int64_t cap, Plan* pl) {
+  gb_status st;
+  if ((st = validate_splats(s)) != GB_OK) return st;
+  if ((st = validate_views(views, n_views)) != GB_OK) return st;
+  if ((st = validate_options(o)) != GB_OK) return st;
+  if ((st = make_plan(s->P, s->N, views, n_views, o, cap, pl)) != GB_OK) return st;
+  if (!ws || !aligned(ws, 256)) return arg_fail("workspace NULL or not 256-byte aligned");
+  if (ws_bytes < pl->total) return arg_fail("workspace too small for this plan");
+  return GB_OK;
+}
+
+// ---- stage timing (measurement only) ------------------------------------------------------
+enum Stage {
+  kStPreprocess, kStDepthSort, kStPairScan, kStDuplicate, kStTileSort, kStRanges, kStBlendFwd,
+  kStBwdClear, kStBlendBwd, kStPreprocessBwd, kNumStages
+};
+const char* const kStageNames[kNumStages] = {
+    "preprocess", "depth_sort", "pair_scan", "duplicate", "tile_sort", "ranges", "blend_fwd",
+    "bwd_clear", "blend_bwd", "preprocess_bwd"};
+
+struct Timing {
+  bool on = false;
+  bool created = false;
+  hipEvent_t ev[kNumStages][2];
+  bool recorded[kNumStages] = {};
+} g_timing;
+
+hipError_t stage_mark(int stage, int end, hipStream_t s) {
+  if (!g_timing.on) return hipSuccess;
+  if (!g_timing.created) {
+    for (int i = 0; i < kNumStages; ++i)
+      for (int j = 0; j < 2; ++j) {
+        hipError_t e = hipEventCreate(&g_timing.ev[i][j]);
+        if (e != hipSuccess) return e;
+      }
+    g_timing.created = true;
+  }
+  if (end) g_timing.recorded[stage] = true;
+  return hipEventRecord(g_timing.ev[stage][end], s);
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off);
+}
+
+#define GBB_TRY(expr, what)                     \
+  do {                                          \
+    hipError_t e_ = (expr);                     \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+gb_status run_preprocess(const gb_splats* s, const gb_view* views, int32_t n_views,
+                         const gb_options* o, void* ws, const Plan& pl, hipStream_t st) {
+  GBB_TRY(stage_mark(kStPreprocess, 0, st), "timing");
+  ViewDev* d_views = at<ViewDev>(ws, pl.off_views);
+  GBB_TRY(launch_upload_views(views, n_views, pl.tile_w, pl.tile_h, d_views, st), "upload views");
+  GBB_TRY(launch_preprocess(*s, d_views, n_views, *o, pl.tile_w, pl.tile_h,
+                            at<uint32_t>(ws, pl.off_depth_key),
+                            at<uint32_t>(ws, pl.off_depth_key_alt), at<uint32_t>(ws, pl.off_count),
+                            at<SplatRec>(ws, pl.off_rec), st),
+          "preprocess");
+  GBB_TRY(stage_mark(kStPreprocess, 1, st), "timing");
+  return GB_OK;
+}
+
+}  // namespace
+}  // namespace gbb
+
+using namespace gbb;
+
+extern "C" {
+
+void gb_default_options(gb_options* o) {
+  if (!o) return;
+  o->sigma = 0.5f;
+  o->alpha_min = 1.0f / 255.0f;
+  o->alpha_max = 0.99f;
+  o->t_min = 1e-4f;
+  o->lowpass_var = 0.5f;
+  o->bg[0] = o->bg[1] = o->bg[2] = 0.f;
+  o->tile_w = 16;
+  o->tile_h = 16;
+  o->batch = 0;
+}
+
+const char* gb_status_string(gb_status s) {
+  switch (s) {
+    case GB_OK: return "ok";
+    case GB_ERR_ARG: return "invalid argument";
+    case GB_ERR_HIP: return "HIP runtime error";
+    case GB_ERR_CAPACITY: return "pair capacity exceeded";
+    case GB_ERR_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+const char* gb_last_error(void) { return g_last_error.c_str(); }
+
+gb_status gb_workspace_layout(int32_t P, int32_t N, const gb_view* views, int32_t n_views,
+                              const gb_options* opts, int64_t pair_capacity, gb_layout* out) {
+  if (!out) return arg_fail("out is NULL");
+  if (P < 1) return arg_fail("P must be >= 1");
+  if (!(N == 1 || N == 2 || N == 4 || N == 8)) {
+    g_last_error = "texture side N must be 1, 2, 4 or 8";
+    return GB_ERR_UNSUPPORTED;
+  }
+  gb_status st;
+  if ((st = validate_views(views, n_views)) != GB_OK) return st;
+  if ((st = validate_options(opts)) != GB_OK) return st;
+  Plan pl;
+  if ((st = make_plan(P, N, views, n_views, opts, pair_capacity, &pl)) != GB_OK) return st;
+  out->total_bytes = pl.total;
+  out->status = pl.off_status;
+  out->depth_key = pl.off_depth_key;
+  out->tile_count = pl.off_count;
+  out->records = pl.off_rec;
+  out->order = pl.off_order;
+  out->pair_keys = pl.off_pair_keys;
+  out->pair_vals = pl.off_pair_vals;
+  out->ranges = pl.off_ranges;
+  out->n_last = pl.off_n_last;
+  out->pair_capacity = pl.capacity;
+  out->total_tiles = pl.total_tiles;
+  return GB_OK;
+}
+
+gb_status gb_count_pairs(const gb_splats* s, const gb_view* views, int32_t n_views,
+                         const gb_options* o, void* ws, size_t ws_bytes, int64_t cap,
+                         int64_t* K_out, void* stream) {
+  if (!K_out) return arg_fail("K_out is NULL");
+  Plan pl;
+  gb_status st = check_common(s, views, n_views, o, ws, ws_bytes, cap, &pl);
+  if (st != GB_OK) return st;
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  if ((st = run_preprocess(s, views, n_views, o, ws, pl, hs)) != GB_OK) return st;
+  Status* d_st = at<Status>(ws, pl.off_status);
+  GBB_TRY(launch_scan_u32(at<uint32_t>(ws, pl.off_count), nullptr, at<uint32_t>(ws, pl.off_offsets),
+                          pl.VP, at<uint32_t>(ws, pl.off_partials), &d_st->K, hs),
+          "count scan");
+  Status h;
+  GBB_TRY(hipMemcpyAsync(&h, d_st, sizeof(Status), hipMemcpyDeviceToHost, hs), "read count");
+  GBB_TRY(hipStreamSynchronize(hs), "sync");
+  *K_out = (int64_t)h.K;
+  return GB_OK;
+}
+
+static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32_t n_views,
+                                 const gb_options* o, void* ws, size_t ws_bytes, int64_t cap,
+                                 float* rgb, float* T_final, bool stats, void* stream) {
+  Plan pl;
+  gb_status st = check_common(s, views, n_views, o, ws, ws_bytes, cap, &pl);
+  if (st != GB_OK) return st;
+  if (!rgb || !T_final || !aligned(rgb, 4) || !aligned(T_final, 4))
+    return arg_fail("rgb / T_final NULL or misaligned");
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  if ((st = run_preprocess(s, views, n_views, o, ws, pl, hs)) != GB_OK) return st;
+
+  Status* d_st = at<Status>(ws, pl.off_status);
+  uint32_t* dk_a = at<uint32_t>(ws, pl.off_depth_key_alt);
+  uint32_t* order = at<uint32_t>(ws, pl.off_order);
+  uint32_t* order_alt = at<uint32_t>(ws, pl.off_order_alt);
+  uint32_t* count = at<uint32_t>(ws, pl.off_count);
+  uint32_t* offsets = at<uint32_t>(ws, pl.off_offsets);
+  uint32_t* partials = at<uint32_t>(ws, pl.off_partials);
+  uint32_t* hist = at<uint32_t>(ws, pl.off_hist);
+  uint32_t* pk = at<uint32_t>(ws, pl.off_pair_keys);
+  uint32_t* pv = at<uint32_t>(ws, pl.off_pair_vals);
+  uint32_t* pk_a = at<uint32_t>(ws, pl.off_pair_keys_alt);
+  uint32_t* pv_a = at<uint32_t>(ws, pl.off_pair_vals_alt);
+  uint32_t* ranges = at<uint32_t>(ws, pl.off_ranges);
+  ViewDev* d_views = at<ViewDev>(ws, pl.off_views);
+  SplatRec* rec = at<SplatRec>(ws, pl.off_rec);
+  unsigned long long* d_stats = at<unsigned long long>(ws, pl.off_stats);
+
+  // depth order of all records: sort the key copy written by the preprocess, carrying
+  // record indices (the offsets array is free until the scan and serves as ping-pong space)
+  GBB_TRY(stage_mark(kStDepthSort, 0, hs), "timing");
+  GBB_TRY(launch_iota_u32(order, pl.VP, hs), "iota");
+  GBB_TRY(launch_radix_sort(dk_a, order, offsets, order_alt, nullptr, pl.VP, 32, hist, partials, hs),
+          "depth sort");
+  GBB_TRY(stage_mark(kStDepthSort, 1, hs), "timing");
+  // tile counts in depth order -> pair offsets and K
+  GBB_TRY(stage_mark(kStPairScan, 0, hs), "timing");
+  GBB_TRY(launch_scan_u32(count, order, offsets, pl.VP, partials, &d_st->K, hs), "pair scan");
+  GBB_TRY(launch_finalize_count(d_st, pl.capacity, hs), "finalize count");
+  GBB_TRY(stage_mark(kStPairScan, 1, hs), "timing");
+  GBB_TRY(stage_mark(kStDuplicate, 0, hs), "timing");
+  GBB_TRY(launch_duplicate(order, count, offsets, rec, d_views, pl.VP, pl.tile_w, pl.tile_h, d_st,
+                           pk, pv, hs),
+          "duplicate");
+  GBB_TRY(stage_mark(kStDuplicate, 1, hs), "timing");
+  GBB_TRY(stage_mark(kStTileSort, 0, hs), "timing");
+  GBB_TRY(launch_radix_sort(pk, pv, pk_a, pv_a, &d_st->n_sorted, pl.capacity, pl.tile_bits, hist,
+                            partials, hs),
+          "tile sort");
+  GBB_TRY(stage_mark(kStTileSort, 1, hs), "timing");
+  GBB_TRY(stage_mark(kStRanges, 0, hs), "timing");
+  GBB_TRY(launch_fill_u32(ranges, 0u, 2 * pl.total_tiles, hs), "clear ranges");
+  GBB_TRY(launch_ranges(pk, d_st, pl.capacity, ranges, hs), "ranges");
+  GBB_TRY(stage_mark(kStRanges, 1, hs), "timing");
+  if (stats)
+    GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_stats), 0u, 8, hs), "clear stats");
+  GBB_TRY(stage_mark(kStBlendFwd, 0, hs), "timing");
+  GBB_TRY(launch_blend_fwd(pl, *s, *o, d_views, n_views, rec, pv, ranges, rgb, T_final,
+                           at<uint32_t>(ws, pl.off_n_last), stats ? d_stats : nullptr, hs),
+          "blend forward");
+  GBB_TRY(stage_mark(kStBlendFwd, 1, hs), "timing");
+  return GB_OK;
+}
+
+gb_status gb_render_fwd(const gb_splats* s, const gb_view* views, int32_t n_views,
+                        const gb_options* o, void* ws, size_t ws_bytes, int64_t cap, float* rgb,
+                        float* T_final, void* stream) {
+  return render_fwd_impl(s, views, n_views, o, ws, ws_bytes, cap, rgb, T_final, false, stream);
+}
+
+gb_status gb_blend_stats(const gb_splats* s, const gb_view* views, int32_t n_views,
+                         const gb_options* o, void* ws, size_t ws_bytes, int64_t cap, float* rgb,
+                         float* T_final, int64_t* counts, void* stream) {
+  if (!counts) return arg_fail("counts_out is NULL");
+  gb_status st = render_fwd_impl(s, views, n_views, o, ws, ws_bytes, cap, rgb, T_final, true,
+                                 stream);
+  if (st != GB_OK) return st;
+  Plan pl;
+  make_plan(s->P, s->N, views, n_views, o, cap, &pl);
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  unsigned long long h[4];
+  GBB_TRY(hipMemcpyAsync(h, at<char>(ws, pl.off_stats), sizeof(h), hipMemcpyDeviceToHost, hs),
+          "read stats");
+  GBB_TRY(hipStreamSynchronize(hs), "sync");
+  for (int i = 0; i < 4; ++i) counts[i] = (int64_t)h[i];
+  return GB_OK;
+}
+
+gb_status gb_timing_enable(int32_t on) {
+  g_timing.on = on != 0;
+  for (int i = 0; i < kNumStages; ++i) g_timing.recorded[i] = false;
+  return GB_OK;
+}
+
+gb_status gb_timing_read(float* ms, int32_t n, int32_t* n_written) {
+  if (!ms || !n_written) return arg_fail("NULL argument");
+  int k = 0;
+  for (int i = 0; i < kNumStages && i < n; ++i, ++k) {
+    ms[i] = -1.f;
+    if (!g_timing.created || !g_timing.recorded[i]) continue;
+    GBB_TRY(hipEventSynchronize(g_timing.ev[i][1]), "event sync");
+    GBB_TRY(hipEventElapsedTime(&ms[i], g_timing.ev[i][0], g_timing.ev[i][1]), "elapsed");
+  }
+  *n_written = k;
+  return GB_OK;
+}
+
+const char* gb_timing_stage_name(int32_t stage) {
+  if (stage < 0 || stage >= kNumStages) return "";
+  return kStageNames[stage];
+}
+
+gb_status gb_render_bwd(const gb_splats* s, const gb_view* views, int32_t n_views,
+                        const gb_options* o, void* ws, size_t ws_bytes, int64_t cap,
+                        const float* T_final, const float* d_rgb, const gb_grads* g,
+                        void* stream) {
+  Plan pl;
+  gb_status st = check_common(s, views, n_views, o, ws, ws_bytes, cap, &pl);
+  if (st != GB_OK) return st;
+  if (!T_final || !d_rgb || !g) return arg_fail("T_final / d_rgb / grads NULL");
+  const void* gp[] = {g->d_means, g->d_tan_u, g->d_tan_v, g->d_scales, g->d_opacity, g->d_textures};
+  for (const void* p : gp)
+    if (!p || !aligned(p, 4)) return arg_fail("gradient array NULL or misaligned");
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  float* d_rec = at<float>(ws, pl.off_drec);
+  GBB_TRY(stage_mark(kStBwdClear, 0, hs), "timing");
+  GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_rec), 0u, kRecGrad * pl.VP, hs), "clear d_rec");
+  GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(g->d_textures), 0u,
+                          (int64_t)s->P * 3 * s->N * s->N, hs),
+          "clear d_textures");
+  GBB_TRY(stage_mark(kStBwdClear, 1, hs), "timing");
+  ViewDev* d_views = at<ViewDev>(ws, pl.off_views);
+  GBB_TRY(stage_mark(kStBlendBwd, 0, hs), "timing");
+  GBB_TRY(launch_blend_bwd(pl, *s, *o, d_views, n_views, at<SplatRec>(ws, pl.off_rec),
+                           at<uint32_t>(ws, pl.off_pair_vals), at<uint32_t>(ws, pl.off_ranges),
+                           T_final, at<uint32_t>(ws, pl.off_n_last), d_rgb, d_rec, g->d_textures,
+                           hs),
+          "blend backward");
+  GBB_TRY(stage_mark(kStBlendBwd, 1, hs), "timing");
+  GBB_TRY(stage_mark(kStPreprocessBwd, 0, hs), "timing");
+  GBB_TRY(launch_preprocess_bwd(*s, d_views, n_views, at<uint32_t>(ws, pl.off_count), d_rec, *g,
+                                hs),
+          "preprocess backward");
+  GBB_TRY(stage_mark(kStPreprocessBwd, 1, hs), "timing");
+  return GB_OK;
+}
+
+gb_status gb_read_status(const void* ws, int64_t* K_out, int32_t* overflow_out, void* stream) {
+  if (!ws || !K_out || !overflow_out) return arg_fail("NULL argument");
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  Status h;
+  GBB_TRY(hipMemcpyAsync(&h, ws, sizeof(Status), hipMemcpyDeviceToHost, hs), "read status");
+  GBB_TRY(hipStreamSynchronize(hs), "sync");
+  *K_out = (int64_t)h.K;
+  *overflow_out = (int32_t)h.overflow;
+  return GB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,288 @@
+// Backward blend (Alg. 1 backward with Alg. 2 adj-bilinear): one workgroup per tile walks the
+// tile's pairs back to front in LDS batches, starting at the last pair any of its pixels
+// blended. Each pixel starts from its saved T_final and S = T_final * bg and, for every splat
+// it blended (index below its saved bound, alpha >= alpha_min), in reverse order:
+//   T_k = T_{k+1} / (1 - alpha_k), w = alpha_k T_k, colour adjoint w g,
+//   adj-bilinear -> texel gradients and (du, dv),
+//   d alpha = g . (col T_k - S / (1 - alpha_k)), S += w col,
+//   d o = d alpha G, dq = -G o d alpha (both zero where alpha was clamped to alpha_max),
+//   uv branch: du += dq u, dv += dq v; low-pass branch: d(dx, dy) += dq 2 (dx, dy) / (2 var),
+//   (u, v) = (rho0, rho1) / rho2 -> d rho -> d H (7 entries) and d(dx, dy) -> d c2 = -d(dx, dy).
+// The ten per-splat scalars are summed over the wave with DPP and added to the batch slot in
+// LDS; texel gradients are added to LDS with ds_add_f32. After each batch the non-zero LDS
+// sums go to global memory with one float atomic each.
+#include "blend_common.h"
+
+namespace gbb {
+
+namespace {
+
+template <int N, bool BF16, int B>
+__global__ void __launch_bounds__(256)
+blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__ rec,
+                 const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ ranges,
+                 const void* __restrict__ textures, BlendParams p,
+                 const float* __restrict__ T_final, const uint32_t* __restrict__ n_last,
+                 const float* __restrict__ d_rgb, float* __restrict__ d_rec,
+                 float* __restrict__ d_tex) {
+  constexpr int TEXG = 3 * N * N;
+  __shared__ float4 s_geo[B][4];
+  __shared__ int32_t s_splat[B];
+  __shared__ uint32_t s_recid[B];
+  __shared__ float4 s_tex[B * N * N];
+  __shared__ float s_gtex[B * TEXG];
+  __shared__ float s_grec[B * kRecGrad];
+  __shared__ uint32_t s_tile_last;
+
+  const int tile = tile_of_block(p);
+  if (tile >= p.total_tiles) return;
+  const int vi = view_of_tile(views, p.n_views, tile);
+  const ViewDev& V = views[vi];
+  const int lt = tile - V.tile_base;
+  const int tile_x0 = (lt % V.tiles_x) * p.tile_w;
+  const int tile_y0 = (lt / V.tiles_x) * p.tile_h;
+
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int w = tid >> 6, lane = tid & 63;
+  const int waves_x = p.tile_w >> 3;
+  const int bx = (w % waves_x) * 8, by = (w / waves_x) * 8;
+  const int lxi = bx + (lane & 7), lyi = by + (lane >> 3);
+  const int px = tile_x0 + lxi, py = tile_y0 + lyi;
+  const bool inside = px < V.W && py < V.H;
+  // pixel centre relative to the tile centre (exact half-integers)
+  const float lx = (float)lxi - 0.5f * (float)(p.tile_w - 1);
+  const float ly = (float)lyi - 0.5f * (float)(p.tile_h - 1);
+  const int wx0 = tile_x0 + bx, wx1 = wx0 + 7, wy0 = tile_y0 + by, wy1 = wy0 + 7;
+
+  const uint32_t start = ranges[2 * tile];
+  float T = 1.0f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
+  uint32_t last = start;
+  if (inside) {
+    const int64_t pix = (int64_t)V.pix_base + (int64_t)py * V.W + px;
+    T = T_final[pix];
+    last = n_last[pix];
+    g0 = d_rgb[3 * pix + 0];
+    g1 = d_rgb[3 * pix + 1];
+    g2 = d_rgb[3 * pix + 2];
+  }
+  float S0 = T * p.bg[0], S1 = T * p.bg[1], S2 = T * p.bg[2];
+
+  if (tid == 0) s_tile_last = start;
+  __syncthreads();
+  {
+    // largest bound over the tile's pixels
+    uint32_t m = last;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t o = __shfl_xor(m, d, 64);
+      m = o > m ? o : m;
+    }
+    if (lane == 0) atomicMax(&s_tile_last, m);
+  }
+  __syncthreads();
+  const uint32_t tile_last = s_tile_last;
+
+  for (uint32_t bend = tile_last; bend > start;) {
+    const uint32_t bstart = (bend - start) > (uint32_t)B ? bend - (uint32_t)B : start;
+    const int nb = (int)(bend - bstart);
+    if (tid < nb) {
+      const uint32_t r = pair_vals[bstart + tid];
+      const SplatRec R = rec[r];
+      const StagedGeo g = stage_geo(R, tile_x0, tile_y0, p.tile_w, p.tile_h);
+      s_geo[tid][0] = g.g0;
+      s_geo[tid][1] = g.g1;
+      s_geo[tid][2] = g.g2;
+      s_geo[tid][3] = g.g3;
+      s_splat[tid] = R.splat;
+      s_recid[tid] = r;
+    }
+    for (int e = tid; e < nb * TEXG; e += nthr) s_gtex[e] = 0.f;
+    for (int e = tid; e < nb * kRecGrad; e += nthr) s_grec[e] = 0.f;
+    __syncthreads();
+    stage_texels<N, BF16>(textures, s_splat, nb, s_tex);
+    __syncthreads();
+
+    for (int j = nb - 1; j >= 0; --j) {
+      const uint32_t jg = bstart + (uint32_t)j;
+      StagedGeo g;
+      g.g3 = s_geo[j][3];
+      const int rx = __float_as_int(g.g3.x), ry = __float_as_int(g.g3.y);
+      const int i0 = rx & 0xffff, i1 = rx >> 16, j0 = ry & 0xffff, j1 = ry >> 16;
+      if (i1 < wx0 || i0 > wx1 || j1 < wy0 || j0 > wy1) continue;
+      if (!__any(jg < last)) continue;
+      g.g0 = s_geo[j][0];
+      g.g1 = s_geo[j][1];
+      g.g2 = s_geo[j][2];
+      const PixelEval e = eval_splat(g, lx, ly, p);
+      const bool act = (jg < last) && e.hit;
+      float gh[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      float gc2x = 0.f, gc2y = 0.f, go = 0.f;
+      if (act) {
+        const float one_m = 1.0f - e.alpha;
+        T = T / one_m;  // transmittance in front of this splat
+        float c0, c1, c2;
+        float du = 0.f, dv = 0.f;
+        const float wgt = e.alpha * T;
+        const float dc0 = wgt * g0, dc1 = wgt * g1, dc2 = wgt * g2;
+        const float4* tex = s_tex + j * N * N;
+        float* gt = s_gtex + j * TEXG;
+        if constexpr (N == 1) {
+          const float4 t = tex[0];
+          c0 = t.x;
+          c1 = t.y;
+          c2 = t.z;
+          atomicAdd(&gt[0], dc0);
+          atomicAdd(&gt[1], dc1);
+          atomicAdd(&gt[2], dc2);
+        } else {
+          int iu, iv;
+          float fu, fv;
+          grid_coord<N>(e.u, p, iu, fu);
+          grid_coord<N>(e.v, p, iv, fv);
+          const int k00 = iu * N + iv, k01 = k00 + 1, k10 = k00 + N, k11 = k00 + N + 1;
+          const float4 t00 = tex[k00], t01 = tex[k01], t10 = tex[k10], t11 = tex[k11];
+          const float a0 = t00.x + fv * (t01.x - t00.x), b0_ = t10.x + fv * (t11.x - t10.x);
+          const float a1 = t00.y + fv * (t01.y - t00.y), b1 = t10.y + fv * (t11.y - t10.y);
+          const float a2 = t00.z + fv * (t01.z - t00.z), b2 = t10.z + fv * (t11.z - t10.z);
+          c0 = a0 + fu * (b0_ - a0);
+          c1 = a1 + fu * (b1 - a1);
+          c2 = a2 + fu * (b2 - a2);
+          // texel adjoints
+          const float w00 = (1.f - fu) * (1.f - fv), w01 = (1.f - fu) * fv;
+          const float w10 = fu * (1.f - fv), w11 = fu * fv;
+          atomicAdd(&gt[3 * k00 + 0], dc0 * w00);
+          atomicAdd(&gt[3 * k00 + 1], dc1 * w00);
+          atomicAdd(&gt[3 * k00 + 2], dc2 * w00);
+          atomicAdd(&gt[3 * k01 + 0], dc0 * w01);
+          atomicAdd(&gt[3 * k01 + 1], dc1 * w01);
+          atomicAdd(&gt[3 * k01 + 2], dc2 * w01);
+          atomicAdd(&gt[3 * k10 + 0], dc0 * w10);
+          atomicAdd(&gt[3 * k10 + 1], dc1 * w10);
+          atomicAdd(&gt[3 * k10 + 2], dc2 * w10);
+          atomicAdd(&gt[3 * k11 + 0], dc0 * w11);
+          atomicAdd(&gt[3 * k11 + 1], dc1 * w11);
+          atomicAdd(&gt[3 * k11 + 2], dc2 * w11);
+          // fractional-position adjoints (Alg. 2), zero where the coordinate is clamped
+          const float dfu = dc0 * (b0_ - a0) + dc1 * (b1 - a1) + dc2 * (b2 - a2);
+          const float fv0 = (t01.x - t00.x) * (1.f - fu) + (t11.x - t10.x) * fu;
+          const float fv1 = (t01.y - t00.y) * (1.f - fu) + (t11.y - t10.y) * fu;
+          const float fv2 = (t01.z - t00.z) * (1.f - fu) + (t11.z - t10.z) * fu;
+          const float dfv = dc0 * fv0 + dc1 * fv1 + dc2 * fv2;
+          du = (e.u > -p.sigma && e.u < p.sigma) ? p.tex_scale * dfu : 0.f;
+          dv = (e.v > -p.sigma && e.v < p.sigma) ? p.tex_scale * dfv : 0.f;
+        }
+        const float inv1m = 1.0f / one_m;
+        const float dalpha = g0 * (c0 * T - S0 * inv1m) + g1 * (c1 * T - S1 * inv1m) +
+                             g2 * (c2 * T - S2 * inv1m);
+        S0 += wgt * c0;
+        S1 += wgt * c1;
+        S2 += wgt * c2;
+        const bool unclamped = g.g0.w * e.G <= p.alpha_max;
+        go = unclamped ? dalpha * e.G : 0.f;
+        const float dq = unclamped ? -e.G * g.g0.w * dalpha : 0.f;
+        float ddx = 0.f, ddy = 0.f;
+        if (e.uv_branch) {
+          du += dq * e.u;
+          dv += dq * e.v;
+        } else {
+          ddx = dq * 2.f * p.lp_scale * e.dx;
+          ddy = dq * 2.f * p.lp_scale * e.dy;
+        }
+        const float dr0 = du * e.inv, dr1 = dv * e.inv;
+        const float dr2 = -(du * e.u + dv * e.v) * e.inv;
+        gh[0] = dr0 * e.dx;
+        gh[1] = dr0 * e.dy;
+        gh[2] = dr1 * e.dx;
+        gh[3] = dr1 * e.dy;
+        gh[4] = dr2 * e.dx;
+        gh[5] = dr2 * e.dy;
+        gh[6] = dr2;
+        ddx += dr0 * g.g1.x + dr1 * g.g1.z + dr2 * g.g2.x;
+        ddy += dr0 * g.g1.y + dr1 * g.g1.w + dr2 * g.g2.y;
+        gc2x = -ddx;
+        gc2y = -ddy;
+      }
+      // wave sums of the per-splat scalars (all lanes take part)
+      float* gr = s_grec + j * kRecGrad;
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        const float s = wave_sum_to_lane63(gh[k]);
+        if (lane == 63) atomicAdd(&gr[k], s);
+      }
+      {
+        const float s7 = wave_sum_to_lane63(gc2x);
+        const float s8 = wave_sum_to_lane63(gc2y);
+        const float s9 = wave_sum_to_lane63(go);
+        if (lane == 63) {
+          atomicAdd(&gr[7], s7);
+          atomicAdd(&gr[8], s8);
+          atomicAdd(&gr[9], s9);
+        }
+      }
+    }
+    __syncthreads();
+    // flush the batch's sums
+    for (int e = tid; e < nb * TEXG; e += nthr) {
+      const float x = s_gtex[e];
+      if (x != 0.f) {
+        const int j = e / TEXG, r = e - j * TEXG;
+        atomicAdd(&d_tex[(int64_t)s_splat[j] * TEXG + r], x);
+      }
+    }
+    for (int e = tid; e < nb * kRecGrad; e += nthr) {
+      const float x = s_grec[e];
+      if (x != 0.f) {
+        const int j = e / kRecGrad, r = e - j * kRecGrad;
+        atomicAdd(&d_rec[(int64_t)s_recid[j] * kRecGrad + r], x);
+      }
+    }
+    __syncthreads();
+    bend = bstart;
+  }
+}
+
+template <int N, bool BF16>
+hipError_t launch_n(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
+                    const ViewDev* views, const SplatRec* rec, const uint32_t* pair_vals,
+                    const uint32_t* ranges, const float* T_final, const uint32_t* n_last,
+                    const float* d_rgb, float* d_rec, float* d_tex, hipStream_t s) {
+  const dim3 grid((unsigned)(8 * (int64_t)bp.tiles_per_xcd));
+  const dim3 block((unsigned)(pl.tile_w * pl.tile_h));
+  switch (pl.batch_bwd) {
+    case 32:
+      hipLaunchKernelGGL((blend_bwd_kernel<N, BF16, 32>), grid, block, 0, s, views, rec,
+                         pair_vals, ranges, sp.textures, bp, T_final, n_last, d_rgb, d_rec, d_tex);
+      break;
+    default:
+      hipLaunchKernelGGL((blend_bwd_kernel<N, BF16, 16>), grid, block, 0, s, views, rec,
+                         pair_vals, ranges, sp.textures, bp, T_final, n_last, d_rgb, d_rec, d_tex);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_blend_bwd(const Plan& pl, const gb_splats& sp, const gb_options& o,
+                            const ViewDev* views, int n_views, const SplatRec* rec,
+                            const uint32_t* pair_vals, const uint32_t* ranges,
+                            const float* T_final, const uint32_t* n_last, const float* d_rgb,
+                            float* d_rec, float* d_tex, hipStream_t s) {
+  const BlendParams bp = make_blend_params(pl, o, n_views);
+  const bool bf = sp.tex_dtype == GB_BF16;
+#define GBB_BWD(NN)                                                                        \
+  return bf ? launch_n<NN, true>(pl, sp, bp, views, rec, pair_vals, ranges, T_final, n_last, \
+                                 d_rgb, d_rec, d_tex, s)                                    \
+            : launch_n<NN, false>(pl, sp, bp, views, rec, pair_vals, ranges, T_final, n_last, \
+                                  d_rgb, d_rec, d_tex, s)
+  switch (pl.N) {
+    case 1: GBB_BWD(1);
+    case 2: GBB_BWD(2);
+    case 4: GBB_BWD(4);
+    case 8: GBB_BWD(8);
+    default: return hipErrorInvalidValue;
+  }
+#undef GBB_BWD
+}
+
+}  // namespace gbb

@@ -1,0 +1,155 @@
+// Pieces shared by the forward and backward blend kernels: the launch parameters, the
+// XCD-aware tile schedule, LDS staging of splat batches (geometry and texels) and the
+// per-pixel evaluation of one splat (ray-splat uv, falloff, opacity, bilinear colour).
+#pragma once
+
+#include "device_util.h"
+#include "gbb_internal.h"
+
+namespace gbb {
+
+struct BlendParams {
+  float tex_scale;    // (N - 1) / (2 sigma): uv -> grid coordinate slope
+  float tex_offset;   // (N - 1) / 2
+  float sigma;
+  float alpha_min, alpha_max, t_min;
+  float lp_scale;     // 1 / (2 lowpass_var)
+  float bg[3];
+  int32_t tile_w, tile_h;
+  int32_t n_views;
+  int32_t total_tiles;
+  int32_t tiles_per_xcd;
+};
+
+BlendParams make_blend_params(const Plan& pl, const gb_options& o, int n_views);
+
+// Workgroups are handed to the 8 XCDs round-robin; give each XCD one contiguous band of
+// tiles so that neighbouring tiles (which share splats) hit the same L2.
+__device__ __forceinline__ int tile_of_block(const BlendParams& p) {
+  const int b = blockIdx.x;
+  return (b & 7) * p.tiles_per_xcd + (b >> 3);
+}
+
+__device__ __forceinline__ int view_of_tile(const ViewDev* views, int n_views, int tile) {
+  int v = 0;
+  while (v + 1 < n_views && views[v + 1].tile_base <= tile) ++v;
+  return v;
+}
+
+// Geometry of one staged splat, re-centred on the tile. With (lx, ly) a pixel's offset from
+// the tile centre (half-integers, exact), rho = A + (h00 lx + h01 ly, h10 lx + h11 ly,
+// h20 lx + h21 ly), where A is rho at the tile centre, evaluated in pair precision.
+//   g0 = (A0, A1, A2, opacity), g1 = (h00, h01, h10, h11), g2 = (h20, h21, ox, oy),
+//   g3 = (rect_x, rect_y, -, -); (ox, oy) = tile centre minus projected centre.
+struct StagedGeo {
+  float4 g0, g1, g2, g3;
+};
+
+__device__ __forceinline__ StagedGeo stage_geo(const SplatRec& r, int tile_x0, int tile_y0,
+                                               int tile_w, int tile_h) {
+  const f2 ox = f2_sub(f2_of((float)tile_x0 + 0.5f * (float)tile_w), f2{r.c2x_hi, r.c2x_lo});
+  const f2 oy = f2_sub(f2_of((float)tile_y0 + 0.5f * (float)tile_h), f2{r.c2y_hi, r.c2y_lo});
+  f2 h[7];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) h[i] = f2{r.h_hi[i], r.h_lo[i]};
+  const f2 A0 = f2_add(f2_mul(h[0], ox), f2_mul(h[1], oy));
+  const f2 A1 = f2_add(f2_mul(h[2], ox), f2_mul(h[3], oy));
+  const f2 A2 = f2_add(f2_add(f2_mul(h[4], ox), f2_mul(h[5], oy)), h[6]);
+  StagedGeo s;
+  s.g0 = make_float4(f2_round(A0), f2_round(A1), f2_round(A2), r.opacity);
+  s.g1 = make_float4(r.h_hi[0], r.h_hi[1], r.h_hi[2], r.h_hi[3]);
+  s.g2 = make_float4(r.h_hi[4], r.h_hi[5], f2_round(ox), f2_round(oy));
+  s.g3 = make_float4(__int_as_float(r.rect_x), __int_as_float(r.rect_y), 0.f, 0.f);
+  return s;
+}
+
+// Copies the texels of `nb` staged splats into LDS as float4 (RGB + pad) per texel.
+template <int N, bool BF16>
+__device__ __forceinline__ void stage_texels(const void* __restrict__ textures,
+                                             const int32_t* s_splat, int nb, float4* s_tex) {
+  constexpr int per = 3 * N * N;  // channel values per splat
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  if constexpr (!BF16 && (per % 4) == 0) {
+    constexpr int per4 = per / 4;
+    const float4* tex4 = reinterpret_cast<const float4*>(textures);
+    for (int e = tid; e < nb * per4; e += nthr) {
+      const int j = e / per4, r4 = e - j * per4;
+      const float4 v = tex4[(int64_t)s_splat[j] * per4 + r4];
+      float* dst = reinterpret_cast<float*>(s_tex + j * N * N);
+      const int r = 4 * r4;
+      // channel value r lives at texel r / 3, component r % 3
+      dst[(r + 0) / 3 * 4 + (r + 0) % 3] = v.x;
+      dst[(r + 1) / 3 * 4 + (r + 1) % 3] = v.y;
+      dst[(r + 2) / 3 * 4 + (r + 2) % 3] = v.z;
+      dst[(r + 3) / 3 * 4 + (r + 3) % 3] = v.w;
+    }
+  } else if constexpr (BF16 && (per % 4) == 0) {
+    constexpr int per4 = per / 4;
+    const uint2* tex4 = reinterpret_cast<const uint2*>(textures);
+    for (int e = tid; e < nb * per4; e += nthr) {
+      const int j = e / per4, r4 = e - j * per4;
+      const uint2 v = tex4[(int64_t)s_splat[j] * per4 + r4];
+      float* dst = reinterpret_cast<float*>(s_tex + j * N * N);
+      const int r = 4 * r4;
+      dst[(r + 0) / 3 * 4 + (r + 0) % 3] = __uint_as_float(v.x << 16);
+      dst[(r + 1) / 3 * 4 + (r + 1) % 3] = __uint_as_float(v.x & 0xffff0000u);
+      dst[(r + 2) / 3 * 4 + (r + 2) % 3] = __uint_as_float(v.y << 16);
+      dst[(r + 3) / 3 * 4 + (r + 3) % 3] = __uint_as_float(v.y & 0xffff0000u);
+    }
+  } else {
+    for (int e = tid; e < nb * per; e += nthr) {
+      const int j = e / per, r = e - j * per;
+      float x;
+      if constexpr (BF16)
+        x = bf16_to_f32(reinterpret_cast<const uint16_t*>(textures)[(int64_t)s_splat[j] * per + r]);
+      else
+        x = reinterpret_cast<const float*>(textures)[(int64_t)s_splat[j] * per + r];
+      reinterpret_cast<float*>(s_tex + j * N * N)[r / 3 * 4 + r % 3] = x;
+    }
+  }
+}
+
+// Ray-splat solve and falloff of one splat at one pixel.
+struct PixelEval {
+  float dx, dy;       // pixel centre minus projected centre (float32; low-pass and gradients)
+  float inv;          // 1 / rho2
+  float u, v;
+  float G;            // exp(-q)
+  float alpha;
+  bool uv_branch;     // q came from the uv Gaussian (else from the screen low-pass)
+  bool hit;           // rho2 != 0 and alpha >= alpha_min
+};
+
+// (lx, ly): pixel centre minus tile centre.
+__device__ __forceinline__ PixelEval eval_splat(const StagedGeo& s, float lx, float ly,
+                                                const BlendParams& p) {
+  PixelEval e;
+  e.dx = lx + s.g2.z;
+  e.dy = ly + s.g2.w;
+  const float r0 = __builtin_fmaf(s.g1.y, ly, __builtin_fmaf(s.g1.x, lx, s.g0.x));
+  const float r1 = __builtin_fmaf(s.g1.w, ly, __builtin_fmaf(s.g1.z, lx, s.g0.y));
+  const float r2 = __builtin_fmaf(s.g2.y, ly, __builtin_fmaf(s.g2.x, lx, s.g0.z));
+  e.inv = __builtin_amdgcn_rcpf(r2);
+  e.u = r0 * e.inv;
+  e.v = r1 * e.inv;
+  const float q_uv = 0.5f * (e.u * e.u + e.v * e.v);
+  const float q_lp = (e.dx * e.dx + e.dy * e.dy) * p.lp_scale;
+  e.uv_branch = q_uv <= q_lp;
+  const float q = e.uv_branch ? q_uv : q_lp;
+  e.G = __builtin_amdgcn_exp2f(-q * 1.4426950408889634f);
+  e.alpha = fminf(p.alpha_max, s.g0.w * e.G);
+  e.hit = (r2 != 0.0f) && (e.alpha >= p.alpha_min);
+  return e;
+}
+
+// Grid coordinate of u on the corner-aligned N-texel grid (Alg. 2 with the cell index taken
+// from the remapped coordinate and limited to N - 2 at the clamped top edge).
+template <int N>
+__device__ __forceinline__ void grid_coord(float u, const BlendParams& p, int& i, float& f) {
+  const float up = fminf(fmaxf(__builtin_fmaf(u, p.tex_scale, p.tex_offset), 0.0f), (float)(N - 1));
+  const int fi = (int)floorf(up);
+  i = fi < N - 2 ? fi : N - 2;
+  f = up - (float)i;
+}
+
+}  // namespace gbb

@@ -1,0 +1,226 @@
+// Forward blend (Alg. 1 forward with Alg. 2 bilinear): one workgroup per tile, one lane per
+// pixel, each wave owning an 8 x 8 pixel block. The tile's depth-sorted splats are staged
+// into LDS in batches (geometry plus texels, bfloat16 decoded on staging). A wave skips a
+// splat whose screen rectangle misses its block, and stops when all of its pixels have
+// terminated; the workgroup stops staging when every wave has.
+//
+// Per pixel and splat: (u, v) from the centre-relative homography, G = exp(-min(q_uv, q_lp)),
+// alpha = min(alpha_max, o G); alpha < alpha_min is skipped; if T (1 - alpha) < t_min the
+// pixel ends without blending it; otherwise acc += alpha T bilinear(C, u, v), T *= 1 - alpha.
+// Saved for the backward: T_final and one past the index of the last blended pair.
+#include "blend_common.h"
+
+namespace gbb {
+
+namespace {
+
+// With STATS the kernel also counts its work into stats[0..3]: blended pairs, pixels stopped
+// by t_min, lane evaluations (64 per wave and evaluated splat) and staged (tile, splat) pairs.
+template <int N, bool BF16, int B, bool STATS>
+__global__ void __launch_bounds__(256)
+blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__ rec,
+                 const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ ranges,
+                 const void* __restrict__ textures, BlendParams p, float* __restrict__ rgb,
+                 float* __restrict__ T_final, uint32_t* __restrict__ n_last,
+                 unsigned long long* __restrict__ stats) {
+  __shared__ float4 s_geo[B][4];
+  __shared__ int32_t s_splat[B];
+  __shared__ float4 s_tex[B * N * N];
+
+  const int tile = tile_of_block(p);
+  if (tile >= p.total_tiles) return;
+  const int vi = view_of_tile(views, p.n_views, tile);
+  const ViewDev& V = views[vi];
+  const int lt = tile - V.tile_base;
+  const int tile_x0 = (lt % V.tiles_x) * p.tile_w;
+  const int tile_y0 = (lt / V.tiles_x) * p.tile_h;
+
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, lane = tid & 63;
+  const int waves_x = p.tile_w >> 3;
+  const int bx = (w % waves_x) * 8, by = (w / waves_x) * 8;
+  const int lxi = bx + (lane & 7), lyi = by + (lane >> 3);
+  const int px = tile_x0 + lxi, py = tile_y0 + lyi;
+  const bool inside = px < V.W && py < V.H;
+  // pixel centre relative to the tile centre (exact half-integers)
+  const float lx = (float)lxi - 0.5f * (float)(p.tile_w - 1);
+  const float ly = (float)lyi - 0.5f * (float)(p.tile_h - 1);
+  // wave block in pixels, for the rectangle test
+  const int wx0 = tile_x0 + bx, wx1 = wx0 + 7, wy0 = tile_y0 + by, wy1 = wy0 + 7;
+
+  const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+  float T = 1.0f;
+  float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+  uint32_t last = start;
+  bool done = !inside;
+  uint32_t st_blend = 0, st_eval = 0;
+  bool st_term = false;
+
+  for (uint32_t b0 = start; b0 < end; b0 += B) {
+    const int nb = (int)((end - b0) < (uint32_t)B ? (end - b0) : (uint32_t)B);
+    if (STATS && tid == 0) atomicAdd(&stats[3], (unsigned long long)nb);
+    if (tid < nb) {
+      const uint32_t r = pair_vals[b0 + tid];
+      const SplatRec R = rec[r];
+      const StagedGeo g = stage_geo(R, tile_x0, tile_y0, p.tile_w, p.tile_h);
+      s_geo[tid][0] = g.g0;
+      s_geo[tid][1] = g.g1;
+      s_geo[tid][2] = g.g2;
+      s_geo[tid][3] = g.g3;
+      s_splat[tid] = R.splat;
+    }
+    __syncthreads();
+    stage_texels<N, BF16>(textures, s_splat, nb, s_tex);
+    __syncthreads();
+
+    if (!__all(done)) {
+      for (int j = 0; j < nb; ++j) {
+        StagedGeo g;
+        g.g3 = s_geo[j][3];
+        const int rx = __float_as_int(g.g3.x), ry = __float_as_int(g.g3.y);
+        const int i0 = rx & 0xffff, i1 = rx >> 16, j0 = ry & 0xffff, j1 = ry >> 16;
+        if (i1 < wx0 || i0 > wx1 || j1 < wy0 || j0 > wy1) continue;
+        g.g0 = s_geo[j][0];
+        g.g1 = s_geo[j][1];
+        g.g2 = s_geo[j][2];
+        const PixelEval e = eval_splat(g, lx, ly, p);
+        if (STATS) ++st_eval;
+        if (!done && e.hit) {
+          const float Tn = T * (1.0f - e.alpha);
+          if (Tn < p.t_min) {
+            done = true;
+            if (STATS) st_term = true;
+          } else {
+            if (STATS) ++st_blend;
+            float c0, c1, c2;
+            const float4* tex = s_tex + j * N * N;
+            if constexpr (N == 1) {
+              const float4 t = tex[0];
+              c0 = t.x;
+              c1 = t.y;
+              c2 = t.z;
+            } else {
+              int iu, iv;
+              float fu, fv;
+              grid_coord<N>(e.u, p, iu, fu);
+              grid_coord<N>(e.v, p, iv, fv);
+              const float4 t00 = tex[iu * N + iv], t01 = tex[iu * N + iv + 1];
+              const float4 t10 = tex[(iu + 1) * N + iv], t11 = tex[(iu + 1) * N + iv + 1];
+              const float a0 = t00.x + fv * (t01.x - t00.x), b0_ = t10.x + fv * (t11.x - t10.x);
+              const float a1 = t00.y + fv * (t01.y - t00.y), b1 = t10.y + fv * (t11.y - t10.y);
+              const float a2 = t00.z + fv * (t01.z - t00.z), b2 = t10.z + fv * (t11.z - t10.z);
+              c0 = a0 + fu * (b0_ - a0);
+              c1 = a1 + fu * (b1 - a1);
+              c2 = a2 + fu * (b2 - a2);
+            }
+            const float wgt = e.alpha * T;
+            acc0 += wgt * c0;
+            acc1 += wgt * c1;
+            acc2 += wgt * c2;
+            T = Tn;
+            last = b0 + (uint32_t)j + 1u;
+          }
+        }
+        if (__all(done)) break;
+      }
+    }
+    if (__syncthreads_and(done)) break;
+  }
+
+  if (inside) {
+    const int64_t pix = (int64_t)V.pix_base + (int64_t)py * V.W + px;
+    rgb[3 * pix + 0] = acc0 + T * p.bg[0];
+    rgb[3 * pix + 1] = acc1 + T * p.bg[1];
+    rgb[3 * pix + 2] = acc2 + T * p.bg[2];
+    T_final[pix] = T;
+    n_last[pix] = last;
+  }
+  if (STATS) {
+    if (st_blend) atomicAdd(&stats[0], (unsigned long long)st_blend);
+    if (st_term) atomicAdd(&stats[1], 1ull);
+    if (lane == 0) atomicAdd(&stats[2], 64ull * st_eval);
+  }
+}
+
+template <int N, bool BF16, bool STATS>
+hipError_t launch_n(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
+                    const ViewDev* views, const SplatRec* rec, const uint32_t* pair_vals,
+                    const uint32_t* ranges, float* rgb, float* T_final, uint32_t* n_last,
+                    unsigned long long* stats, hipStream_t s) {
+  const dim3 grid((unsigned)(8 * (int64_t)bp.tiles_per_xcd));
+  const dim3 block((unsigned)(pl.tile_w * pl.tile_h));
+  switch (pl.batch_fwd) {
+    case 16:
+      hipLaunchKernelGGL((blend_fwd_kernel<N, BF16, 16, STATS>), grid, block, 0, s, views, rec,
+                         pair_vals, ranges, sp.textures, bp, rgb, T_final, n_last, stats);
+      break;
+    case 32:
+      hipLaunchKernelGGL((blend_fwd_kernel<N, BF16, 32, STATS>), grid, block, 0, s, views, rec,
+                         pair_vals, ranges, sp.textures, bp, rgb, T_final, n_last, stats);
+      break;
+    default:
+      hipLaunchKernelGGL((blend_fwd_kernel<N, BF16, 64, STATS>), grid, block, 0, s, views, rec,
+                         pair_vals, ranges, sp.textures, bp, rgb, T_final, n_last, stats);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <int N, bool BF16>
+hipError_t launch_nb(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
+                     const ViewDev* views, const SplatRec* rec, const uint32_t* pair_vals,
+                     const uint32_t* ranges, float* rgb, float* T_final, uint32_t* n_last,
+                     unsigned long long* stats, hipStream_t s) {
+  if (stats)
+    return launch_n<N, BF16, true>(pl, sp, bp, views, rec, pair_vals, ranges, rgb, T_final,
+                                   n_last, stats, s);
+  return launch_n<N, BF16, false>(pl, sp, bp, views, rec, pair_vals, ranges, rgb, T_final,
+                                  n_last, stats, s);
+}
+
+}  // namespace
+
+BlendParams make_blend_params(const Plan& pl, const gb_options& o, int n_views) {
+  BlendParams bp;
+  const int N = pl.N;
+  bp.tex_scale = (float)(N - 1) / (2.0f * o.sigma);
+  bp.tex_offset = 0.5f * (float)(N - 1);
+  bp.sigma = o.sigma;
+  bp.alpha_min = o.alpha_min;
+  bp.alpha_max = o.alpha_max;
+  bp.t_min = o.t_min;
+  bp.lp_scale = 1.0f / (2.0f * o.lowpass_var);
+  bp.bg[0] = o.bg[0];
+  bp.bg[1] = o.bg[1];
+  bp.bg[2] = o.bg[2];
+  bp.tile_w = pl.tile_w;
+  bp.tile_h = pl.tile_h;
+  bp.n_views = n_views;
+  bp.total_tiles = (int32_t)pl.total_tiles;
+  bp.tiles_per_xcd = (int32_t)((pl.total_tiles + 7) / 8);
+  return bp;
+}
+
+hipError_t launch_blend_fwd(const Plan& pl, const gb_splats& sp, const gb_options& o,
+                            const ViewDev* views, int n_views, const SplatRec* rec,
+                            const uint32_t* pair_vals, const uint32_t* ranges, float* rgb,
+                            float* T_final, uint32_t* n_last, unsigned long long* stats,
+                            hipStream_t s) {
+  const BlendParams bp = make_blend_params(pl, o, n_views);
+  const bool bf = sp.tex_dtype == GB_BF16;
+#define GBB_FWD(NN)                                                                          \
+  return bf ? launch_nb<NN, true>(pl, sp, bp, views, rec, pair_vals, ranges, rgb, T_final,   \
+                                  n_last, stats, s)                                          \
+            : launch_nb<NN, false>(pl, sp, bp, views, rec, pair_vals, ranges, rgb, T_final,  \
+                                   n_last, stats, s)
+  switch (pl.N) {
+    case 1: GBB_FWD(1);
+    case 2: GBB_FWD(2);
+    case 4: GBB_FWD(4);
+    case 8: GBB_FWD(8);
+    default: return hipErrorInvalidValue;
+  }
+#undef GBB_FWD
+}
+
+}  // namespace gbb

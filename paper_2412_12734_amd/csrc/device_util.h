@@ -1,0 +1,125 @@
+// Device helpers for gfx950: float-pair ("double-float") arithmetic, wave64 reductions via
+// DPP, ballot helpers and bfloat16 decoding.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gbb {
+
+// ---- unevaluated float pairs (hi + lo), error-free transformations ---------------------
+// Knuth's TwoSum and the FMA-based TwoProduct; contraction is switched off so that the
+// compiler cannot fuse the error terms away.
+struct f2 {
+  float hi, lo;
+};
+
+__device__ __forceinline__ f2 two_sum(float a, float b) {
+#pragma clang fp contract(off)
+  float s = a + b;
+  float bb = s - a;
+  float e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+
+__device__ __forceinline__ f2 fast_two_sum(float a, float b) {
+#pragma clang fp contract(off)
+  float s = a + b;
+  float e = b - (s - a);
+  return {s, e};
+}
+
+__device__ __forceinline__ f2 two_prod(float a, float b) {
+#pragma clang fp contract(off)
+  float p = a * b;
+  float e = __builtin_fmaf(a, b, -p);
+  return {p, e};
+}
+
+__device__ __forceinline__ f2 f2_add(f2 a, f2 b) {
+#pragma clang fp contract(off)
+  f2 s = two_sum(a.hi, b.hi);
+  float lo = s.lo + (a.lo + b.lo);
+  return fast_two_sum(s.hi, lo);
+}
+
+__device__ __forceinline__ f2 f2_add(f2 a, float b) {
+#pragma clang fp contract(off)
+  f2 s = two_sum(a.hi, b);
+  float lo = s.lo + a.lo;
+  return fast_two_sum(s.hi, lo);
+}
+
+__device__ __forceinline__ f2 f2_mul(f2 a, float b) {
+#pragma clang fp contract(off)
+  f2 p = two_prod(a.hi, b);
+  float lo = __builtin_fmaf(a.lo, b, p.lo);
+  return fast_two_sum(p.hi, lo);
+}
+
+__device__ __forceinline__ f2 f2_neg(f2 a) { return {-a.hi, -a.lo}; }
+
+__device__ __forceinline__ f2 f2_sub(f2 a, f2 b) { return f2_add(a, f2_neg(b)); }
+
+__device__ __forceinline__ f2 f2_mul(f2 a, f2 b) {
+#pragma clang fp contract(off)
+  f2 p = two_prod(a.hi, b.hi);
+  float lo = __builtin_fmaf(a.hi, b.lo, __builtin_fmaf(a.lo, b.hi, p.lo));
+  return fast_two_sum(p.hi, lo);
+}
+
+__device__ __forceinline__ f2 f2_of(float a) { return {a, 0.0f}; }
+
+__device__ __forceinline__ float f2_round(f2 a) { return a.hi + a.lo; }
+
+__device__ __forceinline__ f2 f2_div(f2 a, f2 b) {
+#pragma clang fp contract(off)
+  float q1 = a.hi / b.hi;
+  // r = a - q1 * b, exactly enough: q1*b.hi as a pair, then the small terms
+  f2 p = two_prod(q1, b.hi);
+  float r = ((a.hi - p.hi) - p.lo) + (a.lo - q1 * b.lo);
+  float q2 = r / b.hi;
+  return fast_two_sum(q1, q2);
+}
+
+// ---- wave64 helpers ------------------------------------------------------------------
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+__device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__popcll(m); }
+
+// Number of set bits of m below this lane.
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf, bool BOUND_CTRL = true>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK,
+                                                    BANK_MASK, BOUND_CTRL));
+}
+
+// Sum over the 64 lanes of a wave; every lane must be active. The total lands in lane 63.
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+  v += dpp_f<0xB1>(v);             // quad_perm [1,0,3,2]
+  v += dpp_f<0x4E>(v);             // quad_perm [2,3,0,1]
+  v += dpp_f<0x124>(v);            // row_ror:4
+  v += dpp_f<0x128>(v);            // row_ror:8   -> every lane holds its row's sum
+  v += dpp_f<0x142, 0xa, 0xf, false>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f<0x143, 0xc, 0xf, false>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_to_lane63(v)), 63));
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) {
+  return __uint_as_float(((uint32_t)b) << 16);
+}
+
+}  // namespace gbb

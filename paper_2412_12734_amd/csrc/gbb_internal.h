@@ -1,0 +1,120 @@
+// Internal declarations shared by the HIP translation units of libgbb.
+// Each .hip file defines its kernels together with plain host launchers declared here, so
+// the library links without relocatable device code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/gbb.h"
+
+namespace gbb {
+
+constexpr int kWave = 64;
+constexpr uint32_t kCulledKey = 0xFFFFFFFFu;
+constexpr int kRecGrad = 10;  // dh00 dh01 dh10 dh11 dh20 dh21 dh22 dc2x dc2y dopacity
+
+// Device copy of one view, with its place in the global tile and pixel numbering.
+struct ViewDev {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy, z_near;
+  int32_t W, H, tiles_x, tiles_y;
+  int32_t tile_base;   // first global tile index of this view
+  int32_t pix_base;    // first packed pixel index of this view
+  int32_t pad;
+};
+static_assert(sizeof(ViewDev) == 96, "ViewDev layout");
+
+// Per (view, splat) record read by the blend kernels (96 bytes).
+//
+// The ray-splat solve is kept as a homography from the pixel offset (dx, dy) to the
+// projected centre onto homogeneous uv: (rho0, rho1, rho2) = H (dx, dy, 1) with
+// rho0 = h00 dx + h01 dy, rho1 = h10 dx + h11 dy, rho2 = h20 dx + h21 dy + h22,
+// u = rho0 / rho2, v = rho1 / rho2. The entries and the projected centre are unevaluated
+// float pairs (hi + lo): the blend re-centres the solve on each tile in pair precision, so
+// that float32 per-pixel arithmetic only spans offsets within one tile.
+struct SplatRec {
+  float h_hi[7];
+  float h_lo[7];
+  float c2x_hi, c2x_lo, c2y_hi, c2y_lo;
+  float opacity;
+  int32_t rect_x;    // i0 | i1 << 16 (pixel columns, inclusive)
+  int32_t rect_y;    // j0 | j1 << 16 (pixel rows, inclusive)
+  int32_t splat;     // splat index k
+  int32_t view;      // view index v
+  int32_t pad;
+};
+static_assert(sizeof(SplatRec) == 96, "SplatRec layout");
+
+struct Status {
+  uint32_t K;          // total pairs requested by the key stage
+  uint32_t n_sorted;   // pairs actually emitted and sorted (0 on overflow)
+  uint32_t overflow;   // 1 if K exceeded the capacity
+  uint32_t reserved;
+};
+
+// Host-side plan of one call: sizes and workspace carve-up.
+struct Plan {
+  int32_t P, N, V;
+  int64_t VP;
+  int64_t capacity;
+  int64_t total_tiles;
+  int64_t total_pixels;
+  int32_t tile_w, tile_h, batch_fwd, batch_bwd;
+  int32_t tile_bits;
+  int64_t nb_vp;      // radix blocks over V*P records
+  int64_t nb_pairs;   // radix blocks over the pair capacity
+  // byte offsets
+  size_t off_status, off_views, off_depth_key, off_depth_key_alt, off_order, off_order_alt,
+      off_count, off_offsets, off_rec, off_partials, off_hist, off_pair_keys, off_pair_vals,
+      off_pair_keys_alt, off_pair_vals_alt, off_ranges, off_n_last, off_drec, off_stats, total;
+  int64_t partials_len, hist_len;
+};
+
+constexpr int kRadixItems = 16;
+constexpr int kRadixThreads = 256;
+constexpr int kRadixTile = kRadixItems * kRadixThreads;  // 4096 elements per block
+constexpr int kScanTile = 4096;
+
+// ---- launchers (all stream-ordered, no synchronisation) --------------------------------
+hipError_t launch_upload_views(const gb_view* views, int n_views, int tile_w, int tile_h,
+                               ViewDev* d_views, hipStream_t s);
+hipError_t launch_preprocess(const gb_splats& sp, const ViewDev* d_views, int n_views,
+                             const gb_options& o, int tile_w, int tile_h, uint32_t* depth_key,
+                             uint32_t* sort_key, uint32_t* count, SplatRec* rec, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
+hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t s);
+// Exclusive scan of n u32 values (optionally gathered in[gather[i]]); writes out and, if
+// total != nullptr, the sum to *total. partials needs ceil(n / kScanTile) + 1 entries.
+hipError_t launch_scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t n,
+                           uint32_t* partials, uint32_t* total, hipStream_t s);
+// Stable LSD radix sort of (key, value) pairs on bits [0, bits). The element count is
+// read from *d_n on the device (at most n_cap). Buffers ping-pong; the result is written
+// back to keys/vals. hist needs 256 * ceil(n_cap / kRadixTile) entries.
+hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                             uint32_t* vals_alt, const uint32_t* d_n, int64_t n_cap, int bits,
+                             uint32_t* hist, uint32_t* partials, hipStream_t s);
+hipError_t launch_finalize_count(Status* st, int64_t capacity, hipStream_t s);
+hipError_t launch_duplicate(const uint32_t* order, const uint32_t* count,
+                            const uint32_t* offsets, const SplatRec* rec, const ViewDev* views,
+                            int64_t VP, int tile_w, int tile_h, const Status* st,
+                            uint32_t* pair_keys, uint32_t* pair_vals, hipStream_t s);
+hipError_t launch_ranges(const uint32_t* pair_keys, const Status* st, int64_t n_cap,
+                         uint32_t* ranges, hipStream_t s);
+hipError_t launch_blend_fwd(const Plan& pl, const gb_splats& sp, const gb_options& o,
+                            const ViewDev* views, int n_views, const SplatRec* rec,
+                            const uint32_t* pair_vals, const uint32_t* ranges, float* rgb,
+                            float* T_final, uint32_t* n_last, unsigned long long* stats,
+                            hipStream_t s);
+hipError_t launch_blend_bwd(const Plan& pl, const gb_splats& sp, const gb_options& o,
+                            const ViewDev* views, int n_views, const SplatRec* rec,
+                            const uint32_t* pair_vals, const uint32_t* ranges,
+                            const float* T_final, const uint32_t* n_last, const float* d_rgb,
+                            float* d_rec, float* d_tex, hipStream_t s);
+hipError_t launch_preprocess_bwd(const gb_splats& sp, const ViewDev* d_views, int n_views,
+                                 const uint32_t* count, const float* d_rec,
+                                 const gb_grads& g, hipStream_t s);
+
+}  // namespace gbb

@@ -1,0 +1,349 @@
+// Device-wide exclusive scan and stable LSD radix sort of (uint32 key, uint32 value) pairs.
+//
+// Scan: reduce per 4096-element tile -> scan of tile sums in one workgroup -> per-tile scan.
+// Radix pass (8-bit digit): per-tile digit histogram -> exclusive scan of the digit-major
+// [digit][tile] counts -> scatter. The scatter ranks each element stably among equal digits
+// of its tile: elements enter in rounds of 256 in index order; inside a wave the lanes with
+// the same digit are found with eight ballots (one per digit bit), across waves and rounds
+// with running per-digit counters in LDS. Elements are then placed in LDS in digit order and
+// written out so that consecutive lanes store consecutive addresses of one digit run.
+#include "device_util.h"
+#include "gbb_internal.h"
+
+namespace gbb {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = kScanTile / kThreads;  // 16
+
+// Inclusive scan of v over the 256 threads of the block; returns the inclusive value and
+// writes the block total to *total. `wave_tot` is LDS scratch of 4 entries.
+__device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t v, uint32_t* wave_tot,
+                                                         uint32_t* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  if (lane == 63) wave_tot[w] = v;
+  __syncthreads();
+  uint32_t add = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kThreads / 64; ++i) {
+    uint32_t t = wave_tot[i];
+    if (i < w) add += t;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return v + add;
+}
+
+template <bool GATHER>
+__device__ __forceinline__ uint32_t scan_load(const uint32_t* in, const uint32_t* gather,
+                                              int64_t i) {
+  if (GATHER) return in[gather[i]];
+  return in[i];
+}
+
+template <bool GATHER>
+__global__ void __launch_bounds__(kThreads)
+scan_reduce_kernel(const uint32_t* __restrict__ in, const uint32_t* __restrict__ gather,
+                   int64_t n, uint32_t* __restrict__ partials) {
+  __shared__ uint32_t wave_tot[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  uint32_t s = 0;
+#pragma unroll 4
+  for (int k = 0; k < kItems; ++k) {
+    int64_t i = base + k * kThreads + threadIdx.x;
+    if (i < n) s += scan_load<GATHER>(in, gather, i);
+  }
+  uint32_t total;
+  block_inclusive_scan(s, wave_tot, &total);
+  if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
+// One workgroup: exclusive scan of partials[0..nb) in place, total to partials[nb] and *total.
+__global__ void __launch_bounds__(1024)
+scan_partials_kernel(uint32_t* __restrict__ partials, int64_t nb, uint32_t* __restrict__ total) {
+  __shared__ uint32_t wave_tot[16];
+  __shared__ uint32_t carry_s;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) carry_s = 0;
+  __syncthreads();
+  for (int64_t start = 0; start < nb; start += 1024) {
+    int64_t i = start + threadIdx.x;
+    uint32_t x = i < nb ? partials[i] : 0u;
+    uint32_t v = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      uint32_t t = __shfl_up(v, d, 64);
+      if (lane >= d) v += t;
+    }
+    if (lane == 63) wave_tot[w] = v;
+    __syncthreads();
+    uint32_t add = 0, tot = 0;
+    for (int k = 0; k < 16; ++k) {
+      uint32_t t = wave_tot[k];
+      if (k < w) add += t;
+      tot += t;
+    }
+    const uint32_t carry = carry_s;
+    if (i < nb) partials[i] = carry + add + v - x;
+    __syncthreads();
+    if (threadIdx.x == 0) carry_s = carry + tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partials[nb] = carry_s;
+    if (total) *total = carry_s;
+  }
+}
+
+// LDS index with one pad word per 32 so that both the striped and the blocked access
+// patterns below are free of bank conflicts.
+__device__ __forceinline__ int pad_idx(int i) { return i + (i >> 5); }
+
+template <bool GATHER>
+__global__ void __launch_bounds__(kThreads)
+scan_down_kernel(const uint32_t* __restrict__ in, const uint32_t* __restrict__ gather, int64_t n,
+                 const uint32_t* __restrict__ partials, uint32_t* __restrict__ out) {
+  __shared__ uint32_t tile[kScanTile + kScanTile / 32];
+  __shared__ uint32_t wave_tot[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  // coalesced load into LDS, then each thread owns 16 consecutive elements
+#pragma unroll 4
+  for (int k = 0; k < kItems; ++k) {
+    int64_t i = base + k * kThreads + threadIdx.x;
+    tile[pad_idx(k * kThreads + threadIdx.x)] = i < n ? scan_load<GATHER>(in, gather, i) : 0u;
+  }
+  __syncthreads();
+  uint32_t loc[kItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) loc[k] = tile[pad_idx(threadIdx.x * kItems + k)];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) s += loc[k];
+  uint32_t total;
+  uint32_t incl = block_inclusive_scan(s, wave_tot, &total);
+  uint32_t run = partials[blockIdx.x] + incl - s;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    uint32_t x = loc[k];
+    loc[k] = run;
+    run += x;
+  }
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) tile[pad_idx(threadIdx.x * kItems + k)] = loc[k];
+  __syncthreads();
+#pragma unroll 4
+  for (int k = 0; k < kItems; ++k) {
+    int64_t i = base + k * kThreads + threadIdx.x;
+    if (i < n) out[i] = tile[pad_idx(k * kThreads + threadIdx.x)];
+  }
+}
+
+// ---- radix sort --------------------------------------------------------------------------
+__device__ __forceinline__ int64_t sort_count(const uint32_t* d_n, int64_t n_cap) {
+  if (!d_n) return n_cap;
+  int64_t n = (int64_t)(*d_n);
+  return n < n_cap ? n : n_cap;
+}
+
+__global__ void __launch_bounds__(kRadixThreads)
+radix_hist_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ d_n,
+                  int64_t n_cap, int shift, int64_t nb, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[256];
+  const int64_t n = sort_count(d_n, n_cap);
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+  if (base < n) {
+#pragma unroll 4
+    for (int k = 0; k < kRadixItems; ++k) {
+      int64_t i = base + k * kRadixThreads + threadIdx.x;
+      if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kRadixThreads)
+radix_scatter_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+                     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+                     const uint32_t* __restrict__ d_n, int64_t n_cap, int shift, int64_t nb,
+                     const uint32_t* __restrict__ hist_scanned) {
+  __shared__ uint32_t s_keys[kRadixTile];
+  __shared__ uint32_t s_vals[kRadixTile];
+  __shared__ uint32_t s_cnt[4][256];
+  __shared__ uint32_t s_run[256];
+  __shared__ uint32_t s_start[256];
+  __shared__ uint32_t wave_tot[4];
+  const int64_t n = sort_count(d_n, n_cap);
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+  if (base >= n) return;
+  const int nvalid = (int)((n - base) < kRadixTile ? (n - base) : kRadixTile);
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  s_run[tid] = 0;
+  uint32_t key_r[kRadixItems], val_r[kRadixItems], rank_r[kRadixItems];
+#pragma unroll
+  for (int r = 0; r < kRadixItems; ++r) {
+    const int i = r * kRadixThreads + tid;
+    const bool valid = i < nvalid;
+    const uint32_t key = valid ? keys_in[base + i] : 0u;
+    const uint32_t val = valid ? vals_in[base + i] : 0u;
+    const uint32_t d = (key >> shift) & 255u;
+    s_cnt[w][lane] = 0;
+    s_cnt[w][lane + 64] = 0;
+    s_cnt[w][lane + 128] = 0;
+    s_cnt[w][lane + 192] = 0;
+    uint64_t m = ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool set = (d >> bit) & 1u;
+      const uint64_t b = ballot(set);
+      m &= set ? b : ~b;
+    }
+    const uint32_t below = mbcnt(m);
+    if (valid && below == 0) s_cnt[w][d] = popc64(m);
+    __syncthreads();
+    {
+      uint32_t run = s_run[tid];
+#pragma unroll
+      for (int ww = 0; ww < 4; ++ww) {
+        const uint32_t c = s_cnt[ww][tid];
+        s_cnt[ww][tid] = run;
+        run += c;
+      }
+      s_run[tid] = run;
+    }
+    __syncthreads();
+    key_r[r] = key;
+    val_r[r] = val;
+    rank_r[r] = valid ? s_cnt[w][d] + below : 0u;
+    __syncthreads();
+  }
+  // digit starts inside this tile
+  uint32_t total;
+  const uint32_t cnt = s_run[tid];
+  const uint32_t incl = block_inclusive_scan(cnt, wave_tot, &total);
+  s_start[tid] = incl - cnt;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRadixItems; ++r) {
+    const int i = r * kRadixThreads + tid;
+    if (i < nvalid) {
+      const uint32_t d = (key_r[r] >> shift) & 255u;
+      const uint32_t pos = s_start[d] + rank_r[r];
+      s_keys[pos] = key_r[r];
+      s_vals[pos] = val_r[r];
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < nvalid; i += kRadixThreads) {
+    const uint32_t key = s_keys[i];
+    const uint32_t d = (key >> shift) & 255u;
+    const uint64_t gpos = (uint64_t)hist_scanned[(int64_t)d * nb + blockIdx.x] +
+                          (uint64_t)(i - (int)s_start[d]);
+    keys_out[gpos] = key;
+    vals_out[gpos] = s_vals[i];
+  }
+}
+
+__global__ void copy_pairs_kernel(const uint32_t* __restrict__ ka, const uint32_t* __restrict__ va,
+                                  uint32_t* __restrict__ kb, uint32_t* __restrict__ vb,
+                                  const uint32_t* __restrict__ d_n, int64_t n_cap) {
+  const int64_t n = sort_count(d_n, n_cap);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    kb[i] = ka[i];
+    vb[i] = va[i];
+  }
+}
+
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint32_t value, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+__global__ void iota_u32_kernel(uint32_t* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (uint32_t)i;
+}
+
+unsigned grid_for(int64_t n, int threads) {
+  int64_t b = (n + threads - 1) / threads;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, value, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(iota_u32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t n,
+                           uint32_t* partials, uint32_t* total, hipStream_t s) {
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb == 0) return hipSuccess;
+  if (gather)
+    hipLaunchKernelGGL(scan_reduce_kernel<true>, dim3((unsigned)nb), dim3(kThreads), 0, s, in,
+                       gather, n, partials);
+  else
+    hipLaunchKernelGGL(scan_reduce_kernel<false>, dim3((unsigned)nb), dim3(kThreads), 0, s, in,
+                       gather, n, partials);
+  hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, s, partials, nb, total);
+  if (gather)
+    hipLaunchKernelGGL(scan_down_kernel<true>, dim3((unsigned)nb), dim3(kThreads), 0, s, in,
+                       gather, n, partials, out);
+  else
+    hipLaunchKernelGGL(scan_down_kernel<false>, dim3((unsigned)nb), dim3(kThreads), 0, s, in,
+                       gather, n, partials, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                             uint32_t* vals_alt, const uint32_t* d_n, int64_t n_cap, int bits,
+                             uint32_t* hist, uint32_t* partials, hipStream_t s) {
+  const int64_t nb = (n_cap + kRadixTile - 1) / kRadixTile;
+  if (nb == 0 || bits <= 0) return hipSuccess;
+  const int passes = (bits + 7) / 8;
+  uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kRadixThreads), 0, s, ki, d_n,
+                       n_cap, shift, nb, hist);
+    hipError_t e = launch_scan_u32(hist, nullptr, hist, 256 * nb, partials, nullptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kRadixThreads), 0, s, ki,
+                       vi, ko, vo, d_n, n_cap, shift, nb, hist);
+    uint32_t* t = ki;
+    ki = ko;
+    ko = t;
+    t = vi;
+    vi = vo;
+    vo = t;
+  }
+  if (ki != keys) {
+    hipLaunchKernelGGL(copy_pairs_kernel, dim3(grid_for(n_cap, 256)), dim3(256), 0, s, ki, vi,
+                       keys, vals, d_n, n_cap);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gbb

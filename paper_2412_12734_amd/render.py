@@ -1,0 +1,228 @@
+"""Torch-facing binding of libgbb: device buffers, streams and autograd.
+
+PyTorch only provides memory and the stream here; every computation runs in the HIP library
+through the C ABI of include/gbb.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib as L
+
+
+@dataclasses.dataclass
+class Options:
+    sigma: float = 0.5
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    t_min: float = 1e-4
+    lowpass_var: float = 0.5
+    bg: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    tile_w: int = 16
+    tile_h: int = 16
+    batch: int = 0
+
+    def c(self) -> L.GbOptions:
+        return L.make_options(self.sigma, self.alpha_min, self.alpha_max, self.t_min,
+                              self.lowpass_var, tuple(self.bg), self.tile_w, self.tile_h,
+                              self.batch)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Splats:
+    """Device views of the per-splat arrays in the layout the library expects."""
+
+    def __init__(self, means, tan_u, tan_v, scales, opacity, textures):
+        self.means, self.tan_u, self.tan_v = means, tan_u, tan_v
+        self.scales, self.opacity, self.textures = scales, opacity, textures
+        for name in ("means", "tan_u", "tan_v", "scales", "opacity"):
+            t = getattr(self, name)
+            if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+        if textures.dtype not in (torch.float32, torch.bfloat16) or not textures.is_contiguous():
+            raise ValueError("textures must be contiguous float32 or bfloat16 [P,N,N,3]")
+        self.P = int(means.shape[0])
+        self.N = int(textures.shape[1])
+
+    @staticmethod
+    def from_numpy(scene, device="cuda", tex_bf16: bool = False) -> "Splats":
+        f = lambda a: torch.from_numpy(a).to(device)
+        tex = torch.from_numpy(scene.textures).to(device)
+        if tex_bf16:
+            tex = tex.to(torch.bfloat16)
+        return Splats(f(scene.means), f(scene.tan_u), f(scene.tan_v), f(scene.scales),
+                      f(scene.opacity), tex)
+
+    def c(self) -> L.GbSplats:
+        dt = L.GB_BF16 if self.textures.dtype == torch.bfloat16 else L.GB_F32
+        return L.GbSplats(self.P, self.N, dt, _ptr(self.means), _ptr(self.tan_u),
+                          _ptr(self.tan_v), _ptr(self.scales), _ptr(self.opacity),
+                          _ptr(self.textures))
+
+
+class Rasterizer:
+    """Renders splats into a fixed set of views, owning the workspace between calls.
+
+    ``plan`` counts the (tile, splat) pairs on the device (one synchronisation) and sizes
+    the workspace with ``headroom``; ``forward``/``backward`` then run without host
+    synchronisation. With ``check_overflow`` the forward reads the device status after each
+    call and re-plans if the pair capacity was exceeded.
+    """
+
+    def __init__(self, views: Sequence, options: Optional[Options] = None, device="cuda",
+                 headroom: float = 1.25, check_overflow: bool = True):
+        self.lib = L.load()
+        self.views = list(views)
+        self.cviews = L.make_views(self.views)
+        self.nv = len(self.views)
+        self.opts = options or Options()
+        self.copts = self.opts.c()
+        self.device = torch.device(device)
+        self.headroom = headroom
+        self.check_overflow = check_overflow
+        self.capacity = 0
+        self.ws: Optional[torch.Tensor] = None
+        self.layout = L.GbLayout()
+        self.total_pixels = sum(int(v.width) * int(v.height) for v in self.views)
+
+    # -- workspace -------------------------------------------------------------------------
+    def _layout(self, P: int, N: int, capacity: int) -> L.GbLayout:
+        lay = L.GbLayout()
+        L.check(self.lib.gb_workspace_layout(P, N, self.cviews, self.nv, ctypes.byref(self.copts),
+                                             capacity, ctypes.byref(lay)), "gb_workspace_layout")
+        return lay
+
+    def _alloc(self, P: int, N: int, capacity: int) -> None:
+        lay = self._layout(P, N, capacity)
+        if self.ws is None or self.ws.numel() < lay.total_bytes:
+            self.ws = torch.empty(int(lay.total_bytes), dtype=torch.uint8, device=self.device)
+        self.capacity = capacity
+        self.layout = lay
+        self._plan_key = (P, N)
+
+    def count_pairs(self, sp: Splats) -> int:
+        if self.ws is None or getattr(self, "_plan_key", None) != (sp.P, sp.N):
+            self._alloc(sp.P, sp.N, 0)
+        K = ctypes.c_int64(0)
+        L.check(self.lib.gb_count_pairs(ctypes.byref(sp.c()), self.cviews, self.nv,
+                                        ctypes.byref(self.copts), self.ws.data_ptr(),
+                                        self.ws.numel(), self.capacity, ctypes.byref(K),
+                                        _stream(self.device)), "gb_count_pairs")
+        return int(K.value)
+
+    def plan(self, sp: Splats, capacity: Optional[int] = None) -> int:
+        if capacity is None:
+            K = self.count_pairs(sp)
+            capacity = int(K * self.headroom) + 4096
+        self._alloc(sp.P, sp.N, capacity)
+        return capacity
+
+    def status(self) -> Tuple[int, bool]:
+        K = ctypes.c_int64(0)
+        ov = ctypes.c_int32(0)
+        L.check(self.lib.gb_read_status(self.ws.data_ptr(), ctypes.byref(K), ctypes.byref(ov),
+                                        _stream(self.device)), "gb_read_status")
+        return int(K.value), bool(ov.value)
+
+    # -- raw calls -------------------------------------------------------------------------
+    def forward(self, sp: Splats, rgb: Optional[torch.Tensor] = None,
+                T_final: Optional[torch.Tensor] = None):
+        if self.ws is None or getattr(self, "_plan_key", None) != (sp.P, sp.N) or self.capacity == 0:
+            self.plan(sp)
+        if rgb is None:
+            rgb = torch.empty((self.total_pixels, 3), dtype=torch.float32, device=self.device)
+        if T_final is None:
+            T_final = torch.empty((self.total_pixels,), dtype=torch.float32, device=self.device)
+        for _ in range(3):
+            L.check(self.lib.gb_render_fwd(ctypes.byref(sp.c()), self.cviews, self.nv,
+                                           ctypes.byref(self.copts), self.ws.data_ptr(),
+                                           self.ws.numel(), self.capacity, rgb.data_ptr(),
+                                           T_final.data_ptr(), _stream(self.device)),
+                    "gb_render_fwd")
+            if not self.check_overflow:
+                break
+            K, over = self.status()
+            if not over:
+                break
+            self._alloc(sp.P, sp.N, int(K * self.headroom) + 4096)
+        return rgb, T_final
+
+    def backward(self, sp: Splats, T_final: torch.Tensor, d_rgb: torch.Tensor, grads=None):
+        if grads is None:
+            z = lambda *s: torch.empty(s, dtype=torch.float32, device=self.device)
+            grads = dict(means=z(sp.P, 3), tan_u=z(sp.P, 3), tan_v=z(sp.P, 3),
+                         scales=z(sp.P, 2), opacity=z(sp.P),
+                         textures=z(sp.P, sp.N, sp.N, 3))
+        d_rgb = d_rgb.contiguous().float()
+        g = L.GbGrads(_ptr(grads["means"]), _ptr(grads["tan_u"]), _ptr(grads["tan_v"]),
+                      _ptr(grads["scales"]), _ptr(grads["opacity"]), _ptr(grads["textures"]))
+        L.check(self.lib.gb_render_bwd(ctypes.byref(sp.c()), self.cviews, self.nv,
+                                       ctypes.byref(self.copts), self.ws.data_ptr(),
+                                       self.ws.numel(), self.capacity, T_final.data_ptr(),
+                                       d_rgb.data_ptr(), ctypes.byref(g), _stream(self.device)),
+                "gb_render_bwd")
+        return grads
+
+    # -- measurement ---------------------------------------------------------------------------
+    def blend_stats(self, sp: Splats, rgb: torch.Tensor, T_final: torch.Tensor) -> dict:
+        """Forward with work counting (synchronises): blended pairs, t_min stops, lane
+        evaluations and staged (tile, splat) pairs."""
+        c = (ctypes.c_int64 * 4)()
+        L.check(self.lib.gb_blend_stats(ctypes.byref(sp.c()), self.cviews, self.nv,
+                                        ctypes.byref(self.copts), self.ws.data_ptr(),
+                                        self.ws.numel(), self.capacity, rgb.data_ptr(),
+                                        T_final.data_ptr(), c, _stream(self.device)),
+                "gb_blend_stats")
+        return dict(blended=c[0], terminated=c[1], lane_evals=c[2], staged=c[3])
+
+    def timing(self, on: bool) -> None:
+        L.check(self.lib.gb_timing_enable(1 if on else 0), "gb_timing_enable")
+
+    def stage_times(self) -> dict:
+        ms = (ctypes.c_float * 16)()
+        n = ctypes.c_int32(0)
+        L.check(self.lib.gb_timing_read(ms, 16, ctypes.byref(n)), "gb_timing_read")
+        return {self.lib.gb_timing_stage_name(i).decode(): float(ms[i]) for i in range(n.value)}
+
+    # -- workspace read-back (inspection and tests) ------------------------------------------
+    def section(self, name: str, count: int, dtype=torch.int32) -> torch.Tensor:
+        off = getattr(self.layout, name)
+        nbytes = count * torch.tensor([], dtype=dtype).element_size()
+        return self.ws[off:off + nbytes].view(dtype)
+
+
+class _RenderFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rast: Rasterizer, means, tan_u, tan_v, scales, opacity, textures):
+        sp = Splats(means.detach(), tan_u.detach(), tan_v.detach(), scales.detach(),
+                    opacity.detach(), textures.detach())
+        rgb, T = rast.forward(sp)
+        ctx.rast, ctx.sp = rast, sp
+        ctx.save_for_backward(T)
+        ctx.mark_non_differentiable(T)
+        return rgb, T
+
+    @staticmethod
+    def backward(ctx, d_rgb, d_T):
+        (T,) = ctx.saved_tensors
+        g = ctx.rast.backward(ctx.sp, T, d_rgb)
+        dtex = g["textures"]
+        if ctx.sp.textures.dtype != torch.float32:
+            dtex = dtex.to(ctx.sp.textures.dtype)
+        return None, g["means"], g["tan_u"], g["tan_v"], g["scales"], g["opacity"], dtex
+
+
+def render(rast: Rasterizer, means, tan_u, tan_v, scales, opacity, textures):
+    """Differentiable render of all of ``rast``'s views: returns rgb [sum HW, 3] and T_final."""
+    return _RenderFn.apply(rast, means, tan_u, tan_v, scales, opacity, textures)

@@ -53,7 +53,8 @@ class Scene:
 
 @dataclasses.dataclass
 class View:
-    """Pinhole camera: world->camera rotation R (row-major) and translation t."""
+    """Pinhole camera: world->camera rotation R (row-major) and translation t. All values are
+    float32-representable (the renderer's C ABI takes float32)."""
     width: int
     height: int
     fx: float
@@ -65,9 +66,14 @@ class View:
     z_near: float = 0.01
 
 
+def _f32(x: float) -> float:
+    """The value as the float32 the renderer receives (both sides must see the same inputs)."""
+    return float(np.float32(x))
+
+
 def _intrinsics(width: int, height: int, fov_deg: float) -> Tuple[float, float, float, float]:
     f = (width / 2.0) / math.tan(math.radians(fov_deg) / 2.0)
-    return f, f, width / 2.0, height / 2.0
+    return _f32(f), _f32(f), _f32(width / 2.0), _f32(height / 2.0)
 
 
 def look_at_view(pos, width: int, height: int, fov_deg: float = 60.0,
@@ -85,14 +91,15 @@ def look_at_view(pos, width: int, height: int, fov_deg: float = 60.0,
     R = np.stack([r, d, f])
     t = -R @ pos
     fx, fy, cx, cy = _intrinsics(width, height, fov_deg)
-    return View(width, height, fx, fy, cx, cy, R.astype(np.float32), t.astype(np.float32), z_near)
+    return View(width, height, fx, fy, cx, cy, R.astype(np.float32), t.astype(np.float32),
+                _f32(z_near))
 
 
 def frontal_view(width: int, height: int, fov_deg: float = 60.0, z_near: float = 0.01) -> View:
     """Identity camera at the origin looking down +z (the image-fitting set-up)."""
     fx, fy, cx, cy = _intrinsics(width, height, fov_deg)
     return View(width, height, fx, fy, cx, cy, np.eye(3, dtype=np.float32),
-                np.zeros(3, dtype=np.float32), z_near)
+                np.zeros(3, dtype=np.float32), _f32(z_near))
 
 
 def quat_to_tangents(q: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:

@@ -1,0 +1,110 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function declared in
+include/gbb.h, and rejects invalid arguments on the host before any launch."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+L = pytest.importorskip("paper_2412_12734_amd._lib")
+
+
+def _lib():
+    try:
+        return L.load()
+    except ImportError as e:  # not built in this checkout
+        pytest.skip(str(e))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "gbb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gb_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_exports():
+    assert set(declared_functions()) == set(L.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_struct_sizes_match_header_layout():
+    # gb_view: 2 ints + 4 floats + 9 + 3 + 1 floats
+    assert ctypes.sizeof(L.GbView) == 4 * (2 + 4 + 9 + 3 + 1)
+    assert ctypes.sizeof(L.GbOptions) == 4 * (5 + 3 + 3)
+    assert ctypes.sizeof(L.GbSplats) == 16 + 6 * 8
+    assert ctypes.sizeof(L.GbLayout) == 8 * 12
+
+
+def test_default_options():
+    lib = _lib()
+    o = L.GbOptions()
+    lib.gb_default_options(ctypes.byref(o))
+    assert o.sigma == pytest.approx(0.5)
+    assert o.alpha_min == np.float32(1 / 255)
+    assert o.alpha_max == pytest.approx(0.99)
+    assert o.t_min == pytest.approx(1e-4)
+    assert (o.tile_w, o.tile_h, o.batch) == (16, 16, 0)
+
+
+def _layout(P=100, N=4, views=None, opts=None, cap=1000):
+    lib = _lib()
+    views = views or [sg.look_at_view((0, 0, -3), 64, 48)]
+    lay = L.GbLayout()
+    st = lib.gb_workspace_layout(P, N, L.make_views(views), len(views),
+                                 ctypes.byref(opts or L.make_options()), cap, ctypes.byref(lay))
+    return st, lay
+
+
+def test_layout_sections_are_aligned_and_disjoint():
+    views = [sg.look_at_view((0, 0, -3), 64, 48), sg.look_at_view((1, 0, -3), 33, 17)]
+    st, lay = _layout(P=1000, views=views, cap=12345)
+    assert st == L.GB_OK
+    offs = [lay.status, lay.depth_key, lay.tile_count, lay.records, lay.order, lay.pair_keys,
+            lay.pair_vals, lay.ranges, lay.n_last]
+    assert all(o % 256 == 0 for o in offs)
+    assert len(set(offs)) == len(offs)
+    assert max(offs) < lay.total_bytes
+    assert lay.pair_capacity == 12345
+    assert lay.total_tiles == 4 * 3 + 3 * 2
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("tile_w", 12, L.GB_ERR_ARG), ("tile_h", 64, L.GB_ERR_ARG), ("batch", 7, L.GB_ERR_ARG),
+    ("sigma", 0.0, L.GB_ERR_ARG), ("alpha_max", 1.5, L.GB_ERR_ARG), ("t_min", -1.0, L.GB_ERR_ARG),
+    ("lowpass_var", 0.0, L.GB_ERR_ARG),
+])
+def test_invalid_options_are_rejected(field, value, status):
+    o = L.make_options()
+    setattr(o, field, value)
+    st, _ = _layout(opts=o)
+    assert st == status
+
+
+def test_invalid_sizes_are_rejected():
+    assert _layout(P=0)[0] == L.GB_ERR_ARG
+    assert _layout(N=3)[0] == L.GB_ERR_UNSUPPORTED
+    assert _layout(N=16)[0] == L.GB_ERR_UNSUPPORTED
+    assert _layout(cap=-1)[0] == L.GB_ERR_ARG
+    bad = sg.look_at_view((0, 0, -3), 0, 48)
+    assert _layout(views=[bad])[0] == L.GB_ERR_ARG
+
+
+def test_render_rejects_null_pointers_before_launching():
+    lib = _lib()
+    views = L.make_views([sg.look_at_view((0, 0, -3), 32, 32)])
+    sp = L.GbSplats(10, 4, L.GB_F32, None, None, None, None, None, None)
+    opts = L.make_options()
+    st = lib.gb_render_fwd(ctypes.byref(sp), views, 1, ctypes.byref(opts), None, 0, 0, None,
+                           None, None)
+    assert st == L.GB_ERR_ARG
+    assert b"NULL" in lib.gb_last_error()

@@ -1,0 +1,284 @@
+"""Parity of the HIP rasterizer (through the C ABI) against the FP64 oracle.
+
+Bars: key stage, pair keys/values and tile ranges bit-exact; images and final transmittance
+within 1e-5 max-abs over pixels the oracle does not flag as near a decision threshold; each
+gradient tensor within 1e-3 relative L2 of the oracle's analytic gradient.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+from oracle import gb_oracle as O
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 1e-5
+GRAD_TOL = 1e-3
+# Pixels where the oracle finds a decision within its flag threshold (alpha vs alpha_min within
+# 1e-5 relative, T(1 - alpha) vs t_min within 1e-4) are excluded from the image gate and
+# counted; the gradient gate also zeroes the adjoint at pixels near a gradient kink.
+MAX_FLAGGED_FRACTION = 1e-3
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def gb():
+    _require_gpu()
+    import paper_2412_12734_amd as gb
+    gb.load()  # fails loudly if the HIP library is missing
+    return gb
+
+
+def gpu_opts(opts: O.Options, batch=0):
+    import paper_2412_12734_amd as gb
+    return gb.Options(sigma=opts.sigma, alpha_min=opts.alpha_min, alpha_max=opts.alpha_max,
+                      t_min=opts.t_min, lowpass_var=opts.lowpass_var, bg=tuple(opts.bg),
+                      tile_w=opts.tile_w, tile_h=opts.tile_h, batch=batch)
+
+
+def run_gpu(gb, scene, views, opts, tex_bf16=False, batch=0, capacity=None):
+    sp = gb.Splats.from_numpy(scene, tex_bf16=tex_bf16)
+    rast = gb.Rasterizer(views, gpu_opts(opts, batch))
+    rast.plan(sp, capacity)
+    rgb, T = rast.forward(sp)
+    torch.cuda.synchronize()
+    return rast, sp, rgb, T
+
+
+def image_crop(arr, base, W, H, crop, ch=3):
+    x0, y0, w, h = crop
+    a = arr[base:base + W * H].reshape((H, W, ch) if ch else (H, W))
+    return a[y0:y0 + h, x0:x0 + w]
+
+
+def assert_image_parity(rgb_gpu, T_gpu, ref: O.RenderResult, base, W, H):
+    crop = ref.crop
+    g_rgb = image_crop(rgb_gpu, base, W, H, crop).astype(np.float64)
+    g_T = image_crop(T_gpu, base, W, H, crop, ch=0).astype(np.float64)
+    ok = ~O.image_flags(ref)
+    flagged = int((~ok).sum())
+    assert flagged <= MAX_FLAGGED_FRACTION * ok.size + 2, f"{flagged} flagged pixels"
+    d = np.where(ok[..., None], np.abs(g_rgb - ref.rgb), 0.0)
+    dT = np.where(ok, np.abs(g_T - ref.T_final), 0.0)
+    if d.max(initial=0) > IMG_TOL or dT.max(initial=0) > IMG_TOL:
+        j, i, c = np.unravel_index(np.argmax(d), d.shape)
+        print(f"worst pixel (x={i + crop[0]}, y={j + crop[1]}, c={c}): gpu {g_rgb[j, i]} oracle "
+              f"{ref.rgb[j, i]} T gpu {g_T[j, i]} oracle {ref.T_final[j, i]} blended "
+              f"{ref.n_blended[j, i]} terminated {ref.terminated[j, i]} alpha_gap "
+              f"{ref.alpha_gap[j, i]:.3g} t_gap {ref.t_gap[j, i]:.3g}")
+    assert d.max(initial=0) <= IMG_TOL, f"max image error {d.max()}"
+    assert dT.max(initial=0) <= IMG_TOL, f"max transmittance error {dT.max()}"
+    return float(d.max(initial=0)), flagged
+
+
+# --- key stage, pairs, ranges: bit-exact --------------------------------------------------
+def check_tiling(gb, scene, views, opts):
+    rast, sp, rgb, T = run_gpu(gb, scene, views, opts)
+    P, V = scene.P, len(views)
+    depth = rast.section("depth_key", V * P, torch.int32).cpu().numpy().view(np.uint32)
+    count = rast.section("tile_count", V * P, torch.int32).cpu().numpy().view(np.uint32)
+    recs = rast.section("records", V * P * 24, torch.int32).cpu().numpy().reshape(V * P, 24)
+    for v, view in enumerate(views):
+        ks = O.key_stage(scene, view, opts)
+        sl = slice(v * P, (v + 1) * P)
+        vis = ks["visible"]
+        want_key = np.where(vis, ks["depth"].view(np.uint32), np.uint32(0xFFFFFFFF))
+        np.testing.assert_array_equal(depth[sl], want_key)
+        np.testing.assert_array_equal(count[sl], ks["count"].astype(np.uint32))
+        rx, ry = recs[sl, 19], recs[sl, 20]
+        i0, i1 = rx & 0xFFFF, rx >> 16
+        j0, j1 = ry & 0xFFFF, ry >> 16
+        got = np.stack([i0, i1, j0, j1], 1)[vis]
+        np.testing.assert_array_equal(got, ks["rect"][vis])
+    keys, vals, ranges = O.tile_pairs(scene, views, opts)
+    K, over = rast.status()
+    assert not over and K == keys.size
+    gk = rast.section("pair_keys", K, torch.int32).cpu().numpy().view(np.uint32)
+    gv = rast.section("pair_vals", K, torch.int32).cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(gk, keys)
+    np.testing.assert_array_equal(gv, vals)
+    gr = rast.section("ranges", 2 * ranges.shape[0], torch.int32).cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(gr.reshape(-1, 2).astype(np.int64), ranges)
+    return rast, rgb, T
+
+
+def test_tiling_bit_exact_config1(gb):
+    scene, views = sg.config("C1")
+    check_tiling(gb, scene, views, O.Options())
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (16, 8), (8, 16), (16, 16)])
+def test_tiling_bit_exact_multiview_tile_shapes(gb, tile):
+    scene = sg.make_scene(5, 3000, -1.5, 1.5, 0.01, 0.3, 2)
+    views = [sg.look_at_view((0.5, 0.3, -3.0), 97, 61), sg.look_at_view((-2.0, 1.0, -2.0), 64, 80),
+             sg.look_at_view((0.0, 3.0, 0.1), 33, 17)]
+    check_tiling(gb, scene, views, O.Options(tile_w=tile[0], tile_h=tile[1]))
+
+
+# --- images -------------------------------------------------------------------------------
+def test_image_parity_config1_full_frame(gb):
+    scene, views = sg.config("C1")
+    opts = O.Options()
+    rast, sp, rgb, T = run_gpu(gb, scene, views, opts)
+    ref = O.render(scene, views[0], opts)
+    err, flagged = assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 128, 128)
+    print(f"config1 image max err {err:.3g}, flagged {flagged}")
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_image_parity_tiny_scenes(gb, seed):
+    rng = np.random.default_rng(seed)
+    P = int(rng.integers(1, 11))
+    N = [1, 2, 4, 8][seed % 4]
+    scene = sg.make_scene(100 + seed, P, -0.5, 0.5, 0.03, 0.4, N)
+    W, H = int(rng.integers(16, 65)), int(rng.integers(16, 65))
+    view = sg.look_at_view(rng.standard_normal(3) * 0.5 + np.array([0, 0, -2.5]), W, H)
+    tile = [(16, 16), (8, 8), (16, 8), (8, 16)][seed % 4]
+    bg = tuple(rng.uniform(0, 1, 3))
+    opts = O.Options(tile_w=tile[0], tile_h=tile[1], bg=bg)
+    rast, sp, rgb, T = run_gpu(gb, scene, [view], opts)
+    ref = O.render(scene, view, opts)
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, W, H)
+
+
+def test_image_parity_thresholds_off(gb):
+    scene = sg.make_scene(9, 6, -0.4, 0.4, 0.05, 0.3, 4)
+    view = sg.look_at_view((0.1, 0.2, -2.0), 40, 30)
+    opts = O.Options(alpha_min=0.0, t_min=0.0, alpha_max=1.0, bg=(0.3, 0.2, 0.1))
+    rast, sp, rgb, T = run_gpu(gb, scene, [view], opts)
+    ref = O.render(scene, view, opts)
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 40, 30)
+
+
+def test_image_parity_config2_crops(gb):
+    scene, views = sg.config("C2")
+    opts = O.Options()
+    rast, sp, rgb, T = run_gpu(gb, scene, views, opts)
+    rgb, T = rgb.cpu().numpy(), T.cpu().numpy()
+    for crop in [(368, 368, 64, 64), (0, 0, 48, 40), (760, 750, 40, 50)]:
+        ref = O.render(scene, views[0], opts, crop=crop)
+        assert_image_parity(rgb, T, ref, 0, 800, 800)
+
+
+# --- gradients ------------------------------------------------------------------------------
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def check_grads(gb, scene, view, opts, crop, seed=0, tex_bf16=False):
+    rast, sp, rgb, T = run_gpu(gb, scene, [view], opts, tex_bf16=tex_bf16)
+    ref = O.render(scene, view, opts, crop=crop, keep_saved=True)
+    W, H = view.width, view.height
+    g_full = sg.make_dl_drgb(seed, [view]).reshape(H, W, 3)
+    x0, y0, w, h = crop
+    mask = np.zeros((H, W), dtype=bool)
+    mask[y0:y0 + h, x0:x0 + w] = ~O.grad_flags(ref)
+    g_full = np.where(mask[..., None], g_full, 0.0).astype(np.float32)
+    g_crop = g_full[y0:y0 + h, x0:x0 + w].reshape(-1, 3).astype(np.float64)
+    ref_g = O.render_backward(scene, view, opts, ref, g_crop)
+    d_rgb = torch.from_numpy(g_full.reshape(-1, 3)).cuda()
+    grads = rast.backward(sp, T, d_rgb)
+    torch.cuda.synchronize()
+    errs = {}
+    for name in ("means", "tan_u", "tan_v", "scales", "opacity", "textures"):
+        got = grads[name].cpu().numpy().astype(np.float64)
+        want = getattr(ref_g, name)
+        errs[name] = rel_l2(got, want)
+    print("gradient rel L2:", {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= GRAD_TOL, (k, v)
+    return errs
+
+
+def test_gradient_parity_config1_full_frame(gb):
+    scene, views = sg.config("C1")
+    check_grads(gb, scene, views[0], O.Options(), (0, 0, 128, 128))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_gradient_parity_tiny_scenes(gb, seed):
+    rng = np.random.default_rng(50 + seed)
+    P = int(rng.integers(2, 9))
+    N = [2, 4, 8, 1][seed]
+    scene = sg.make_scene(200 + seed, P, -0.4, 0.4, 0.05, 0.4, N)
+    W, H = int(rng.integers(20, 50)), int(rng.integers(20, 50))
+    view = sg.look_at_view(rng.standard_normal(3) * 0.5 + np.array([0, 0, -2.5]), W, H)
+    opts = O.Options(bg=tuple(rng.uniform(0, 1, 3)), tile_w=[16, 8, 16, 8][seed],
+                     tile_h=[16, 8, 8, 16][seed])
+    check_grads(gb, scene, view, opts, (0, 0, W, H), seed=seed)
+
+
+def test_gradient_parity_config2_crop(gb):
+    scene, views = sg.config("C2")
+    check_grads(gb, scene, views[0], O.Options(), (368, 368, 64, 64))
+
+
+# --- precision: bfloat16 texture storage ---------------------------------------------------
+def test_bf16_exact_texels_give_identical_images(gb):
+    scene, views = sg.config("C1")
+    q = (np.round(scene.textures * 256) / 256).astype(np.float32)  # exact in bfloat16
+    s = sg.Scene(scene.means, scene.tan_u, scene.tan_v, scene.scales, scene.opacity, q)
+    _, _, rgb32, T32 = run_gpu(gb, s, views, O.Options())
+    _, _, rgb16, T16 = run_gpu(gb, s, views, O.Options(), tex_bf16=True)
+    assert torch.equal(rgb32, rgb16) and torch.equal(T32, T16)
+
+
+def test_bf16_textures_match_oracle_on_rounded_texels(gb):
+    scene, views = sg.config("C1")
+    rast, sp, rgb, T = run_gpu(gb, scene, views, O.Options(), tex_bf16=True)
+    rounded = sg.bf16_bits_to_f32(sg.to_bf16_bits(scene.textures)).reshape(scene.textures.shape)
+    s = sg.Scene(scene.means, scene.tan_u, scene.tan_v, scene.scales, scene.opacity, rounded)
+    ref = O.render(s, views[0], O.Options())
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 128, 128)
+
+
+# --- batching: many views in one launch sequence --------------------------------------------
+def test_batched_views_equal_single_views(gb):
+    scene = sg.make_scene(11, 5000, -2, 2, 0.01, 0.2, 4)
+    views = sg.orbit_views(3, 4, 6.0, [(96, 64), (64, 80), (128, 72), (50, 50)],
+                           pick_resolution=True)
+    opts = O.Options()
+    _, _, rgb_b, T_b = run_gpu(gb, scene, views, opts)
+    base = 0
+    for v in views:
+        _, _, rgb1, T1 = run_gpu(gb, scene, [v], opts)
+        n = v.width * v.height
+        assert torch.equal(rgb_b[base:base + n], rgb1)
+        assert torch.equal(T_b[base:base + n], T1)
+        base += n
+
+
+# --- capacity and degenerate inputs ---------------------------------------------------------
+def test_capacity_overflow_is_reported_then_replanned(gb):
+    scene, views = sg.config("C1")
+    sp = gb.Splats.from_numpy(scene)
+    rast = gb.Rasterizer(views, gpu_opts(O.Options()), check_overflow=False)
+    rast.plan(sp, capacity=100)
+    rgb, T = rast.forward(sp)
+    K, over = rast.status()
+    assert over and K > 100
+    assert float(rgb.abs().max()) == 0.0 and float(T.min()) == 1.0
+    rast.check_overflow = True
+    rgb2, T2 = rast.forward(sp)
+    K2, over2 = rast.status()
+    assert not over2 and K2 == K
+    ref = O.render(scene, views[0], O.Options())
+    assert_image_parity(rgb2.cpu().numpy(), T2.cpu().numpy(), ref, 0, 128, 128)
+
+
+def test_all_splats_culled_gives_background(gb):
+    scene, _ = sg.config("C1", P=50)
+    view = sg.look_at_view((0, 0, 3.0), 32, 24, target=(0, 0, 6.0))  # looking away
+    opts = O.Options(bg=(0.25, 0.5, 0.75))
+    rast, sp, rgb, T = run_gpu(gb, scene, [view], opts)
+    assert rast.status() == (0, False)
+    np.testing.assert_array_equal(rgb.cpu().numpy(), np.broadcast_to([0.25, 0.5, 0.75], (32 * 24, 3)).astype(np.float32))
+    assert float(T.min()) == 1.0
