@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark: forward + backward of the textured 2D-Gaussian rasterizer on one MI355X.
+
+Workload (default): 1,000,000 splats with 8x8 FP32 textures (centres U[-4,4]^3, random
+orientations, scales log-U[0.02,0.2], opacity U(0.05,0.95)), one 1920x1080 view at distance 8,
+dL/drgb ~ N(0,1), seed 0. One step = one forward + one backward over the whole image. The
+inputs are resident in device memory before the timed region starts.
+
+Prints one JSON line: whole-job throughput in Mpixels/s (fwd+bwd), the roofline of the dominant
+kernel (blend backward, measured with HIP events on its launch stream), variants (bfloat16
+textures; four 1080p views in one batched call) and the FP64 oracle's rate on a bounded crop of
+the same workload on the host CPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Peaks of one MI355X (gfx950): 256 CUs x 4 SIMD16 x 2.4 GHz = 39.3 T FP32 lane-ops/s
+# without packed FP32 (this build never emits packed FP32), i.e. 78.6 TFLOP/s counting an
+# FMA as two flops; HBM3E 8 TB/s.
+PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic FP32 flops of the blend kernels per unit of work, counted from the formulas
+# (add/mul/min 1, FMA 2, rcp/exp 1; compares and integer ops not counted). The unit counts
+# come from the forward's work counters.
+#  forward, per evaluated (pixel, splat): offsets 2, uv solve 3x2 FMA 12, rcp 1, u and v 2,
+#    q_uv 4, q_lp 4, min 1, exp with scale 2, alpha 2 = 30
+#  forward, per blended (pixel, splat), in addition: T(1-alpha) 2, grid coordinates 2x6 12,
+#    bilinear 9 lerps 27, weight 1, accumulation 3 FMA 6 = 48
+#  backward, per blended (pixel, splat): recompute 30 + 12 + 27, T recovery 2, weight and
+#    colour adjoint 4, corner weights 6, texel adjoints 12, fraction adjoints 27, uv adjoints 2,
+#    alpha adjoint 15, S update 6, opacity and falloff adjoints 4, uv branch 4, rho adjoint 6,
+#    dH 6, dc2 12 + 2 = 177
+FLOPS_FWD_EVAL = 30
+FLOPS_FWD_BLEND = 48
+FLOPS_BWD_BLEND = 177
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_steps(rast, sp, rgb, T, g, grads, steps, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rast.forward(sp, rgb, T)
+        rast.backward(sp, T, g, grads)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def setup(gb, sg, torch, name, views=None):
+    scene, v = sg.config(name)
+    views = views or v
+    sp = gb.Splats.from_numpy(scene, tex_bf16=sg.CONFIGS[name]["bf16"])
+    rast = gb.Rasterizer(views, gb.Options(), check_overflow=False)
+    rast.plan(sp)
+    g = torch.from_numpy(sg.make_dl_drgb(0, views)).cuda()
+    rgb, T = rast.forward(sp)
+    grads = rast.backward(sp, T, g)
+    K, over = rast.status()
+    if over:
+        raise RuntimeError("pair capacity exceeded after planning")
+    return scene, views, sp, rast, g, rgb, T, grads, K
+
+
+def cpu_baseline(scene, view, crop):
+    """FP64 oracle (one process) on a crop of the workload: forward + analytic backward."""
+    import numpy as np
+    from oracle import gb_oracle as O
+    t0 = time.perf_counter()
+    r = O.render(scene, view, O.Options(), crop=crop, keep_saved=True)
+    g = np.random.default_rng(0).standard_normal((crop[2] * crop[3], 3))
+    O.render_backward(scene, view, O.Options(), r, g)
+    dt = time.perf_counter() - t0
+    return crop[2] * crop[3] / dt / 1e6, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the rasterizer has no "
+              "multi-GPU path in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2412_12734_amd as gb
+    import scenegen as sg
+
+    gb.load()
+    log("setting up T0 (1M splats, 8x8 FP32 textures, 1920x1080)")
+    scene, views, sp, rast, g, rgb, T, grads, K = setup(gb, sg, torch, "T0")
+    pixels = sum(v.width * v.height for v in views)
+    for _ in range(args.warmup):
+        rast.forward(sp, rgb, T)
+        rast.backward(sp, T, g, grads)
+    sec = time_steps(rast, sp, rgb, T, g, grads, args.steps, torch)
+    value = pixels / sec / 1e6
+    log(f"T0 fp32: {sec * 1e3:.3f} ms/step, {value:.1f} Mpx/s, K={K}")
+
+    # per-stage durations from HIP events recorded on the launch stream
+    stage_sum = {}
+    rast.timing(True)
+    for _ in range(args.steps):
+        rast.forward(sp, rgb, T)
+        rast.backward(sp, T, g, grads)
+        for k, v in rast.stage_times().items():
+            stage_sum[k] = stage_sum.get(k, 0.0) + v
+    rast.timing(False)
+    stages = {k: v / args.steps for k, v in stage_sum.items()}
+    log("stages (ms): " + ", ".join(f"{k}={v:.3f}" for k, v in stages.items()))
+
+    st = rast.blend_stats(sp, rgb, T)
+    e_eval, e_blend = st["lane_evals"], st["blended"]
+    bwd_ms = stages["blend_bwd"]
+    fwd_ms = stages["blend_fwd"]
+    bwd_flops = e_blend * FLOPS_BWD_BLEND
+    fwd_flops = e_eval * FLOPS_FWD_EVAL + e_blend * FLOPS_FWD_BLEND
+    achieved = bwd_flops / (bwd_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "blend_bwd", "achieved": round(achieved, 3),
+                "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "units_per_launch": {"blended_pairs": e_blend},
+                "flops_per_unit": FLOPS_BWD_BLEND, "avg_ms": round(bwd_ms, 4)}
+    fwd_tf = fwd_flops / (fwd_ms * 1e-3) / 1e12
+
+    variants = {}
+    if not args.no_variants:
+        del rast
+        torch.cuda.empty_cache()
+        log("variant: bf16 textures, one view")
+        _, views_b, sp_b, rast_b, g_b, rgb_b, T_b, grads_b, _ = setup(gb, sg, torch, "T0_BF16")
+        for _ in range(args.warmup):
+            rast_b.forward(sp_b, rgb_b, T_b)
+            rast_b.backward(sp_b, T_b, g_b, grads_b)
+        s_b = time_steps(rast_b, sp_b, rgb_b, T_b, g_b, grads_b, args.steps, torch)
+        variants["bf16_single_view"] = {"ms_per_step": round(s_b * 1e3, 3),
+                                        "mpix_per_s": round(pixels / s_b / 1e6, 1)}
+        del rast_b
+        torch.cuda.empty_cache()
+        log("variant: bf16 textures, four 1080p views batched in one call")
+        views4 = sg.orbit_views(0, 4, 8.0, [(1920, 1080)])
+        _, _, sp4, rast4, g4, rgb4, T4, grads4, K4 = setup(gb, sg, torch, "T0_BF16", views=views4)
+        for _ in range(args.warmup):
+            rast4.forward(sp4, rgb4, T4)
+            rast4.backward(sp4, T4, g4, grads4)
+        s_4 = time_steps(rast4, sp4, rgb4, T4, g4, grads4, args.steps, torch)
+        px4 = 4 * 1920 * 1080
+        variants["bf16_batched_4x1080p"] = {"ms_per_step": round(s_4 * 1e3, 3),
+                                            "mpix_per_s": round(px4 / s_4 / 1e6, 1),
+                                            "pairs": K4}
+        variants["speedup_bf16_batched_vs_fp32_single"] = round((px4 / s_4) / (pixels / sec), 3)
+        del rast4
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        crop = (896, 476, 128, 128)
+        log("cpu baseline: FP64 oracle on a 128x128 centre crop (fwd + bwd)")
+        mpx, dt = cpu_baseline(scene, views[0], crop)
+        cpu = {"value": round(mpx, 6), "unit": "Mpixels/s", "cores": 1, "kind": "oracle",
+               "sample": "128x128 centre crop of the 1920x1080 view, forward + analytic "
+                         f"backward, one process ({dt:.1f} s)"}
+
+    out = {
+        "metric": "fwd+bwd Mpixels/s & ms/iter at 1M textured splats, 1080p; batched BF16 vs FP32",
+        "value": round(value, 2), "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "T0: 1M splats, 8x8 FP32 textures, one 1920x1080 view, fwd+bwd",
+                   "pixels": pixels, "pairs": K, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "stage_ms": {k: round(v, 4) for k, v in stages.items()},
+        "blend_fwd_tflops": round(fwd_tf, 3),
+        "work": st,
+        "variants": variants,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
