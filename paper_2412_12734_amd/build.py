@@ -20,6 +20,8 @@ HIP_FLAGS = [
     f"--offload-arch={ARCH}",
     # hardware float atomics (global_atomic_add_f32) instead of CAS loops
     "-munsafe-fp-atomics",
+    # atomics here are issued by one lane or to distinct addresses: no cross-lane pre-scan
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     # never emit packed FP32 arithmetic
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",

@@ -9,8 +9,9 @@
 //   uv branch: du += dq u, dv += dq v; low-pass branch: d(dx, dy) += dq 2 (dx, dy) / (2 var),
 //   (u, v) = (rho0, rho1) / rho2 -> d rho -> d H (7 entries) and d(dx, dy) -> d c2 = -d(dx, dy).
 // The ten per-splat scalars are summed over the wave with DPP and added to the batch slot in
-// LDS; texel gradients are added to LDS with ds_add_f32. After each batch the non-zero LDS
-// sums go to global memory with one float atomic each.
+// LDS; texel gradients are grouped by grid cell, summed over the wave and added to LDS with
+// ds_add_f32. After each batch the non-zero LDS sums go to global memory with one float
+// atomic each.
 #include "blend_common.h"
 
 namespace gbb {
@@ -52,7 +53,9 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   // pixel centre relative to the tile centre (exact half-integers)
   const float lx = (float)lxi - 0.5f * (float)(p.tile_w - 1);
   const float ly = (float)lyi - 0.5f * (float)(p.tile_h - 1);
-  const int wx0 = tile_x0 + bx, wx1 = wx0 + 7, wy0 = tile_y0 + by, wy1 = wy0 + 7;
+  const int wx0 = tile_x0 + bx, wy0 = tile_y0 + by;
+  const float bcx = (float)bx + 3.5f - 0.5f * (float)(p.tile_w - 1);
+  const float bcy = (float)by + 3.5f - 0.5f * (float)(p.tile_h - 1);
 
   const uint32_t start = ranges[2 * tile];
   float T = 1.0f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
@@ -102,14 +105,23 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
     stage_texels<N, BF16>(textures, s_splat, nb, s_tex);
     __syncthreads();
 
-    for (int j = nb - 1; j >= 0; --j) {
+    // splats of this batch that can reach the wave's 8 x 8 block, walked back to front
+    bool may = false;
+    if (lane < nb) {
+      StagedGeo c;
+      c.g0 = s_geo[lane][0];
+      c.g1 = s_geo[lane][1];
+      c.g2 = s_geo[lane][2];
+      c.g3 = s_geo[lane][3];
+      may = block_may_contribute(c, bcx, bcy, wx0, wy0, p);
+    }
+    uint64_t todo = ballot(may);
+    while (todo != 0) {
+      const int j = 63 - (int)__builtin_clzll(todo);
+      todo &= ~(1ull << j);
       const uint32_t jg = bstart + (uint32_t)j;
-      StagedGeo g;
-      g.g3 = s_geo[j][3];
-      const int rx = __float_as_int(g.g3.x), ry = __float_as_int(g.g3.y);
-      const int i0 = rx & 0xffff, i1 = rx >> 16, j0 = ry & 0xffff, j1 = ry >> 16;
-      if (i1 < wx0 || i0 > wx1 || j1 < wy0 || j0 > wy1) continue;
       if (!__any(jg < last)) continue;
+      StagedGeo g;
       g.g0 = s_geo[j][0];
       g.g1 = s_geo[j][1];
       g.g2 = s_geo[j][2];
@@ -117,51 +129,43 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
       const bool act = (jg < last) && e.hit;
       float gh[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       float gc2x = 0.f, gc2y = 0.f, go = 0.f;
+      // colour adjoint and bilinear corner weights of this lane (texel scatter below)
+      int k00 = 0;
+      float w00 = 0.f, w01 = 0.f, w10 = 0.f, w11 = 0.f;
+      float dc0 = 0.f, dc1 = 0.f, dc2 = 0.f;
       if (act) {
-        const float one_m = 1.0f - e.alpha;
-        T = T / one_m;  // transmittance in front of this splat
+        const float inv1m = __builtin_amdgcn_rcpf(1.0f - e.alpha);
+        T = T * inv1m;  // transmittance in front of this splat
         float c0, c1, c2;
         float du = 0.f, dv = 0.f;
         const float wgt = e.alpha * T;
-        const float dc0 = wgt * g0, dc1 = wgt * g1, dc2 = wgt * g2;
+        dc0 = wgt * g0;
+        dc1 = wgt * g1;
+        dc2 = wgt * g2;
         const float4* tex = s_tex + j * N * N;
-        float* gt = s_gtex + j * TEXG;
         if constexpr (N == 1) {
           const float4 t = tex[0];
           c0 = t.x;
           c1 = t.y;
           c2 = t.z;
-          atomicAdd(&gt[0], dc0);
-          atomicAdd(&gt[1], dc1);
-          atomicAdd(&gt[2], dc2);
+          w00 = 1.f;
         } else {
           int iu, iv;
           float fu, fv;
           grid_coord<N>(e.u, p, iu, fu);
           grid_coord<N>(e.v, p, iv, fv);
-          const int k00 = iu * N + iv, k01 = k00 + 1, k10 = k00 + N, k11 = k00 + N + 1;
-          const float4 t00 = tex[k00], t01 = tex[k01], t10 = tex[k10], t11 = tex[k11];
+          k00 = iu * N + iv;
+          const float4 t00 = tex[k00], t01 = tex[k00 + 1], t10 = tex[k00 + N], t11 = tex[k00 + N + 1];
           const float a0 = t00.x + fv * (t01.x - t00.x), b0_ = t10.x + fv * (t11.x - t10.x);
           const float a1 = t00.y + fv * (t01.y - t00.y), b1 = t10.y + fv * (t11.y - t10.y);
           const float a2 = t00.z + fv * (t01.z - t00.z), b2 = t10.z + fv * (t11.z - t10.z);
           c0 = a0 + fu * (b0_ - a0);
           c1 = a1 + fu * (b1 - a1);
           c2 = a2 + fu * (b2 - a2);
-          // texel adjoints
-          const float w00 = (1.f - fu) * (1.f - fv), w01 = (1.f - fu) * fv;
-          const float w10 = fu * (1.f - fv), w11 = fu * fv;
-          atomicAdd(&gt[3 * k00 + 0], dc0 * w00);
-          atomicAdd(&gt[3 * k00 + 1], dc1 * w00);
-          atomicAdd(&gt[3 * k00 + 2], dc2 * w00);
-          atomicAdd(&gt[3 * k01 + 0], dc0 * w01);
-          atomicAdd(&gt[3 * k01 + 1], dc1 * w01);
-          atomicAdd(&gt[3 * k01 + 2], dc2 * w01);
-          atomicAdd(&gt[3 * k10 + 0], dc0 * w10);
-          atomicAdd(&gt[3 * k10 + 1], dc1 * w10);
-          atomicAdd(&gt[3 * k10 + 2], dc2 * w10);
-          atomicAdd(&gt[3 * k11 + 0], dc0 * w11);
-          atomicAdd(&gt[3 * k11 + 1], dc1 * w11);
-          atomicAdd(&gt[3 * k11 + 2], dc2 * w11);
+          w00 = (1.f - fu) * (1.f - fv);
+          w01 = (1.f - fu) * fv;
+          w10 = fu * (1.f - fv);
+          w11 = fu * fv;
           // fractional-position adjoints (Alg. 2), zero where the coordinate is clamped
           const float dfu = dc0 * (b0_ - a0) + dc1 * (b1 - a1) + dc2 * (b2 - a2);
           const float fv0 = (t01.x - t00.x) * (1.f - fu) + (t11.x - t10.x) * fu;
@@ -171,7 +175,6 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
           du = (e.u > -p.sigma && e.u < p.sigma) ? p.tex_scale * dfu : 0.f;
           dv = (e.v > -p.sigma && e.v < p.sigma) ? p.tex_scale * dfv : 0.f;
         }
-        const float inv1m = 1.0f / one_m;
         const float dalpha = g0 * (c0 * T - S0 * inv1m) + g1 * (c1 * T - S1 * inv1m) +
                              g2 * (c2 * T - S2 * inv1m);
         S0 += wgt * c0;
@@ -202,21 +205,59 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
         gc2x = -ddx;
         gc2y = -ddy;
       }
-      // wave sums of the per-splat scalars (all lanes take part)
+      // wave sums of the per-splat scalars (all lanes take part); lane 0 adds them to LDS
       float* gr = s_grec + j * kRecGrad;
-#pragma unroll
-      for (int k = 0; k < 7; ++k) {
-        const float s = wave_sum_to_lane63(gh[k]);
-        if (lane == 63) atomicAdd(&gr[k], s);
-      }
       {
-        const float s7 = wave_sum_to_lane63(gc2x);
-        const float s8 = wave_sum_to_lane63(gc2y);
-        const float s9 = wave_sum_to_lane63(go);
-        if (lane == 63) {
-          atomicAdd(&gr[7], s7);
-          atomicAdd(&gr[8], s8);
-          atomicAdd(&gr[9], s9);
+        float red[kRecGrad] = {gh[0], gh[1], gh[2], gh[3], gh[4], gh[5], gh[6], gc2x, gc2y, go};
+        wave_sum_all<kRecGrad>(red);
+        if (lane == 0) {
+#pragma unroll
+          for (int k = 0; k < kRecGrad; ++k) atomicAdd(&gr[k], red[k]);
+        }
+      }
+      // Texel gradients. Most blended pixels of a wave fall into one or two cells of the
+      // grid (the grid covers only the splat's core and clamped pixels share border cells),
+      // so lanes are grouped by cell and each group is summed over the wave before one lane
+      // adds it to LDS; corners whose weights vanish for the whole group are skipped. After
+      // a few groups the remaining lanes add their own contributions.
+      float* gt = s_gtex + j * TEXG;
+      uint64_t pending = ballot(act);
+#pragma unroll 1
+      for (int it = 0; it < 4 && pending != 0; ++it) {
+        const int leader = (int)__builtin_ctzll(pending);
+        const int lead_cell = __builtin_amdgcn_readlane(k00, leader);
+        const bool in = act && k00 == lead_cell && ((pending >> lane) & 1ull);
+        const uint64_t grp = ballot(in);
+        const float wq[4] = {w00, w01, w10, w11};
+        const int offq[4] = {0, 1, N, N + 1};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (N == 1 && q > 0) break;
+          if (!__any(in && wq[q] != 0.f)) continue;
+          const float wv = in ? wq[q] : 0.f;
+          float red[3] = {wv * dc0, wv * dc1, wv * dc2};
+          wave_sum_all<3>(red);
+          if (lane == 0) {
+            float* dst = gt + 3 * (lead_cell + offq[q]);
+            atomicAdd(dst + 0, red[0]);
+            atomicAdd(dst + 1, red[1]);
+            atomicAdd(dst + 2, red[2]);
+          }
+        }
+        pending &= ~grp;
+      }
+      if ((pending >> lane) & 1ull) {
+        const float wq[4] = {w00, w01, w10, w11};
+        const int offq[4] = {0, 1, N, N + 1};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (N == 1 && q > 0) break;
+          if (wq[q] != 0.f) {
+            float* dst = gt + 3 * (k00 + offq[q]);
+            atomicAdd(dst + 0, wq[q] * dc0);
+            atomicAdd(dst + 1, wq[q] * dc1);
+            atomicAdd(dst + 2, wq[q] * dc2);
+          }
         }
       }
     }

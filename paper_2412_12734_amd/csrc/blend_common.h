@@ -63,38 +63,46 @@ __device__ __forceinline__ StagedGeo stage_geo(const SplatRec& r, int tile_x0, i
   return s;
 }
 
-// Copies the texels of `nb` staged splats into LDS as float4 (RGB + pad) per texel.
+// Copies the texels of `nb` staged splats into LDS as float4 (RGB + pad) per texel. For even
+// N a splat's 3 N^2 channel values split into groups of 12 (four texels): each thread moves
+// whole groups, three 16-byte (float32) or 8-byte (bfloat16) loads in, four LDS stores out.
 template <int N, bool BF16>
 __device__ __forceinline__ void stage_texels(const void* __restrict__ textures,
                                              const int32_t* s_splat, int nb, float4* s_tex) {
   constexpr int per = 3 * N * N;  // channel values per splat
   const int tid = threadIdx.x, nthr = blockDim.x;
-  if constexpr (!BF16 && (per % 4) == 0) {
-    constexpr int per4 = per / 4;
-    const float4* tex4 = reinterpret_cast<const float4*>(textures);
-    for (int e = tid; e < nb * per4; e += nthr) {
-      const int j = e / per4, r4 = e - j * per4;
-      const float4 v = tex4[(int64_t)s_splat[j] * per4 + r4];
-      float* dst = reinterpret_cast<float*>(s_tex + j * N * N);
-      const int r = 4 * r4;
-      // channel value r lives at texel r / 3, component r % 3
-      dst[(r + 0) / 3 * 4 + (r + 0) % 3] = v.x;
-      dst[(r + 1) / 3 * 4 + (r + 1) % 3] = v.y;
-      dst[(r + 2) / 3 * 4 + (r + 2) % 3] = v.z;
-      dst[(r + 3) / 3 * 4 + (r + 3) % 3] = v.w;
-    }
-  } else if constexpr (BF16 && (per % 4) == 0) {
-    constexpr int per4 = per / 4;
-    const uint2* tex4 = reinterpret_cast<const uint2*>(textures);
-    for (int e = tid; e < nb * per4; e += nthr) {
-      const int j = e / per4, r4 = e - j * per4;
-      const uint2 v = tex4[(int64_t)s_splat[j] * per4 + r4];
-      float* dst = reinterpret_cast<float*>(s_tex + j * N * N);
-      const int r = 4 * r4;
-      dst[(r + 0) / 3 * 4 + (r + 0) % 3] = __uint_as_float(v.x << 16);
-      dst[(r + 1) / 3 * 4 + (r + 1) % 3] = __uint_as_float(v.x & 0xffff0000u);
-      dst[(r + 2) / 3 * 4 + (r + 2) % 3] = __uint_as_float(v.y << 16);
-      dst[(r + 3) / 3 * 4 + (r + 3) % 3] = __uint_as_float(v.y & 0xffff0000u);
+  if constexpr ((per % 12) == 0) {
+    constexpr int groups = per / 12;  // = N^2 / 4
+    for (int gi = tid; gi < nb * groups; gi += nthr) {
+      const int j = gi / groups, a = gi - j * groups;
+      const int64_t src = ((int64_t)s_splat[j] * groups + a) * 3;
+      float v[12];
+      if constexpr (BF16) {
+        const uint2* t = reinterpret_cast<const uint2*>(textures) + src;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const uint2 x = t[k];
+          v[4 * k + 0] = __uint_as_float(x.x << 16);
+          v[4 * k + 1] = __uint_as_float(x.x & 0xffff0000u);
+          v[4 * k + 2] = __uint_as_float(x.y << 16);
+          v[4 * k + 3] = __uint_as_float(x.y & 0xffff0000u);
+        }
+      } else {
+        const float4* t = reinterpret_cast<const float4*>(textures) + src;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const float4 x = t[k];
+          v[4 * k + 0] = x.x;
+          v[4 * k + 1] = x.y;
+          v[4 * k + 2] = x.z;
+          v[4 * k + 3] = x.w;
+        }
+      }
+      float4* dst = s_tex + j * N * N + 4 * a;
+      dst[0] = make_float4(v[0], v[1], v[2], 0.f);
+      dst[1] = make_float4(v[3], v[4], v[5], 0.f);
+      dst[2] = make_float4(v[6], v[7], v[8], 0.f);
+      dst[3] = make_float4(v[9], v[10], v[11], 0.f);
     }
   } else {
     for (int e = tid; e < nb * per; e += nthr) {
@@ -140,6 +148,36 @@ __device__ __forceinline__ PixelEval eval_splat(const StagedGeo& s, float lx, fl
   e.alpha = fminf(p.alpha_max, s.g0.w * e.G);
   e.hit = (r2 != 0.0f) && (e.alpha >= p.alpha_min);
   return e;
+}
+
+// Conservative test whether a staged splat can reach alpha >= alpha_min anywhere in a wave's
+// 8 x 8 pixel block: (cx, cy) is the block centre relative to the tile centre, (bx0, by0) the
+// block's first pixel. rho is affine in the pixel offset, so its range over the block is
+// exact; where rho2 keeps its sign, |u| >= min|rho0| / max|rho2| (likewise v), and the
+// low-pass term is bounded by the block's distance to the projected centre. A splat is
+// skipped only if even the largest possible opacity is clearly below alpha_min, so skipping
+// never changes a result.
+__device__ __forceinline__ bool block_may_contribute(const StagedGeo& s, float cx, float cy,
+                                                     int bx0, int by0, const BlendParams& p) {
+  const int rx = __float_as_int(s.g3.x), ry = __float_as_int(s.g3.y);
+  const int i0 = rx & 0xffff, i1 = rx >> 16, j0 = ry & 0xffff, j1 = ry >> 16;
+  if (i1 < bx0 || i0 > bx0 + 7 || j1 < by0 || j0 > by0 + 7) return false;
+  const float h00 = s.g1.x, h01 = s.g1.y, h10 = s.g1.z, h11 = s.g1.w, h20 = s.g2.x, h21 = s.g2.y;
+  const float r2c = __builtin_fmaf(h21, cy, __builtin_fmaf(h20, cx, s.g0.z));
+  const float r2e = 3.5f * (fabsf(h20) + fabsf(h21));
+  if (!(fabsf(r2c) > 1.001f * r2e)) return true;  // the vanishing line may cross the block
+  const float r0c = __builtin_fmaf(h01, cy, __builtin_fmaf(h00, cx, s.g0.x));
+  const float r1c = __builtin_fmaf(h11, cy, __builtin_fmaf(h10, cx, s.g0.y));
+  const float r0m = fmaxf(fabsf(r0c) - 3.5f * (fabsf(h00) + fabsf(h01)), 0.f);
+  const float r1m = fmaxf(fabsf(r1c) - 3.5f * (fabsf(h10) + fabsf(h11)), 0.f);
+  const float inv = 1.0f / (fabsf(r2c) + r2e);
+  const float um = r0m * inv, vm = r1m * inv;
+  const float q_uv = 0.5f * (um * um + vm * vm);
+  const float dxm = fmaxf(fabsf(cx + s.g2.z) - 3.5f, 0.f);
+  const float dym = fmaxf(fabsf(cy + s.g2.w) - 3.5f, 0.f);
+  const float q_lp = (dxm * dxm + dym * dym) * p.lp_scale;
+  const float q = fminf(q_uv, q_lp);
+  return s.g0.w * __builtin_amdgcn_exp2f(-q * 1.4426950408889634f) >= 0.99f * p.alpha_min;
 }
 
 // Grid coordinate of u on the corner-aligned N-texel grid (Alg. 2 with the cell index taken

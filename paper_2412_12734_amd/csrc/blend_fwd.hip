@@ -45,8 +45,10 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   // pixel centre relative to the tile centre (exact half-integers)
   const float lx = (float)lxi - 0.5f * (float)(p.tile_w - 1);
   const float ly = (float)lyi - 0.5f * (float)(p.tile_h - 1);
-  // wave block in pixels, for the rectangle test
-  const int wx0 = tile_x0 + bx, wx1 = wx0 + 7, wy0 = tile_y0 + by, wy1 = wy0 + 7;
+  // wave block: first pixel, and centre relative to the tile centre
+  const int wx0 = tile_x0 + bx, wy0 = tile_y0 + by;
+  const float bcx = (float)bx + 3.5f - 0.5f * (float)(p.tile_w - 1);
+  const float bcy = (float)by + 3.5f - 0.5f * (float)(p.tile_h - 1);
 
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
   float T = 1.0f;
@@ -74,12 +76,21 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
     __syncthreads();
 
     if (!__all(done)) {
-      for (int j = 0; j < nb; ++j) {
+      // splats of this batch that can reach the wave's 8 x 8 block (one lane per splat)
+      bool may = false;
+      if (lane < nb) {
+        StagedGeo c;
+        c.g0 = s_geo[lane][0];
+        c.g1 = s_geo[lane][1];
+        c.g2 = s_geo[lane][2];
+        c.g3 = s_geo[lane][3];
+        may = block_may_contribute(c, bcx, bcy, wx0, wy0, p);
+      }
+      uint64_t todo = ballot(may);
+      while (todo != 0) {
+        const int j = (int)__builtin_ctzll(todo);
+        todo &= todo - 1;
         StagedGeo g;
-        g.g3 = s_geo[j][3];
-        const int rx = __float_as_int(g.g3.x), ry = __float_as_int(g.g3.y);
-        const int i0 = rx & 0xffff, i1 = rx >> 16, j0 = ry & 0xffff, j1 = ry >> 16;
-        if (i1 < wx0 || i0 > wx1 || j1 < wy0 || j0 > wy1) continue;
         g.g0 = s_geo[j][0];
         g.g1 = s_geo[j][1];
         g.g2 = s_geo[j][2];
@@ -136,9 +147,14 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
     n_last[pix] = last;
   }
   if (STATS) {
-    if (st_blend) atomicAdd(&stats[0], (unsigned long long)st_blend);
-    if (st_term) atomicAdd(&stats[1], 1ull);
-    if (lane == 0) atomicAdd(&stats[2], 64ull * st_eval);
+    // per-wave totals (exact in float32: at most 64 x 2^17 per wave), one atomic each
+    float red[2] = {(float)st_blend, st_term ? 1.f : 0.f};
+    wave_sum_all<2>(red);
+    if (lane == 0) {
+      atomicAdd(&stats[0], (unsigned long long)red[0]);
+      atomicAdd(&stats[1], (unsigned long long)red[1]);
+      atomicAdd(&stats[2], 64ull * st_eval);
+    }
   }
 }
 

@@ -114,6 +114,35 @@ __device__ __forceinline__ float wave_sum_to_lane63(float v) {
   return v;
 }
 
+// Sums of K values over the 64 lanes, every lane receiving the totals. The K reductions are
+// interleaved step by step so that independent DPP operations fill the VALU-to-DPP wait
+// states. Within each row of 16 lanes: xor 1 and xor 2 (quad permutes), rotate by 4 and by 8;
+// across rows: swap with the neighbouring row (permlane16) and with the other half of the
+// wave (permlane32), each followed by an add.
+template <int K>
+__device__ __forceinline__ void wave_sum_all(float (&v)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_f<0xB1>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_f<0x4E>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_f<0x124>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_f<0x128>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[k]), __float_as_uint(v[k]),
+                                                    false, false);
+    v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[k]), __float_as_uint(v[k]),
+                                                    false, false);
+    v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_to_lane63(v)), 63));
 }

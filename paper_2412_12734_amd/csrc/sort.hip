@@ -3,10 +3,11 @@
 // Scan: reduce per 4096-element tile -> scan of tile sums in one workgroup -> per-tile scan.
 // Radix pass (8-bit digit): per-tile digit histogram -> exclusive scan of the digit-major
 // [digit][tile] counts -> scatter. The scatter ranks each element stably among equal digits
-// of its tile: elements enter in rounds of 256 in index order; inside a wave the lanes with
-// the same digit are found with eight ballots (one per digit bit), across waves and rounds
-// with running per-digit counters in LDS. Elements are then placed in LDS in digit order and
-// written out so that consecutive lanes store consecutive addresses of one digit run.
+// of its tile: each wave takes a contiguous quarter of the tile in rounds of 64; lanes with
+// the same digit are found with eight ballots (one per digit bit) and counted against the
+// wave's running per-digit counters in LDS. Wave offsets and digit starts then place every
+// element in LDS in digit order, and the tile is written out so that consecutive lanes store
+// consecutive addresses of one digit run.
 #include "device_util.h"
 #include "gbb_internal.h"
 
@@ -146,6 +147,14 @@ scan_down_kernel(const uint32_t* __restrict__ in, const uint32_t* __restrict__ g
 }
 
 // ---- radix sort --------------------------------------------------------------------------
+// Workgroups are dealt to the 8 XCDs round-robin; tile t of a pass is handled by the block
+// that puts consecutive tiles on one XCD, so the per-tile digit counts (stored digit-major,
+// one column per tile) fill whole cache lines in that XCD's L2.
+__device__ __forceinline__ int64_t radix_tile_of_block(int64_t nb) {
+  const int64_t per_xcd = (nb + 7) / 8;
+  return (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+}
+
 __device__ __forceinline__ int64_t sort_count(const uint32_t* d_n, int64_t n_cap) {
   if (!d_n) return n_cap;
   int64_t n = (int64_t)(*d_n);
@@ -157,18 +166,36 @@ radix_hist_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict_
                   int64_t n_cap, int shift, int64_t nb, uint32_t* __restrict__ hist) {
   __shared__ uint32_t h[256];
   const int64_t n = sort_count(d_n, n_cap);
+  const int64_t tile = radix_tile_of_block(nb);
+  if (tile >= nb) return;
   h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+  const int64_t base = tile * kRadixTile;
   if (base < n) {
-#pragma unroll 4
+    // all loads first (memory-level parallelism), then lanes with equal digits are grouped
+    // with eight ballots and one add per group
+    uint32_t d_r[kRadixItems];
+#pragma unroll
     for (int k = 0; k < kRadixItems; ++k) {
-      int64_t i = base + k * kRadixThreads + threadIdx.x;
-      if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+      const int64_t i = base + k * kRadixThreads + threadIdx.x;
+      d_r[k] = i < n ? (keys[i] >> shift) & 255u : 256u;
+    }
+#pragma unroll
+    for (int k = 0; k < kRadixItems; ++k) {
+      const uint32_t d = d_r[k];
+      const bool valid = d < 256u;
+      uint64_t m = ballot(valid);
+#pragma unroll
+      for (int bit = 0; bit < 8; ++bit) {
+        const bool set = (d >> bit) & 1u;
+        const uint64_t b = ballot(set);
+        m &= set ? b : ~b;
+      }
+      if (valid && mbcnt(m) == 0) atomicAdd(&h[d], popc64(m));
     }
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+  hist[(int64_t)threadIdx.x * nb + tile] = h[threadIdx.x];
 }
 
 __global__ void __launch_bounds__(kRadixThreads)
@@ -176,30 +203,38 @@ radix_scatter_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __res
                      uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
                      const uint32_t* __restrict__ d_n, int64_t n_cap, int shift, int64_t nb,
                      const uint32_t* __restrict__ hist_scanned) {
+  constexpr int kWaves = kRadixThreads / 64;
+  constexpr int kPerWave = kRadixTile / kWaves;  // contiguous elements ranked by one wave
   __shared__ uint32_t s_keys[kRadixTile];
   __shared__ uint32_t s_vals[kRadixTile];
-  __shared__ uint32_t s_cnt[4][256];
-  __shared__ uint32_t s_run[256];
+  __shared__ uint32_t s_cnt[kWaves][256];  // running per-wave digit counts, then wave offsets
   __shared__ uint32_t s_start[256];
   __shared__ uint32_t wave_tot[4];
   const int64_t n = sort_count(d_n, n_cap);
-  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
-  if (base >= n) return;
+  const int64_t tile = radix_tile_of_block(nb);
+  const int64_t base = tile * kRadixTile;
+  if (tile >= nb || base >= n) return;
   const int nvalid = (int)((n - base) < kRadixTile ? (n - base) : kRadixTile);
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  s_run[tid] = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s_cnt[w][lane + 64 * k] = 0;
+  __builtin_amdgcn_wave_barrier();
+  // Each wave ranks its own contiguous quarter of the tile in rounds of 64 elements; program
+  // order inside the wave keeps equal digits in index order.
   uint32_t key_r[kRadixItems], val_r[kRadixItems], rank_r[kRadixItems];
+  // all loads first (memory-level parallelism)
 #pragma unroll
   for (int r = 0; r < kRadixItems; ++r) {
-    const int i = r * kRadixThreads + tid;
+    const int i = w * kPerWave + r * 64 + lane;
     const bool valid = i < nvalid;
-    const uint32_t key = valid ? keys_in[base + i] : 0u;
-    const uint32_t val = valid ? vals_in[base + i] : 0u;
-    const uint32_t d = (key >> shift) & 255u;
-    s_cnt[w][lane] = 0;
-    s_cnt[w][lane + 64] = 0;
-    s_cnt[w][lane + 128] = 0;
-    s_cnt[w][lane + 192] = 0;
+    key_r[r] = valid ? keys_in[base + i] : 0u;
+    val_r[r] = valid ? vals_in[base + i] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < kRadixItems; ++r) {
+    const int i = w * kPerWave + r * 64 + lane;
+    const bool valid = i < nvalid;
+    const uint32_t d = (key_r[r] >> shift) & 255u;
     uint64_t m = ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < 8; ++bit) {
@@ -208,36 +243,31 @@ radix_scatter_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __res
       m &= set ? b : ~b;
     }
     const uint32_t below = mbcnt(m);
-    if (valid && below == 0) s_cnt[w][d] = popc64(m);
-    __syncthreads();
-    {
-      uint32_t run = s_run[tid];
-#pragma unroll
-      for (int ww = 0; ww < 4; ++ww) {
-        const uint32_t c = s_cnt[ww][tid];
-        s_cnt[ww][tid] = run;
-        run += c;
-      }
-      s_run[tid] = run;
-    }
-    __syncthreads();
-    key_r[r] = key;
-    val_r[r] = val;
-    rank_r[r] = valid ? s_cnt[w][d] + below : 0u;
-    __syncthreads();
+    const uint32_t cnt = s_cnt[w][d];
+    __builtin_amdgcn_wave_barrier();
+    if (valid && below == 0) s_cnt[w][d] = cnt + popc64(m);
+    __builtin_amdgcn_wave_barrier();
+    rank_r[r] = cnt + below;
   }
-  // digit starts inside this tile
+  __syncthreads();
+  // digit totals of the tile, offsets of each wave inside a digit, digit starts
+  uint32_t tot = 0;
+#pragma unroll
+  for (int ww = 0; ww < kWaves; ++ww) {
+    const uint32_t c = s_cnt[ww][tid];
+    s_cnt[ww][tid] = tot;
+    tot += c;
+  }
   uint32_t total;
-  const uint32_t cnt = s_run[tid];
-  const uint32_t incl = block_inclusive_scan(cnt, wave_tot, &total);
-  s_start[tid] = incl - cnt;
+  const uint32_t incl = block_inclusive_scan(tot, wave_tot, &total);
+  s_start[tid] = incl - tot;
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRadixItems; ++r) {
-    const int i = r * kRadixThreads + tid;
+    const int i = w * kPerWave + r * 64 + lane;
     if (i < nvalid) {
       const uint32_t d = (key_r[r] >> shift) & 255u;
-      const uint32_t pos = s_start[d] + rank_r[r];
+      const uint32_t pos = s_start[d] + s_cnt[w][d] + rank_r[r];
       s_keys[pos] = key_r[r];
       s_vals[pos] = val_r[r];
     }
@@ -246,7 +276,7 @@ radix_scatter_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __res
   for (int i = tid; i < nvalid; i += kRadixThreads) {
     const uint32_t key = s_keys[i];
     const uint32_t d = (key >> shift) & 255u;
-    const uint64_t gpos = (uint64_t)hist_scanned[(int64_t)d * nb + blockIdx.x] +
+    const uint64_t gpos = (uint64_t)hist_scanned[(int64_t)d * nb + tile] +
                           (uint64_t)(i - (int)s_start[d]);
     keys_out[gpos] = key;
     vals_out[gpos] = s_vals[i];
@@ -324,13 +354,14 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
   if (nb == 0 || bits <= 0) return hipSuccess;
   const int passes = (bits + 7) / 8;
   uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+  const unsigned grid = (unsigned)(8 * ((nb + 7) / 8));
   for (int p = 0; p < passes; ++p) {
     const int shift = 8 * p;
-    hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kRadixThreads), 0, s, ki, d_n,
+    hipLaunchKernelGGL(radix_hist_kernel, dim3(grid), dim3(kRadixThreads), 0, s, ki, d_n,
                        n_cap, shift, nb, hist);
     hipError_t e = launch_scan_u32(hist, nullptr, hist, 256 * nb, partials, nullptr, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kRadixThreads), 0, s, ki,
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3(grid), dim3(kRadixThreads), 0, s, ki,
                        vi, ko, vo, d_n, n_cap, shift, nb, hist);
     uint32_t* t = ki;
     ki = ko;

@@ -68,6 +68,7 @@ duplicate_kernel(const uint32_t* __restrict__ order, const uint32_t* __restrict_
   __syncthreads();
   const uint32_t q0 = s_off[0];
   const uint32_t q1 = s_off[n - 1] + s_cnt[n - 1];
+  // one pair per lane, consecutive lanes on consecutive slots (coalesced stores)
   for (uint32_t q = q0 + t; q < q1; q += 256) {
     // last record of the block whose first slot is <= q (it has a non-zero count)
     int lo = 0, hi = n - 1;
@@ -87,12 +88,23 @@ duplicate_kernel(const uint32_t* __restrict__ order, const uint32_t* __restrict_
 
 __global__ void ranges_kernel(const uint32_t* __restrict__ keys, const Status* __restrict__ st,
                               uint32_t* __restrict__ ranges) {
+  // four consecutive keys per thread; a tile starts where its key differs from the previous
+  // one and ends where it differs from the next
   const int64_t n = st->n_sorted;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t k = keys[i];
-    if (i == 0 || keys[i - 1] != k) ranges[2 * (int64_t)k] = (uint32_t)i;
-    if (i == n - 1 || keys[i + 1] != k) ranges[2 * (int64_t)k + 1] = (uint32_t)(i + 1);
+  for (int64_t i0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); i0 < n;
+       i0 += 4 * (int64_t)gridDim.x * blockDim.x) {
+    uint32_t k[6];
+    k[0] = i0 > 0 ? keys[i0 - 1] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) k[j + 1] = i0 + j < n ? keys[i0 + j] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t i = i0 + j;
+      if (i < n) {
+        if (k[j + 1] != k[j]) ranges[2 * (int64_t)k[j + 1]] = (uint32_t)i;
+        if (k[j + 2] != k[j + 1]) ranges[2 * (int64_t)k[j + 1] + 1] = (uint32_t)(i + 1);
+      }
+    }
   }
 }
 
@@ -116,7 +128,7 @@ hipError_t launch_duplicate(const uint32_t* order, const uint32_t* count,
 
 hipError_t launch_ranges(const uint32_t* pair_keys, const Status* st, int64_t n_cap,
                          uint32_t* ranges, hipStream_t s) {
-  int64_t blocks = (n_cap + 255) / 256;
+  int64_t blocks = (n_cap + 1023) / 1024;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)blocks), dim3(256), 0, s, pair_keys, st,

@@ -123,6 +123,14 @@ def test_tiling_bit_exact_multiview_tile_shapes(gb, tile):
     check_tiling(gb, scene, views, O.Options(tile_w=tile[0], tile_h=tile[1]))
 
 
+def test_tiling_bit_exact_three_pass_tile_sort(gb):
+    """Three 1080p views with 8x8 tiles: 97,200 tiles need 17 key bits (three radix passes)."""
+    scene = sg.make_scene(8, 1500, -4.0, 4.0, 0.01, 0.05, 1)
+    views = sg.orbit_views(4, 3, 8.0, [(1920, 1080)])
+    rast, rgb, T = check_tiling(gb, scene, views, O.Options(tile_w=8, tile_h=8))
+    assert rast.layout.total_tiles == 3 * 240 * 135
+
+
 # --- images -------------------------------------------------------------------------------
 def test_image_parity_config1_full_frame(gb):
     scene, views = sg.config("C1")
