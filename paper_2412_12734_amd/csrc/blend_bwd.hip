@@ -30,9 +30,9 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   __shared__ float4 s_geo[B][4];
   __shared__ int32_t s_splat[B];
   __shared__ uint32_t s_recid[B];
-  __shared__ float4 s_tex[B * N * N];
+  __shared__ float4 s_tex[B * TexLayout<N>::kPerSplat];
   __shared__ float s_gtex[B * TEXG];
-  __shared__ float s_grec[B * kRecGrad];
+  __shared__ float s_grec[B * 4 * kRecGrad];  // per splat, per 16-lane row of a wave
   __shared__ uint32_t s_tile_last;
 
   const int tile = tile_of_block(p);
@@ -100,7 +100,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
       s_recid[tid] = r;
     }
     for (int e = tid; e < nb * TEXG; e += nthr) s_gtex[e] = 0.f;
-    for (int e = tid; e < nb * kRecGrad; e += nthr) s_grec[e] = 0.f;
+    for (int e = tid; e < nb * 4 * kRecGrad; e += nthr) s_grec[e] = 0.f;
     __syncthreads();
     stage_texels<N, BF16>(textures, s_splat, nb, s_tex);
     __syncthreads();
@@ -142,7 +142,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
         dc0 = wgt * g0;
         dc1 = wgt * g1;
         dc2 = wgt * g2;
-        const float4* tex = s_tex + j * N * N;
+        const float4* tex = s_tex + j * TexLayout<N>::kPerSplat;
         if constexpr (N == 1) {
           const float4 t = tex[0];
           c0 = t.x;
@@ -154,8 +154,9 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
           float fu, fv;
           grid_coord<N>(e.u, p, iu, fu);
           grid_coord<N>(e.v, p, iv, fv);
-          k00 = iu * N + iv;
-          const float4 t00 = tex[k00], t01 = tex[k00 + 1], t10 = tex[k00 + N], t11 = tex[k00 + N + 1];
+          k00 = iu * N + iv;  // texel index in the gradient grid [N][N]
+          const int l00 = TexLayout<N>::at(iu, iv), kr = TexLayout<N>::kRow;
+          const float4 t00 = tex[l00], t01 = tex[l00 + 1], t10 = tex[l00 + kr], t11 = tex[l00 + kr + 1];
           const float a0 = t00.x + fv * (t01.x - t00.x), b0_ = t10.x + fv * (t11.x - t10.x);
           const float a1 = t00.y + fv * (t01.y - t00.y), b1 = t10.y + fv * (t11.y - t10.y);
           const float a2 = t00.z + fv * (t01.z - t00.z), b2 = t10.z + fv * (t11.z - t10.z);
@@ -205,21 +206,26 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
         gc2x = -ddx;
         gc2y = -ddy;
       }
-      // wave sums of the per-splat scalars (all lanes take part); lane 0 adds them to LDS
-      float* gr = s_grec + j * kRecGrad;
+      // Row sums (16 lanes) of the per-splat scalars; the first lane of each row adds them to
+      // the row's slot in LDS (the flush adds the four rows).
+      const int row = lane >> 4;
+      const bool row_head = (lane & 15) == 0;
       {
         float red[kRecGrad] = {gh[0], gh[1], gh[2], gh[3], gh[4], gh[5], gh[6], gc2x, gc2y, go};
-        wave_sum_all<kRecGrad>(red);
-        if (lane == 0) {
+        row_sum_all<kRecGrad>(red);
+        float* gr = s_grec + (j * 4 + row) * kRecGrad;
+        // ballot taken by the whole wave (not inside the lane condition)
+        const bool row_act = ((ballot(act) >> (16 * row)) & 0xffffull) != 0;
+        if (row_head && row_act) {
 #pragma unroll
           for (int k = 0; k < kRecGrad; ++k) atomicAdd(&gr[k], red[k]);
         }
       }
       // Texel gradients. Most blended pixels of a wave fall into one or two cells of the
       // grid (the grid covers only the splat's core and clamped pixels share border cells),
-      // so lanes are grouped by cell and each group is summed over the wave before one lane
-      // adds it to LDS; corners whose weights vanish for the whole group are skipped. After
-      // a few groups the remaining lanes add their own contributions.
+      // so lanes are grouped by cell and each group is summed over each 16-lane row before the
+      // row's first lane adds it to LDS; corners whose weights vanish for the whole group are
+      // skipped. After a few groups the remaining lanes add their own contributions.
       float* gt = s_gtex + j * TEXG;
       uint64_t pending = ballot(act);
 #pragma unroll 1
@@ -228,6 +234,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
         const int lead_cell = __builtin_amdgcn_readlane(k00, leader);
         const bool in = act && k00 == lead_cell && ((pending >> lane) & 1ull);
         const uint64_t grp = ballot(in);
+        const bool row_in = ((grp >> (16 * row)) & 0xffffull) != 0;
         const float wq[4] = {w00, w01, w10, w11};
         const int offq[4] = {0, 1, N, N + 1};
 #pragma unroll
@@ -236,8 +243,8 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
           if (!__any(in && wq[q] != 0.f)) continue;
           const float wv = in ? wq[q] : 0.f;
           float red[3] = {wv * dc0, wv * dc1, wv * dc2};
-          wave_sum_all<3>(red);
-          if (lane == 0) {
+          row_sum_all<3>(red);
+          if (row_head && row_in) {
             float* dst = gt + 3 * (lead_cell + offq[q]);
             atomicAdd(dst + 0, red[0]);
             atomicAdd(dst + 1, red[1]);
@@ -271,11 +278,10 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
       }
     }
     for (int e = tid; e < nb * kRecGrad; e += nthr) {
-      const float x = s_grec[e];
-      if (x != 0.f) {
-        const int j = e / kRecGrad, r = e - j * kRecGrad;
-        atomicAdd(&d_rec[(int64_t)s_recid[j] * kRecGrad + r], x);
-      }
+      const int j = e / kRecGrad, r = e - j * kRecGrad;
+      const float* g4 = s_grec + j * 4 * kRecGrad + r;
+      const float x = (g4[0] + g4[kRecGrad]) + (g4[2 * kRecGrad] + g4[3 * kRecGrad]);
+      if (x != 0.f) atomicAdd(&d_rec[(int64_t)s_recid[j] * kRecGrad + r], x);
     }
     __syncthreads();
     bend = bstart;

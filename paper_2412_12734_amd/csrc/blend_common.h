@@ -63,6 +63,15 @@ __device__ __forceinline__ StagedGeo stage_geo(const SplatRec& r, int tile_x0, i
   return s;
 }
 
+// LDS texel layout per staged splat: N rows of N + 1 float4 (RGB + pad), so that texels
+// (i, j) and (i + 1, j) fall into different LDS banks.
+template <int N>
+struct TexLayout {
+  static constexpr int kRow = N + 1;
+  static constexpr int kPerSplat = N * (N + 1);
+  __device__ static constexpr int at(int iu, int iv) { return iu * kRow + iv; }
+};
+
 // Copies the texels of `nb` staged splats into LDS as float4 (RGB + pad) per texel. For even
 // N a splat's 3 N^2 channel values split into groups of 12 (four texels): each thread moves
 // whole groups, three 16-byte (float32) or 8-byte (bfloat16) loads in, four LDS stores out.
@@ -98,11 +107,12 @@ __device__ __forceinline__ void stage_texels(const void* __restrict__ textures,
           v[4 * k + 3] = x.w;
         }
       }
-      float4* dst = s_tex + j * N * N + 4 * a;
-      dst[0] = make_float4(v[0], v[1], v[2], 0.f);
-      dst[1] = make_float4(v[3], v[4], v[5], 0.f);
-      dst[2] = make_float4(v[6], v[7], v[8], 0.f);
-      dst[3] = make_float4(v[9], v[10], v[11], 0.f);
+      float4* dst = s_tex + j * TexLayout<N>::kPerSplat;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int t = 4 * a + k, iu = t / N, iv = t - iu * N;
+        dst[TexLayout<N>::at(iu, iv)] = make_float4(v[3 * k], v[3 * k + 1], v[3 * k + 2], 0.f);
+      }
     }
   } else {
     for (int e = tid; e < nb * per; e += nthr) {
@@ -112,7 +122,8 @@ __device__ __forceinline__ void stage_texels(const void* __restrict__ textures,
         x = bf16_to_f32(reinterpret_cast<const uint16_t*>(textures)[(int64_t)s_splat[j] * per + r]);
       else
         x = reinterpret_cast<const float*>(textures)[(int64_t)s_splat[j] * per + r];
-      reinterpret_cast<float*>(s_tex + j * N * N)[r / 3 * 4 + r % 3] = x;
+      const int t = r / 3, iu = t / N, iv = t - iu * N;
+      reinterpret_cast<float*>(s_tex + j * TexLayout<N>::kPerSplat + TexLayout<N>::at(iu, iv))[r % 3] = x;
     }
   }
 }

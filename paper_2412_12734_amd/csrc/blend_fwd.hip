@@ -25,7 +25,7 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
                  unsigned long long* __restrict__ stats) {
   __shared__ float4 s_geo[B][4];
   __shared__ int32_t s_splat[B];
-  __shared__ float4 s_tex[B * N * N];
+  __shared__ float4 s_tex[B * TexLayout<N>::kPerSplat];
 
   const int tile = tile_of_block(p);
   if (tile >= p.total_tiles) return;
@@ -104,7 +104,7 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
           } else {
             if (STATS) ++st_blend;
             float c0, c1, c2;
-            const float4* tex = s_tex + j * N * N;
+            const float4* tex = s_tex + j * TexLayout<N>::kPerSplat;
             if constexpr (N == 1) {
               const float4 t = tex[0];
               c0 = t.x;
@@ -115,8 +115,9 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
               float fu, fv;
               grid_coord<N>(e.u, p, iu, fu);
               grid_coord<N>(e.v, p, iv, fv);
-              const float4 t00 = tex[iu * N + iv], t01 = tex[iu * N + iv + 1];
-              const float4 t10 = tex[(iu + 1) * N + iv], t11 = tex[(iu + 1) * N + iv + 1];
+              const int k00 = TexLayout<N>::at(iu, iv), kr = TexLayout<N>::kRow;
+              const float4 t00 = tex[k00], t01 = tex[k00 + 1];
+              const float4 t10 = tex[k00 + kr], t11 = tex[k00 + kr + 1];
               const float a0 = t00.x + fv * (t01.x - t00.x), b0_ = t10.x + fv * (t11.x - t10.x);
               const float a1 = t00.y + fv * (t01.y - t00.y), b1 = t10.y + fv * (t11.y - t10.y);
               const float a2 = t00.z + fv * (t01.z - t00.z), b2 = t10.z + fv * (t11.z - t10.z);

@@ -143,6 +143,20 @@ __device__ __forceinline__ void wave_sum_all(float (&v)[K]) {
   }
 }
 
+// Sums of K values over each row of 16 lanes (every lane receives its row's totals),
+// interleaved like wave_sum_all.
+template <int K>
+__device__ __forceinline__ void row_sum_all(float (&v)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_f<0xB1>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_f<0x4E>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_f<0x124>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_f<0x128>(v[k]);
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_to_lane63(v)), 63));
 }
