@@ -8,9 +8,14 @@
 //   d o = d alpha G, dq = -G o d alpha (both zero where alpha was clamped to alpha_max),
 //   uv branch: du += dq u, dv += dq v; low-pass branch: d(dx, dy) += dq 2 (dx, dy) / (2 var),
 //   (u, v) = (rho0, rho1) / rho2 -> d rho -> d H (7 entries) and d(dx, dy) -> d c2 = -d(dx, dy).
-// The ten per-splat scalars are summed over the wave with DPP and added to the batch slot in
-// LDS; texel gradients are grouped by grid cell, summed over the wave and added to LDS with
-// ds_add_f32. After each batch the non-zero LDS sums go to global memory with one float
+//
+// A lane owns PIX vertically adjacent pixels (the launch uses PIX = 1: waves of 8 x 8 pixels).
+// Per splat, a lane first adds up its pixels' contributions; the ten per-splat scalars are
+// then summed over each 16-lane row with DPP and added to the row's LDS slot. Texel
+// gradients are grouped by grid cell (with sigma = 0.5 the grid covers only the splat's core,
+// so most blended pixels are border-clamped and share a few cells), summed per row and added
+// to LDS by the row's first lane; after a few groups the remaining pixels add their own
+// contributions. After each batch the non-zero LDS sums go to global memory with one float
 // atomic each.
 #include "blend_common.h"
 
@@ -18,7 +23,108 @@ namespace gbb {
 
 namespace {
 
-template <int N, bool BF16, int B>
+// Per-pixel backward state and the outputs of one (pixel, splat) step.
+struct PixState {
+  float T, S0, S1, S2, g0, g1, g2;
+  uint32_t last;
+};
+
+struct PixOut {
+  bool act;
+  int k00;                       // cell (first corner) in the [N][N] gradient grid
+  float w[4];                    // corner weights (00, 01, 10, 11)
+  float dc0, dc1, dc2;           // colour adjoint alpha T g
+  float gh[7], gc2x, gc2y, go;   // record gradients
+};
+
+template <int N>
+__device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex, float lx,
+                                           float ly, uint32_t jg, PixState& ps,
+                                           const BlendParams& p, PixOut& o) {
+  o.act = false;
+  o.k00 = 0;
+  o.w[0] = o.w[1] = o.w[2] = o.w[3] = 0.f;
+  o.dc0 = o.dc1 = o.dc2 = 0.f;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) o.gh[k] = 0.f;
+  o.gc2x = o.gc2y = o.go = 0.f;
+  const PixelEval e = eval_splat(g, lx, ly, p);
+  if (!((jg < ps.last) && e.hit)) return;
+  o.act = true;
+  const float inv1m = __builtin_amdgcn_rcpf(1.0f - e.alpha);
+  ps.T = ps.T * inv1m;  // transmittance in front of this splat
+  float c0, c1, c2;
+  float du = 0.f, dv = 0.f;
+  const float wgt = e.alpha * ps.T;
+  o.dc0 = wgt * ps.g0;
+  o.dc1 = wgt * ps.g1;
+  o.dc2 = wgt * ps.g2;
+  if constexpr (N == 1) {
+    const float4 t = tex[0];
+    c0 = t.x;
+    c1 = t.y;
+    c2 = t.z;
+    o.w[0] = 1.f;
+  } else {
+    int iu, iv;
+    float fu, fv;
+    grid_coord<N>(e.u, p, iu, fu);
+    grid_coord<N>(e.v, p, iv, fv);
+    o.k00 = iu * N + iv;
+    const int l00 = TexLayout<N>::at(iu, iv), kr = TexLayout<N>::kRow;
+    const float4 t00 = tex[l00], t01 = tex[l00 + 1], t10 = tex[l00 + kr], t11 = tex[l00 + kr + 1];
+    const float a0 = t00.x + fv * (t01.x - t00.x), b0_ = t10.x + fv * (t11.x - t10.x);
+    const float a1 = t00.y + fv * (t01.y - t00.y), b1 = t10.y + fv * (t11.y - t10.y);
+    const float a2 = t00.z + fv * (t01.z - t00.z), b2 = t10.z + fv * (t11.z - t10.z);
+    c0 = a0 + fu * (b0_ - a0);
+    c1 = a1 + fu * (b1 - a1);
+    c2 = a2 + fu * (b2 - a2);
+    o.w[0] = (1.f - fu) * (1.f - fv);
+    o.w[1] = (1.f - fu) * fv;
+    o.w[2] = fu * (1.f - fv);
+    o.w[3] = fu * fv;
+    // fractional-position adjoints (Alg. 2), zero where the coordinate is clamped
+    const float dfu = o.dc0 * (b0_ - a0) + o.dc1 * (b1 - a1) + o.dc2 * (b2 - a2);
+    const float fv0 = (t01.x - t00.x) * (1.f - fu) + (t11.x - t10.x) * fu;
+    const float fv1 = (t01.y - t00.y) * (1.f - fu) + (t11.y - t10.y) * fu;
+    const float fv2 = (t01.z - t00.z) * (1.f - fu) + (t11.z - t10.z) * fu;
+    const float dfv = o.dc0 * fv0 + o.dc1 * fv1 + o.dc2 * fv2;
+    du = (e.u > -p.sigma && e.u < p.sigma) ? p.tex_scale * dfu : 0.f;
+    dv = (e.v > -p.sigma && e.v < p.sigma) ? p.tex_scale * dfv : 0.f;
+  }
+  const float dalpha = ps.g0 * (c0 * ps.T - ps.S0 * inv1m) + ps.g1 * (c1 * ps.T - ps.S1 * inv1m) +
+                       ps.g2 * (c2 * ps.T - ps.S2 * inv1m);
+  ps.S0 += wgt * c0;
+  ps.S1 += wgt * c1;
+  ps.S2 += wgt * c2;
+  const bool unclamped = g.g0.w * e.G <= p.alpha_max;
+  o.go = unclamped ? dalpha * e.G : 0.f;
+  const float dq = unclamped ? -e.G * g.g0.w * dalpha : 0.f;
+  float ddx = 0.f, ddy = 0.f;
+  if (e.uv_branch) {
+    du += dq * e.u;
+    dv += dq * e.v;
+  } else {
+    ddx = dq * 2.f * p.lp_scale * e.dx;
+    ddy = dq * 2.f * p.lp_scale * e.dy;
+  }
+  const float dr0 = du * e.inv, dr1 = dv * e.inv;
+  const float dr2 = -(du * e.u + dv * e.v) * e.inv;
+  o.gh[0] = dr0 * e.dx;
+  o.gh[1] = dr0 * e.dy;
+  o.gh[2] = dr1 * e.dx;
+  o.gh[3] = dr1 * e.dy;
+  o.gh[4] = dr2 * e.dx;
+  o.gh[5] = dr2 * e.dy;
+  o.gh[6] = dr2;
+  // d c2 collects the low-pass term and the uv term through rho's dependence on the offset
+  ddx += dr0 * g.g1.x + dr1 * g.g1.z + dr2 * g.g2.x;
+  ddy += dr0 * g.g1.y + dr1 * g.g1.w + dr2 * g.g2.y;
+  o.gc2x = -ddx;
+  o.gc2y = -ddy;
+}
+
+template <int N, bool BF16, int B, int PIX>
 __global__ void __launch_bounds__(256)
 blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__ rec,
                  const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ ranges,
@@ -27,6 +133,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
                  const float* __restrict__ d_rgb, float* __restrict__ d_rec,
                  float* __restrict__ d_tex) {
   constexpr int TEXG = 3 * N * N;
+  constexpr int BH = 8 * PIX;  // wave block: 8 columns x BH rows
   __shared__ float4 s_geo[B][4];
   __shared__ int32_t s_splat[B];
   __shared__ uint32_t s_recid[B];
@@ -46,35 +153,45 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int w = tid >> 6, lane = tid & 63;
   const int waves_x = p.tile_w >> 3;
-  const int bx = (w % waves_x) * 8, by = (w / waves_x) * 8;
-  const int lxi = bx + (lane & 7), lyi = by + (lane >> 3);
-  const int px = tile_x0 + lxi, py = tile_y0 + lyi;
-  const bool inside = px < V.W && py < V.H;
-  // pixel centre relative to the tile centre (exact half-integers)
-  const float lx = (float)lxi - 0.5f * (float)(p.tile_w - 1);
-  const float ly = (float)lyi - 0.5f * (float)(p.tile_h - 1);
+  const int bx = (w % waves_x) * 8, by = (w / waves_x) * BH;
+  const int lxi = bx + (lane & 7);
   const int wx0 = tile_x0 + bx, wy0 = tile_y0 + by;
   const float bcx = (float)bx + 3.5f - 0.5f * (float)(p.tile_w - 1);
-  const float bcy = (float)by + 3.5f - 0.5f * (float)(p.tile_h - 1);
-
+  const float bcy = (float)by + 0.5f * (float)(BH - 1) - 0.5f * (float)(p.tile_h - 1);
+  // pixel centres relative to the tile centre (exact half-integers)
+  const float lx = (float)lxi - 0.5f * (float)(p.tile_w - 1);
+  float ly[PIX];
+  PixState ps[PIX];
   const uint32_t start = ranges[2 * tile];
-  float T = 1.0f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
-  uint32_t last = start;
-  if (inside) {
-    const int64_t pix = (int64_t)V.pix_base + (int64_t)py * V.W + px;
-    T = T_final[pix];
-    last = n_last[pix];
-    g0 = d_rgb[3 * pix + 0];
-    g1 = d_rgb[3 * pix + 1];
-    g2 = d_rgb[3 * pix + 2];
+#pragma unroll
+  for (int s = 0; s < PIX; ++s) {
+    const int lyi = by + PIX * (lane >> 3) + s;
+    ly[s] = (float)lyi - 0.5f * (float)(p.tile_h - 1);
+    const int px = tile_x0 + lxi, py = tile_y0 + lyi;
+    ps[s].T = 1.0f;
+    ps[s].g0 = ps[s].g1 = ps[s].g2 = 0.f;
+    ps[s].last = start;
+    if (px < V.W && py < V.H) {
+      const int64_t pix = (int64_t)V.pix_base + (int64_t)py * V.W + px;
+      ps[s].T = T_final[pix];
+      ps[s].last = n_last[pix];
+      ps[s].g0 = d_rgb[3 * pix + 0];
+      ps[s].g1 = d_rgb[3 * pix + 1];
+      ps[s].g2 = d_rgb[3 * pix + 2];
+    }
+    ps[s].S0 = ps[s].T * p.bg[0];
+    ps[s].S1 = ps[s].T * p.bg[1];
+    ps[s].S2 = ps[s].T * p.bg[2];
   }
-  float S0 = T * p.bg[0], S1 = T * p.bg[1], S2 = T * p.bg[2];
+  uint32_t lane_last = ps[0].last;
+#pragma unroll
+  for (int s = 1; s < PIX; ++s) lane_last = ps[s].last > lane_last ? ps[s].last : lane_last;
 
   if (tid == 0) s_tile_last = start;
   __syncthreads();
   {
     // largest bound over the tile's pixels
-    uint32_t m = last;
+    uint32_t m = lane_last;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       const uint32_t o = __shfl_xor(m, d, 64);
@@ -84,6 +201,8 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   }
   __syncthreads();
   const uint32_t tile_last = s_tile_last;
+  const int row = lane >> 4;
+  const bool row_head = (lane & 15) == 0;
 
   for (uint32_t bend = tile_last; bend > start;) {
     const uint32_t bstart = (bend - start) > (uint32_t)B ? bend - (uint32_t)B : start;
@@ -105,7 +224,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
     stage_texels<N, BF16>(textures, s_splat, nb, s_tex);
     __syncthreads();
 
-    // splats of this batch that can reach the wave's 8 x 8 block, walked back to front
+    // splats of this batch that can reach the wave's block, walked back to front
     bool may = false;
     if (lane < nb) {
       StagedGeo c;
@@ -113,136 +232,91 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
       c.g1 = s_geo[lane][1];
       c.g2 = s_geo[lane][2];
       c.g3 = s_geo[lane][3];
-      may = block_may_contribute(c, bcx, bcy, wx0, wy0, p);
+      may = block_may_contribute(c, bcx, bcy, wx0, wy0, p, 8, BH);
     }
     uint64_t todo = ballot(may);
     while (todo != 0) {
       const int j = 63 - (int)__builtin_clzll(todo);
       todo &= ~(1ull << j);
       const uint32_t jg = bstart + (uint32_t)j;
-      if (!__any(jg < last)) continue;
+      if (!__any(jg < lane_last)) continue;
       StagedGeo g;
       g.g0 = s_geo[j][0];
       g.g1 = s_geo[j][1];
       g.g2 = s_geo[j][2];
-      const PixelEval e = eval_splat(g, lx, ly, p);
-      const bool act = (jg < last) && e.hit;
-      float gh[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      float gc2x = 0.f, gc2y = 0.f, go = 0.f;
-      // colour adjoint and bilinear corner weights of this lane (texel scatter below)
-      int k00 = 0;
-      float w00 = 0.f, w01 = 0.f, w10 = 0.f, w11 = 0.f;
-      float dc0 = 0.f, dc1 = 0.f, dc2 = 0.f;
-      if (act) {
-        const float inv1m = __builtin_amdgcn_rcpf(1.0f - e.alpha);
-        T = T * inv1m;  // transmittance in front of this splat
-        float c0, c1, c2;
-        float du = 0.f, dv = 0.f;
-        const float wgt = e.alpha * T;
-        dc0 = wgt * g0;
-        dc1 = wgt * g1;
-        dc2 = wgt * g2;
-        const float4* tex = s_tex + j * TexLayout<N>::kPerSplat;
-        if constexpr (N == 1) {
-          const float4 t = tex[0];
-          c0 = t.x;
-          c1 = t.y;
-          c2 = t.z;
-          w00 = 1.f;
-        } else {
-          int iu, iv;
-          float fu, fv;
-          grid_coord<N>(e.u, p, iu, fu);
-          grid_coord<N>(e.v, p, iv, fv);
-          k00 = iu * N + iv;  // texel index in the gradient grid [N][N]
-          const int l00 = TexLayout<N>::at(iu, iv), kr = TexLayout<N>::kRow;
-          const float4 t00 = tex[l00], t01 = tex[l00 + 1], t10 = tex[l00 + kr], t11 = tex[l00 + kr + 1];
-          const float a0 = t00.x + fv * (t01.x - t00.x), b0_ = t10.x + fv * (t11.x - t10.x);
-          const float a1 = t00.y + fv * (t01.y - t00.y), b1 = t10.y + fv * (t11.y - t10.y);
-          const float a2 = t00.z + fv * (t01.z - t00.z), b2 = t10.z + fv * (t11.z - t10.z);
-          c0 = a0 + fu * (b0_ - a0);
-          c1 = a1 + fu * (b1 - a1);
-          c2 = a2 + fu * (b2 - a2);
-          w00 = (1.f - fu) * (1.f - fv);
-          w01 = (1.f - fu) * fv;
-          w10 = fu * (1.f - fv);
-          w11 = fu * fv;
-          // fractional-position adjoints (Alg. 2), zero where the coordinate is clamped
-          const float dfu = dc0 * (b0_ - a0) + dc1 * (b1 - a1) + dc2 * (b2 - a2);
-          const float fv0 = (t01.x - t00.x) * (1.f - fu) + (t11.x - t10.x) * fu;
-          const float fv1 = (t01.y - t00.y) * (1.f - fu) + (t11.y - t10.y) * fu;
-          const float fv2 = (t01.z - t00.z) * (1.f - fu) + (t11.z - t10.z) * fu;
-          const float dfv = dc0 * fv0 + dc1 * fv1 + dc2 * fv2;
-          du = (e.u > -p.sigma && e.u < p.sigma) ? p.tex_scale * dfu : 0.f;
-          dv = (e.v > -p.sigma && e.v < p.sigma) ? p.tex_scale * dfv : 0.f;
-        }
-        const float dalpha = g0 * (c0 * T - S0 * inv1m) + g1 * (c1 * T - S1 * inv1m) +
-                             g2 * (c2 * T - S2 * inv1m);
-        S0 += wgt * c0;
-        S1 += wgt * c1;
-        S2 += wgt * c2;
-        const bool unclamped = g.g0.w * e.G <= p.alpha_max;
-        go = unclamped ? dalpha * e.G : 0.f;
-        const float dq = unclamped ? -e.G * g.g0.w * dalpha : 0.f;
-        float ddx = 0.f, ddy = 0.f;
-        if (e.uv_branch) {
-          du += dq * e.u;
-          dv += dq * e.v;
-        } else {
-          ddx = dq * 2.f * p.lp_scale * e.dx;
-          ddy = dq * 2.f * p.lp_scale * e.dy;
-        }
-        const float dr0 = du * e.inv, dr1 = dv * e.inv;
-        const float dr2 = -(du * e.u + dv * e.v) * e.inv;
-        gh[0] = dr0 * e.dx;
-        gh[1] = dr0 * e.dy;
-        gh[2] = dr1 * e.dx;
-        gh[3] = dr1 * e.dy;
-        gh[4] = dr2 * e.dx;
-        gh[5] = dr2 * e.dy;
-        gh[6] = dr2;
-        ddx += dr0 * g.g1.x + dr1 * g.g1.z + dr2 * g.g2.x;
-        ddy += dr0 * g.g1.y + dr1 * g.g1.w + dr2 * g.g2.y;
-        gc2x = -ddx;
-        gc2y = -ddy;
-      }
-      // Row sums (16 lanes) of the per-splat scalars; the first lane of each row adds them to
-      // the row's slot in LDS (the flush adds the four rows).
-      const int row = lane >> 4;
-      const bool row_head = (lane & 15) == 0;
+      const float4* tex = s_tex + j * TexLayout<N>::kPerSplat;
+      PixOut po[PIX];
+#pragma unroll
+      for (int s = 0; s < PIX; ++s) pixel_step<N>(g, tex, lx, ly[s], jg, ps[s], p, po[s]);
+
+      // Row sums of the per-splat scalars (a lane first adds its own pixels); the first
+      // lane of each row adds them to the row's LDS slot.
       {
-        float red[kRecGrad] = {gh[0], gh[1], gh[2], gh[3], gh[4], gh[5], gh[6], gc2x, gc2y, go};
+        float red[kRecGrad];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) red[k] = po[0].gh[k];
+        red[7] = po[0].gc2x;
+        red[8] = po[0].gc2y;
+        red[9] = po[0].go;
+        bool any_act = po[0].act;
+#pragma unroll
+        for (int s = 1; s < PIX; ++s) {
+#pragma unroll
+          for (int k = 0; k < 7; ++k) red[k] += po[s].gh[k];
+          red[7] += po[s].gc2x;
+          red[8] += po[s].gc2y;
+          red[9] += po[s].go;
+          any_act = any_act || po[s].act;
+        }
         row_sum_all<kRecGrad>(red);
-        float* gr = s_grec + (j * 4 + row) * kRecGrad;
         // ballot taken by the whole wave (not inside the lane condition)
-        const bool row_act = ((ballot(act) >> (16 * row)) & 0xffffull) != 0;
+        const bool row_act = ((ballot(any_act) >> (16 * row)) & 0xffffull) != 0;
+        float* gr = s_grec + (j * 4 + row) * kRecGrad;
         if (row_head && row_act) {
 #pragma unroll
           for (int k = 0; k < kRecGrad; ++k) atomicAdd(&gr[k], red[k]);
         }
       }
-      // Texel gradients. Most blended pixels of a wave fall into one or two cells of the
-      // grid (the grid covers only the splat's core and clamped pixels share border cells),
-      // so lanes are grouped by cell and each group is summed over each 16-lane row before the
-      // row's first lane adds it to LDS; corners whose weights vanish for the whole group are
-      // skipped. After a few groups the remaining lanes add their own contributions.
+
+      // Texel gradients, grouped by cell over all pixels of the wave.
       float* gt = s_gtex + j * TEXG;
-      uint64_t pending = ballot(act);
+      uint64_t pend[PIX];
+#pragma unroll
+      for (int s = 0; s < PIX; ++s) pend[s] = ballot(po[s].act);
+      const int offq[4] = {0, 1, N, N + 1};
 #pragma unroll 1
-      for (int it = 0; it < 4 && pending != 0; ++it) {
-        const int leader = (int)__builtin_ctzll(pending);
-        const int lead_cell = __builtin_amdgcn_readlane(k00, leader);
-        const bool in = act && k00 == lead_cell && ((pending >> lane) & 1ull);
-        const uint64_t grp = ballot(in);
-        const bool row_in = ((grp >> (16 * row)) & 0xffffull) != 0;
-        const float wq[4] = {w00, w01, w10, w11};
-        const int offq[4] = {0, 1, N, N + 1};
+      for (int it = 0; it < 4; ++it) {
+        int lead_cell = -1;
+#pragma unroll
+        for (int s = 0; s < PIX; ++s) {
+          if (lead_cell < 0 && pend[s] != 0)
+            lead_cell = __builtin_amdgcn_readlane(po[s].k00, (int)__builtin_ctzll(pend[s]));
+        }
+        if (lead_cell < 0) break;
+        bool in[PIX];
+        uint64_t grp_any = 0;
+#pragma unroll
+        for (int s = 0; s < PIX; ++s) {
+          in[s] = ((pend[s] >> lane) & 1ull) && po[s].k00 == lead_cell;
+          const uint64_t grp = ballot(in[s]);
+          pend[s] &= ~grp;
+          grp_any |= grp;
+        }
+        const bool row_in = ((grp_any >> (16 * row)) & 0xffffull) != 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (N == 1 && q > 0) break;
-          if (!__any(in && wq[q] != 0.f)) continue;
-          const float wv = in ? wq[q] : 0.f;
-          float red[3] = {wv * dc0, wv * dc1, wv * dc2};
+          float red[3] = {0.f, 0.f, 0.f};
+          bool nz = false;
+#pragma unroll
+          for (int s = 0; s < PIX; ++s) {
+            const float wv = in[s] ? po[s].w[q] : 0.f;
+            nz = nz || wv != 0.f;
+            red[0] += wv * po[s].dc0;
+            red[1] += wv * po[s].dc1;
+            red[2] += wv * po[s].dc2;
+          }
+          if (!__any(nz)) continue;
           row_sum_all<3>(red);
           if (row_head && row_in) {
             float* dst = gt + 3 * (lead_cell + offq[q]);
@@ -251,19 +325,20 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
             atomicAdd(dst + 2, red[2]);
           }
         }
-        pending &= ~grp;
       }
-      if ((pending >> lane) & 1ull) {
-        const float wq[4] = {w00, w01, w10, w11};
-        const int offq[4] = {0, 1, N, N + 1};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (N == 1 && q > 0) break;
-          if (wq[q] != 0.f) {
-            float* dst = gt + 3 * (k00 + offq[q]);
-            atomicAdd(dst + 0, wq[q] * dc0);
-            atomicAdd(dst + 1, wq[q] * dc1);
-            atomicAdd(dst + 2, wq[q] * dc2);
+      for (int s = 0; s < PIX; ++s) {
+        if ((pend[s] >> lane) & 1ull) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (N == 1 && q > 0) break;
+            const float wq = po[s].w[q];
+            if (wq != 0.f) {
+              float* dst = gt + 3 * (po[s].k00 + offq[q]);
+              atomicAdd(dst + 0, wq * po[s].dc0);
+              atomicAdd(dst + 1, wq * po[s].dc1);
+              atomicAdd(dst + 2, wq * po[s].dc2);
+            }
           }
         }
       }
@@ -288,24 +363,36 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   }
 }
 
+template <int N, bool BF16, int PIX>
+hipError_t launch_np(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
+                     const ViewDev* views, const SplatRec* rec, const uint32_t* pair_vals,
+                     const uint32_t* ranges, const float* T_final, const uint32_t* n_last,
+                     const float* d_rgb, float* d_rec, float* d_tex, hipStream_t s) {
+  const dim3 grid((unsigned)(8 * (int64_t)bp.tiles_per_xcd));
+  const dim3 block((unsigned)(pl.tile_w * pl.tile_h / PIX));
+  switch (pl.batch_bwd) {
+    case 32:
+      hipLaunchKernelGGL((blend_bwd_kernel<N, BF16, 32, PIX>), grid, block, 0, s, views, rec,
+                         pair_vals, ranges, sp.textures, bp, T_final, n_last, d_rgb, d_rec, d_tex);
+      break;
+    default:
+      hipLaunchKernelGGL((blend_bwd_kernel<N, BF16, 16, PIX>), grid, block, 0, s, views, rec,
+                         pair_vals, ranges, sp.textures, bp, T_final, n_last, d_rgb, d_rec, d_tex);
+      break;
+  }
+  return hipGetLastError();
+}
+
 template <int N, bool BF16>
 hipError_t launch_n(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
                     const ViewDev* views, const SplatRec* rec, const uint32_t* pair_vals,
                     const uint32_t* ranges, const float* T_final, const uint32_t* n_last,
                     const float* d_rgb, float* d_rec, float* d_tex, hipStream_t s) {
-  const dim3 grid((unsigned)(8 * (int64_t)bp.tiles_per_xcd));
-  const dim3 block((unsigned)(pl.tile_w * pl.tile_h));
-  switch (pl.batch_bwd) {
-    case 32:
-      hipLaunchKernelGGL((blend_bwd_kernel<N, BF16, 32>), grid, block, 0, s, views, rec,
-                         pair_vals, ranges, sp.textures, bp, T_final, n_last, d_rgb, d_rec, d_tex);
-      break;
-    default:
-      hipLaunchKernelGGL((blend_bwd_kernel<N, BF16, 16>), grid, block, 0, s, views, rec,
-                         pair_vals, ranges, sp.textures, bp, T_final, n_last, d_rgb, d_rec, d_tex);
-      break;
-  }
-  return hipGetLastError();
+  // One pixel per lane. Two pixels per lane (8 x 16 wave blocks) measured slower on the
+  // 1M-splat 1080p workload (3.0 vs 2.3 ms): LDS limits such blocks to two waves per SIMD and
+  // the per-wave cull is coarser.
+  return launch_np<N, BF16, 1>(pl, sp, bp, views, rec, pair_vals, ranges, T_final, n_last, d_rgb,
+                               d_rec, d_tex, s);
 }
 
 }  // namespace

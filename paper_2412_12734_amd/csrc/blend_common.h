@@ -162,30 +162,33 @@ __device__ __forceinline__ PixelEval eval_splat(const StagedGeo& s, float lx, fl
 }
 
 // Conservative test whether a staged splat can reach alpha >= alpha_min anywhere in a wave's
-// 8 x 8 pixel block: (cx, cy) is the block centre relative to the tile centre, (bx0, by0) the
-// block's first pixel. rho is affine in the pixel offset, so its range over the block is
+// bw x bh pixel block: (cx, cy) is the block centre relative to the tile centre, (bx0, by0)
+// the block's first pixel. rho is affine in the pixel offset, so its range over the block is
 // exact; where rho2 keeps its sign, |u| >= min|rho0| / max|rho2| (likewise v), and the
 // low-pass term is bounded by the block's distance to the projected centre. A splat is
 // skipped only if even the largest possible opacity is clearly below alpha_min, so skipping
 // never changes a result.
 __device__ __forceinline__ bool block_may_contribute(const StagedGeo& s, float cx, float cy,
-                                                     int bx0, int by0, const BlendParams& p) {
+                                                     int bx0, int by0, const BlendParams& p,
+                                                     int bw = 8, int bh = 8) {
   const int rx = __float_as_int(s.g3.x), ry = __float_as_int(s.g3.y);
   const int i0 = rx & 0xffff, i1 = rx >> 16, j0 = ry & 0xffff, j1 = ry >> 16;
-  if (i1 < bx0 || i0 > bx0 + 7 || j1 < by0 || j0 > by0 + 7) return false;
+  if (i1 < bx0 || i0 > bx0 + bw - 1 || j1 < by0 || j0 > by0 + bh - 1) return false;
+  // half extents of the block's pixel centres
+  const float ex = 0.5f * (float)(bw - 1), ey = 0.5f * (float)(bh - 1);
   const float h00 = s.g1.x, h01 = s.g1.y, h10 = s.g1.z, h11 = s.g1.w, h20 = s.g2.x, h21 = s.g2.y;
   const float r2c = __builtin_fmaf(h21, cy, __builtin_fmaf(h20, cx, s.g0.z));
-  const float r2e = 3.5f * (fabsf(h20) + fabsf(h21));
+  const float r2e = ex * fabsf(h20) + ey * fabsf(h21);
   if (!(fabsf(r2c) > 1.001f * r2e)) return true;  // the vanishing line may cross the block
   const float r0c = __builtin_fmaf(h01, cy, __builtin_fmaf(h00, cx, s.g0.x));
   const float r1c = __builtin_fmaf(h11, cy, __builtin_fmaf(h10, cx, s.g0.y));
-  const float r0m = fmaxf(fabsf(r0c) - 3.5f * (fabsf(h00) + fabsf(h01)), 0.f);
-  const float r1m = fmaxf(fabsf(r1c) - 3.5f * (fabsf(h10) + fabsf(h11)), 0.f);
+  const float r0m = fmaxf(fabsf(r0c) - (ex * fabsf(h00) + ey * fabsf(h01)), 0.f);
+  const float r1m = fmaxf(fabsf(r1c) - (ex * fabsf(h10) + ey * fabsf(h11)), 0.f);
   const float inv = 1.0f / (fabsf(r2c) + r2e);
   const float um = r0m * inv, vm = r1m * inv;
   const float q_uv = 0.5f * (um * um + vm * vm);
-  const float dxm = fmaxf(fabsf(cx + s.g2.z) - 3.5f, 0.f);
-  const float dym = fmaxf(fabsf(cy + s.g2.w) - 3.5f, 0.f);
+  const float dxm = fmaxf(fabsf(cx + s.g2.z) - ex, 0.f);
+  const float dym = fmaxf(fabsf(cy + s.g2.w) - ey, 0.f);
   const float q_lp = (dxm * dxm + dym * dym) * p.lp_scale;
   const float q = fminf(q_uv, q_lp);
   return s.g0.w * __builtin_amdgcn_exp2f(-q * 1.4426950408889634f) >= 0.99f * p.alpha_min;
