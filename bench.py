@@ -14,6 +14,7 @@ the same workload on the host CPU.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -43,9 +44,47 @@ FLOPS_FWD_EVAL = 30
 FLOPS_FWD_BLEND = 48
 FLOPS_BWD_BLEND = 177
 
+# Size of the plain device-to-device copy issued once at start-up. Its FETCH_SIZE and
+# WRITE_SIZE readings under rocprofv3 --pmc calibrate those counters to bytes.
+COPY_BYTES = 256 << 20
+
+# HBM traffic of one blend_bwd launch on the default workload: FETCH_SIZE and WRITE_SIZE of
+# the kernel (KiB per dispatch, two rocprofv3 --pmc runs of this script), each scaled by
+# COPY_BYTES over the same counter's reading for the start-up copy. It is reported only while
+# the kernel's sources hash to the value they had when the counters were taken.
+BWD_SOURCES = ["blend_bwd.hip", "blend_common.h", "device_util.h"]
+BWD_TRAFFIC = {"sources_sha1": "4204c7acc41a598bad28c74828283914823e0b73",
+               "fetch_bytes": 131912529, "write_bytes": 132708800}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def sources_sha1(names):
+    h = hashlib.sha1()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2412_12734_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def copy_probe(torch):
+    """One plain device copy of COPY_BYTES (counter calibration) and its bandwidth."""
+    n = COPY_BYTES // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    del a, b
+    return 2 * COPY_BYTES / (ms * 1e-3) / 1e9
 
 
 def time_steps(rast, sp, rgb, T, g, grads, steps, torch):
@@ -103,6 +142,8 @@ def main():
     import scenegen as sg
 
     gb.load()
+    copy_gbs = copy_probe(torch)
+    log(f"plain device copy of {COPY_BYTES >> 20} MiB: {copy_gbs:.0f} GB/s (read + write)")
     log("setting up T0 (1M splats, 8x8 FP32 textures, 1920x1080)")
     scene, views, sp, rast, g, rgb, T, grads, K = setup(gb, sg, torch, "T0")
     pixels = sum(v.width * v.height for v in views)
@@ -132,9 +173,12 @@ def main():
     bwd_flops = e_blend * FLOPS_BWD_BLEND
     fwd_flops = e_eval * FLOPS_FWD_EVAL + e_blend * FLOPS_FWD_BLEND
     achieved = bwd_flops / (bwd_ms * 1e-3) / 1e12
+    traffic = None
+    if BWD_TRAFFIC and BWD_TRAFFIC["sources_sha1"] == sources_sha1(BWD_SOURCES):
+        traffic = BWD_TRAFFIC["fetch_bytes"] + BWD_TRAFFIC["write_bytes"]
     roofline = {"bound": "alu", "kernel": "blend_bwd", "achieved": round(achieved, 3),
                 "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
                 "units_per_launch": {"blended_pairs": e_blend},
                 "flops_per_unit": FLOPS_BWD_BLEND, "avg_ms": round(bwd_ms, 4)}
     fwd_tf = fwd_flops / (fwd_ms * 1e-3) / 1e12
@@ -187,6 +231,7 @@ def main():
         "roofline": roofline,
         "stage_ms": {k: round(v, 4) for k, v in stages.items()},
         "blend_fwd_tflops": round(fwd_tf, 3),
+        "hbm_copy_gbs": round(copy_gbs, 1),
         "work": st,
         "variants": variants,
         "cpu_baseline": cpu,

@@ -83,8 +83,11 @@ typedef struct {
   float lowpass_var;  /* variance of the screen-space low-pass in px^2, e.g. 0.5 */
   float bg[3];        /* background colour composited with the final transmittance */
   int32_t tile_w;     /* tile width in px: 8, 16 or 32 */
-  int32_t tile_h;     /* tile height in px: 8, 16 or 32; tile_w * tile_h <= 1024 */
-  int32_t batch;      /* splats staged in LDS per batch: 0 = default, else 8..64 (mult. of 8) */
+  int32_t tile_h;     /* tile height in px: 8, 16 or 32; tile_w * tile_h <= 256 */
+  int32_t batch;      /* splats staged in LDS per forward batch: 0 = default (16 for N = 8,
+                         else 64), or 8, 16, 32, 64 */
+  int32_t batch_bwd;  /* splats staged in LDS per backward batch: 0 = default (8 for N = 8,
+                         else 32), or 8, 16, 32 */
 } gb_options;
 
 /* Output gradients (device, float32, overwritten -- not accumulated). */

@@ -39,7 +39,8 @@ class GbSplats(ctypes.Structure):
 class GbOptions(ctypes.Structure):
     _fields_ = [("sigma", c_float), ("alpha_min", c_float), ("alpha_max", c_float),
                 ("t_min", c_float), ("lowpass_var", c_float), ("bg", c_float * 3),
-                ("tile_w", c_int32), ("tile_h", c_int32), ("batch", c_int32)]
+                ("tile_w", c_int32), ("tile_h", c_int32), ("batch", c_int32),
+                ("batch_bwd", c_int32)]
 
 
 class GbGrads(ctypes.Structure):
@@ -123,6 +124,7 @@ def make_views(views) -> ctypes.Array:
 
 
 def make_options(sigma=0.5, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4,
-                 lowpass_var=0.5, bg=(0.0, 0.0, 0.0), tile_w=16, tile_h=16, batch=0) -> GbOptions:
+                 lowpass_var=0.5, bg=(0.0, 0.0, 0.0), tile_w=16, tile_h=16, batch=0,
+                 batch_bwd=0) -> GbOptions:
     return GbOptions(sigma, alpha_min, alpha_max, t_min, lowpass_var, (c_float * 3)(*bg),
-                     tile_w, tile_h, batch)
+                     tile_w, tile_h, batch, batch_bwd)

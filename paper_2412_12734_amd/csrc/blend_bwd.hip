@@ -371,6 +371,10 @@ hipError_t launch_np(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
   const dim3 grid((unsigned)(8 * (int64_t)bp.tiles_per_xcd));
   const dim3 block((unsigned)(pl.tile_w * pl.tile_h / PIX));
   switch (pl.batch_bwd) {
+    case 8:
+      hipLaunchKernelGGL((blend_bwd_kernel<N, BF16, 8, PIX>), grid, block, 0, s, views, rec,
+                         pair_vals, ranges, sp.textures, bp, T_final, n_last, d_rgb, d_rec, d_tex);
+      break;
     case 32:
       hipLaunchKernelGGL((blend_bwd_kernel<N, BF16, 32, PIX>), grid, block, 0, s, views, rec,
                          pair_vals, ranges, sp.textures, bp, T_final, n_last, d_rgb, d_rec, d_tex);

@@ -167,6 +167,10 @@ hipError_t launch_n(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
   const dim3 grid((unsigned)(8 * (int64_t)bp.tiles_per_xcd));
   const dim3 block((unsigned)(pl.tile_w * pl.tile_h));
   switch (pl.batch_fwd) {
+    case 8:
+      hipLaunchKernelGGL((blend_fwd_kernel<N, BF16, 8, STATS>), grid, block, 0, s, views, rec,
+                         pair_vals, ranges, sp.textures, bp, rgb, T_final, n_last, stats);
+      break;
     case 16:
       hipLaunchKernelGGL((blend_fwd_kernel<N, BF16, 16, STATS>), grid, block, 0, s, views, rec,
                          pair_vals, ranges, sp.textures, bp, rgb, T_final, n_last, stats);

@@ -49,10 +49,11 @@ struct SplatRec {
 static_assert(sizeof(SplatRec) == 96, "SplatRec layout");
 
 struct Status {
-  uint32_t K;          // total pairs requested by the key stage
+  uint32_t K;          // pair total of the 32-bit offset scan (equals K64 when no overflow)
   uint32_t n_sorted;   // pairs actually emitted and sorted (0 on overflow)
-  uint32_t overflow;   // 1 if K exceeded the capacity
+  uint32_t overflow;   // 1 if K64 exceeded the capacity
   uint32_t reserved;
+  unsigned long long K64;  // exact total of pairs requested by the key stage
 };
 
 // Host-side plan of one call: sizes and workspace carve-up.
@@ -86,10 +87,13 @@ hipError_t launch_preprocess(const gb_splats& sp, const ViewDev* d_views, int n_
                              uint32_t* sort_key, uint32_t* count, SplatRec* rec, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
 hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t s);
-// Exclusive scan of n u32 values (optionally gathered in[gather[i]]); writes out and, if
-// total != nullptr, the sum to *total. partials needs ceil(n / kScanTile) + 1 entries.
+// Exclusive scan of n u32 values (optionally gathered in[gather[i]]) in 32-bit arithmetic;
+// writes out and, if total != nullptr, the sum to *total. If total64 != nullptr the exact
+// 64-bit sum is added to *total64 (which the caller clears). partials needs
+// ceil(n / kScanTile) + 1 entries.
 hipError_t launch_scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t n,
-                           uint32_t* partials, uint32_t* total, hipStream_t s);
+                           uint32_t* partials, uint32_t* total, unsigned long long* total64,
+                           hipStream_t s);
 // Stable LSD radix sort of (key, value) pairs on bits [0, bits). The element count is
 // read from *d_n on the device (at most n_cap). Buffers ping-pong; the result is written
 // back to keys/vals. hist needs 256 * ceil(n_cap / kRadixTile) entries.

@@ -1,12 +1,13 @@
 // Device-wide exclusive scan and stable LSD radix sort of (uint32 key, uint32 value) pairs.
 //
 // Scan: reduce per 4096-element tile -> scan of tile sums in one workgroup -> per-tile scan.
-// Radix pass (8-bit digit): per-tile digit histogram -> exclusive scan of the digit-major
+// Radix pass (a digit of at most 8 bits; a key of b bits takes ceil(b/8) passes with the bits
+// spread evenly over them): per-tile digit histogram -> exclusive scan of the digit-major
 // [digit][tile] counts -> scatter. The scatter ranks each element stably among equal digits
 // of its tile: each wave takes a contiguous quarter of the tile in rounds of 64; lanes with
-// the same digit are found with eight ballots (one per digit bit) and counted against the
-// wave's running per-digit counters in LDS. Wave offsets and digit starts then place every
-// element in LDS in digit order, and the tile is written out so that consecutive lanes store
+// the same digit are found with one ballot per digit bit and counted against the wave's
+// running per-digit counters in LDS. Wave offsets and digit starts then place every element
+// in LDS in digit order, and the tile is written out so that consecutive lanes store
 // consecutive addresses of one digit run.
 #include "device_util.h"
 #include "gbb_internal.h"
@@ -52,14 +53,26 @@ __device__ __forceinline__ uint32_t scan_load(const uint32_t* in, const uint32_t
 template <bool GATHER>
 __global__ void __launch_bounds__(kThreads)
 scan_reduce_kernel(const uint32_t* __restrict__ in, const uint32_t* __restrict__ gather,
-                   int64_t n, uint32_t* __restrict__ partials) {
+                   int64_t n, uint32_t* __restrict__ partials,
+                   unsigned long long* __restrict__ total64) {
   __shared__ uint32_t wave_tot[4];
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   uint32_t s = 0;
+  unsigned long long s64 = 0;
 #pragma unroll 4
   for (int k = 0; k < kItems; ++k) {
     int64_t i = base + k * kThreads + threadIdx.x;
-    if (i < n) s += scan_load<GATHER>(in, gather, i);
+    if (i < n) {
+      const uint32_t x = scan_load<GATHER>(in, gather, i);
+      s += x;
+      s64 += x;
+    }
+  }
+  if (total64) {
+    // exact sum: wave reduction in 64 bits, one global atomic per wave
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s64 += __shfl_xor(s64, d, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(total64, s64);
   }
   uint32_t total;
   block_inclusive_scan(s, wave_tot, &total);
@@ -161,54 +174,73 @@ __device__ __forceinline__ int64_t sort_count(const uint32_t* d_n, int64_t n_cap
   return n < n_cap ? n : n_cap;
 }
 
+// Digit counts of one tile. Each wave counts into its own LDS histogram with plain LDS
+// atomics (lanes that hit one bin are served one after another by the LDS, which is cheaper
+// than grouping equal digits with ballots); each lane loads four consecutive keys at a time.
+template <int NBITS>
 __global__ void __launch_bounds__(kRadixThreads)
 radix_hist_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ d_n,
                   int64_t n_cap, int shift, int64_t nb, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[256];
+  constexpr int kBins = 1 << NBITS;
+  constexpr uint32_t kMask = (uint32_t)kBins - 1u;
+  constexpr int kWaves = kRadixThreads / 64;
+  __shared__ uint32_t h[kWaves][kBins];
   const int64_t n = sort_count(d_n, n_cap);
   const int64_t tile = radix_tile_of_block(nb);
   if (tile >= nb) return;
-  h[threadIdx.x] = 0;
+  const int w = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < kWaves * kBins; i += kRadixThreads) (&h[0][0])[i] = 0;
   __syncthreads();
   const int64_t base = tile * kRadixTile;
   if (base < n) {
-    // all loads first (memory-level parallelism), then lanes with equal digits are grouped
-    // with eight ballots and one add per group
-    uint32_t d_r[kRadixItems];
+    const int nvalid = (int)((n - base) < kRadixTile ? (n - base) : kRadixTile);
+    const uint32_t* kt = keys + base;
+    uint4 q[kRadixItems / 4];
 #pragma unroll
-    for (int k = 0; k < kRadixItems; ++k) {
-      const int64_t i = base + k * kRadixThreads + threadIdx.x;
-      d_r[k] = i < n ? (keys[i] >> shift) & 255u : 256u;
+    for (int k = 0; k < kRadixItems / 4; ++k) {
+      const int i = 4 * (k * kRadixThreads + threadIdx.x);
+      if (i + 3 < nvalid) {
+        q[k] = *reinterpret_cast<const uint4*>(kt + i);
+      } else {
+        q[k].x = i < nvalid ? kt[i] : 0u;
+        q[k].y = i + 1 < nvalid ? kt[i + 1] : 0u;
+        q[k].z = i + 2 < nvalid ? kt[i + 2] : 0u;
+        q[k].w = 0u;
+      }
     }
 #pragma unroll
-    for (int k = 0; k < kRadixItems; ++k) {
-      const uint32_t d = d_r[k];
-      const bool valid = d < 256u;
-      uint64_t m = ballot(valid);
-#pragma unroll
-      for (int bit = 0; bit < 8; ++bit) {
-        const bool set = (d >> bit) & 1u;
-        const uint64_t b = ballot(set);
-        m &= set ? b : ~b;
-      }
-      if (valid && mbcnt(m) == 0) atomicAdd(&h[d], popc64(m));
+    for (int k = 0; k < kRadixItems / 4; ++k) {
+      const int i = 4 * (k * kRadixThreads + threadIdx.x);
+      if (i < nvalid) atomicAdd(&h[w][(q[k].x >> shift) & kMask], 1u);
+      if (i + 1 < nvalid) atomicAdd(&h[w][(q[k].y >> shift) & kMask], 1u);
+      if (i + 2 < nvalid) atomicAdd(&h[w][(q[k].z >> shift) & kMask], 1u);
+      if (i + 3 < nvalid) atomicAdd(&h[w][(q[k].w >> shift) & kMask], 1u);
     }
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nb + tile] = h[threadIdx.x];
+  for (int d = threadIdx.x; d < kBins; d += kRadixThreads) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int ww = 0; ww < kWaves; ++ww) c += h[ww][d];
+    hist[(int64_t)d * nb + tile] = c;
+  }
 }
 
+template <int NBITS>
 __global__ void __launch_bounds__(kRadixThreads)
 radix_scatter_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
                      uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
                      const uint32_t* __restrict__ d_n, int64_t n_cap, int shift, int64_t nb,
                      const uint32_t* __restrict__ hist_scanned) {
+  constexpr int kBins = 1 << NBITS;
+  constexpr uint32_t kMask = (uint32_t)kBins - 1u;
   constexpr int kWaves = kRadixThreads / 64;
   constexpr int kPerWave = kRadixTile / kWaves;  // contiguous elements ranked by one wave
   __shared__ uint32_t s_keys[kRadixTile];
   __shared__ uint32_t s_vals[kRadixTile];
   __shared__ uint32_t s_cnt[kWaves][256];  // running per-wave digit counts, then wave offsets
   __shared__ uint32_t s_start[256];
+  __shared__ uint32_t s_gofs[kBins];  // output index of the tile's element 0 of each digit
   __shared__ uint32_t wave_tot[4];
   const int64_t n = sort_count(d_n, n_cap);
   const int64_t tile = radix_tile_of_block(nb);
@@ -216,6 +248,8 @@ radix_scatter_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __res
   if (tile >= nb || base >= n) return;
   const int nvalid = (int)((n - base) < kRadixTile ? (n - base) : kRadixTile);
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  // where each digit of this tile starts in the output (loaded early, used at the end)
+  const uint32_t gstart = tid < kBins ? hist_scanned[(int64_t)tid * nb + tile] : 0u;
 #pragma unroll
   for (int k = 0; k < 4; ++k) s_cnt[w][lane + 64 * k] = 0;
   __builtin_amdgcn_wave_barrier();
@@ -234,10 +268,11 @@ radix_scatter_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __res
   for (int r = 0; r < kRadixItems; ++r) {
     const int i = w * kPerWave + r * 64 + lane;
     const bool valid = i < nvalid;
-    const uint32_t d = (key_r[r] >> shift) & 255u;
+    const uint32_t d = (key_r[r] >> shift) & kMask;
+    // lanes holding the same digit: one ballot per digit bit
     uint64_t m = ballot(valid);
 #pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
+    for (int bit = 0; bit < NBITS; ++bit) {
       const bool set = (d >> bit) & 1u;
       const uint64_t b = ballot(set);
       m &= set ? b : ~b;
@@ -261,12 +296,14 @@ radix_scatter_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __res
   uint32_t total;
   const uint32_t incl = block_inclusive_scan(tot, wave_tot, &total);
   s_start[tid] = incl - tot;
+  // element counts fit in 32 bits, so output indices do too
+  if (tid < kBins) s_gofs[tid] = gstart - (incl - tot);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRadixItems; ++r) {
     const int i = w * kPerWave + r * 64 + lane;
     if (i < nvalid) {
-      const uint32_t d = (key_r[r] >> shift) & 255u;
+      const uint32_t d = (key_r[r] >> shift) & kMask;
       const uint32_t pos = s_start[d] + s_cnt[w][d] + rank_r[r];
       s_keys[pos] = key_r[r];
       s_vals[pos] = val_r[r];
@@ -275,9 +312,7 @@ radix_scatter_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __res
   __syncthreads();
   for (int i = tid; i < nvalid; i += kRadixThreads) {
     const uint32_t key = s_keys[i];
-    const uint32_t d = (key >> shift) & 255u;
-    const uint64_t gpos = (uint64_t)hist_scanned[(int64_t)d * nb + tile] +
-                          (uint64_t)(i - (int)s_start[d]);
+    const uint32_t gpos = s_gofs[(key >> shift) & kMask] + (uint32_t)i;
     keys_out[gpos] = key;
     vals_out[gpos] = s_vals[i];
   }
@@ -328,15 +363,16 @@ hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t s) {
 }
 
 hipError_t launch_scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t n,
-                           uint32_t* partials, uint32_t* total, hipStream_t s) {
+                           uint32_t* partials, uint32_t* total, unsigned long long* total64,
+                           hipStream_t s) {
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
   if (nb == 0) return hipSuccess;
   if (gather)
     hipLaunchKernelGGL(scan_reduce_kernel<true>, dim3((unsigned)nb), dim3(kThreads), 0, s, in,
-                       gather, n, partials);
+                       gather, n, partials, total64);
   else
     hipLaunchKernelGGL(scan_reduce_kernel<false>, dim3((unsigned)nb), dim3(kThreads), 0, s, in,
-                       gather, n, partials);
+                       gather, n, partials, total64);
   hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, s, partials, nb, total);
   if (gather)
     hipLaunchKernelGGL(scan_down_kernel<true>, dim3((unsigned)nb), dim3(kThreads), 0, s, in,
@@ -347,22 +383,46 @@ hipError_t launch_scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t*
   return hipGetLastError();
 }
 
+template <int NBITS>
+hipError_t radix_pass(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo,
+                      const uint32_t* d_n, int64_t n_cap, int shift, int64_t nb, uint32_t* hist,
+                      uint32_t* partials, hipStream_t s) {
+  const unsigned grid = (unsigned)(8 * ((nb + 7) / 8));
+  hipLaunchKernelGGL(radix_hist_kernel<NBITS>, dim3(grid), dim3(kRadixThreads), 0, s, ki, d_n,
+                     n_cap, shift, nb, hist);
+  hipError_t e = launch_scan_u32(hist, nullptr, hist, ((int64_t)1 << NBITS) * nb, partials,
+                                 nullptr, nullptr, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(radix_scatter_kernel<NBITS>, dim3(grid), dim3(kRadixThreads), 0, s, ki, vi,
+                     ko, vo, d_n, n_cap, shift, nb, hist);
+  return hipGetLastError();
+}
+
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                              uint32_t* vals_alt, const uint32_t* d_n, int64_t n_cap, int bits,
                              uint32_t* hist, uint32_t* partials, hipStream_t s) {
   const int64_t nb = (n_cap + kRadixTile - 1) / kRadixTile;
   if (nb == 0 || bits <= 0) return hipSuccess;
+  if (bits > 32) return hipErrorInvalidValue;
+  // the fewest 8-bit-or-narrower passes, with the key bits spread evenly over them
   const int passes = (bits + 7) / 8;
   uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
-  const unsigned grid = (unsigned)(8 * ((nb + 7) / 8));
+  int shift = 0;
   for (int p = 0; p < passes; ++p) {
-    const int shift = 8 * p;
-    hipLaunchKernelGGL(radix_hist_kernel, dim3(grid), dim3(kRadixThreads), 0, s, ki, d_n,
-                       n_cap, shift, nb, hist);
-    hipError_t e = launch_scan_u32(hist, nullptr, hist, 256 * nb, partials, nullptr, s);
+    const int nbits = bits / passes + (p < bits % passes ? 1 : 0);
+    hipError_t e;
+    switch (nbits) {
+      case 1: e = radix_pass<1>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, partials, s); break;
+      case 2: e = radix_pass<2>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, partials, s); break;
+      case 3: e = radix_pass<3>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, partials, s); break;
+      case 4: e = radix_pass<4>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, partials, s); break;
+      case 5: e = radix_pass<5>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, partials, s); break;
+      case 6: e = radix_pass<6>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, partials, s); break;
+      case 7: e = radix_pass<7>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, partials, s); break;
+      default: e = radix_pass<8>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, partials, s); break;
+    }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3(grid), dim3(kRadixThreads), 0, s, ki,
-                       vi, ko, vo, d_n, n_cap, shift, nb, hist);
+    shift += nbits;
     uint32_t* t = ki;
     ki = ko;
     ko = t;

@@ -25,11 +25,12 @@ class Options:
     tile_w: int = 16
     tile_h: int = 16
     batch: int = 0
+    batch_bwd: int = 0
 
     def c(self) -> L.GbOptions:
         return L.make_options(self.sigma, self.alpha_min, self.alpha_max, self.t_min,
                               self.lowpass_var, tuple(self.bg), self.tile_w, self.tile_h,
-                              self.batch)
+                              self.batch, self.batch_bwd)
 
 
 def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:

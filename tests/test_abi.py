@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_header_layout():
     # gb_view: 2 ints + 4 floats + 9 + 3 + 1 floats
     assert ctypes.sizeof(L.GbView) == 4 * (2 + 4 + 9 + 3 + 1)
-    assert ctypes.sizeof(L.GbOptions) == 4 * (5 + 3 + 3)
+    assert ctypes.sizeof(L.GbOptions) == 4 * (5 + 3 + 4)
     assert ctypes.sizeof(L.GbSplats) == 16 + 6 * 8
     assert ctypes.sizeof(L.GbLayout) == 8 * 12
 
@@ -53,7 +53,7 @@ def test_default_options():
     assert o.alpha_min == np.float32(1 / 255)
     assert o.alpha_max == pytest.approx(0.99)
     assert o.t_min == pytest.approx(1e-4)
-    assert (o.tile_w, o.tile_h, o.batch) == (16, 16, 0)
+    assert (o.tile_w, o.tile_h, o.batch, o.batch_bwd) == (16, 16, 0, 0)
 
 
 def _layout(P=100, N=4, views=None, opts=None, cap=1000):
@@ -80,6 +80,7 @@ def test_layout_sections_are_aligned_and_disjoint():
 
 @pytest.mark.parametrize("field,value,status", [
     ("tile_w", 12, L.GB_ERR_ARG), ("tile_h", 64, L.GB_ERR_ARG), ("batch", 7, L.GB_ERR_ARG),
+    ("batch_bwd", 64, L.GB_ERR_ARG),
     ("sigma", 0.0, L.GB_ERR_ARG), ("alpha_max", 1.5, L.GB_ERR_ARG), ("t_min", -1.0, L.GB_ERR_ARG),
     ("lowpass_var", 0.0, L.GB_ERR_ARG),
 ])

@@ -37,16 +37,16 @@ def gb():
     return gb
 
 
-def gpu_opts(opts: O.Options, batch=0):
+def gpu_opts(opts: O.Options, batch=0, batch_bwd=0):
     import paper_2412_12734_amd as gb
     return gb.Options(sigma=opts.sigma, alpha_min=opts.alpha_min, alpha_max=opts.alpha_max,
                       t_min=opts.t_min, lowpass_var=opts.lowpass_var, bg=tuple(opts.bg),
-                      tile_w=opts.tile_w, tile_h=opts.tile_h, batch=batch)
+                      tile_w=opts.tile_w, tile_h=opts.tile_h, batch=batch, batch_bwd=batch_bwd)
 
 
-def run_gpu(gb, scene, views, opts, tex_bf16=False, batch=0, capacity=None):
+def run_gpu(gb, scene, views, opts, tex_bf16=False, batch=0, capacity=None, batch_bwd=0):
     sp = gb.Splats.from_numpy(scene, tex_bf16=tex_bf16)
-    rast = gb.Rasterizer(views, gpu_opts(opts, batch))
+    rast = gb.Rasterizer(views, gpu_opts(opts, batch, batch_bwd))
     rast.plan(sp, capacity)
     rgb, T = rast.forward(sp)
     torch.cuda.synchronize()
@@ -181,8 +181,9 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
-def check_grads(gb, scene, view, opts, crop, seed=0, tex_bf16=False):
-    rast, sp, rgb, T = run_gpu(gb, scene, [view], opts, tex_bf16=tex_bf16)
+def check_grads(gb, scene, view, opts, crop, seed=0, tex_bf16=False, batch=0, batch_bwd=0):
+    rast, sp, rgb, T = run_gpu(gb, scene, [view], opts, tex_bf16=tex_bf16, batch=batch,
+                               batch_bwd=batch_bwd)
     ref = O.render(scene, view, opts, crop=crop, keep_saved=True)
     W, H = view.width, view.height
     g_full = sg.make_dl_drgb(seed, [view]).reshape(H, W, 3)
@@ -227,6 +228,19 @@ def test_gradient_parity_tiny_scenes(gb, seed):
 def test_gradient_parity_config2_crop(gb):
     scene, views = sg.config("C2")
     check_grads(gb, scene, views[0], O.Options(), (368, 368, 64, 64))
+
+
+# --- LDS batch sizes: same images, gradients within tolerance -------------------------------
+@pytest.mark.parametrize("batch,batch_bwd", [(8, 8), (16, 32), (64, 16), (32, 8)])
+def test_batch_sizes(gb, batch, batch_bwd):
+    scene = sg.make_scene(21, 3000, -1.5, 1.5, 0.02, 0.25, 8)
+    view = sg.look_at_view((0.0, 0.0, -4.0), 96, 80)
+    opts = O.Options()
+    _, _, rgb0, T0 = run_gpu(gb, scene, [view], opts)
+    _, _, rgb1, T1 = run_gpu(gb, scene, [view], opts, batch=batch, batch_bwd=batch_bwd)
+    assert torch.equal(rgb0, rgb1) and torch.equal(T0, T1)
+    check_grads(gb, scene, view, opts, (16, 16, 48, 40), seed=3, batch=batch,
+                batch_bwd=batch_bwd)
 
 
 # --- precision: bfloat16 texture storage ---------------------------------------------------
