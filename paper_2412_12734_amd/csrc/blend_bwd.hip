@@ -11,12 +11,13 @@
 //
 // A lane owns PIX vertically adjacent pixels (the launch uses PIX = 1: waves of 8 x 8 pixels).
 // Per splat, a lane first adds up its pixels' contributions; the ten per-splat scalars are
-// then summed over each 16-lane row with DPP and added to the row's LDS slot. Texel
-// gradients are grouped by grid cell (with sigma = 0.5 the grid covers only the splat's core,
-// so most blended pixels are border-clamped and share a few cells), summed per row and added
-// to LDS by the row's first lane; after a few groups the remaining pixels add their own
-// contributions. After each batch the non-zero LDS sums go to global memory with one float
-// atomic each.
+// then summed over each 16-lane row with a transposing DPP butterfly that leaves each total
+// in one lane, which adds it to the row's LDS slot. Texel gradients are grouped by grid cell
+// (with sigma = 0.5 the grid covers only the splat's core, so most blended pixels are
+// border-clamped and share a few cells), summed per row the same way and added to LDS; after a
+// few groups the remaining pixels add their own contributions. A splat that no pixel of the
+// wave blended is skipped after evaluation. After each batch the non-zero LDS sums go to
+// global memory with one float atomic each.
 #include "blend_common.h"
 
 namespace gbb {
@@ -202,7 +203,11 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   __syncthreads();
   const uint32_t tile_last = s_tile_last;
   const int row = lane >> 4;
-  const bool row_head = (lane & 15) == 0;
+  // which row total each lane receives from the row reductions below
+  int rec_slot, tex_slot;
+  bool rec_owner, tex_owner;
+  row_scatter_slot<kRecGrad>(rec_slot, rec_owner);
+  row_scatter_slot<3>(tex_slot, tex_owner);
 
   for (uint32_t bend = tile_last; bend > start;) {
     const uint32_t bstart = (bend - start) > (uint32_t)B ? bend - (uint32_t)B : start;
@@ -248,9 +253,13 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
       PixOut po[PIX];
 #pragma unroll
       for (int s = 0; s < PIX; ++s) pixel_step<N>(g, tex, lx, ly[s], jg, ps[s], p, po[s]);
+      bool wave_act = false;
+#pragma unroll
+      for (int s = 0; s < PIX; ++s) wave_act = wave_act || po[s].act;
+      if (!__any(wave_act)) continue;  // no pixel of the wave blended this splat
 
-      // Row sums of the per-splat scalars (a lane first adds its own pixels); the first
-      // lane of each row adds them to the row's LDS slot.
+      // Row sums of the per-splat scalars (a lane first adds its own pixels); each total lands
+      // in one lane of the row, which adds it to the row's LDS slot.
       {
         float red[kRecGrad];
 #pragma unroll
@@ -268,14 +277,10 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
           red[9] += po[s].go;
           any_act = any_act || po[s].act;
         }
-        row_sum_all<kRecGrad>(red);
+        const float tot = row_reduce_scatter<kRecGrad>(red);
         // ballot taken by the whole wave (not inside the lane condition)
         const bool row_act = ((ballot(any_act) >> (16 * row)) & 0xffffull) != 0;
-        float* gr = s_grec + (j * 4 + row) * kRecGrad;
-        if (row_head && row_act) {
-#pragma unroll
-          for (int k = 0; k < kRecGrad; ++k) atomicAdd(&gr[k], red[k]);
-        }
+        if (rec_owner && row_act) atomicAdd(&s_grec[(j * 4 + row) * kRecGrad + rec_slot], tot);
       }
 
       // Texel gradients, grouped by cell over all pixels of the wave.
@@ -317,13 +322,8 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
             red[2] += wv * po[s].dc2;
           }
           if (!__any(nz)) continue;
-          row_sum_all<3>(red);
-          if (row_head && row_in) {
-            float* dst = gt + 3 * (lead_cell + offq[q]);
-            atomicAdd(dst + 0, red[0]);
-            atomicAdd(dst + 1, red[1]);
-            atomicAdd(dst + 2, red[2]);
-          }
+          const float tot = row_reduce_scatter<3>(red);
+          if (tex_owner && row_in) atomicAdd(gt + 3 * (lead_cell + offq[q]) + tex_slot, tot);
         }
       }
 #pragma unroll

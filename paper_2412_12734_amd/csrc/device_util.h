@@ -157,6 +157,77 @@ __device__ __forceinline__ void row_sum_all(float (&v)[K]) {
   for (int k = 0; k < K; ++k) v[k] += dpp_f<0x128>(v[k]);
 }
 
+// Row sums of K values (K <= 16) by a transposing butterfly. In each of four steps a lane and
+// its partner inside the 16-lane row (lane ^ 15, ^ 7, ^ 3, ^ 1: DPP row_mirror,
+// row_half_mirror, quad_perm [3,2,1,0], quad_perm [1,0,3,2]) split their values pairwise:
+// each keeps one value of a pair, chosen by one bit of its row position, and adds the
+// partner's copy of it; a value left without a pair is added whole on both sides. The masks
+// span all 16 positions, so each lane ends with the row total of one value: about 3K/2 + 4
+// instructions instead of 4K for plain reductions. row_scatter_slot gives that value's index
+// and whether this lane is the one lane of the row that owns it.
+template <int CTRL, int KI>
+__device__ __forceinline__ void rs_step(const float (&in)[KI], float (&out)[(KI + 1) / 2],
+                                        bool hi) {
+#pragma unroll
+  for (int i = 0; i < KI / 2; ++i) {
+    const float keep = hi ? in[2 * i + 1] : in[2 * i];
+    const float send = hi ? in[2 * i] : in[2 * i + 1];
+    out[i] = keep + dpp_f<CTRL>(send);
+  }
+  if (KI & 1) out[KI / 2] = in[KI - 1] + dpp_f<CTRL>(in[KI - 1]);
+}
+
+template <int K>
+__device__ __forceinline__ float row_reduce_scatter(const float (&v)[K]) {
+  static_assert(K >= 1 && K <= 16, "at most 16 values per row");
+  constexpr int K1 = (K + 1) / 2, K2 = (K1 + 1) / 2, K3 = (K2 + 1) / 2;
+  const int l = threadIdx.x & 15;
+  float a[K1], b[K2], c[K3], d[1];
+  rs_step<0x140>(v, a, (l & 8) != 0);
+  rs_step<0x141>(a, b, (l & 4) != 0);
+  rs_step<0x1B>(b, c, (l & 2) != 0);
+  rs_step<0xB1>(c, d, (l & 1) != 0);
+  return d[0];
+}
+
+// The value index that row_reduce_scatter<K> leaves in this lane, and whether the lane owns
+// it (a value that went unpaired at some step is held by several lanes; only the one on the
+// low side of every such step owns it).
+template <int K>
+__device__ __forceinline__ void row_scatter_slot(int& idx, bool& owner) {
+  const int l = threadIdx.x & 15;
+  int ids[16];
+  bool dup[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    ids[i] = i;
+    dup[i] = false;
+  }
+  int n = K;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const bool hi = ((l >> (3 - s)) & 1) != 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (i < n / 2) {
+        ids[i] = hi ? ids[2 * i + 1] : ids[2 * i];
+        dup[i] = hi ? dup[2 * i + 1] : dup[2 * i];
+      }
+    }
+    if (n & 1) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (i == n / 2) {
+          ids[i] = ids[n - 1];
+          dup[i] = dup[n - 1] || hi;
+        }
+    }
+    n = (n + 1) / 2;
+  }
+  idx = ids[0];
+  owner = !dup[0];
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_to_lane63(v)), 63));
 }
