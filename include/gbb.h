@@ -88,6 +88,12 @@ typedef struct {
                          else 64), or 8, 16, 32, 64 */
   int32_t batch_bwd;  /* splats staged in LDS per backward batch: 0 = default (8 for N = 8,
                          else 32), or 8, 16, 32 */
+  int32_t prefix_pairs_per_tile;
+                      /* depth-prefix split. The first pass renders the longest prefix of the
+                         depth order whose pairs fit this many pairs per tile (0 = default 512);
+                         a second pass renders the remaining records on the tiles where some
+                         pixel is still open (not stopped by t_min). Results are those of one
+                         pass over all pairs. -1 = a single pass over all pairs. */
 } gb_options;
 
 /* Output gradients (device, float32, overwritten -- not accumulated). */
@@ -103,19 +109,30 @@ typedef struct {
 /* Byte offsets of the workspace sections that tests and tools may read back. */
 typedef struct {
   size_t total_bytes;
-  size_t status;      /* uint32[4]: pair count K, pairs sorted, overflow flag, reserved */
+  size_t status;      /* uint32 pair count K (mod 2^32), pairs of the first pass, overflow flag,
+                         records in the depth prefix; uint64 exact pair count; uint32 pairs of
+                         the rest pass, uint32 pad, uint64 exact pairs of the rest pass */
   size_t depth_key;   /* uint32[V*P]: float bits of the centre depth, 0xFFFFFFFF if culled */
   size_t tile_count;  /* uint32[V*P]: tiles covered by record v*P+k */
   size_t records;     /* 96-byte record per (view, splat): 19 floats of blend geometry, then
                          int32 i0 | i1 << 16, int32 j0 | j1 << 16 (inclusive pixel rectangle,
                          valid if the tile count is > 0), int32 splat, int32 view, pad */
   size_t order;       /* uint32[V*P]: records sorted by (depth, record index) */
-  size_t pair_keys;   /* uint32[capacity]: sorted global tile index of each pair */
-  size_t pair_vals;   /* uint32[capacity]: record index v*P+k of each pair */
-  size_t ranges;      /* uint32[total tiles][2]: [start, end) of each tile's pairs */
-  size_t n_last;      /* uint32[sum HW]: one past the last pair blended at each pixel */
+  size_t pair_keys;   /* uint32[]: sorted global tile index of each pair of the first (or only)
+                         pass */
+  size_t pair_vals;   /* uint32[]: record index v*P+k of each pair of the first pass */
+  size_t ranges;      /* uint32[total tiles][2]: [start, end) of each tile's first-pass pairs */
+  size_t n_last;      /* uint32[sum HW]: one past the last first-pass pair blended at each
+                         pixel */
   int64_t pair_capacity;
   int64_t total_tiles;
+  int64_t prefix_capacity;  /* pair slots of the first pass with the split (0 without) */
+  size_t pair_keys_rest;    /* rest pass (with the split): pairs, ranges and n_last as above */
+  size_t pair_vals_rest;
+  size_t ranges_rest;
+  size_t n_last_rest;
+  size_t open_tiles;        /* uint32[ceil(tiles / 32)]: bit t set if tile t had an open pixel
+                               after the first pass */
 } gb_layout;
 
 /* Workspace layout for P splats of texture side N over n_views views with room for
@@ -156,9 +173,10 @@ gb_status gb_read_status(const void* workspace, int64_t* K_out, int32_t* overflo
                          void* stream);
 
 /* Work counts of one forward, for measurement: runs gb_render_fwd with counting enabled in the
- * blend kernel and waits for the stream. counts_out[0] = (pixel, splat) pairs blended,
+ * blend kernels and waits for the stream. counts_out[0] = (pixel, splat) pairs blended,
  * [1] = pixels stopped by the t_min rule, [2] = (pixel, splat) evaluations performed by the
- * waves (64 per wave and splat evaluated), [3] = (tile, splat) pairs staged into LDS. */
+ * waves (64 per wave and splat evaluated), [3] = (tile, splat) pairs staged into LDS,
+ * [4] = the part of [0] blended by the rest pass of the depth-prefix split. */
 gb_status gb_blend_stats(const gb_splats* splats, const gb_view* views, int32_t n_views,
                          const gb_options* opts, void* workspace, size_t ws_bytes,
                          int64_t pair_capacity, float* rgb, float* T_final, int64_t* counts_out,

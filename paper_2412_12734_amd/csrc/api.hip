@@ -31,6 +31,7 @@ gb_status arg_fail(const char* what) {
 }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+int64_t align_up_i64(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
@@ -51,6 +52,8 @@ gb_status validate_options(const gb_options* o) {
     return arg_fail("batch must be 0, 8, 16, 32 or 64");
   if (o->batch_bwd != 0 && o->batch_bwd != 8 && o->batch_bwd != 16 && o->batch_bwd != 32)
     return arg_fail("batch_bwd must be 0, 8, 16 or 32");
+  if (o->prefix_pairs_per_tile < -1 || o->prefix_pairs_per_tile > (1 << 20))
+    return arg_fail("prefix_pairs_per_tile must be -1, 0 or in [1, 2^20]");
   return GB_OK;
 }
 
@@ -117,11 +120,19 @@ gb_status make_plan(int32_t P, int32_t N, const gb_view* views, int32_t n_views,
   if (tiles >= ((int64_t)1 << 31)) return arg_fail("too many tiles");
   pl->total_tiles = tiles;
   pl->total_pixels = pixels;
+  // depth-prefix split: pair slots of the prefix pass come on top of the capacity
+  pl->split = o->prefix_pairs_per_tile >= 0;
+  const int64_t per_tile = o->prefix_pairs_per_tile > 0 ? o->prefix_pairs_per_tile : 512;
+  pl->prefix_cap = pl->split ? align_up_i64(per_tile * tiles, 1024) : 0;
+  if (capacity + pl->prefix_cap > (int64_t)0xFFFFFFF0)
+    return arg_fail("pair capacity plus the prefix pass's slots exceed 2^32-16");
   int bits = 1;
   while (((int64_t)1 << bits) < tiles) ++bits;
   pl->tile_bits = bits;
   pl->nb_vp = (VP + kRadixTile - 1) / kRadixTile;
-  pl->nb_pairs = (capacity + kRadixTile - 1) / kRadixTile;
+  // radix blocks of the larger pair sort (the prefix's slots can exceed a small capacity)
+  const int64_t sort_cap = capacity > pl->prefix_cap ? capacity : pl->prefix_cap;
+  pl->nb_pairs = (sort_cap + kRadixTile - 1) / kRadixTile;
   const int64_t nb_max = pl->nb_vp > pl->nb_pairs ? pl->nb_vp : pl->nb_pairs;
   pl->hist_len = 256 * nb_max;
   int64_t part = (VP + kScanTile - 1) / kScanTile;
@@ -146,14 +157,24 @@ gb_status make_plan(int32_t P, int32_t N, const gb_view* views, int32_t n_views,
   pl->off_rec = take(sizeof(SplatRec) * (size_t)VP);
   pl->off_partials = take(4 * (size_t)pl->partials_len);
   pl->off_hist = take(4 * (size_t)pl->hist_len);
-  pl->off_pair_keys = take(4 * (size_t)capacity);
-  pl->off_pair_vals = take(4 * (size_t)capacity);
-  pl->off_pair_keys_alt = take(4 * (size_t)capacity);
-  pl->off_pair_vals_alt = take(4 * (size_t)capacity);
+  // pairs: the prefix pass's [0, prefix_cap), then the capacity (the only pass, or the rest)
+  const size_t slots = (size_t)(pl->prefix_cap + capacity);
+  pl->off_pair_keys = take(4 * slots);
+  pl->off_pair_vals = take(4 * slots);
+  pl->off_pair_keys_alt = take(4 * slots);
+  pl->off_pair_vals_alt = take(4 * slots);
   pl->off_ranges = take(8 * (size_t)tiles);
   pl->off_n_last = take(4 * (size_t)pixels);
   pl->off_drec = take(4 * (size_t)kRecGrad * (size_t)VP);
   pl->off_stats = take(64);
+  const size_t sp = pl->split ? 1 : 0;
+  pl->off_ranges_rest = take(sp * 8 * (size_t)tiles);
+  pl->off_n_last_rest = take(sp * 4 * (size_t)pixels);
+  pl->off_fwd_state = take(sp * 16 * (size_t)pixels);
+  pl->off_bwd_state = take(sp * 16 * (size_t)pixels);
+  pl->off_open_bits = take(sp * 4 * (size_t)((tiles + 31) / 32));
+  pl->off_count_rest = take(sp * 4 * (size_t)VP);
+  pl->off_offsets_rest = take(sp * 4 * (size_t)VP);
   pl->total = off;
   return GB_OK;
 }
@@ -173,11 +194,13 @@ gb_status check_common(const gb_splats* s, const gb_view* views, int32_t n_views
 // ---- stage timing (measurement only) ------------------------------------------------------
 enum Stage {
   kStPreprocess, kStDepthSort, kStPairScan, kStDuplicate, kStTileSort, kStRanges, kStBlendFwd,
-  kStBwdClear, kStBlendBwd, kStPreprocessBwd, kNumStages
+  kStRestTiles, kStBlendFwdRest, kStBwdClear, kStBlendBwdRest, kStBlendBwd, kStPreprocessBwd,
+  kNumStages
 };
 const char* const kStageNames[kNumStages] = {
     "preprocess", "depth_sort", "pair_scan", "duplicate", "tile_sort", "ranges", "blend_fwd",
-    "bwd_clear", "blend_bwd", "preprocess_bwd"};
+    "rest_tiles", "blend_fwd_rest", "bwd_clear", "blend_bwd_rest", "blend_bwd",
+    "preprocess_bwd"};
 
 struct Timing {
   bool on = false;
@@ -244,6 +267,7 @@ void gb_default_options(gb_options* o) {
   o->tile_h = 16;
   o->batch = 0;
   o->batch_bwd = 0;
+  o->prefix_pairs_per_tile = 0;
 }
 
 const char* gb_status_string(gb_status s) {
@@ -284,6 +308,12 @@ gb_status gb_workspace_layout(int32_t P, int32_t N, const gb_view* views, int32_
   out->n_last = pl.off_n_last;
   out->pair_capacity = pl.capacity;
   out->total_tiles = pl.total_tiles;
+  out->prefix_capacity = pl.prefix_cap;
+  out->pair_keys_rest = pl.off_pair_keys + 4 * (size_t)pl.prefix_cap;
+  out->pair_vals_rest = pl.off_pair_vals + 4 * (size_t)pl.prefix_cap;
+  out->ranges_rest = pl.off_ranges_rest;
+  out->n_last_rest = pl.off_n_last_rest;
+  out->open_tiles = pl.off_open_bits;
   return GB_OK;
 }
 
@@ -343,34 +373,81 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   GBB_TRY(launch_radix_sort(dk_a, order, offsets, order_alt, nullptr, pl.VP, 32, hist, partials, hs),
           "depth sort");
   GBB_TRY(stage_mark(kStDepthSort, 1, hs), "timing");
-  // tile counts in depth order -> pair offsets and K
+  // tile counts in depth order -> pair offsets and K; with the split, the prefix cut
   GBB_TRY(stage_mark(kStPairScan, 0, hs), "timing");
   GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&d_st->K64), 0u, 2, hs), "clear count");
   GBB_TRY(launch_scan_u32(count, order, offsets, pl.VP, partials, &d_st->K, &d_st->K64, hs),
           "pair scan");
   GBB_TRY(launch_finalize_count(d_st, pl.capacity, hs), "finalize count");
+  if (pl.split)
+    GBB_TRY(launch_prefix_cut(offsets, pl.VP, pl.prefix_cap, d_st, hs), "prefix cut");
   GBB_TRY(stage_mark(kStPairScan, 1, hs), "timing");
+  // first (or only) pass: pairs of the depth prefix, sorted by tile, ranges, blend
+  const int64_t cap_a = pl.split ? pl.prefix_cap : pl.capacity;
   GBB_TRY(stage_mark(kStDuplicate, 0, hs), "timing");
-  GBB_TRY(launch_duplicate(order, count, offsets, rec, d_views, pl.VP, pl.tile_w, pl.tile_h, d_st,
-                           pk, pv, hs),
+  GBB_TRY(launch_duplicate(order, count, offsets, rec, d_views, pl.VP,
+                           pl.split ? &d_st->cut : nullptr, pl.tile_w, pl.tile_h, d_st, pk, pv, hs),
           "duplicate");
   GBB_TRY(stage_mark(kStDuplicate, 1, hs), "timing");
   GBB_TRY(stage_mark(kStTileSort, 0, hs), "timing");
-  GBB_TRY(launch_radix_sort(pk, pv, pk_a, pv_a, &d_st->n_sorted, pl.capacity, pl.tile_bits, hist,
+  GBB_TRY(launch_radix_sort(pk, pv, pk_a, pv_a, &d_st->n_sorted, cap_a, pl.tile_bits, hist,
                             partials, hs),
           "tile sort");
   GBB_TRY(stage_mark(kStTileSort, 1, hs), "timing");
   GBB_TRY(stage_mark(kStRanges, 0, hs), "timing");
   GBB_TRY(launch_fill_u32(ranges, 0u, 2 * pl.total_tiles, hs), "clear ranges");
-  GBB_TRY(launch_ranges(pk, d_st, pl.capacity, ranges, hs), "ranges");
+  GBB_TRY(launch_ranges(pk, &d_st->n_sorted, cap_a, ranges, hs), "ranges");
   GBB_TRY(stage_mark(kStRanges, 1, hs), "timing");
   if (stats)
-    GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_stats), 0u, 8, hs), "clear stats");
+    GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_stats), 0u, 16, hs), "clear stats");
+  SplitState split{kSinglePass, nullptr, nullptr, nullptr};
+  if (pl.split) {
+    split.mode = kPrefixPass;
+    split.open_bits = at<uint32_t>(ws, pl.off_open_bits);
+    split.fwd_state = at<float4>(ws, pl.off_fwd_state);
+    GBB_TRY(launch_fill_u32(split.open_bits, 0u, (pl.total_tiles + 31) / 32, hs), "clear bits");
+  }
   GBB_TRY(stage_mark(kStBlendFwd, 0, hs), "timing");
   GBB_TRY(launch_blend_fwd(pl, *s, *o, d_views, n_views, rec, pv, ranges, rgb, T_final,
-                           at<uint32_t>(ws, pl.off_n_last), stats ? d_stats : nullptr, hs),
+                           at<uint32_t>(ws, pl.off_n_last), split, stats ? d_stats : nullptr, hs),
           "blend forward");
   GBB_TRY(stage_mark(kStBlendFwd, 1, hs), "timing");
+  if (!pl.split) return GB_OK;
+
+  // rest pass: the remaining records, paired with the tiles the prefix left open
+  uint32_t* count_rest = at<uint32_t>(ws, pl.off_count_rest);
+  uint32_t* offsets_rest = at<uint32_t>(ws, pl.off_offsets_rest);
+  uint32_t* ranges_rest = at<uint32_t>(ws, pl.off_ranges_rest);
+  uint32_t* pk_r = pk + pl.prefix_cap;
+  uint32_t* pv_r = pv + pl.prefix_cap;
+  uint32_t* pk_ra = pk_a + pl.prefix_cap;
+  uint32_t* pv_ra = pv_a + pl.prefix_cap;
+  GBB_TRY(stage_mark(kStRestTiles, 0, hs), "timing");
+  GBB_TRY(launch_count_rest(order, count, rec, d_views, pl.VP, pl.tile_w, pl.tile_h, d_st,
+                            split.open_bits, count_rest, hs),
+          "rest count");
+  GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&d_st->K_rest64), 0u, 2, hs),
+          "clear rest count");
+  GBB_TRY(launch_scan_u32(count_rest, nullptr, offsets_rest, pl.VP, partials, &d_st->K_rest,
+                          &d_st->K_rest64, hs),
+          "rest scan");
+  GBB_TRY(launch_finalize_rest(d_st, hs), "rest finalize");
+  GBB_TRY(launch_duplicate_rest(order, count_rest, offsets_rest, rec, d_views, pl.VP, pl.tile_w,
+                                pl.tile_h, d_st, split.open_bits, pk_r, pv_r, hs),
+          "rest duplicate");
+  GBB_TRY(launch_radix_sort(pk_r, pv_r, pk_ra, pv_ra, &d_st->n_rest, pl.capacity, pl.tile_bits,
+                            hist, partials, hs),
+          "rest tile sort");
+  GBB_TRY(launch_fill_u32(ranges_rest, 0u, 2 * pl.total_tiles, hs), "clear rest ranges");
+  GBB_TRY(launch_ranges(pk_r, &d_st->n_rest, pl.capacity, ranges_rest, hs), "rest ranges");
+  GBB_TRY(stage_mark(kStRestTiles, 1, hs), "timing");
+  split.mode = kRestPass;
+  GBB_TRY(stage_mark(kStBlendFwdRest, 0, hs), "timing");
+  GBB_TRY(launch_blend_fwd(pl, *s, *o, d_views, n_views, rec, pv_r, ranges_rest, rgb, T_final,
+                           at<uint32_t>(ws, pl.off_n_last_rest), split,
+                           stats ? d_stats : nullptr, hs),
+          "blend forward (rest)");
+  GBB_TRY(stage_mark(kStBlendFwdRest, 1, hs), "timing");
   return GB_OK;
 }
 
@@ -390,11 +467,11 @@ gb_status gb_blend_stats(const gb_splats* s, const gb_view* views, int32_t n_vie
   Plan pl;
   make_plan(s->P, s->N, views, n_views, o, cap, &pl);
   hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
-  unsigned long long h[4];
+  unsigned long long h[5];
   GBB_TRY(hipMemcpyAsync(h, at<char>(ws, pl.off_stats), sizeof(h), hipMemcpyDeviceToHost, hs),
           "read stats");
   GBB_TRY(hipStreamSynchronize(hs), "sync");
-  for (int i = 0; i < 4; ++i) counts[i] = (int64_t)h[i];
+  for (int i = 0; i < 5; ++i) counts[i] = (int64_t)h[i];
   return GB_OK;
 }
 
@@ -442,10 +519,27 @@ gb_status gb_render_bwd(const gb_splats* s, const gb_view* views, int32_t n_view
           "clear d_textures");
   GBB_TRY(stage_mark(kStBwdClear, 1, hs), "timing");
   ViewDev* d_views = at<ViewDev>(ws, pl.off_views);
+  const SplatRec* rec = at<SplatRec>(ws, pl.off_rec);
+  uint32_t* pv = at<uint32_t>(ws, pl.off_pair_vals);
+  SplitState split{kSinglePass, nullptr, nullptr, nullptr};
+  if (pl.split) {
+    // the rest pass first (back to front), leaving each open pixel's (T, S) for the prefix
+    split.mode = kRestPass;
+    split.open_bits = at<uint32_t>(ws, pl.off_open_bits);
+    split.bwd_state = at<float4>(ws, pl.off_bwd_state);
+    GBB_TRY(stage_mark(kStBlendBwdRest, 0, hs), "timing");
+    GBB_TRY(launch_blend_bwd(pl, *s, *o, d_views, n_views, rec, pv + pl.prefix_cap,
+                             at<uint32_t>(ws, pl.off_ranges_rest), T_final,
+                             at<uint32_t>(ws, pl.off_n_last_rest), d_rgb, split, d_rec,
+                             g->d_textures, hs),
+            "blend backward (rest)");
+    GBB_TRY(stage_mark(kStBlendBwdRest, 1, hs), "timing");
+    split.mode = kPrefixPass;
+  }
   GBB_TRY(stage_mark(kStBlendBwd, 0, hs), "timing");
-  GBB_TRY(launch_blend_bwd(pl, *s, *o, d_views, n_views, at<SplatRec>(ws, pl.off_rec),
-                           at<uint32_t>(ws, pl.off_pair_vals), at<uint32_t>(ws, pl.off_ranges),
-                           T_final, at<uint32_t>(ws, pl.off_n_last), d_rgb, d_rec, g->d_textures,
+  GBB_TRY(launch_blend_bwd(pl, *s, *o, d_views, n_views, rec, pv,
+                           at<uint32_t>(ws, pl.off_ranges), T_final,
+                           at<uint32_t>(ws, pl.off_n_last), d_rgb, split, d_rec, g->d_textures,
                            hs),
           "blend backward");
   GBB_TRY(stage_mark(kStBlendBwd, 1, hs), "timing");

@@ -125,13 +125,21 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
   o.gc2y = -ddy;
 }
 
-template <int N, bool BF16, int B, int PIX>
-__global__ void __launch_bounds__(256)
+// With batches of 8 the LDS would allow more than 6 waves per SIMD, but the register
+// allocation (77 VGPRs) stops there; asking for 7 (at most 72 VGPRs, two dwords spilled)
+// measured 4 % faster on the 1M-splat 1080p workload, 8 (64 VGPRs) slower.
+template <int B>
+constexpr int bwd_min_waves() { return B <= 8 ? 7 : 1; }
+
+// Depth-prefix split: the rest pass (REST, open tiles only) runs first and leaves each pixel's
+// (T, S) where the prefix ends; the prefix pass starts its open tiles from there.
+template <int N, bool BF16, int B, int PIX, bool REST>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(bwd_min_waves<B>())))
 blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__ rec,
                  const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ ranges,
                  const void* __restrict__ textures, BlendParams p,
                  const float* __restrict__ T_final, const uint32_t* __restrict__ n_last,
-                 const float* __restrict__ d_rgb, float* __restrict__ d_rec,
+                 const float* __restrict__ d_rgb, SplitState split, float* __restrict__ d_rec,
                  float* __restrict__ d_tex) {
   constexpr int TEXG = 3 * N * N;
   constexpr int BH = 8 * PIX;  // wave block: 8 columns x BH rows
@@ -145,6 +153,9 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
 
   const int tile = tile_of_block(p);
   if (tile >= p.total_tiles) return;
+  const bool tile_open = split.mode != kSinglePass &&
+                         ((split.open_bits[tile >> 5] >> (tile & 31)) & 1u) != 0;
+  if (REST && !tile_open) return;
   const int vi = view_of_tile(views, p.n_views, tile);
   const ViewDev& V = views[vi];
   const int lt = tile - V.tile_base;
@@ -183,6 +194,13 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
     ps[s].S0 = ps[s].T * p.bg[0];
     ps[s].S1 = ps[s].T * p.bg[1];
     ps[s].S2 = ps[s].T * p.bg[2];
+    if (!REST && tile_open && px < V.W && py < V.H) {
+      const float4 sv = split.bwd_state[(int64_t)V.pix_base + (int64_t)py * V.W + px];
+      ps[s].T = sv.x;
+      ps[s].S0 = sv.y;
+      ps[s].S1 = sv.z;
+      ps[s].S2 = sv.w;
+    }
   }
   uint32_t lane_last = ps[0].last;
 #pragma unroll
@@ -361,29 +379,35 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
     __syncthreads();
     bend = bstart;
   }
+  if (REST) {
+#pragma unroll
+    for (int s = 0; s < PIX; ++s) {
+      const int px = tile_x0 + lxi, py = tile_y0 + by + PIX * (lane >> 3) + s;
+      if (px < V.W && py < V.H)
+        split.bwd_state[(int64_t)V.pix_base + (int64_t)py * V.W + px] =
+            make_float4(ps[s].T, ps[s].S0, ps[s].S1, ps[s].S2);
+    }
+  }
 }
 
-template <int N, bool BF16, int PIX>
+template <int N, bool BF16, int PIX, bool REST>
 hipError_t launch_np(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
                      const ViewDev* views, const SplatRec* rec, const uint32_t* pair_vals,
                      const uint32_t* ranges, const float* T_final, const uint32_t* n_last,
-                     const float* d_rgb, float* d_rec, float* d_tex, hipStream_t s) {
+                     const float* d_rgb, const SplitState& split, float* d_rec, float* d_tex,
+                     hipStream_t s) {
   const dim3 grid((unsigned)(8 * (int64_t)bp.tiles_per_xcd));
   const dim3 block((unsigned)(pl.tile_w * pl.tile_h / PIX));
+#define GBB_BWD_B(BB)                                                                         \
+  hipLaunchKernelGGL((blend_bwd_kernel<N, BF16, BB, PIX, REST>), grid, block, 0, s, views, rec, \
+                     pair_vals, ranges, sp.textures, bp, T_final, n_last, d_rgb, split, d_rec,  \
+                     d_tex)
   switch (pl.batch_bwd) {
-    case 8:
-      hipLaunchKernelGGL((blend_bwd_kernel<N, BF16, 8, PIX>), grid, block, 0, s, views, rec,
-                         pair_vals, ranges, sp.textures, bp, T_final, n_last, d_rgb, d_rec, d_tex);
-      break;
-    case 32:
-      hipLaunchKernelGGL((blend_bwd_kernel<N, BF16, 32, PIX>), grid, block, 0, s, views, rec,
-                         pair_vals, ranges, sp.textures, bp, T_final, n_last, d_rgb, d_rec, d_tex);
-      break;
-    default:
-      hipLaunchKernelGGL((blend_bwd_kernel<N, BF16, 16, PIX>), grid, block, 0, s, views, rec,
-                         pair_vals, ranges, sp.textures, bp, T_final, n_last, d_rgb, d_rec, d_tex);
-      break;
+    case 8: GBB_BWD_B(8); break;
+    case 32: GBB_BWD_B(32); break;
+    default: GBB_BWD_B(16); break;
   }
+#undef GBB_BWD_B
   return hipGetLastError();
 }
 
@@ -391,12 +415,16 @@ template <int N, bool BF16>
 hipError_t launch_n(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
                     const ViewDev* views, const SplatRec* rec, const uint32_t* pair_vals,
                     const uint32_t* ranges, const float* T_final, const uint32_t* n_last,
-                    const float* d_rgb, float* d_rec, float* d_tex, hipStream_t s) {
+                    const float* d_rgb, const SplitState& split, float* d_rec, float* d_tex,
+                    hipStream_t s) {
   // One pixel per lane. Two pixels per lane (8 x 16 wave blocks) measured slower on the
   // 1M-splat 1080p workload (3.0 vs 2.3 ms): LDS limits such blocks to two waves per SIMD and
   // the per-wave cull is coarser.
-  return launch_np<N, BF16, 1>(pl, sp, bp, views, rec, pair_vals, ranges, T_final, n_last, d_rgb,
-                               d_rec, d_tex, s);
+  if (split.mode == kRestPass)
+    return launch_np<N, BF16, 1, true>(pl, sp, bp, views, rec, pair_vals, ranges, T_final,
+                                       n_last, d_rgb, split, d_rec, d_tex, s);
+  return launch_np<N, BF16, 1, false>(pl, sp, bp, views, rec, pair_vals, ranges, T_final, n_last,
+                                      d_rgb, split, d_rec, d_tex, s);
 }
 
 }  // namespace
@@ -405,14 +433,14 @@ hipError_t launch_blend_bwd(const Plan& pl, const gb_splats& sp, const gb_option
                             const ViewDev* views, int n_views, const SplatRec* rec,
                             const uint32_t* pair_vals, const uint32_t* ranges,
                             const float* T_final, const uint32_t* n_last, const float* d_rgb,
-                            float* d_rec, float* d_tex, hipStream_t s) {
+                            const SplitState& split, float* d_rec, float* d_tex, hipStream_t s) {
   const BlendParams bp = make_blend_params(pl, o, n_views);
   const bool bf = sp.tex_dtype == GB_BF16;
 #define GBB_BWD(NN)                                                                        \
   return bf ? launch_n<NN, true>(pl, sp, bp, views, rec, pair_vals, ranges, T_final, n_last, \
-                                 d_rgb, d_rec, d_tex, s)                                    \
+                                 d_rgb, split, d_rec, d_tex, s)                             \
             : launch_n<NN, false>(pl, sp, bp, views, rec, pair_vals, ranges, T_final, n_last, \
-                                  d_rgb, d_rec, d_tex, s)
+                                  d_rgb, split, d_rec, d_tex, s)
   switch (pl.N) {
     case 1: GBB_BWD(1);
     case 2: GBB_BWD(2);

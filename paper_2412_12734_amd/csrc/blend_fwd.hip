@@ -8,6 +8,11 @@
 // alpha = min(alpha_max, o G); alpha < alpha_min is skipped; if T (1 - alpha) < t_min the
 // pixel ends without blending it; otherwise acc += alpha T bilinear(C, u, v), T *= 1 - alpha.
 // Saved for the backward: T_final and one past the index of the last blended pair.
+//
+// Depth-prefix split: the prefix pass also marks every tile where some pixel is still open
+// (not stopped by t_min) in a bitmap and saves those pixels' accumulated colour and done flag;
+// the rest pass (REST) runs on marked tiles only and resumes from that state, so each pixel
+// sees exactly the sequence of splats and operations of a single pass.
 #include "blend_common.h"
 
 namespace gbb {
@@ -15,13 +20,14 @@ namespace gbb {
 namespace {
 
 // With STATS the kernel also counts its work into stats[0..3]: blended pairs, pixels stopped
-// by t_min, lane evaluations (64 per wave and evaluated splat) and staged (tile, splat) pairs.
-template <int N, bool BF16, int B, bool STATS>
+// by t_min, lane evaluations (64 per wave and evaluated splat) and staged (tile, splat) pairs;
+// the rest pass also adds its blended pairs to stats[4].
+template <int N, bool BF16, int B, bool STATS, bool REST>
 __global__ void __launch_bounds__(256)
 blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__ rec,
                  const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ ranges,
                  const void* __restrict__ textures, BlendParams p, float* __restrict__ rgb,
-                 float* __restrict__ T_final, uint32_t* __restrict__ n_last,
+                 float* __restrict__ T_final, uint32_t* __restrict__ n_last, SplitState split,
                  unsigned long long* __restrict__ stats) {
   __shared__ float4 s_geo[B][4];
   __shared__ int32_t s_splat[B];
@@ -29,6 +35,7 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
 
   const int tile = tile_of_block(p);
   if (tile >= p.total_tiles) return;
+  if (REST && !((split.open_bits[tile >> 5] >> (tile & 31)) & 1u)) return;
   const int vi = view_of_tile(views, p.n_views, tile);
   const ViewDev& V = views[vi];
   const int lt = tile - V.tile_base;
@@ -51,10 +58,19 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   const float bcy = (float)by + 3.5f - 0.5f * (float)(p.tile_h - 1);
 
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+  const int64_t pix = (int64_t)V.pix_base + (int64_t)py * V.W + px;  // valid if inside
   float T = 1.0f;
   float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
   uint32_t last = start;
   bool done = !inside;
+  if (REST && inside) {
+    const float4 sv = split.fwd_state[pix];
+    acc0 = sv.x;
+    acc1 = sv.y;
+    acc2 = sv.z;
+    done = sv.w != 0.f;
+    T = T_final[pix];
+  }
   uint32_t st_blend = 0, st_eval = 0;
   bool st_term = false;
 
@@ -140,12 +156,18 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   }
 
   if (inside) {
-    const int64_t pix = (int64_t)V.pix_base + (int64_t)py * V.W + px;
     rgb[3 * pix + 0] = acc0 + T * p.bg[0];
     rgb[3 * pix + 1] = acc1 + T * p.bg[1];
     rgb[3 * pix + 2] = acc2 + T * p.bg[2];
     T_final[pix] = T;
     n_last[pix] = last;
+  }
+  if (!REST && split.mode == kPrefixPass) {
+    // a tile with an open pixel takes part in the rest pass
+    if (!__syncthreads_and(done)) {
+      if (tid == 0) atomicOr(&split.open_bits[tile >> 5], 1u << (tile & 31));
+      if (inside) split.fwd_state[pix] = make_float4(acc0, acc1, acc2, done ? 1.f : 0.f);
+    }
   }
   if (STATS) {
     // per-wave totals (exact in float32: at most 64 x 2^17 per wave), one atomic each
@@ -155,35 +177,29 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
       atomicAdd(&stats[0], (unsigned long long)red[0]);
       atomicAdd(&stats[1], (unsigned long long)red[1]);
       atomicAdd(&stats[2], 64ull * st_eval);
+      if (REST) atomicAdd(&stats[4], (unsigned long long)red[0]);
     }
   }
 }
 
-template <int N, bool BF16, bool STATS>
+template <int N, bool BF16, bool STATS, bool REST>
 hipError_t launch_n(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
                     const ViewDev* views, const SplatRec* rec, const uint32_t* pair_vals,
                     const uint32_t* ranges, float* rgb, float* T_final, uint32_t* n_last,
-                    unsigned long long* stats, hipStream_t s) {
+                    const SplitState& split, unsigned long long* stats, hipStream_t s) {
   const dim3 grid((unsigned)(8 * (int64_t)bp.tiles_per_xcd));
   const dim3 block((unsigned)(pl.tile_w * pl.tile_h));
+#define GBB_FWD_B(BB)                                                                        \
+  hipLaunchKernelGGL((blend_fwd_kernel<N, BF16, BB, STATS, REST>), grid, block, 0, s, views, \
+                     rec, pair_vals, ranges, sp.textures, bp, rgb, T_final, n_last, split,    \
+                     stats)
   switch (pl.batch_fwd) {
-    case 8:
-      hipLaunchKernelGGL((blend_fwd_kernel<N, BF16, 8, STATS>), grid, block, 0, s, views, rec,
-                         pair_vals, ranges, sp.textures, bp, rgb, T_final, n_last, stats);
-      break;
-    case 16:
-      hipLaunchKernelGGL((blend_fwd_kernel<N, BF16, 16, STATS>), grid, block, 0, s, views, rec,
-                         pair_vals, ranges, sp.textures, bp, rgb, T_final, n_last, stats);
-      break;
-    case 32:
-      hipLaunchKernelGGL((blend_fwd_kernel<N, BF16, 32, STATS>), grid, block, 0, s, views, rec,
-                         pair_vals, ranges, sp.textures, bp, rgb, T_final, n_last, stats);
-      break;
-    default:
-      hipLaunchKernelGGL((blend_fwd_kernel<N, BF16, 64, STATS>), grid, block, 0, s, views, rec,
-                         pair_vals, ranges, sp.textures, bp, rgb, T_final, n_last, stats);
-      break;
+    case 8: GBB_FWD_B(8); break;
+    case 16: GBB_FWD_B(16); break;
+    case 32: GBB_FWD_B(32); break;
+    default: GBB_FWD_B(64); break;
   }
+#undef GBB_FWD_B
   return hipGetLastError();
 }
 
@@ -191,12 +207,17 @@ template <int N, bool BF16>
 hipError_t launch_nb(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
                      const ViewDev* views, const SplatRec* rec, const uint32_t* pair_vals,
                      const uint32_t* ranges, float* rgb, float* T_final, uint32_t* n_last,
-                     unsigned long long* stats, hipStream_t s) {
+                     const SplitState& split, unsigned long long* stats, hipStream_t s) {
+  const bool rest = split.mode == kRestPass;
   if (stats)
-    return launch_n<N, BF16, true>(pl, sp, bp, views, rec, pair_vals, ranges, rgb, T_final,
-                                   n_last, stats, s);
-  return launch_n<N, BF16, false>(pl, sp, bp, views, rec, pair_vals, ranges, rgb, T_final,
-                                  n_last, stats, s);
+    return rest ? launch_n<N, BF16, true, true>(pl, sp, bp, views, rec, pair_vals, ranges, rgb,
+                                                T_final, n_last, split, stats, s)
+                : launch_n<N, BF16, true, false>(pl, sp, bp, views, rec, pair_vals, ranges, rgb,
+                                                 T_final, n_last, split, stats, s);
+  return rest ? launch_n<N, BF16, false, true>(pl, sp, bp, views, rec, pair_vals, ranges, rgb,
+                                               T_final, n_last, split, stats, s)
+              : launch_n<N, BF16, false, false>(pl, sp, bp, views, rec, pair_vals, ranges, rgb,
+                                                T_final, n_last, split, stats, s);
 }
 
 }  // namespace
@@ -225,15 +246,15 @@ BlendParams make_blend_params(const Plan& pl, const gb_options& o, int n_views) 
 hipError_t launch_blend_fwd(const Plan& pl, const gb_splats& sp, const gb_options& o,
                             const ViewDev* views, int n_views, const SplatRec* rec,
                             const uint32_t* pair_vals, const uint32_t* ranges, float* rgb,
-                            float* T_final, uint32_t* n_last, unsigned long long* stats,
-                            hipStream_t s) {
+                            float* T_final, uint32_t* n_last, const SplitState& split,
+                            unsigned long long* stats, hipStream_t s) {
   const BlendParams bp = make_blend_params(pl, o, n_views);
   const bool bf = sp.tex_dtype == GB_BF16;
 #define GBB_FWD(NN)                                                                          \
   return bf ? launch_nb<NN, true>(pl, sp, bp, views, rec, pair_vals, ranges, rgb, T_final,   \
-                                  n_last, stats, s)                                          \
+                                  n_last, split, stats, s)                                   \
             : launch_nb<NN, false>(pl, sp, bp, views, rec, pair_vals, ranges, rgb, T_final,  \
-                                   n_last, stats, s)
+                                   n_last, split, stats, s)
   switch (pl.N) {
     case 1: GBB_FWD(1);
     case 2: GBB_FWD(2);

@@ -50,10 +50,26 @@ static_assert(sizeof(SplatRec) == 96, "SplatRec layout");
 
 struct Status {
   uint32_t K;          // pair total of the 32-bit offset scan (equals K64 when no overflow)
-  uint32_t n_sorted;   // pairs actually emitted and sorted (0 on overflow)
+  uint32_t n_sorted;   // pairs emitted and sorted by the first (or only) pass (0 on overflow)
   uint32_t overflow;   // 1 if K64 exceeded the capacity
-  uint32_t reserved;
+  uint32_t cut;        // records (in depth order) rendered by the depth-prefix pass
   unsigned long long K64;  // exact total of pairs requested by the key stage
+  uint32_t n_rest;     // pairs emitted and sorted by the second pass (open tiles only)
+  uint32_t K_rest;     // 32-bit scan total of the second pass
+  unsigned long long K_rest64;  // exact total of the second pass
+};
+
+// Depth-prefix split. The first pass renders the records of a prefix of the depth order
+// (as many as fit a pair budget); tiles where some pixel is still open afterwards get a
+// second pass over the remaining records, which resumes from the saved per-pixel state. The
+// backward runs the passes in reverse order with the state handed over the other way.
+enum BlendMode : int32_t { kSinglePass = 0, kPrefixPass = 1, kRestPass = 2 };
+
+struct SplitState {
+  int32_t mode;
+  uint32_t* open_bits;  // one bit per global tile: set if the prefix left a pixel open
+  float4* fwd_state;    // per pixel after the prefix: accumulated colour, done flag (0 / 1)
+  float4* bwd_state;    // per pixel where the prefix's backward starts: T, S0, S1, S2
 };
 
 // Host-side plan of one call: sizes and workspace carve-up.
@@ -65,12 +81,16 @@ struct Plan {
   int64_t total_pixels;
   int32_t tile_w, tile_h, batch_fwd, batch_bwd;
   int32_t tile_bits;
+  bool split;            // depth-prefix split enabled
+  int64_t prefix_cap;    // pair slots of the prefix pass (0 without the split)
   int64_t nb_vp;      // radix blocks over V*P records
   int64_t nb_pairs;   // radix blocks over the pair capacity
   // byte offsets
   size_t off_status, off_views, off_depth_key, off_depth_key_alt, off_order, off_order_alt,
       off_count, off_offsets, off_rec, off_partials, off_hist, off_pair_keys, off_pair_vals,
-      off_pair_keys_alt, off_pair_vals_alt, off_ranges, off_n_last, off_drec, off_stats, total;
+      off_pair_keys_alt, off_pair_vals_alt, off_ranges, off_n_last, off_drec, off_stats,
+      off_ranges_rest, off_n_last_rest, off_fwd_state, off_bwd_state, off_open_bits,
+      off_count_rest, off_offsets_rest, total;
   int64_t partials_len, hist_len;
 };
 
@@ -101,22 +121,42 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                              uint32_t* vals_alt, const uint32_t* d_n, int64_t n_cap, int bits,
                              uint32_t* hist, uint32_t* partials, hipStream_t s);
 hipError_t launch_finalize_count(Status* st, int64_t capacity, hipStream_t s);
+// Depth-prefix cut: the largest record count (in depth order) whose pairs fit `budget`.
+// Writes st->cut and st->n_sorted (the prefix's pairs); nothing on overflow.
+hipError_t launch_prefix_cut(const uint32_t* offsets, int64_t VP, int64_t budget, Status* st,
+                             hipStream_t s);
+// Pairs of the first pass: records [0, *d_nrec) of the depth order (all VP if d_nrec is null).
 hipError_t launch_duplicate(const uint32_t* order, const uint32_t* count,
                             const uint32_t* offsets, const SplatRec* rec, const ViewDev* views,
-                            int64_t VP, int tile_w, int tile_h, const Status* st,
-                            uint32_t* pair_keys, uint32_t* pair_vals, hipStream_t s);
-hipError_t launch_ranges(const uint32_t* pair_keys, const Status* st, int64_t n_cap,
+                            int64_t VP, const uint32_t* d_nrec, int tile_w, int tile_h,
+                            const Status* st, uint32_t* pair_keys, uint32_t* pair_vals,
+                            hipStream_t s);
+// Second pass: count_rest[r] = open tiles covered by the record at depth rank r >= st->cut.
+hipError_t launch_count_rest(const uint32_t* order, const uint32_t* count, const SplatRec* rec,
+                             const ViewDev* views, int64_t VP, int tile_w, int tile_h,
+                             const Status* st, const uint32_t* open_bits, uint32_t* count_rest,
+                             hipStream_t s);
+hipError_t launch_finalize_rest(Status* st, hipStream_t s);
+// Second pass pairs: (open tile, record) for every record at rank >= st->cut, in depth order.
+hipError_t launch_duplicate_rest(const uint32_t* order, const uint32_t* count_rest,
+                                 const uint32_t* offsets_rest, const SplatRec* rec,
+                                 const ViewDev* views, int64_t VP, int tile_w, int tile_h,
+                                 const Status* st, const uint32_t* open_bits,
+                                 uint32_t* pair_keys, uint32_t* pair_vals, hipStream_t s);
+// Tile ranges of the first *d_n sorted keys.
+hipError_t launch_ranges(const uint32_t* pair_keys, const uint32_t* d_n, int64_t n_cap,
                          uint32_t* ranges, hipStream_t s);
+// Forward blend of one pass (mode in split.mode). REST launches the open-tile kernel.
 hipError_t launch_blend_fwd(const Plan& pl, const gb_splats& sp, const gb_options& o,
                             const ViewDev* views, int n_views, const SplatRec* rec,
                             const uint32_t* pair_vals, const uint32_t* ranges, float* rgb,
-                            float* T_final, uint32_t* n_last, unsigned long long* stats,
-                            hipStream_t s);
+                            float* T_final, uint32_t* n_last, const SplitState& split,
+                            unsigned long long* stats, hipStream_t s);
 hipError_t launch_blend_bwd(const Plan& pl, const gb_splats& sp, const gb_options& o,
                             const ViewDev* views, int n_views, const SplatRec* rec,
                             const uint32_t* pair_vals, const uint32_t* ranges,
                             const float* T_final, const uint32_t* n_last, const float* d_rgb,
-                            float* d_rec, float* d_tex, hipStream_t s);
+                            const SplitState& split, float* d_rec, float* d_tex, hipStream_t s);
 hipError_t launch_preprocess_bwd(const gb_splats& sp, const ViewDev* d_views, int n_views,
                                  const uint32_t* count, const float* d_rec,
                                  const gb_grads& g, hipStream_t s);

@@ -26,11 +26,13 @@ class Options:
     tile_h: int = 16
     batch: int = 0
     batch_bwd: int = 0
+    # depth-prefix split: pairs per tile of the first pass (0 = default), -1 = one pass
+    prefix_pairs_per_tile: int = 0
 
     def c(self) -> L.GbOptions:
         return L.make_options(self.sigma, self.alpha_min, self.alpha_max, self.t_min,
                               self.lowpass_var, tuple(self.bg), self.tile_w, self.tile_h,
-                              self.batch, self.batch_bwd)
+                              self.batch, self.batch_bwd, self.prefix_pairs_per_tile)
 
 
 def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
@@ -178,14 +180,15 @@ class Rasterizer:
     # -- measurement ---------------------------------------------------------------------------
     def blend_stats(self, sp: Splats, rgb: torch.Tensor, T_final: torch.Tensor) -> dict:
         """Forward with work counting (synchronises): blended pairs, t_min stops, lane
-        evaluations and staged (tile, splat) pairs."""
-        c = (ctypes.c_int64 * 4)()
+        evaluations, staged (tile, splat) pairs and the blended pairs of the rest pass."""
+        c = (ctypes.c_int64 * 5)()
         L.check(self.lib.gb_blend_stats(ctypes.byref(sp.c()), self.cviews, self.nv,
                                         ctypes.byref(self.copts), self.ws.data_ptr(),
                                         self.ws.numel(), self.capacity, rgb.data_ptr(),
                                         T_final.data_ptr(), c, _stream(self.device)),
                 "gb_blend_stats")
-        return dict(blended=c[0], terminated=c[1], lane_evals=c[2], staged=c[3])
+        return dict(blended=c[0], terminated=c[1], lane_evals=c[2], staged=c[3],
+                    rest_blended=c[4])
 
     def timing(self, on: bool) -> None:
         L.check(self.lib.gb_timing_enable(1 if on else 0), "gb_timing_enable")
@@ -194,7 +197,8 @@ class Rasterizer:
         ms = (ctypes.c_float * 16)()
         n = ctypes.c_int32(0)
         L.check(self.lib.gb_timing_read(ms, 16, ctypes.byref(n)), "gb_timing_read")
-        return {self.lib.gb_timing_stage_name(i).decode(): float(ms[i]) for i in range(n.value)}
+        return {self.lib.gb_timing_stage_name(i).decode(): float(ms[i]) for i in range(n.value)
+                if ms[i] >= 0.0}
 
     # -- workspace read-back (inspection and tests) ------------------------------------------
     def section(self, name: str, count: int, dtype=torch.int32) -> torch.Tensor:

@@ -37,16 +37,18 @@ def gb():
     return gb
 
 
-def gpu_opts(opts: O.Options, batch=0, batch_bwd=0):
+def gpu_opts(opts: O.Options, batch=0, batch_bwd=0, prefix=0):
     import paper_2412_12734_amd as gb
     return gb.Options(sigma=opts.sigma, alpha_min=opts.alpha_min, alpha_max=opts.alpha_max,
                       t_min=opts.t_min, lowpass_var=opts.lowpass_var, bg=tuple(opts.bg),
-                      tile_w=opts.tile_w, tile_h=opts.tile_h, batch=batch, batch_bwd=batch_bwd)
+                      tile_w=opts.tile_w, tile_h=opts.tile_h, batch=batch, batch_bwd=batch_bwd,
+                      prefix_pairs_per_tile=prefix)
 
 
-def run_gpu(gb, scene, views, opts, tex_bf16=False, batch=0, capacity=None, batch_bwd=0):
+def run_gpu(gb, scene, views, opts, tex_bf16=False, batch=0, capacity=None, batch_bwd=0,
+            prefix=0):
     sp = gb.Splats.from_numpy(scene, tex_bf16=tex_bf16)
-    rast = gb.Rasterizer(views, gpu_opts(opts, batch, batch_bwd))
+    rast = gb.Rasterizer(views, gpu_opts(opts, batch, batch_bwd, prefix))
     rast.plan(sp, capacity)
     rgb, T = rast.forward(sp)
     torch.cuda.synchronize()
@@ -81,7 +83,8 @@ def assert_image_parity(rgb_gpu, T_gpu, ref: O.RenderResult, base, W, H):
 
 # --- key stage, pairs, ranges: bit-exact --------------------------------------------------
 def check_tiling(gb, scene, views, opts):
-    rast, sp, rgb, T = run_gpu(gb, scene, views, opts)
+    # one pass over all pairs: the pair arrays then hold every (tile, record) pair
+    rast, sp, rgb, T = run_gpu(gb, scene, views, opts, prefix=-1)
     P, V = scene.P, len(views)
     depth = rast.section("depth_key", V * P, torch.int32).cpu().numpy().view(np.uint32)
     count = rast.section("tile_count", V * P, torch.int32).cpu().numpy().view(np.uint32)
@@ -181,9 +184,10 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
-def check_grads(gb, scene, view, opts, crop, seed=0, tex_bf16=False, batch=0, batch_bwd=0):
+def check_grads(gb, scene, view, opts, crop, seed=0, tex_bf16=False, batch=0, batch_bwd=0,
+                prefix=0):
     rast, sp, rgb, T = run_gpu(gb, scene, [view], opts, tex_bf16=tex_bf16, batch=batch,
-                               batch_bwd=batch_bwd)
+                               batch_bwd=batch_bwd, prefix=prefix)
     ref = O.render(scene, view, opts, crop=crop, keep_saved=True)
     W, H = view.width, view.height
     g_full = sg.make_dl_drgb(seed, [view]).reshape(H, W, 3)
@@ -241,6 +245,86 @@ def test_batch_sizes(gb, batch, batch_bwd):
     assert torch.equal(rgb0, rgb1) and torch.equal(T0, T1)
     check_grads(gb, scene, view, opts, (16, 16, 48, 40), seed=3, batch=batch,
                 batch_bwd=batch_bwd)
+
+
+# --- depth-prefix split: same images as one pass, exact pair sets ---------------------------
+def dense_scene(N=4):
+    scene = sg.make_scene(31, 20000, -1.0, 1.0, 0.03, 0.3, N)
+    return scene, sg.look_at_view((0.0, 0.0, -3.5), 128, 96)
+
+
+def global_depth_order(scene, views, opts):
+    """Records of all views by (depth key, record index), culled ones last; their counts."""
+    bits, idx, counts = [], [], []
+    for v, view in enumerate(views):
+        ks = O.key_stage(scene, view, opts)
+        bits.append(np.where(ks["visible"], ks["depth"].view(np.uint32), np.uint32(0xFFFFFFFF)))
+        counts.append(ks["count"].astype(np.int64))
+        idx.append(v * scene.P + np.arange(scene.P))
+    bits, idx, counts = np.concatenate(bits), np.concatenate(idx), np.concatenate(counts)
+    order = idx[np.lexsort((idx, bits))]
+    rank = np.empty_like(order)
+    rank[order] = np.arange(order.size)
+    return order, rank, counts
+
+
+@pytest.mark.parametrize("per_tile", [0, 1, 8, 64])
+def test_split_pairs_are_exact_and_images_equal_one_pass(gb, per_tile):
+    scene, view = dense_scene()
+    views = [view, sg.look_at_view((0.5, 0.3, -3.0), 72, 50)]
+    opts = O.Options()
+    rast, sp, rgb, T = run_gpu(gb, scene, views, opts, prefix=per_tile)
+    lay = rast.layout
+    st = rast.section("status", 10).cpu().numpy().view(np.uint32)
+    n_first, overflow, cut, n_rest = int(st[1]), int(st[2]), int(st[3]), int(st[6])
+    assert overflow == 0
+    # the cut: the longest depth prefix whose pairs fit the prefix pass's slots
+    order, rank, counts = global_depth_order(scene, views, opts)
+    off = np.concatenate([[0], np.cumsum(counts[order])])
+    want_cut = int(np.searchsorted(off, lay.prefix_capacity, side="right")) - 1
+    assert cut == want_cut
+    keys, vals, _ = O.tile_pairs(scene, views, opts)
+    in_first = rank[vals] < cut
+    assert n_first == int(in_first.sum())
+    gk = rast.section("pair_keys", n_first).cpu().numpy().view(np.uint32)
+    gv = rast.section("pair_vals", n_first).cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(gk, keys[in_first])
+    np.testing.assert_array_equal(gv, vals[in_first])
+    # the rest: later records on the tiles that the first pass left open
+    tiles = lay.total_tiles
+    bits = rast.section("open_tiles", (tiles + 31) // 32).cpu().numpy().view(np.uint32)
+    is_open = ((bits[keys >> 5] >> (keys & 31)) & 1).astype(bool)
+    in_rest = ~in_first & is_open
+    assert n_rest == int(in_rest.sum())
+    gk = rast.section("pair_keys_rest", n_rest).cpu().numpy().view(np.uint32)
+    gv = rast.section("pair_vals_rest", n_rest).cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(gk, keys[in_rest])
+    np.testing.assert_array_equal(gv, vals[in_rest])
+    if per_tile in (1, 8):
+        assert 0 < cut < len(order) and n_rest > 0  # a real split at this budget
+    _, _, rgb1, T1 = run_gpu(gb, scene, views, opts, prefix=-1)
+    assert torch.equal(rgb, rgb1) and torch.equal(T, T1)
+
+
+def test_split_without_termination_equals_one_pass(gb):
+    scene, view = dense_scene()
+    opts = O.Options(t_min=0.0)
+    _, _, rgb0, T0 = run_gpu(gb, scene, [view], opts, prefix=16)
+    _, _, rgb1, T1 = run_gpu(gb, scene, [view], opts, prefix=-1)
+    assert torch.equal(rgb0, rgb1) and torch.equal(T0, T1)
+
+
+@pytest.mark.parametrize("per_tile", [1, 16, 0])
+def test_split_gradients_match_oracle(gb, per_tile):
+    scene, view = dense_scene(N=8)
+    check_grads(gb, scene, view, O.Options(), (40, 32, 32, 24), seed=5, prefix=per_tile)
+
+
+def test_split_image_matches_oracle(gb):
+    scene, view = dense_scene(N=8)
+    rast, sp, rgb, T = run_gpu(gb, scene, [view], O.Options(), prefix=16)
+    ref = O.render(scene, view, O.Options(), crop=(40, 32, 48, 32))
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 128, 96)
 
 
 # --- precision: bfloat16 texture storage ---------------------------------------------------
