@@ -167,10 +167,10 @@ def main():
     log("stages (ms): " + ", ".join(f"{k}={v:.3f}" for k, v in stages.items()))
 
     st = rast.blend_stats(sp, rgb, T)
-    # the dominant kernel is the backward of the depth-prefix pass; its units are the pairs that
-    # pass blended (the rest pass has its own, much smaller launch)
+    # the dominant kernel is the blend backward: one launch walks the pairs of both passes of
+    # the depth-prefix split, so its units are all blended pairs
     e_eval, e_blend = st["lane_evals"], st["blended"]
-    e_blend_bwd = e_blend - st["rest_blended"]
+    e_blend_bwd = e_blend
     bwd_ms = stages["blend_bwd"]
     fwd_ms = stages["blend_fwd"] + stages.get("blend_fwd_rest", 0.0)
     bwd_flops = e_blend_bwd * FLOPS_BWD_BLEND

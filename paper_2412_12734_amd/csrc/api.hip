@@ -171,7 +171,6 @@ gb_status make_plan(int32_t P, int32_t N, const gb_view* views, int32_t n_views,
   pl->off_ranges_rest = take(sp * 8 * (size_t)tiles);
   pl->off_n_last_rest = take(sp * 4 * (size_t)pixels);
   pl->off_fwd_state = take(sp * 16 * (size_t)pixels);
-  pl->off_bwd_state = take(sp * 16 * (size_t)pixels);
   pl->off_open_bits = take(sp * 4 * (size_t)((tiles + 31) / 32));
   pl->off_count_rest = take(sp * 4 * (size_t)VP);
   pl->off_offsets_rest = take(sp * 4 * (size_t)VP);
@@ -194,13 +193,11 @@ gb_status check_common(const gb_splats* s, const gb_view* views, int32_t n_views
 // ---- stage timing (measurement only) ------------------------------------------------------
 enum Stage {
   kStPreprocess, kStDepthSort, kStPairScan, kStDuplicate, kStTileSort, kStRanges, kStBlendFwd,
-  kStRestTiles, kStBlendFwdRest, kStBwdClear, kStBlendBwdRest, kStBlendBwd, kStPreprocessBwd,
-  kNumStages
+  kStRestTiles, kStBlendFwdRest, kStBwdClear, kStBlendBwd, kStPreprocessBwd, kNumStages
 };
 const char* const kStageNames[kNumStages] = {
     "preprocess", "depth_sort", "pair_scan", "duplicate", "tile_sort", "ranges", "blend_fwd",
-    "rest_tiles", "blend_fwd_rest", "bwd_clear", "blend_bwd_rest", "blend_bwd",
-    "preprocess_bwd"};
+    "rest_tiles", "blend_fwd_rest", "bwd_clear", "blend_bwd", "preprocess_bwd"};
 
 struct Timing {
   bool on = false;
@@ -400,7 +397,7 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   GBB_TRY(stage_mark(kStRanges, 1, hs), "timing");
   if (stats)
     GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_stats), 0u, 16, hs), "clear stats");
-  SplitState split{kSinglePass, nullptr, nullptr, nullptr};
+  SplitState split{kSinglePass, nullptr, nullptr};
   if (pl.split) {
     split.mode = kPrefixPass;
     split.open_bits = at<uint32_t>(ws, pl.off_open_bits);
@@ -520,27 +517,18 @@ gb_status gb_render_bwd(const gb_splats* s, const gb_view* views, int32_t n_view
   GBB_TRY(stage_mark(kStBwdClear, 1, hs), "timing");
   ViewDev* d_views = at<ViewDev>(ws, pl.off_views);
   const SplatRec* rec = at<SplatRec>(ws, pl.off_rec);
-  uint32_t* pv = at<uint32_t>(ws, pl.off_pair_vals);
-  SplitState split{kSinglePass, nullptr, nullptr, nullptr};
+  const uint32_t* pv = at<uint32_t>(ws, pl.off_pair_vals);
+  const PairList first{pv, at<uint32_t>(ws, pl.off_ranges), at<uint32_t>(ws, pl.off_n_last)};
+  PairList rest{nullptr, nullptr, nullptr};
+  const uint32_t* open_bits = nullptr;
   if (pl.split) {
-    // the rest pass first (back to front), leaving each open pixel's (T, S) for the prefix
-    split.mode = kRestPass;
-    split.open_bits = at<uint32_t>(ws, pl.off_open_bits);
-    split.bwd_state = at<float4>(ws, pl.off_bwd_state);
-    GBB_TRY(stage_mark(kStBlendBwdRest, 0, hs), "timing");
-    GBB_TRY(launch_blend_bwd(pl, *s, *o, d_views, n_views, rec, pv + pl.prefix_cap,
-                             at<uint32_t>(ws, pl.off_ranges_rest), T_final,
-                             at<uint32_t>(ws, pl.off_n_last_rest), d_rgb, split, d_rec,
-                             g->d_textures, hs),
-            "blend backward (rest)");
-    GBB_TRY(stage_mark(kStBlendBwdRest, 1, hs), "timing");
-    split.mode = kPrefixPass;
+    rest = PairList{pv + pl.prefix_cap, at<uint32_t>(ws, pl.off_ranges_rest),
+                    at<uint32_t>(ws, pl.off_n_last_rest)};
+    open_bits = at<uint32_t>(ws, pl.off_open_bits);
   }
   GBB_TRY(stage_mark(kStBlendBwd, 0, hs), "timing");
-  GBB_TRY(launch_blend_bwd(pl, *s, *o, d_views, n_views, rec, pv,
-                           at<uint32_t>(ws, pl.off_ranges), T_final,
-                           at<uint32_t>(ws, pl.off_n_last), d_rgb, split, d_rec, g->d_textures,
-                           hs),
+  GBB_TRY(launch_blend_bwd(pl, *s, *o, d_views, n_views, rec, first, rest, open_bits, T_final,
+                           d_rgb, d_rec, g->d_textures, hs),
           "blend backward");
   GBB_TRY(stage_mark(kStBlendBwd, 1, hs), "timing");
   GBB_TRY(stage_mark(kStPreprocessBwd, 0, hs), "timing");

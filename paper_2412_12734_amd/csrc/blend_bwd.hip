@@ -131,16 +131,16 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
 template <int B>
 constexpr int bwd_min_waves() { return B <= 8 ? 7 : 1; }
 
-// Depth-prefix split: the rest pass (REST, open tiles only) runs first and leaves each pixel's
-// (T, S) where the prefix ends; the prefix pass starts its open tiles from there.
-template <int N, bool BF16, int B, int PIX, bool REST>
+// Depth-prefix split: on a tile that the prefix left open the block first walks the rest
+// pass's list (the later splats) and then, with each pixel's T and S carried over in
+// registers, the prefix pass's list; other tiles only walk the prefix list.
+template <int N, bool BF16, int B, int PIX>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(bwd_min_waves<B>())))
 blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__ rec,
-                 const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ ranges,
+                 PairList first, PairList rest, const uint32_t* __restrict__ open_bits,
                  const void* __restrict__ textures, BlendParams p,
-                 const float* __restrict__ T_final, const uint32_t* __restrict__ n_last,
-                 const float* __restrict__ d_rgb, SplitState split, float* __restrict__ d_rec,
-                 float* __restrict__ d_tex) {
+                 const float* __restrict__ T_final, const float* __restrict__ d_rgb,
+                 float* __restrict__ d_rec, float* __restrict__ d_tex) {
   constexpr int TEXG = 3 * N * N;
   constexpr int BH = 8 * PIX;  // wave block: 8 columns x BH rows
   __shared__ float4 s_geo[B][4];
@@ -153,9 +153,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
 
   const int tile = tile_of_block(p);
   if (tile >= p.total_tiles) return;
-  const bool tile_open = split.mode != kSinglePass &&
-                         ((split.open_bits[tile >> 5] >> (tile & 31)) & 1u) != 0;
-  if (REST && !tile_open) return;
+  const bool tile_open = open_bits && ((open_bits[tile >> 5] >> (tile & 31)) & 1u) != 0;
   const int vi = view_of_tile(views, p.n_views, tile);
   const ViewDev& V = views[vi];
   const int lt = tile - V.tile_base;
@@ -174,19 +172,20 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   const float lx = (float)lxi - 0.5f * (float)(p.tile_w - 1);
   float ly[PIX];
   PixState ps[PIX];
-  const uint32_t start = ranges[2 * tile];
+  // packed index of the lane's s-th pixel, or -1 outside the view (recomputed when needed)
+  auto pixel_index = [&](int s) -> int64_t {
+    const int px = tile_x0 + lxi, py = tile_y0 + by + PIX * (lane >> 3) + s;
+    return (px < V.W && py < V.H) ? (int64_t)V.pix_base + (int64_t)py * V.W + px : -1;
+  };
 #pragma unroll
   for (int s = 0; s < PIX; ++s) {
     const int lyi = by + PIX * (lane >> 3) + s;
     ly[s] = (float)lyi - 0.5f * (float)(p.tile_h - 1);
-    const int px = tile_x0 + lxi, py = tile_y0 + lyi;
+    const int64_t pix = pixel_index(s);
     ps[s].T = 1.0f;
     ps[s].g0 = ps[s].g1 = ps[s].g2 = 0.f;
-    ps[s].last = start;
-    if (px < V.W && py < V.H) {
-      const int64_t pix = (int64_t)V.pix_base + (int64_t)py * V.W + px;
+    if (pix >= 0) {
       ps[s].T = T_final[pix];
-      ps[s].last = n_last[pix];
       ps[s].g0 = d_rgb[3 * pix + 0];
       ps[s].g1 = d_rgb[3 * pix + 1];
       ps[s].g2 = d_rgb[3 * pix + 2];
@@ -194,32 +193,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
     ps[s].S0 = ps[s].T * p.bg[0];
     ps[s].S1 = ps[s].T * p.bg[1];
     ps[s].S2 = ps[s].T * p.bg[2];
-    if (!REST && tile_open && px < V.W && py < V.H) {
-      const float4 sv = split.bwd_state[(int64_t)V.pix_base + (int64_t)py * V.W + px];
-      ps[s].T = sv.x;
-      ps[s].S0 = sv.y;
-      ps[s].S1 = sv.z;
-      ps[s].S2 = sv.w;
-    }
   }
-  uint32_t lane_last = ps[0].last;
-#pragma unroll
-  for (int s = 1; s < PIX; ++s) lane_last = ps[s].last > lane_last ? ps[s].last : lane_last;
-
-  if (tid == 0) s_tile_last = start;
-  __syncthreads();
-  {
-    // largest bound over the tile's pixels
-    uint32_t m = lane_last;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t o = __shfl_xor(m, d, 64);
-      m = o > m ? o : m;
-    }
-    if (lane == 0) atomicMax(&s_tile_last, m);
-  }
-  __syncthreads();
-  const uint32_t tile_last = s_tile_last;
   const int row = lane >> 4;
   // which row total each lane receives from the row reductions below
   int rec_slot, tex_slot;
@@ -227,181 +201,201 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   row_scatter_slot<kRecGrad>(rec_slot, rec_owner);
   row_scatter_slot<3>(tex_slot, tex_owner);
 
-  for (uint32_t bend = tile_last; bend > start;) {
-    const uint32_t bstart = (bend - start) > (uint32_t)B ? bend - (uint32_t)B : start;
-    const int nb = (int)(bend - bstart);
-    if (tid < nb) {
-      const uint32_t r = pair_vals[bstart + tid];
-      const SplatRec R = rec[r];
-      const StagedGeo g = stage_geo(R, tile_x0, tile_y0, p.tile_w, p.tile_h);
-      s_geo[tid][0] = g.g0;
-      s_geo[tid][1] = g.g1;
-      s_geo[tid][2] = g.g2;
-      s_geo[tid][3] = g.g3;
-      s_splat[tid] = R.splat;
-      s_recid[tid] = r;
-    }
-    for (int e = tid; e < nb * TEXG; e += nthr) s_gtex[e] = 0.f;
-    for (int e = tid; e < nb * 4 * kRecGrad; e += nthr) s_grec[e] = 0.f;
-    __syncthreads();
-    stage_texels<N, BF16>(textures, s_splat, nb, s_tex);
-    __syncthreads();
-
-    // splats of this batch that can reach the wave's block, walked back to front
-    bool may = false;
-    if (lane < nb) {
-      StagedGeo c;
-      c.g0 = s_geo[lane][0];
-      c.g1 = s_geo[lane][1];
-      c.g2 = s_geo[lane][2];
-      c.g3 = s_geo[lane][3];
-      may = block_may_contribute(c, bcx, bcy, wx0, wy0, p, 8, BH);
-    }
-    uint64_t todo = ballot(may);
-    while (todo != 0) {
-      const int j = 63 - (int)__builtin_clzll(todo);
-      todo &= ~(1ull << j);
-      const uint32_t jg = bstart + (uint32_t)j;
-      if (!__any(jg < lane_last)) continue;
-      StagedGeo g;
-      g.g0 = s_geo[j][0];
-      g.g1 = s_geo[j][1];
-      g.g2 = s_geo[j][2];
-      const float4* tex = s_tex + j * TexLayout<N>::kPerSplat;
-      PixOut po[PIX];
-#pragma unroll
-      for (int s = 0; s < PIX; ++s) pixel_step<N>(g, tex, lx, ly[s], jg, ps[s], p, po[s]);
-      bool wave_act = false;
-#pragma unroll
-      for (int s = 0; s < PIX; ++s) wave_act = wave_act || po[s].act;
-      if (!__any(wave_act)) continue;  // no pixel of the wave blended this splat
-
-      // Row sums of the per-splat scalars (a lane first adds its own pixels); each total lands
-      // in one lane of the row, which adds it to the row's LDS slot.
-      {
-        float red[kRecGrad];
-#pragma unroll
-        for (int k = 0; k < 7; ++k) red[k] = po[0].gh[k];
-        red[7] = po[0].gc2x;
-        red[8] = po[0].gc2y;
-        red[9] = po[0].go;
-        bool any_act = po[0].act;
-#pragma unroll
-        for (int s = 1; s < PIX; ++s) {
-#pragma unroll
-          for (int k = 0; k < 7; ++k) red[k] += po[s].gh[k];
-          red[7] += po[s].gc2x;
-          red[8] += po[s].gc2y;
-          red[9] += po[s].go;
-          any_act = any_act || po[s].act;
-        }
-        const float tot = row_reduce_scatter<kRecGrad>(red);
-        // ballot taken by the whole wave (not inside the lane condition)
-        const bool row_act = ((ballot(any_act) >> (16 * row)) & 0xffffull) != 0;
-        if (rec_owner && row_act) atomicAdd(&s_grec[(j * 4 + row) * kRecGrad + rec_slot], tot);
-      }
-
-      // Texel gradients, grouped by cell over all pixels of the wave.
-      float* gt = s_gtex + j * TEXG;
-      uint64_t pend[PIX];
-#pragma unroll
-      for (int s = 0; s < PIX; ++s) pend[s] = ballot(po[s].act);
-      const int offq[4] = {0, 1, N, N + 1};
 #pragma unroll 1
-      for (int it = 0; it < 4; ++it) {
-        int lead_cell = -1;
+  for (int li = tile_open ? 0 : 1; li < 2; ++li) {
+    const PairList L = li == 0 ? rest : first;
+    const uint32_t* __restrict__ pair_vals = L.pair_vals;
+    const uint32_t start = L.ranges[2 * tile];
 #pragma unroll
-        for (int s = 0; s < PIX; ++s) {
-          if (lead_cell < 0 && pend[s] != 0)
-            lead_cell = __builtin_amdgcn_readlane(po[s].k00, (int)__builtin_ctzll(pend[s]));
+    for (int s = 0; s < PIX; ++s) {
+      const int64_t pix = pixel_index(s);
+      ps[s].last = pix >= 0 ? L.n_last[pix] : start;
+    }
+    uint32_t lane_last = ps[0].last;
+#pragma unroll
+    for (int s = 1; s < PIX; ++s) lane_last = ps[s].last > lane_last ? ps[s].last : lane_last;
+
+    __syncthreads();  // every thread has read the previous list's bound
+    if (tid == 0) s_tile_last = start;
+    __syncthreads();
+    {
+      // largest bound over the tile's pixels
+      uint32_t m = lane_last;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_xor(m, d, 64);
+        m = o > m ? o : m;
+      }
+      if (lane == 0) atomicMax(&s_tile_last, m);
+    }
+    __syncthreads();
+    const uint32_t tile_last = s_tile_last;
+
+    for (uint32_t bend = tile_last; bend > start;) {
+      const uint32_t bstart = (bend - start) > (uint32_t)B ? bend - (uint32_t)B : start;
+      const int nb = (int)(bend - bstart);
+      if (tid < nb) {
+        const uint32_t r = pair_vals[bstart + tid];
+        const SplatRec R = rec[r];
+        const StagedGeo g = stage_geo(R, tile_x0, tile_y0, p.tile_w, p.tile_h);
+        s_geo[tid][0] = g.g0;
+        s_geo[tid][1] = g.g1;
+        s_geo[tid][2] = g.g2;
+        s_geo[tid][3] = g.g3;
+        s_splat[tid] = R.splat;
+        s_recid[tid] = r;
+      }
+      for (int e = tid; e < nb * TEXG; e += nthr) s_gtex[e] = 0.f;
+      for (int e = tid; e < nb * 4 * kRecGrad; e += nthr) s_grec[e] = 0.f;
+      __syncthreads();
+      stage_texels<N, BF16>(textures, s_splat, nb, s_tex);
+      __syncthreads();
+
+      // splats of this batch that can reach the wave's block, walked back to front
+      bool may = false;
+      if (lane < nb) {
+        StagedGeo c;
+        c.g0 = s_geo[lane][0];
+        c.g1 = s_geo[lane][1];
+        c.g2 = s_geo[lane][2];
+        c.g3 = s_geo[lane][3];
+        may = block_may_contribute(c, bcx, bcy, wx0, wy0, p, 8, BH);
+      }
+      uint64_t todo = ballot(may);
+      while (todo != 0) {
+        const int j = 63 - (int)__builtin_clzll(todo);
+        todo &= ~(1ull << j);
+        const uint32_t jg = bstart + (uint32_t)j;
+        if (!__any(jg < lane_last)) continue;
+        StagedGeo g;
+        g.g0 = s_geo[j][0];
+        g.g1 = s_geo[j][1];
+        g.g2 = s_geo[j][2];
+        const float4* tex = s_tex + j * TexLayout<N>::kPerSplat;
+        PixOut po[PIX];
+#pragma unroll
+        for (int s = 0; s < PIX; ++s) pixel_step<N>(g, tex, lx, ly[s], jg, ps[s], p, po[s]);
+        bool wave_act = false;
+#pragma unroll
+        for (int s = 0; s < PIX; ++s) wave_act = wave_act || po[s].act;
+        if (!__any(wave_act)) continue;  // no pixel of the wave blended this splat
+
+        // Row sums of the per-splat scalars (a lane first adds its own pixels); each total lands
+        // in one lane of the row, which adds it to the row's LDS slot.
+        {
+          float red[kRecGrad];
+#pragma unroll
+          for (int k = 0; k < 7; ++k) red[k] = po[0].gh[k];
+          red[7] = po[0].gc2x;
+          red[8] = po[0].gc2y;
+          red[9] = po[0].go;
+          bool any_act = po[0].act;
+#pragma unroll
+          for (int s = 1; s < PIX; ++s) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) red[k] += po[s].gh[k];
+            red[7] += po[s].gc2x;
+            red[8] += po[s].gc2y;
+            red[9] += po[s].go;
+            any_act = any_act || po[s].act;
+          }
+          const float tot = row_reduce_scatter<kRecGrad>(red);
+          // ballot taken by the whole wave (not inside the lane condition)
+          const bool row_act = ((ballot(any_act) >> (16 * row)) & 0xffffull) != 0;
+          if (rec_owner && row_act) atomicAdd(&s_grec[(j * 4 + row) * kRecGrad + rec_slot], tot);
         }
-        if (lead_cell < 0) break;
-        bool in[PIX];
-        uint64_t grp_any = 0;
+
+        // Texel gradients, grouped by cell over all pixels of the wave.
+        float* gt = s_gtex + j * TEXG;
+        uint64_t pend[PIX];
 #pragma unroll
-        for (int s = 0; s < PIX; ++s) {
-          in[s] = ((pend[s] >> lane) & 1ull) && po[s].k00 == lead_cell;
-          const uint64_t grp = ballot(in[s]);
-          pend[s] &= ~grp;
-          grp_any |= grp;
-        }
-        const bool row_in = ((grp_any >> (16 * row)) & 0xffffull) != 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (N == 1 && q > 0) break;
-          float red[3] = {0.f, 0.f, 0.f};
-          bool nz = false;
+        for (int s = 0; s < PIX; ++s) pend[s] = ballot(po[s].act);
+        const int offq[4] = {0, 1, N, N + 1};
+#pragma unroll 1
+        for (int it = 0; it < 4; ++it) {
+          int lead_cell = -1;
 #pragma unroll
           for (int s = 0; s < PIX; ++s) {
-            const float wv = in[s] ? po[s].w[q] : 0.f;
-            nz = nz || wv != 0.f;
-            red[0] += wv * po[s].dc0;
-            red[1] += wv * po[s].dc1;
-            red[2] += wv * po[s].dc2;
+            if (lead_cell < 0 && pend[s] != 0)
+              lead_cell = __builtin_amdgcn_readlane(po[s].k00, (int)__builtin_ctzll(pend[s]));
           }
-          if (!__any(nz)) continue;
-          const float tot = row_reduce_scatter<3>(red);
-          if (tex_owner && row_in) atomicAdd(gt + 3 * (lead_cell + offq[q]) + tex_slot, tot);
-        }
-      }
+          if (lead_cell < 0) break;
+          bool in[PIX];
+          uint64_t grp_any = 0;
 #pragma unroll
-      for (int s = 0; s < PIX; ++s) {
-        if ((pend[s] >> lane) & 1ull) {
+          for (int s = 0; s < PIX; ++s) {
+            in[s] = ((pend[s] >> lane) & 1ull) && po[s].k00 == lead_cell;
+            const uint64_t grp = ballot(in[s]);
+            pend[s] &= ~grp;
+            grp_any |= grp;
+          }
+          const bool row_in = ((grp_any >> (16 * row)) & 0xffffull) != 0;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             if (N == 1 && q > 0) break;
-            const float wq = po[s].w[q];
-            if (wq != 0.f) {
-              float* dst = gt + 3 * (po[s].k00 + offq[q]);
-              atomicAdd(dst + 0, wq * po[s].dc0);
-              atomicAdd(dst + 1, wq * po[s].dc1);
-              atomicAdd(dst + 2, wq * po[s].dc2);
+            float red[3] = {0.f, 0.f, 0.f};
+            bool nz = false;
+#pragma unroll
+            for (int s = 0; s < PIX; ++s) {
+              const float wv = in[s] ? po[s].w[q] : 0.f;
+              nz = nz || wv != 0.f;
+              red[0] += wv * po[s].dc0;
+              red[1] += wv * po[s].dc1;
+              red[2] += wv * po[s].dc2;
+            }
+            if (!__any(nz)) continue;
+            const float tot = row_reduce_scatter<3>(red);
+            if (tex_owner && row_in) atomicAdd(gt + 3 * (lead_cell + offq[q]) + tex_slot, tot);
+          }
+        }
+#pragma unroll
+        for (int s = 0; s < PIX; ++s) {
+          if ((pend[s] >> lane) & 1ull) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              if (N == 1 && q > 0) break;
+              const float wq = po[s].w[q];
+              if (wq != 0.f) {
+                float* dst = gt + 3 * (po[s].k00 + offq[q]);
+                atomicAdd(dst + 0, wq * po[s].dc0);
+                atomicAdd(dst + 1, wq * po[s].dc1);
+                atomicAdd(dst + 2, wq * po[s].dc2);
+              }
             }
           }
         }
       }
-    }
-    __syncthreads();
-    // flush the batch's sums
-    for (int e = tid; e < nb * TEXG; e += nthr) {
-      const float x = s_gtex[e];
-      if (x != 0.f) {
-        const int j = e / TEXG, r = e - j * TEXG;
-        atomicAdd(&d_tex[(int64_t)s_splat[j] * TEXG + r], x);
+      __syncthreads();
+      // flush the batch's sums
+      for (int e = tid; e < nb * TEXG; e += nthr) {
+        const float x = s_gtex[e];
+        if (x != 0.f) {
+          const int j = e / TEXG, r = e - j * TEXG;
+          atomicAdd(&d_tex[(int64_t)s_splat[j] * TEXG + r], x);
+        }
       }
+      for (int e = tid; e < nb * kRecGrad; e += nthr) {
+        const int j = e / kRecGrad, r = e - j * kRecGrad;
+        const float* g4 = s_grec + j * 4 * kRecGrad + r;
+        const float x = (g4[0] + g4[kRecGrad]) + (g4[2 * kRecGrad] + g4[3 * kRecGrad]);
+        if (x != 0.f) atomicAdd(&d_rec[(int64_t)s_recid[j] * kRecGrad + r], x);
+      }
+      __syncthreads();
+      bend = bstart;
     }
-    for (int e = tid; e < nb * kRecGrad; e += nthr) {
-      const int j = e / kRecGrad, r = e - j * kRecGrad;
-      const float* g4 = s_grec + j * 4 * kRecGrad + r;
-      const float x = (g4[0] + g4[kRecGrad]) + (g4[2 * kRecGrad] + g4[3 * kRecGrad]);
-      if (x != 0.f) atomicAdd(&d_rec[(int64_t)s_recid[j] * kRecGrad + r], x);
-    }
-    __syncthreads();
-    bend = bstart;
-  }
-  if (REST) {
-#pragma unroll
-    for (int s = 0; s < PIX; ++s) {
-      const int px = tile_x0 + lxi, py = tile_y0 + by + PIX * (lane >> 3) + s;
-      if (px < V.W && py < V.H)
-        split.bwd_state[(int64_t)V.pix_base + (int64_t)py * V.W + px] =
-            make_float4(ps[s].T, ps[s].S0, ps[s].S1, ps[s].S2);
-    }
-  }
+  }  // lists
 }
 
-template <int N, bool BF16, int PIX, bool REST>
+template <int N, bool BF16, int PIX>
 hipError_t launch_np(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
-                     const ViewDev* views, const SplatRec* rec, const uint32_t* pair_vals,
-                     const uint32_t* ranges, const float* T_final, const uint32_t* n_last,
-                     const float* d_rgb, const SplitState& split, float* d_rec, float* d_tex,
-                     hipStream_t s) {
+                     const ViewDev* views, const SplatRec* rec, const PairList& first,
+                     const PairList& rest, const uint32_t* open_bits, const float* T_final,
+                     const float* d_rgb, float* d_rec, float* d_tex, hipStream_t s) {
   const dim3 grid((unsigned)(8 * (int64_t)bp.tiles_per_xcd));
   const dim3 block((unsigned)(pl.tile_w * pl.tile_h / PIX));
 #define GBB_BWD_B(BB)                                                                         \
-  hipLaunchKernelGGL((blend_bwd_kernel<N, BF16, BB, PIX, REST>), grid, block, 0, s, views, rec, \
-                     pair_vals, ranges, sp.textures, bp, T_final, n_last, d_rgb, split, d_rec,  \
-                     d_tex)
+  hipLaunchKernelGGL((blend_bwd_kernel<N, BF16, BB, PIX>), grid, block, 0, s, views, rec, first, \
+                     rest, open_bits, sp.textures, bp, T_final, d_rgb, d_rec, d_tex)
   switch (pl.batch_bwd) {
     case 8: GBB_BWD_B(8); break;
     case 32: GBB_BWD_B(32); break;
@@ -411,36 +405,23 @@ hipError_t launch_np(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
   return hipGetLastError();
 }
 
-template <int N, bool BF16>
-hipError_t launch_n(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
-                    const ViewDev* views, const SplatRec* rec, const uint32_t* pair_vals,
-                    const uint32_t* ranges, const float* T_final, const uint32_t* n_last,
-                    const float* d_rgb, const SplitState& split, float* d_rec, float* d_tex,
-                    hipStream_t s) {
-  // One pixel per lane. Two pixels per lane (8 x 16 wave blocks) measured slower on the
-  // 1M-splat 1080p workload (3.0 vs 2.3 ms): LDS limits such blocks to two waves per SIMD and
-  // the per-wave cull is coarser.
-  if (split.mode == kRestPass)
-    return launch_np<N, BF16, 1, true>(pl, sp, bp, views, rec, pair_vals, ranges, T_final,
-                                       n_last, d_rgb, split, d_rec, d_tex, s);
-  return launch_np<N, BF16, 1, false>(pl, sp, bp, views, rec, pair_vals, ranges, T_final, n_last,
-                                      d_rgb, split, d_rec, d_tex, s);
-}
-
 }  // namespace
 
 hipError_t launch_blend_bwd(const Plan& pl, const gb_splats& sp, const gb_options& o,
                             const ViewDev* views, int n_views, const SplatRec* rec,
-                            const uint32_t* pair_vals, const uint32_t* ranges,
-                            const float* T_final, const uint32_t* n_last, const float* d_rgb,
-                            const SplitState& split, float* d_rec, float* d_tex, hipStream_t s) {
+                            const PairList& first, const PairList& rest,
+                            const uint32_t* open_bits, const float* T_final, const float* d_rgb,
+                            float* d_rec, float* d_tex, hipStream_t s) {
   const BlendParams bp = make_blend_params(pl, o, n_views);
   const bool bf = sp.tex_dtype == GB_BF16;
-#define GBB_BWD(NN)                                                                        \
-  return bf ? launch_n<NN, true>(pl, sp, bp, views, rec, pair_vals, ranges, T_final, n_last, \
-                                 d_rgb, split, d_rec, d_tex, s)                             \
-            : launch_n<NN, false>(pl, sp, bp, views, rec, pair_vals, ranges, T_final, n_last, \
-                                  d_rgb, split, d_rec, d_tex, s)
+  // One pixel per lane. Two pixels per lane (8 x 16 wave blocks) measured slower on the
+  // 1M-splat 1080p workload (3.0 vs 2.3 ms): LDS limits such blocks to two waves per SIMD and
+  // the per-wave cull is coarser.
+#define GBB_BWD(NN)                                                                           \
+  return bf ? launch_np<NN, true, 1>(pl, sp, bp, views, rec, first, rest, open_bits, T_final, \
+                                     d_rgb, d_rec, d_tex, s)                                  \
+            : launch_np<NN, false, 1>(pl, sp, bp, views, rec, first, rest, open_bits, T_final,\
+                                      d_rgb, d_rec, d_tex, s)
   switch (pl.N) {
     case 1: GBB_BWD(1);
     case 2: GBB_BWD(2);

@@ -62,14 +62,21 @@ struct Status {
 // Depth-prefix split. The first pass renders the records of a prefix of the depth order
 // (as many as fit a pair budget); tiles where some pixel is still open afterwards get a
 // second pass over the remaining records, which resumes from the saved per-pixel state. The
-// backward runs the passes in reverse order with the state handed over the other way.
+// backward walks, on each such tile, the second pass's pairs and then the first's, with the
+// per-pixel state kept in registers.
 enum BlendMode : int32_t { kSinglePass = 0, kPrefixPass = 1, kRestPass = 2 };
 
 struct SplitState {
   int32_t mode;
   uint32_t* open_bits;  // one bit per global tile: set if the prefix left a pixel open
   float4* fwd_state;    // per pixel after the prefix: accumulated colour, done flag (0 / 1)
-  float4* bwd_state;    // per pixel where the prefix's backward starts: T, S0, S1, S2
+};
+
+// The sorted pairs of one pass as the backward reads them.
+struct PairList {
+  const uint32_t* pair_vals;  // record of each pair, sorted by tile
+  const uint32_t* ranges;     // [tile][2]: [start, end) of the tile's pairs
+  const uint32_t* n_last;     // per pixel: one past the last pair it blended
 };
 
 // Host-side plan of one call: sizes and workspace carve-up.
@@ -89,7 +96,7 @@ struct Plan {
   size_t off_status, off_views, off_depth_key, off_depth_key_alt, off_order, off_order_alt,
       off_count, off_offsets, off_rec, off_partials, off_hist, off_pair_keys, off_pair_vals,
       off_pair_keys_alt, off_pair_vals_alt, off_ranges, off_n_last, off_drec, off_stats,
-      off_ranges_rest, off_n_last_rest, off_fwd_state, off_bwd_state, off_open_bits,
+      off_ranges_rest, off_n_last_rest, off_fwd_state, off_open_bits,
       off_count_rest, off_offsets_rest, total;
   int64_t partials_len, hist_len;
 };
@@ -152,11 +159,13 @@ hipError_t launch_blend_fwd(const Plan& pl, const gb_splats& sp, const gb_option
                             const uint32_t* pair_vals, const uint32_t* ranges, float* rgb,
                             float* T_final, uint32_t* n_last, const SplitState& split,
                             unsigned long long* stats, hipStream_t s);
+// Backward blend over the prefix (or only) pass's pairs `first`; with open_bits != null the
+// tiles marked there first walk `rest` (the rest pass's pairs).
 hipError_t launch_blend_bwd(const Plan& pl, const gb_splats& sp, const gb_options& o,
                             const ViewDev* views, int n_views, const SplatRec* rec,
-                            const uint32_t* pair_vals, const uint32_t* ranges,
-                            const float* T_final, const uint32_t* n_last, const float* d_rgb,
-                            const SplitState& split, float* d_rec, float* d_tex, hipStream_t s);
+                            const PairList& first, const PairList& rest,
+                            const uint32_t* open_bits, const float* T_final, const float* d_rgb,
+                            float* d_rec, float* d_tex, hipStream_t s);
 hipError_t launch_preprocess_bwd(const gb_splats& sp, const ViewDev* d_views, int n_views,
                                  const uint32_t* count, const float* d_rec,
                                  const gb_grads& g, hipStream_t s);
