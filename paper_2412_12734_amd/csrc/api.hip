@@ -111,13 +111,16 @@ gb_status make_plan(int32_t P, int32_t N, const gb_view* views, int32_t n_views,
   // per block lets more blocks share a CU
   pl->batch_fwd = o->batch != 0 ? o->batch : (N >= 8 ? 16 : 64);
   pl->batch_bwd = o->batch_bwd != 0 ? o->batch_bwd : (N >= 8 ? 8 : 32);
-  int64_t tiles = 0, pixels = 0;
+  int64_t tiles = 0, pixels = 0, sat = 0;
   for (int i = 0; i < n_views; ++i) {
-    tiles += (int64_t)((views[i].width + pl->tile_w - 1) / pl->tile_w) *
-             ((views[i].height + pl->tile_h - 1) / pl->tile_h);
+    const int64_t tx = (views[i].width + pl->tile_w - 1) / pl->tile_w;
+    const int64_t ty = (views[i].height + pl->tile_h - 1) / pl->tile_h;
+    tiles += tx * ty;
+    sat += (tx + 1) * (ty + 1);
     pixels += (int64_t)views[i].width * views[i].height;
   }
-  if (tiles >= ((int64_t)1 << 31)) return arg_fail("too many tiles");
+  if (sat >= ((int64_t)1 << 31)) return arg_fail("too many tiles");
+  pl->sat_len = sat;
   pl->total_tiles = tiles;
   pl->total_pixels = pixels;
   // depth-prefix split: pair slots of the prefix pass come on top of the capacity
@@ -156,6 +159,7 @@ gb_status make_plan(int32_t P, int32_t N, const gb_view* views, int32_t n_views,
   pl->off_offsets = take(4 * (size_t)VP);
   pl->off_rec = take(sizeof(SplatRec) * (size_t)VP);
   pl->off_partials = take(4 * (size_t)pl->partials_len);
+  pl->off_partials64 = take(8 * (size_t)pl->partials_len);
   pl->off_hist = take(4 * (size_t)pl->hist_len);
   // pairs: the prefix pass's [0, prefix_cap), then the capacity (the only pass, or the rest)
   const size_t slots = (size_t)(pl->prefix_cap + capacity);
@@ -174,6 +178,9 @@ gb_status make_plan(int32_t P, int32_t N, const gb_view* views, int32_t n_views,
   pl->off_open_bits = take(sp * 4 * (size_t)((tiles + 31) / 32));
   pl->off_count_rest = take(sp * 4 * (size_t)VP);
   pl->off_offsets_rest = take(sp * 4 * (size_t)VP);
+  pl->n_chunks = (sort_cap + kChunkSlots - 1) / kChunkSlots + 1;
+  pl->off_chunk_owner = take(4 * (size_t)pl->n_chunks);
+  pl->off_sat = take(sp * 4 * (size_t)pl->sat_len);
   pl->total = off;
   return GB_OK;
 }
@@ -324,9 +331,9 @@ gb_status gb_count_pairs(const gb_splats* s, const gb_view* views, int32_t n_vie
   hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
   if ((st = run_preprocess(s, views, n_views, o, ws, pl, hs)) != GB_OK) return st;
   Status* d_st = at<Status>(ws, pl.off_status);
-  GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&d_st->K64), 0u, 2, hs), "clear count");
   GBB_TRY(launch_scan_u32(at<uint32_t>(ws, pl.off_count), nullptr, at<uint32_t>(ws, pl.off_offsets),
-                          pl.VP, at<uint32_t>(ws, pl.off_partials), &d_st->K, &d_st->K64, hs),
+                          pl.VP, at<uint32_t>(ws, pl.off_partials), &d_st->K, &d_st->K64,
+                          at<unsigned long long>(ws, pl.off_partials64), hs),
           "count scan");
   Status h;
   GBB_TRY(hipMemcpyAsync(&h, d_st, sizeof(Status), hipMemcpyDeviceToHost, hs), "read count");
@@ -372,18 +379,20 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   GBB_TRY(stage_mark(kStDepthSort, 1, hs), "timing");
   // tile counts in depth order -> pair offsets and K; with the split, the prefix cut
   GBB_TRY(stage_mark(kStPairScan, 0, hs), "timing");
-  GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&d_st->K64), 0u, 2, hs), "clear count");
-  GBB_TRY(launch_scan_u32(count, order, offsets, pl.VP, partials, &d_st->K, &d_st->K64, hs),
+  uint32_t* chunk_owner = at<uint32_t>(ws, pl.off_chunk_owner);
+  unsigned long long* partials64 = at<unsigned long long>(ws, pl.off_partials64);
+  GBB_TRY(launch_scan_u32(count, order, offsets, pl.VP, partials, &d_st->K, &d_st->K64,
+                          partials64, hs, chunk_owner, pl.n_chunks),
           "pair scan");
-  GBB_TRY(launch_finalize_count(d_st, pl.capacity, hs), "finalize count");
+  GBB_TRY(launch_finalize_count(offsets, pl.VP, d_st, pl.capacity, hs), "finalize count");
   if (pl.split)
     GBB_TRY(launch_prefix_cut(offsets, pl.VP, pl.prefix_cap, d_st, hs), "prefix cut");
   GBB_TRY(stage_mark(kStPairScan, 1, hs), "timing");
   // first (or only) pass: pairs of the depth prefix, sorted by tile, ranges, blend
   const int64_t cap_a = pl.split ? pl.prefix_cap : pl.capacity;
   GBB_TRY(stage_mark(kStDuplicate, 0, hs), "timing");
-  GBB_TRY(launch_duplicate(order, count, offsets, rec, d_views, pl.VP,
-                           pl.split ? &d_st->cut : nullptr, pl.tile_w, pl.tile_h, d_st, pk, pv, hs),
+  GBB_TRY(launch_duplicate(order, count, offsets, chunk_owner, rec, d_views, pl.tile_w, pl.tile_h,
+                           d_st, cap_a, pk, pv, hs),
           "duplicate");
   GBB_TRY(stage_mark(kStDuplicate, 1, hs), "timing");
   GBB_TRY(stage_mark(kStTileSort, 0, hs), "timing");
@@ -419,18 +428,19 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   uint32_t* pv_r = pv + pl.prefix_cap;
   uint32_t* pk_ra = pk_a + pl.prefix_cap;
   uint32_t* pv_ra = pv_a + pl.prefix_cap;
+  uint32_t* sat = at<uint32_t>(ws, pl.off_sat);
   GBB_TRY(stage_mark(kStRestTiles, 0, hs), "timing");
-  GBB_TRY(launch_count_rest(order, count, rec, d_views, pl.VP, pl.tile_w, pl.tile_h, d_st,
-                            split.open_bits, count_rest, hs),
+  GBB_TRY(launch_open_sat(d_views, n_views, split.open_bits, sat, hs), "open-tile table");
+  GBB_TRY(launch_count_rest(order, count, rec, d_views, pl.VP, pl.tile_w, pl.tile_h, d_st, sat,
+                            count_rest, hs),
           "rest count");
-  GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&d_st->K_rest64), 0u, 2, hs),
-          "clear rest count");
   GBB_TRY(launch_scan_u32(count_rest, nullptr, offsets_rest, pl.VP, partials, &d_st->K_rest,
-                          &d_st->K_rest64, hs),
+                          &d_st->K_rest64, partials64, hs, chunk_owner, pl.n_chunks),
           "rest scan");
-  GBB_TRY(launch_finalize_rest(d_st, hs), "rest finalize");
-  GBB_TRY(launch_duplicate_rest(order, count_rest, offsets_rest, rec, d_views, pl.VP, pl.tile_w,
-                                pl.tile_h, d_st, split.open_bits, pk_r, pv_r, hs),
+  GBB_TRY(launch_finalize_rest(offsets_rest, pl.VP, d_st, hs), "rest finalize");
+  GBB_TRY(launch_duplicate_rest(order, count_rest, offsets_rest, chunk_owner, rec, d_views,
+                                pl.tile_w, pl.tile_h, d_st, split.open_bits, sat, pl.capacity,
+                                pk_r, pv_r, hs),
           "rest duplicate");
   GBB_TRY(launch_radix_sort(pk_r, pv_r, pk_ra, pv_ra, &d_st->n_rest, pl.capacity, pl.tile_bits,
                             hist, partials, hs),

@@ -23,7 +23,7 @@ struct ViewDev {
   int32_t W, H, tiles_x, tiles_y;
   int32_t tile_base;   // first global tile index of this view
   int32_t pix_base;    // first packed pixel index of this view
-  int32_t pad;
+  int32_t sat_base;    // first entry of this view's (tiles_y + 1) x (tiles_x + 1) open-tile table
 };
 static_assert(sizeof(ViewDev) == 96, "ViewDev layout");
 
@@ -57,6 +57,8 @@ struct Status {
   uint32_t n_rest;     // pairs emitted and sorted by the second pass (open tiles only)
   uint32_t K_rest;     // 32-bit scan total of the second pass
   unsigned long long K_rest64;  // exact total of the second pass
+  uint32_t last_first; // depth rank of the record owning the first pass's last pair slot
+  uint32_t last_rest;  // the same for the second pass
 };
 
 // Depth-prefix split. The first pass renders the records of a prefix of the depth order
@@ -96,8 +98,11 @@ struct Plan {
   size_t off_status, off_views, off_depth_key, off_depth_key_alt, off_order, off_order_alt,
       off_count, off_offsets, off_rec, off_partials, off_hist, off_pair_keys, off_pair_vals,
       off_pair_keys_alt, off_pair_vals_alt, off_ranges, off_n_last, off_drec, off_stats,
+      off_partials64,
       off_ranges_rest, off_n_last_rest, off_fwd_state, off_open_bits,
-      off_count_rest, off_offsets_rest, total;
+      off_count_rest, off_offsets_rest, off_chunk_owner, off_sat, total;
+  int64_t n_chunks;  // entries of the chunk-owner table
+  int64_t sat_len;   // entries of the open-tile summed-area tables of all views
   int64_t partials_len, hist_len;
 };
 
@@ -114,42 +119,65 @@ hipError_t launch_preprocess(const gb_splats& sp, const ViewDev* d_views, int n_
                              uint32_t* sort_key, uint32_t* count, SplatRec* rec, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
 hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t s);
+// Pair slots per chunk of the duplicate kernels (one workgroup round).
+constexpr int kChunkSlots = 1024;
+
+// Optional device-side length of a scan: ceil(*d_count / per) * mult elements (never more
+// than the host-side n, which sizes the launch).
+struct ScanLen {
+  const uint32_t* d_count = nullptr;
+  int64_t per = 1, mult = 1;
+};
+
 // Exclusive scan of n u32 values (optionally gathered in[gather[i]]) in 32-bit arithmetic;
 // writes out and, if total != nullptr, the sum to *total. If total64 != nullptr the exact
-// 64-bit sum is added to *total64 (which the caller clears). partials needs
+// 64-bit sum is written to *total64 (partials64 then holds per-block sums). With chunk_owner,
+// the index of the element whose run [prefix, prefix + value) holds slot c * kChunkSlots is
+// written to chunk_owner[c] for c < n_chunks. partials and partials64 need
 // ceil(n / kScanTile) + 1 entries.
 hipError_t launch_scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t n,
                            uint32_t* partials, uint32_t* total, unsigned long long* total64,
-                           hipStream_t s);
+                           unsigned long long* partials64, hipStream_t s,
+                           uint32_t* chunk_owner = nullptr, int64_t n_chunks = 0,
+                           ScanLen len = ScanLen());
 // Stable LSD radix sort of (key, value) pairs on bits [0, bits). The element count is
-// read from *d_n on the device (at most n_cap). Buffers ping-pong; the result is written
-// back to keys/vals. hist needs 256 * ceil(n_cap / kRadixTile) entries.
+// read from *d_n on the device (at most n_cap); the work of every kernel follows that count,
+// the launch sizes follow n_cap. Buffers ping-pong; the result is written back to keys/vals.
+// hist needs 256 * ceil(n_cap / kRadixTile) entries.
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                              uint32_t* vals_alt, const uint32_t* d_n, int64_t n_cap, int bits,
                              uint32_t* hist, uint32_t* partials, hipStream_t s);
-hipError_t launch_finalize_count(Status* st, int64_t capacity, hipStream_t s);
+hipError_t launch_finalize_count(const uint32_t* offsets, int64_t VP, Status* st,
+                                 int64_t capacity, hipStream_t s);
 // Depth-prefix cut: the largest record count (in depth order) whose pairs fit `budget`.
 // Writes st->cut and st->n_sorted (the prefix's pairs); nothing on overflow.
 hipError_t launch_prefix_cut(const uint32_t* offsets, int64_t VP, int64_t budget, Status* st,
                              hipStream_t s);
-// Pairs of the first pass: records [0, *d_nrec) of the depth order (all VP if d_nrec is null).
+// Pairs of the first pass: the st->n_sorted slots of the depth order's offsets, expanded in
+// chunks of kChunkSlots (chunk_owner from the offset scan); cap bounds the slot count.
 hipError_t launch_duplicate(const uint32_t* order, const uint32_t* count,
-                            const uint32_t* offsets, const SplatRec* rec, const ViewDev* views,
-                            int64_t VP, const uint32_t* d_nrec, int tile_w, int tile_h,
-                            const Status* st, uint32_t* pair_keys, uint32_t* pair_vals,
-                            hipStream_t s);
+                            const uint32_t* offsets, const uint32_t* chunk_owner,
+                            const SplatRec* rec, const ViewDev* views, int tile_w, int tile_h,
+                            const Status* st, int64_t cap, uint32_t* pair_keys,
+                            uint32_t* pair_vals, hipStream_t s);
 // Second pass: count_rest[r] = open tiles covered by the record at depth rank r >= st->cut.
 hipError_t launch_count_rest(const uint32_t* order, const uint32_t* count, const SplatRec* rec,
                              const ViewDev* views, int64_t VP, int tile_w, int tile_h,
-                             const Status* st, const uint32_t* open_bits, uint32_t* count_rest,
+                             const Status* st, const uint32_t* sat, uint32_t* count_rest,
                              hipStream_t s);
-hipError_t launch_finalize_rest(Status* st, hipStream_t s);
+hipError_t launch_finalize_rest(const uint32_t* offsets_rest, int64_t VP, Status* st,
+                                hipStream_t s);
+// Summed-area tables of the open-tile bitmap, one per view: sat[y][x] = open tiles in rows
+// below y and columns below x (row stride tiles_x + 1).
+hipError_t launch_open_sat(const ViewDev* views, int n_views, const uint32_t* open_bits,
+                           uint32_t* sat, hipStream_t s);
 // Second pass pairs: (open tile, record) for every record at rank >= st->cut, in depth order.
 hipError_t launch_duplicate_rest(const uint32_t* order, const uint32_t* count_rest,
-                                 const uint32_t* offsets_rest, const SplatRec* rec,
-                                 const ViewDev* views, int64_t VP, int tile_w, int tile_h,
-                                 const Status* st, const uint32_t* open_bits,
-                                 uint32_t* pair_keys, uint32_t* pair_vals, hipStream_t s);
+                                 const uint32_t* offsets_rest, const uint32_t* chunk_owner,
+                                 const SplatRec* rec, const ViewDev* views, int tile_w,
+                                 int tile_h, const Status* st, const uint32_t* open_bits,
+                                 const uint32_t* sat, int64_t cap, uint32_t* pair_keys,
+                                 uint32_t* pair_vals, hipStream_t s);
 // Tile ranges of the first *d_n sorted keys.
 hipError_t launch_ranges(const uint32_t* pair_keys, const uint32_t* d_n, int64_t n_cap,
                          uint32_t* ranges, hipStream_t s);

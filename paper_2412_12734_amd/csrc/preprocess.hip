@@ -24,6 +24,7 @@ struct ViewChunk {
   gb_view v[8];
   int32_t tile_base[8];
   int32_t pix_base[8];
+  int32_t sat_base[8];
   int32_t count;
   int32_t first;
 };
@@ -46,7 +47,7 @@ __global__ void upload_views_kernel(ViewChunk c, int tile_w, int tile_h, ViewDev
   d.tiles_y = (v.height + tile_h - 1) / tile_h;
   d.tile_base = c.tile_base[i];
   d.pix_base = c.pix_base[i];
-  d.pad = 0;
+  d.sat_base = c.sat_base[i];
   out[c.first + i] = d;
 }
 
@@ -216,7 +217,7 @@ preprocess_kernel(const float* __restrict__ means, const float* __restrict__ tan
 
 hipError_t launch_upload_views(const gb_view* views, int n_views, int tile_w, int tile_h,
                                ViewDev* d_views, hipStream_t s) {
-  int tile_base = 0, pix_base = 0;
+  int tile_base = 0, pix_base = 0, sat_base = 0;
   for (int first = 0; first < n_views; first += 8) {
     ViewChunk c;
     c.count = n_views - first < 8 ? n_views - first : 8;
@@ -226,6 +227,9 @@ hipError_t launch_upload_views(const gb_view* views, int n_views, int tile_w, in
       c.v[i] = v;
       c.tile_base[i] = tile_base;
       c.pix_base[i] = pix_base;
+      c.sat_base[i] = sat_base;
+      const int tx = (v.width + tile_w - 1) / tile_w, ty = (v.height + tile_h - 1) / tile_h;
+      sat_base += (tx + 1) * (ty + 1);
       tile_base += ((v.width + tile_w - 1) / tile_w) * ((v.height + tile_h - 1) / tile_h);
       pix_base += v.width * v.height;
     }

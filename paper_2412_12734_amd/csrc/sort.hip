@@ -50,13 +50,22 @@ __device__ __forceinline__ uint32_t scan_load(const uint32_t* in, const uint32_t
   return in[i];
 }
 
+__device__ __forceinline__ int64_t scan_len(int64_t n, const ScanLen& L) {
+  if (!L.d_count) return n;
+  const int64_t m = ((int64_t)*L.d_count + L.per - 1) / L.per * L.mult;
+  return m < n ? m : n;
+}
+
 template <bool GATHER>
 __global__ void __launch_bounds__(kThreads)
 scan_reduce_kernel(const uint32_t* __restrict__ in, const uint32_t* __restrict__ gather,
-                   int64_t n, uint32_t* __restrict__ partials,
-                   unsigned long long* __restrict__ total64) {
+                   int64_t n_cap, ScanLen L, uint32_t* __restrict__ partials,
+                   unsigned long long* __restrict__ partials64) {
   __shared__ uint32_t wave_tot[4];
+  __shared__ unsigned long long wave_tot64[4];
+  const int64_t n = scan_len(n_cap, L);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  if (base >= n && base > 0) return;
   uint32_t s = 0;
   unsigned long long s64 = 0;
 #pragma unroll 4
@@ -68,22 +77,45 @@ scan_reduce_kernel(const uint32_t* __restrict__ in, const uint32_t* __restrict__
       s64 += x;
     }
   }
-  if (total64) {
-    // exact sum: wave reduction in 64 bits, one global atomic per wave
+  if (partials64) {
+    // exact block sum in 64 bits (the partials kernel adds the blocks up)
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) s64 += __shfl_xor(s64, d, 64);
-    if ((threadIdx.x & 63) == 0) atomicAdd(total64, s64);
+    if ((threadIdx.x & 63) == 0) wave_tot64[threadIdx.x >> 6] = s64;
   }
   uint32_t total;
-  block_inclusive_scan(s, wave_tot, &total);
-  if (threadIdx.x == 0) partials[blockIdx.x] = total;
+  block_inclusive_scan(s, wave_tot, &total);  // its barriers also publish wave_tot64
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = total;
+    if (partials64)
+      partials64[blockIdx.x] = (wave_tot64[0] + wave_tot64[1]) + (wave_tot64[2] + wave_tot64[3]);
+  }
 }
 
 // One workgroup: exclusive scan of partials[0..nb) in place, total to partials[nb] and *total.
 __global__ void __launch_bounds__(1024)
-scan_partials_kernel(uint32_t* __restrict__ partials, int64_t nb, uint32_t* __restrict__ total) {
+scan_partials_kernel(uint32_t* __restrict__ partials, int64_t n_cap, ScanLen L,
+                     uint32_t* __restrict__ total,
+                     const unsigned long long* __restrict__ partials64,
+                     unsigned long long* __restrict__ total64) {
   __shared__ uint32_t wave_tot[16];
   __shared__ uint32_t carry_s;
+  __shared__ unsigned long long wave_sum64[16];
+  const int64_t n = scan_len(n_cap, L);
+  const int64_t nb = n > 0 ? (n + kScanTile - 1) / kScanTile : 1;
+  if (total64) {
+    unsigned long long s64 = 0;
+    for (int64_t i = threadIdx.x; i < nb; i += 1024) s64 += partials64[i];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s64 += __shfl_xor(s64, d, 64);
+    if ((threadIdx.x & 63) == 0) wave_sum64[threadIdx.x >> 6] = s64;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long t = 0;
+      for (int k = 0; k < 16; ++k) t += wave_sum64[k];
+      *total64 = t;
+    }
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (threadIdx.x == 0) carry_s = 0;
   __syncthreads();
@@ -120,13 +152,20 @@ scan_partials_kernel(uint32_t* __restrict__ partials, int64_t nb, uint32_t* __re
 // patterns below are free of bank conflicts.
 __device__ __forceinline__ int pad_idx(int i) { return i + (i >> 5); }
 
+// With chunk_owner, element i with value x > 0 and exclusive prefix o also records itself as
+// the owner of every chunk of kChunkSlots slots that starts inside [o, o + x) (chunk indices
+// below n_chunks).
 template <bool GATHER>
 __global__ void __launch_bounds__(kThreads)
-scan_down_kernel(const uint32_t* __restrict__ in, const uint32_t* __restrict__ gather, int64_t n,
-                 const uint32_t* __restrict__ partials, uint32_t* __restrict__ out) {
+scan_down_kernel(const uint32_t* __restrict__ in, const uint32_t* __restrict__ gather,
+                 int64_t n_cap, ScanLen L, const uint32_t* __restrict__ partials,
+                 uint32_t* __restrict__ out, uint32_t* __restrict__ chunk_owner,
+                 int64_t n_chunks) {
   __shared__ uint32_t tile[kScanTile + kScanTile / 32];
   __shared__ uint32_t wave_tot[4];
+  const int64_t n = scan_len(n_cap, L);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  if (base >= n) return;
   // coalesced load into LDS, then each thread owns 16 consecutive elements
 #pragma unroll 4
   for (int k = 0; k < kItems; ++k) {
@@ -147,6 +186,13 @@ scan_down_kernel(const uint32_t* __restrict__ in, const uint32_t* __restrict__ g
   for (int k = 0; k < kItems; ++k) {
     uint32_t x = loc[k];
     loc[k] = run;
+    if (chunk_owner && x > 0) {
+      const int64_t i = base + threadIdx.x * kItems + k;
+      const uint64_t o = run, e = (uint64_t)run + x;
+      for (uint64_t c = (o + kChunkSlots - 1) / kChunkSlots;
+           c * kChunkSlots < e && (int64_t)c < n_chunks; ++c)
+        chunk_owner[c] = (uint32_t)i;
+    }
     run += x;
   }
 #pragma unroll
@@ -160,13 +206,11 @@ scan_down_kernel(const uint32_t* __restrict__ in, const uint32_t* __restrict__ g
 }
 
 // ---- radix sort --------------------------------------------------------------------------
-// Workgroups are dealt to the 8 XCDs round-robin; tile t of a pass is handled by the block
-// that puts consecutive tiles on one XCD, so the per-tile digit counts (stored digit-major,
-// one column per tile) fill whole cache lines in that XCD's L2.
-__device__ __forceinline__ int64_t radix_tile_of_block(int64_t nb) {
-  const int64_t per_xcd = (nb + 7) / 8;
-  return (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-}
+// A pass works on tiles of kRadixTile elements; the tile count follows the device-side
+// element count, and workgroups take tiles in turn (at most kRadixGrid workgroups), so a
+// short sort in a large buffer costs what its elements cost. Digit counts are stored
+// digit-major, one column per tile.
+constexpr int kRadixGrid = 2048;
 
 __device__ __forceinline__ int64_t sort_count(const uint32_t* d_n, int64_t n_cap) {
   if (!d_n) return n_cap;
@@ -180,49 +224,51 @@ __device__ __forceinline__ int64_t sort_count(const uint32_t* d_n, int64_t n_cap
 template <int NBITS>
 __global__ void __launch_bounds__(kRadixThreads)
 radix_hist_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ d_n,
-                  int64_t n_cap, int shift, int64_t nb, uint32_t* __restrict__ hist) {
+                  int64_t n_cap, int shift, uint32_t* __restrict__ hist) {
   constexpr int kBins = 1 << NBITS;
   constexpr uint32_t kMask = (uint32_t)kBins - 1u;
   constexpr int kWaves = kRadixThreads / 64;
   __shared__ uint32_t h[kWaves][kBins];
   const int64_t n = sort_count(d_n, n_cap);
-  const int64_t tile = radix_tile_of_block(nb);
-  if (tile >= nb) return;
+  const int64_t nb = (n + kRadixTile - 1) / kRadixTile;
   const int w = threadIdx.x >> 6;
-  for (int i = threadIdx.x; i < kWaves * kBins; i += kRadixThreads) (&h[0][0])[i] = 0;
-  __syncthreads();
-  const int64_t base = tile * kRadixTile;
-  if (base < n) {
-    const int nvalid = (int)((n - base) < kRadixTile ? (n - base) : kRadixTile);
-    const uint32_t* kt = keys + base;
-    uint4 q[kRadixItems / 4];
+  for (int64_t tile = blockIdx.x; tile < nb; tile += gridDim.x) {
+    for (int i = threadIdx.x; i < kWaves * kBins; i += kRadixThreads) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t base = tile * kRadixTile;
+    {
+      const int nvalid = (int)((n - base) < kRadixTile ? (n - base) : kRadixTile);
+      const uint32_t* kt = keys + base;
+      uint4 q[kRadixItems / 4];
 #pragma unroll
-    for (int k = 0; k < kRadixItems / 4; ++k) {
-      const int i = 4 * (k * kRadixThreads + threadIdx.x);
-      if (i + 3 < nvalid) {
-        q[k] = *reinterpret_cast<const uint4*>(kt + i);
-      } else {
-        q[k].x = i < nvalid ? kt[i] : 0u;
-        q[k].y = i + 1 < nvalid ? kt[i + 1] : 0u;
-        q[k].z = i + 2 < nvalid ? kt[i + 2] : 0u;
-        q[k].w = 0u;
+      for (int k = 0; k < kRadixItems / 4; ++k) {
+        const int i = 4 * (k * kRadixThreads + threadIdx.x);
+        if (i + 3 < nvalid) {
+          q[k] = *reinterpret_cast<const uint4*>(kt + i);
+        } else {
+          q[k].x = i < nvalid ? kt[i] : 0u;
+          q[k].y = i + 1 < nvalid ? kt[i + 1] : 0u;
+          q[k].z = i + 2 < nvalid ? kt[i + 2] : 0u;
+          q[k].w = 0u;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kRadixItems / 4; ++k) {
+        const int i = 4 * (k * kRadixThreads + threadIdx.x);
+        if (i < nvalid) atomicAdd(&h[w][(q[k].x >> shift) & kMask], 1u);
+        if (i + 1 < nvalid) atomicAdd(&h[w][(q[k].y >> shift) & kMask], 1u);
+        if (i + 2 < nvalid) atomicAdd(&h[w][(q[k].z >> shift) & kMask], 1u);
+        if (i + 3 < nvalid) atomicAdd(&h[w][(q[k].w >> shift) & kMask], 1u);
       }
     }
+    __syncthreads();
+    for (int d = threadIdx.x; d < kBins; d += kRadixThreads) {
+      uint32_t c = 0;
 #pragma unroll
-    for (int k = 0; k < kRadixItems / 4; ++k) {
-      const int i = 4 * (k * kRadixThreads + threadIdx.x);
-      if (i < nvalid) atomicAdd(&h[w][(q[k].x >> shift) & kMask], 1u);
-      if (i + 1 < nvalid) atomicAdd(&h[w][(q[k].y >> shift) & kMask], 1u);
-      if (i + 2 < nvalid) atomicAdd(&h[w][(q[k].z >> shift) & kMask], 1u);
-      if (i + 3 < nvalid) atomicAdd(&h[w][(q[k].w >> shift) & kMask], 1u);
+      for (int ww = 0; ww < kWaves; ++ww) c += h[ww][d];
+      hist[(int64_t)d * nb + tile] = c;
     }
-  }
-  __syncthreads();
-  for (int d = threadIdx.x; d < kBins; d += kRadixThreads) {
-    uint32_t c = 0;
-#pragma unroll
-    for (int ww = 0; ww < kWaves; ++ww) c += h[ww][d];
-    hist[(int64_t)d * nb + tile] = c;
+    __syncthreads();  // the next tile reuses the LDS histograms
   }
 }
 
@@ -230,7 +276,7 @@ template <int NBITS>
 __global__ void __launch_bounds__(kRadixThreads)
 radix_scatter_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
                      uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
-                     const uint32_t* __restrict__ d_n, int64_t n_cap, int shift, int64_t nb,
+                     const uint32_t* __restrict__ d_n, int64_t n_cap, int shift,
                      const uint32_t* __restrict__ hist_scanned) {
   constexpr int kBins = 1 << NBITS;
   constexpr uint32_t kMask = (uint32_t)kBins - 1u;
@@ -243,78 +289,80 @@ radix_scatter_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __res
   __shared__ uint32_t s_gofs[kBins];  // output index of the tile's element 0 of each digit
   __shared__ uint32_t wave_tot[4];
   const int64_t n = sort_count(d_n, n_cap);
-  const int64_t tile = radix_tile_of_block(nb);
-  const int64_t base = tile * kRadixTile;
-  if (tile >= nb || base >= n) return;
-  const int nvalid = (int)((n - base) < kRadixTile ? (n - base) : kRadixTile);
+  const int64_t nb = (n + kRadixTile - 1) / kRadixTile;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  // where each digit of this tile starts in the output (loaded early, used at the end)
-  const uint32_t gstart = tid < kBins ? hist_scanned[(int64_t)tid * nb + tile] : 0u;
+  for (int64_t tile = blockIdx.x; tile < nb; tile += gridDim.x) {
+    const int64_t base = tile * kRadixTile;
+    const int nvalid = (int)((n - base) < kRadixTile ? (n - base) : kRadixTile);
+    // where each digit of this tile starts in the output (loaded early, used at the end)
+    const uint32_t gstart = tid < kBins ? hist_scanned[(int64_t)tid * nb + tile] : 0u;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) s_cnt[w][lane + 64 * k] = 0;
-  __builtin_amdgcn_wave_barrier();
-  // Each wave ranks its own contiguous quarter of the tile in rounds of 64 elements; program
-  // order inside the wave keeps equal digits in index order.
-  uint32_t key_r[kRadixItems], val_r[kRadixItems], rank_r[kRadixItems];
-  // all loads first (memory-level parallelism)
+    for (int k = 0; k < 4; ++k) s_cnt[w][lane + 64 * k] = 0;
+    __builtin_amdgcn_wave_barrier();
+    // Each wave ranks its own contiguous quarter of the tile in rounds of 64 elements; program
+    // order inside the wave keeps equal digits in index order.
+    uint32_t key_r[kRadixItems], val_r[kRadixItems], rank_r[kRadixItems];
+    // all loads first (memory-level parallelism)
 #pragma unroll
-  for (int r = 0; r < kRadixItems; ++r) {
-    const int i = w * kPerWave + r * 64 + lane;
-    const bool valid = i < nvalid;
-    key_r[r] = valid ? keys_in[base + i] : 0u;
-    val_r[r] = valid ? vals_in[base + i] : 0u;
-  }
-#pragma unroll
-  for (int r = 0; r < kRadixItems; ++r) {
-    const int i = w * kPerWave + r * 64 + lane;
-    const bool valid = i < nvalid;
-    const uint32_t d = (key_r[r] >> shift) & kMask;
-    // lanes holding the same digit: one ballot per digit bit
-    uint64_t m = ballot(valid);
-#pragma unroll
-    for (int bit = 0; bit < NBITS; ++bit) {
-      const bool set = (d >> bit) & 1u;
-      const uint64_t b = ballot(set);
-      m &= set ? b : ~b;
+    for (int r = 0; r < kRadixItems; ++r) {
+      const int i = w * kPerWave + r * 64 + lane;
+      const bool valid = i < nvalid;
+      key_r[r] = valid ? keys_in[base + i] : 0u;
+      val_r[r] = valid ? vals_in[base + i] : 0u;
     }
-    const uint32_t below = mbcnt(m);
-    const uint32_t cnt = s_cnt[w][d];
-    __builtin_amdgcn_wave_barrier();
-    if (valid && below == 0) s_cnt[w][d] = cnt + popc64(m);
-    __builtin_amdgcn_wave_barrier();
-    rank_r[r] = cnt + below;
-  }
-  __syncthreads();
-  // digit totals of the tile, offsets of each wave inside a digit, digit starts
-  uint32_t tot = 0;
 #pragma unroll
-  for (int ww = 0; ww < kWaves; ++ww) {
-    const uint32_t c = s_cnt[ww][tid];
-    s_cnt[ww][tid] = tot;
-    tot += c;
-  }
-  uint32_t total;
-  const uint32_t incl = block_inclusive_scan(tot, wave_tot, &total);
-  s_start[tid] = incl - tot;
-  // element counts fit in 32 bits, so output indices do too
-  if (tid < kBins) s_gofs[tid] = gstart - (incl - tot);
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < kRadixItems; ++r) {
-    const int i = w * kPerWave + r * 64 + lane;
-    if (i < nvalid) {
+    for (int r = 0; r < kRadixItems; ++r) {
+      const int i = w * kPerWave + r * 64 + lane;
+      const bool valid = i < nvalid;
       const uint32_t d = (key_r[r] >> shift) & kMask;
-      const uint32_t pos = s_start[d] + s_cnt[w][d] + rank_r[r];
-      s_keys[pos] = key_r[r];
-      s_vals[pos] = val_r[r];
+      // lanes holding the same digit: one ballot per digit bit
+      uint64_t m = ballot(valid);
+#pragma unroll
+      for (int bit = 0; bit < NBITS; ++bit) {
+        const bool set = (d >> bit) & 1u;
+        const uint64_t b = ballot(set);
+        m &= set ? b : ~b;
+      }
+      const uint32_t below = mbcnt(m);
+      const uint32_t cnt = s_cnt[w][d];
+      __builtin_amdgcn_wave_barrier();
+      if (valid && below == 0) s_cnt[w][d] = cnt + popc64(m);
+      __builtin_amdgcn_wave_barrier();
+      rank_r[r] = cnt + below;
     }
-  }
-  __syncthreads();
-  for (int i = tid; i < nvalid; i += kRadixThreads) {
-    const uint32_t key = s_keys[i];
-    const uint32_t gpos = s_gofs[(key >> shift) & kMask] + (uint32_t)i;
-    keys_out[gpos] = key;
-    vals_out[gpos] = s_vals[i];
+    __syncthreads();
+    // digit totals of the tile, offsets of each wave inside a digit, digit starts
+    uint32_t tot = 0;
+#pragma unroll
+    for (int ww = 0; ww < kWaves; ++ww) {
+      const uint32_t c = s_cnt[ww][tid];
+      s_cnt[ww][tid] = tot;
+      tot += c;
+    }
+    uint32_t total;
+    const uint32_t incl = block_inclusive_scan(tot, wave_tot, &total);
+    s_start[tid] = incl - tot;
+    // element counts fit in 32 bits, so output indices do too
+    if (tid < kBins) s_gofs[tid] = gstart - (incl - tot);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRadixItems; ++r) {
+      const int i = w * kPerWave + r * 64 + lane;
+      if (i < nvalid) {
+        const uint32_t d = (key_r[r] >> shift) & kMask;
+        const uint32_t pos = s_start[d] + s_cnt[w][d] + rank_r[r];
+        s_keys[pos] = key_r[r];
+        s_vals[pos] = val_r[r];
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < nvalid; i += kRadixThreads) {
+      const uint32_t key = s_keys[i];
+      const uint32_t gpos = s_gofs[(key >> shift) & kMask] + (uint32_t)i;
+      keys_out[gpos] = key;
+      vals_out[gpos] = s_vals[i];
+    }
+    __syncthreads();  // the next tile reuses the LDS
   }
 }
 
@@ -364,22 +412,26 @@ hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t s) {
 
 hipError_t launch_scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t n,
                            uint32_t* partials, uint32_t* total, unsigned long long* total64,
-                           hipStream_t s) {
+                           unsigned long long* partials64, hipStream_t s,
+                           uint32_t* chunk_owner, int64_t n_chunks, ScanLen len) {
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
   if (nb == 0) return hipSuccess;
+  if (!total64) partials64 = nullptr;
+  if (total64 && !partials64) return hipErrorInvalidValue;
   if (gather)
     hipLaunchKernelGGL(scan_reduce_kernel<true>, dim3((unsigned)nb), dim3(kThreads), 0, s, in,
-                       gather, n, partials, total64);
+                       gather, n, len, partials, partials64);
   else
     hipLaunchKernelGGL(scan_reduce_kernel<false>, dim3((unsigned)nb), dim3(kThreads), 0, s, in,
-                       gather, n, partials, total64);
-  hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, s, partials, nb, total);
+                       gather, n, len, partials, partials64);
+  hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, s, partials, n, len, total,
+                     partials64, total64);
   if (gather)
     hipLaunchKernelGGL(scan_down_kernel<true>, dim3((unsigned)nb), dim3(kThreads), 0, s, in,
-                       gather, n, partials, out);
+                       gather, n, len, partials, out, chunk_owner, n_chunks);
   else
     hipLaunchKernelGGL(scan_down_kernel<false>, dim3((unsigned)nb), dim3(kThreads), 0, s, in,
-                       gather, n, partials, out);
+                       gather, n, len, partials, out, chunk_owner, n_chunks);
   return hipGetLastError();
 }
 
@@ -387,14 +439,16 @@ template <int NBITS>
 hipError_t radix_pass(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo,
                       const uint32_t* d_n, int64_t n_cap, int shift, int64_t nb, uint32_t* hist,
                       uint32_t* partials, hipStream_t s) {
-  const unsigned grid = (unsigned)(8 * ((nb + 7) / 8));
+  const unsigned grid = (unsigned)(nb < kRadixGrid ? nb : kRadixGrid);
   hipLaunchKernelGGL(radix_hist_kernel<NBITS>, dim3(grid), dim3(kRadixThreads), 0, s, ki, d_n,
-                     n_cap, shift, nb, hist);
+                     n_cap, shift, hist);
+  ScanLen len;
+  if (d_n) len = ScanLen{d_n, kRadixTile, (int64_t)1 << NBITS};
   hipError_t e = launch_scan_u32(hist, nullptr, hist, ((int64_t)1 << NBITS) * nb, partials,
-                                 nullptr, nullptr, s);
+                                 nullptr, nullptr, nullptr, s, nullptr, 0, len);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(radix_scatter_kernel<NBITS>, dim3(grid), dim3(kRadixThreads), 0, s, ki, vi,
-                     ko, vo, d_n, n_cap, shift, nb, hist);
+                     ko, vo, d_n, n_cap, shift, hist);
   return hipGetLastError();
 }
 
