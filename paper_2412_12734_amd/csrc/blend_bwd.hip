@@ -161,7 +161,8 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   const int tile_y0 = (lt / V.tiles_x) * p.tile_h;
 
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int w = tid >> 6, lane = tid & 63;
+  // the wave index is uniform: keep it (and the wave block's geometry) in scalar registers
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int waves_x = p.tile_w >> 3;
   const int bx = (w % waves_x) * 8, by = (w / waves_x) * BH;
   const int lxi = bx + (lane & 7);
@@ -218,16 +219,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
     __syncthreads();  // every thread has read the previous list's bound
     if (tid == 0) s_tile_last = start;
     __syncthreads();
-    {
-      // largest bound over the tile's pixels
-      uint32_t m = lane_last;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_xor(m, d, 64);
-        m = o > m ? o : m;
-      }
-      if (lane == 0) atomicMax(&s_tile_last, m);
-    }
+    atomicMax(&s_tile_last, lane_last);  // largest bound over the tile's pixels
     __syncthreads();
     const uint32_t tile_last = s_tile_last;
 

@@ -13,6 +13,7 @@ struct BlendParams {
   float tex_offset;   // (N - 1) / 2
   float sigma;
   float alpha_min, alpha_max, t_min;
+  float cull_alpha;   // 0.99 alpha_min: the per-wave cull's margin below alpha_min
   float lp_scale;     // 1 / (2 lowpass_var)
   float bg[3];
   int32_t tile_w, tile_h;
@@ -191,7 +192,7 @@ __device__ __forceinline__ bool block_may_contribute(const StagedGeo& s, float c
   const float dym = fmaxf(fabsf(cy + s.g2.w) - ey, 0.f);
   const float q_lp = (dxm * dxm + dym * dym) * p.lp_scale;
   const float q = fminf(q_uv, q_lp);
-  return s.g0.w * __builtin_amdgcn_exp2f(-q * 1.4426950408889634f) >= 0.99f * p.alpha_min;
+  return s.g0.w * __builtin_amdgcn_exp2f(-q * 1.4426950408889634f) >= p.cull_alpha;
 }
 
 // Grid coordinate of u on the corner-aligned N-texel grid (Alg. 2 with the cell index taken

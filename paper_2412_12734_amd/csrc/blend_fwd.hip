@@ -43,7 +43,8 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   const int tile_y0 = (lt / V.tiles_x) * p.tile_h;
 
   const int tid = threadIdx.x;
-  const int w = tid >> 6, lane = tid & 63;
+  // the wave index is uniform: keep it (and the wave block's geometry) in scalar registers
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int waves_x = p.tile_w >> 3;
   const int bx = (w % waves_x) * 8, by = (w / waves_x) * 8;
   const int lxi = bx + (lane & 7), lyi = by + (lane >> 3);
@@ -229,6 +230,7 @@ BlendParams make_blend_params(const Plan& pl, const gb_options& o, int n_views) 
   bp.tex_offset = 0.5f * (float)(N - 1);
   bp.sigma = o.sigma;
   bp.alpha_min = o.alpha_min;
+  bp.cull_alpha = 0.99f * o.alpha_min;
   bp.alpha_max = o.alpha_max;
   bp.t_min = o.t_min;
   bp.lp_scale = 1.0f / (2.0f * o.lowpass_var);
