@@ -139,11 +139,17 @@ def make_scene(seed: int, P: int, lo: float, hi: float, s_lo: float, s_hi: float
     tu, tv = quat_to_tangents(q)
     scales = np.exp(rng.uniform(math.log(s_lo), math.log(s_hi), (P, 2)))
     opacity = rng.uniform(op_lo, op_hi, P)
-    textures = rng.uniform(0.0, 1.0, (P, N, N, 3))
+    # textures: the same stream values as one (P, N, N, 3) draw, generated and cast in chunks of
+    # splats so that millions of splats do not need the full float64 array at once
+    tex = np.empty((P, N, N, 3), dtype=np.float32)
+    flat = tex.reshape(P, N * N * 3)
+    step = max(1, (1 << 22) // (N * N * 3))
+    for i in range(0, P, step):
+        part = flat[i:i + step]
+        part[...] = rng.uniform(0.0, 1.0, part.shape)
+        if tex_bf16:
+            part[...] = bf16_bits_to_f32(to_bf16_bits(part)).reshape(part.shape)
     f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
-    tex = f32(textures)
-    if tex_bf16:
-        tex = bf16_bits_to_f32(to_bf16_bits(tex)).reshape(tex.shape)
     return Scene(f32(means), f32(tu), f32(tv), f32(scales), f32(opacity), tex)
 
 

@@ -22,6 +22,11 @@ GRAD_TOL = 1e-3
 # 1e-5 relative, T(1 - alpha) vs t_min within 1e-4) are excluded from the image gate and
 # counted; the gradient gate also zeroes the adjoint at pixels near a gradient kink.
 MAX_FLAGGED_FRACTION = 1e-3
+# Every splat a pixel evaluates is one alpha-versus-alpha_min decision, so the share of pixels
+# with some decision inside the flag band grows with the scene's depth complexity: at 1M splats
+# a pixel evaluates hundreds of splats (a T0 crop flags 8 of 4096 pixels). The cap on the
+# full-size workloads allows for that; real errors show up on the unflagged pixels.
+MAX_FLAGGED_FRACTION_DENSE = 1e-2
 
 
 def _require_gpu():
@@ -61,13 +66,14 @@ def image_crop(arr, base, W, H, crop, ch=3):
     return a[y0:y0 + h, x0:x0 + w]
 
 
-def assert_image_parity(rgb_gpu, T_gpu, ref: O.RenderResult, base, W, H):
+def assert_image_parity(rgb_gpu, T_gpu, ref: O.RenderResult, base, W, H,
+                        max_flagged=MAX_FLAGGED_FRACTION):
     crop = ref.crop
     g_rgb = image_crop(rgb_gpu, base, W, H, crop).astype(np.float64)
     g_T = image_crop(T_gpu, base, W, H, crop, ch=0).astype(np.float64)
     ok = ~O.image_flags(ref)
     flagged = int((~ok).sum())
-    assert flagged <= MAX_FLAGGED_FRACTION * ok.size + 2, f"{flagged} flagged pixels"
+    assert flagged <= max_flagged * ok.size + 2, f"{flagged} flagged pixels"
     d = np.where(ok[..., None], np.abs(g_rgb - ref.rgb), 0.0)
     dT = np.where(ok, np.abs(g_T - ref.T_final), 0.0)
     if d.max(initial=0) > IMG_TOL or dT.max(initial=0) > IMG_TOL:
@@ -232,6 +238,61 @@ def test_gradient_parity_tiny_scenes(gb, seed):
 def test_gradient_parity_config2_crop(gb):
     scene, views = sg.config("C2")
     check_grads(gb, scene, views[0], O.Options(), (368, 368, 64, 64))
+
+
+# --- full-size workloads: 64 x 64 crops against the oracle ----------------------------------
+# The whole workload is rendered in the default launch configuration (depth-prefix split on,
+# default batches); the oracle evaluates one crop of one view. dL/drgb is zero outside the crop
+# (and at flagged pixels) on both sides, so every splat gradient is comparable: the splats the
+# oracle blended inside the crop are compared by relative L2, and the GPU gradient of every
+# other splat must carry no more than a 1e-6 share of the energy.
+def check_full_size_crop(gb, name, vi, seed=0):
+    import scenegen as sgm
+    scene, views = sg.config(name)
+    bf16 = sgm.CONFIGS[name]["bf16"]
+    opts = O.Options()
+    sp = gb.Splats.from_numpy(scene, tex_bf16=bf16)
+    rast = gb.Rasterizer(views, gpu_opts(opts))
+    rast.plan(sp)
+    rgb, T = rast.forward(sp)
+    torch.cuda.synchronize()
+    view = views[vi]
+    W, H = view.width, view.height
+    base = sum(v.width * v.height for v in views[:vi])
+    crop = ((W - 64) // 2, (H - 64) // 2, 64, 64)
+    ref = O.render(scene, view, opts, crop=crop, keep_saved=True)
+    img_err, flagged = assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, base, W, H,
+                                           max_flagged=MAX_FLAGGED_FRACTION_DENSE)
+    x0, y0, w, h = crop
+    g_view = sg.make_dl_drgb(seed, [view]).reshape(H, W, 3)
+    mask = np.zeros((H, W), dtype=bool)
+    mask[y0:y0 + h, x0:x0 + w] = ~O.grad_flags(ref)
+    g_view = np.where(mask[..., None], g_view, 0.0).astype(np.float32)
+    g_crop = g_view[y0:y0 + h, x0:x0 + w].reshape(-1, 3).astype(np.float64)
+    ref_g = O.render_backward(scene, view, opts, ref, g_crop)
+    d_rgb = torch.zeros((rast.total_pixels, 3), dtype=torch.float32, device="cuda")
+    d_rgb[base:base + W * H] = torch.from_numpy(g_view.reshape(-1, 3)).cuda()
+    grads = rast.backward(sp, T, d_rgb)
+    torch.cuda.synchronize()
+    ks = np.unique(np.array([k for k, _, _, _ in ref.saved], dtype=np.int64))
+    idx = torch.from_numpy(ks).cuda()
+    errs = {}
+    for gname in ("means", "tan_u", "tan_v", "scales", "opacity", "textures"):
+        full = grads[gname]
+        got = full[idx].double()
+        want = getattr(ref_g, gname)[ks]
+        errs[gname] = rel_l2(got.cpu().numpy(), want)
+        outside = float((full.double() ** 2).sum() - (got ** 2).sum())
+        assert outside <= 1e-6 * float((got ** 2).sum()) + 1e-30, (gname, outside)
+    print(f"{name} view {vi} crop {crop}: image max err {img_err:.2e}, {flagged} flagged px, "
+          f"{ks.size} splats, gradient rel L2", {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= GRAD_TOL, (k, v)
+
+
+@pytest.mark.parametrize("name,vi", [("T0", 0), ("C3", 3), ("C3", 12), ("C4", 1)])
+def test_full_size_crop_parity(gb, name, vi):
+    check_full_size_crop(gb, name, vi)
 
 
 # --- LDS batch sizes: same images, gradients within tolerance -------------------------------
