@@ -212,7 +212,28 @@ def main():
                                             "mpix_per_s": round(px4 / s_4 / 1e6, 1),
                                             "pairs": K4}
         variants["speedup_bf16_batched_vs_fp32_single"] = round((px4 / s_4) / (pixels / sec), 3)
-        del rast4
+        del rast4, rgb4, T4, grads4
+        torch.cuda.empty_cache()
+        log("variant: the same, with autotuned tile shape, batch sizes and prefix budget")
+        from paper_2412_12734_amd import autotune as at
+        opts_t, rec = at.autotune(sp4, views4, steps=3)
+        rast_t = gb.Rasterizer(views4, opts_t, check_overflow=False)
+        rast_t.plan(sp4)
+        rgb_t, T_t = rast_t.forward(sp4)
+        grads_t = rast_t.backward(sp4, T_t, g4)
+        for _ in range(args.warmup):
+            rast_t.forward(sp4, rgb_t, T_t)
+            rast_t.backward(sp4, T_t, g4, grads_t)
+        s_t = time_steps(rast_t, sp4, rgb_t, T_t, g4, grads_t, args.steps, torch)
+        variants["bf16_batched_4x1080p_autotuned"] = {
+            "ms_per_step": round(s_t * 1e3, 3), "mpix_per_s": round(px4 / s_t / 1e6, 1),
+            "options": {k: v for k, v in rec["options"].items()
+                        if k in ("tile_w", "tile_h", "batch", "batch_bwd",
+                                 "prefix_pairs_per_tile")},
+            "candidates_timed": len(rec["candidates"])}
+        variants["speedup_autotuned_bf16_batched_vs_fp32_single"] = round(
+            (px4 / s_t) / (pixels / sec), 3)
+        del rast_t, rgb_t, T_t, grads_t
         torch.cuda.empty_cache()
 
     cpu = None

@@ -388,6 +388,27 @@ def test_split_image_matches_oracle(gb):
     assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 128, 96)
 
 
+# --- autotuner: whatever it picks keeps oracle parity ---------------------------------------
+def test_autotuned_options_keep_parity(gb, tmp_path):
+    from paper_2412_12734_amd import autotune as at
+    scene = sg.make_scene(41, 20000, -1.0, 1.0, 0.02, 0.25, 8)
+    view = sg.look_at_view((0.0, 0.0, -3.0), 160, 120)
+    sp = gb.Splats.from_numpy(scene)
+    knobs = {"tile": [(16, 16), (16, 8), (8, 8)], "batch": [16, 32], "batch_bwd": [8, 16],
+             "prefix_pairs_per_tile": [512, -1]}
+    path = str(tmp_path / "tune.json")
+    opts, rec = at.autotune(sp, [view], base=gpu_opts(O.Options()), cache_path=path,
+                            knobs=knobs, steps=2)
+    assert rec["ms"] <= rec["default_ms"] and len(rec["candidates"]) >= 6
+    rast = gb.Rasterizer([view], opts)
+    rast.plan(sp)
+    rgb, T = rast.forward(sp)
+    ref = O.render(scene, view, O.Options(), crop=(48, 36, 64, 48))
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 160, 120)
+    opts2, rec2 = at.autotune(sp, [view], cache_path=path, knobs=knobs)
+    assert opts2 == opts  # second call served from the cache
+
+
 # --- precision: bfloat16 texture storage ---------------------------------------------------
 def test_bf16_exact_texels_give_identical_images(gb):
     scene, views = sg.config("C1")
