@@ -154,6 +154,19 @@ def main():
     value = pixels / sec / 1e6
     log(f"T0 fp32: {sec * 1e3:.3f} ms/step, {value:.1f} Mpx/s, K={K}")
 
+    # the same step captured once into a HIP graph and replayed
+    graph = rast.capture_step(sp, rgb, T, g, grads)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    sec_graph = (time.perf_counter() - t0) / args.steps
+    del graph
+    log(f"T0 fp32, HIP graph replay: {sec_graph * 1e3:.3f} ms/step")
+
     # per-stage durations from HIP events recorded on the launch stream
     stage_sum = {}
     rast.timing(True)
@@ -256,6 +269,7 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stages.items()},
         "blend_fwd_tflops": round(fwd_tf, 3),
         "hbm_copy_gbs": round(copy_gbs, 1),
+        "graph_replay_ms_per_step": round(sec_graph * 1e3, 3),
         "work": st,
         "variants": variants,
         "cpu_baseline": cpu,

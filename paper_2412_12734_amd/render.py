@@ -177,6 +177,34 @@ class Rasterizer:
                 "gb_render_bwd")
         return grads
 
+    def capture_step(self, sp: Splats, rgb: torch.Tensor, T_final: torch.Tensor,
+                     d_rgb: torch.Tensor, grads: dict) -> "torch.cuda.CUDAGraph":
+        """Records one forward + backward over the given preallocated tensors into a HIP graph
+        (torch.cuda.CUDAGraph); ``replay()`` reruns it. Every launch reads the pair count from
+        the workspace, so nothing in the step returns to the host; the capacity must fit the
+        scene (plan first; inside a graph an overflow is not re-planned: check ``status()``
+        after a replay). The library clears memory with kernels, never hipMemsetAsync."""
+        if self.ws is None or getattr(self, "_plan_key", None) != (sp.P, sp.N):
+            self.plan(sp)
+        if d_rgb.dtype != torch.float32 or not d_rgb.is_contiguous():
+            raise ValueError("d_rgb must be a contiguous float32 tensor")
+        keep = self.check_overflow
+        self.check_overflow = False
+        try:
+            side = torch.cuda.Stream(self.device)
+            side.wait_stream(torch.cuda.current_stream(self.device))
+            with torch.cuda.stream(side):  # warm-up outside the capture
+                self.forward(sp, rgb, T_final)
+                self.backward(sp, T_final, d_rgb, grads)
+            torch.cuda.current_stream(self.device).wait_stream(side)
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                self.forward(sp, rgb, T_final)
+                self.backward(sp, T_final, d_rgb, grads)
+        finally:
+            self.check_overflow = keep
+        return graph
+
     # -- measurement ---------------------------------------------------------------------------
     def blend_stats(self, sp: Splats, rgb: torch.Tensor, T_final: torch.Tensor) -> dict:
         """Forward with work counting (synchronises): blended pairs, t_min stops, lane

@@ -409,6 +409,37 @@ def test_autotuned_options_keep_parity(gb, tmp_path):
     assert opts2 == opts  # second call served from the cache
 
 
+# --- HIP graph: a captured forward + backward replays the eager results ----------------------
+def test_graph_replay_matches_eager(gb):
+    scene, view = dense_scene(N=8)
+    views = [view, sg.look_at_view((0.4, -0.2, -3.2), 72, 50)]
+    sp = gb.Splats.from_numpy(scene)
+    rast = gb.Rasterizer(views, gpu_opts(O.Options()), check_overflow=False)
+    rast.plan(sp)
+    rgb, T = rast.forward(sp)
+    g = torch.from_numpy(sg.make_dl_drgb(7, views)).cuda()
+    grads = rast.backward(sp, T, g)
+    torch.cuda.synchronize()
+    want_rgb, want_T = rgb.clone(), T.clone()
+    want = {k: v.clone() for k, v in grads.items()}
+    graph = rast.capture_step(sp, rgb, T, g, grads)
+    for rep in range(3):
+        # eager work between replays: spoil the outputs, then replay and compare
+        rgb.fill_(-1.0)
+        T.fill_(-1.0)
+        for v in grads.values():
+            v.fill_(123.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(rgb, want_rgb) and torch.equal(T, want_T), rep
+        for k, v in want.items():
+            # gradients accumulate with float atomics: the order may differ between runs
+            err = float((grads[k].double() - v.double()).norm() / v.double().norm().clamp_min(1e-30))
+            assert err <= 1e-5, (rep, k, err)
+        assert not rast.status()[1]
+
+
 # --- precision: bfloat16 texture storage ---------------------------------------------------
 def test_bf16_exact_texels_give_identical_images(gb):
     scene, views = sg.config("C1")
