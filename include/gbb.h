@@ -190,6 +190,45 @@ gb_status gb_timing_enable(int32_t on);
 gb_status gb_timing_read(float* ms_out, int32_t n, int32_t* n_written);
 const char* gb_timing_stage_name(int32_t stage);
 
+/* ---- Training glue (Sec. 3.3: the splats are trained with an image loss and Adam) ---------
+ * All arrays are device float32 unless stated, caller-owned, and stream-ordered on `stream`;
+ * nothing is allocated. Errors: GB_ERR_ARG for NULL or misaligned pointers or negative sizes
+ * (checked before any launch), GB_ERR_HIP for launch failures. */
+
+/* Parameter activations of 2D Gaussian splats: quats [P][4] = (w, x, y, z), any non-zero
+ * length -> tan_u, tan_v [P][3], the first two columns of the rotation of q / |q|;
+ * log_scales [P][2] -> scales = exp(log_scales); opacity_logits [P] -> opacity = 1 / (1 +
+ * exp(-logit)). */
+gb_status gb_activate_fwd(int32_t P, const float* quats, const float* log_scales,
+                          const float* opacity_logits, float* tan_u, float* tan_v, float* scales,
+                          float* opacity, void* stream);
+
+/* Backward of gb_activate_fwd: from dL/d(tan_u, tan_v, scales, opacity) (layouts as above)
+ * writes dL/d(quats, log_scales, opacity_logits) (overwritten, not accumulated). */
+gb_status gb_activate_bwd(int32_t P, const float* quats, const float* log_scales,
+                          const float* opacity_logits, const float* d_tan_u,
+                          const float* d_tan_v, const float* d_scales, const float* d_opacity,
+                          float* d_quats, float* d_log_scales, float* d_opacity_logits,
+                          void* stream);
+
+/* L1 image loss over n values: *loss (one device float) = scale * sum |rgb - target|, and
+ * d_rgb = scale * sign(rgb - target) (0 where equal). rgb, target and d_rgb 16-byte aligned. */
+gb_status gb_l1_loss(int64_t n, const float* rgb, const float* target, float scale,
+                     float* loss, float* d_rgb, void* stream);
+
+/* One Adam step (Kingma and Ba) on n parameters: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * param -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps), in place; step >= 1.
+ * With bf16_copy != NULL the updated parameters are also written rounded to bfloat16 (nearest,
+ * ties to even) as uint16 bit patterns (the render copy of BF16 textures). param, grad, m, v
+ * 16-byte aligned, bf16_copy 8-byte aligned. */
+gb_status gb_adam_step(int64_t n, float* param, const float* grad, float* m, float* v,
+                       int32_t step, float lr, float beta1, float beta2, float eps,
+                       uint16_t* bf16_copy, void* stream);
+
+/* dst[i] = src[i] rounded to bfloat16 (nearest, ties to even) as uint16 bit patterns: the
+ * initial render copy of float32 textures. */
+gb_status gb_to_bf16(int64_t n, const float* src, uint16_t* dst, void* stream);
+
 /* Fills *out with the default options (sigma 0.5, alpha_min 1/255, alpha_max 0.99,
  * t_min 1e-4, lowpass_var 0.5, black background, 16 x 16 tiles, default batch). */
 void gb_default_options(gb_options* out);

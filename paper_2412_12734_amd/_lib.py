@@ -21,6 +21,7 @@ EXPORTS = (
     "gb_workspace_layout", "gb_count_pairs", "gb_render_fwd", "gb_render_bwd",
     "gb_read_status", "gb_blend_stats", "gb_timing_enable", "gb_timing_read",
     "gb_timing_stage_name", "gb_default_options", "gb_status_string", "gb_last_error",
+    "gb_activate_fwd", "gb_activate_bwd", "gb_l1_loss", "gb_adam_step", "gb_to_bf16",
 )
 
 
@@ -101,8 +102,16 @@ def load() -> ctypes.CDLL:
     lib.gb_status_string.restype = c_char_p
     lib.gb_last_error.argtypes = []
     lib.gb_last_error.restype = c_char_p
+    lib.gb_activate_fwd.argtypes = [c_int32] + [c_void_p] * 7 + [c_void_p]
+    lib.gb_activate_bwd.argtypes = [c_int32] + [c_void_p] * 10 + [c_void_p]
+    lib.gb_l1_loss.argtypes = [c_int64, c_void_p, c_void_p, c_float, c_void_p, c_void_p, c_void_p]
+    lib.gb_adam_step.argtypes = [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
+                                 c_float, c_float, c_float, c_float, c_void_p, c_void_p]
+    lib.gb_to_bf16.argtypes = [c_int64, c_void_p, c_void_p, c_void_p]
     for name in ("gb_workspace_layout", "gb_count_pairs", "gb_render_fwd", "gb_render_bwd",
-                 "gb_read_status", "gb_blend_stats", "gb_timing_enable", "gb_timing_read"):
+                 "gb_read_status", "gb_blend_stats", "gb_timing_enable", "gb_timing_read",
+                 "gb_activate_fwd", "gb_activate_bwd", "gb_l1_loss", "gb_adam_step",
+                 "gb_to_bf16"):
         getattr(lib, name).restype = c_int32
     _lib = lib
     return lib

@@ -549,6 +549,79 @@ gb_status gb_render_bwd(const gb_splats* s, const gb_view* views, int32_t n_view
   return GB_OK;
 }
 
+gb_status gb_activate_fwd(int32_t P, const float* quats, const float* log_scales,
+                          const float* opacity_logits, float* tan_u, float* tan_v, float* scales,
+                          float* opacity, void* stream) {
+  if (P < 0) return arg_fail("P must be >= 0");
+  if (P == 0) return GB_OK;
+  const void* ptrs[] = {quats, log_scales, opacity_logits, tan_u, tan_v, scales, opacity};
+  for (const void* p : ptrs)
+    if (!p || !aligned(p, 4)) return arg_fail("activation array NULL or misaligned");
+  GBB_TRY(launch_activate_fwd(P, quats, log_scales, opacity_logits, tan_u, tan_v, scales, opacity,
+                              reinterpret_cast<hipStream_t>(stream)),
+          "activate forward");
+  return GB_OK;
+}
+
+gb_status gb_activate_bwd(int32_t P, const float* quats, const float* log_scales,
+                          const float* opacity_logits, const float* d_tan_u,
+                          const float* d_tan_v, const float* d_scales, const float* d_opacity,
+                          float* d_quats, float* d_log_scales, float* d_opacity_logits,
+                          void* stream) {
+  if (P < 0) return arg_fail("P must be >= 0");
+  if (P == 0) return GB_OK;
+  const void* ptrs[] = {quats, log_scales, opacity_logits, d_tan_u, d_tan_v, d_scales,
+                        d_opacity, d_quats, d_log_scales, d_opacity_logits};
+  for (const void* p : ptrs)
+    if (!p || !aligned(p, 4)) return arg_fail("activation array NULL or misaligned");
+  GBB_TRY(launch_activate_bwd(P, quats, log_scales, opacity_logits, d_tan_u, d_tan_v, d_scales,
+                              d_opacity, d_quats, d_log_scales, d_opacity_logits,
+                              reinterpret_cast<hipStream_t>(stream)),
+          "activate backward");
+  return GB_OK;
+}
+
+gb_status gb_l1_loss(int64_t n, const float* rgb, const float* target, float scale, float* loss,
+                     float* d_rgb, void* stream) {
+  if (n < 0) return arg_fail("n must be >= 0");
+  if (!loss || !aligned(loss, 4)) return arg_fail("loss NULL or misaligned");
+  const void* ptrs[] = {rgb, target, d_rgb};
+  for (const void* p : ptrs)
+    if (!p || !aligned(p, 16)) return arg_fail("loss array NULL or not 16-byte aligned");
+  GBB_TRY(launch_l1_loss(n, rgb, target, scale, loss, d_rgb, reinterpret_cast<hipStream_t>(stream)),
+          "l1 loss");
+  return GB_OK;
+}
+
+gb_status gb_adam_step(int64_t n, float* param, const float* grad, float* m, float* v,
+                       int32_t step, float lr, float beta1, float beta2, float eps,
+                       uint16_t* bf16_copy, void* stream) {
+  if (n < 0) return arg_fail("n must be >= 0");
+  if (step < 1) return arg_fail("step must be >= 1");
+  if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f))
+    return arg_fail("betas must be in [0, 1)");
+  if (n == 0) return GB_OK;
+  const void* ptrs[] = {param, grad, m, v};
+  for (const void* p : ptrs)
+    if (!p || !aligned(p, 16)) return arg_fail("Adam array NULL or not 16-byte aligned");
+  if (bf16_copy && !aligned(bf16_copy, 8)) return arg_fail("bf16 copy not 8-byte aligned");
+  // bias corrections in double precision
+  const double c1 = 1.0 / (1.0 - std::pow((double)beta1, (double)step));
+  const double c2 = 1.0 / (1.0 - std::pow((double)beta2, (double)step));
+  GBB_TRY(launch_adam(n, param, grad, m, v, lr, beta1, beta2, (float)c1, (float)c2, eps, bf16_copy,
+                      reinterpret_cast<hipStream_t>(stream)),
+          "adam");
+  return GB_OK;
+}
+
+gb_status gb_to_bf16(int64_t n, const float* src, uint16_t* dst, void* stream) {
+  if (n < 0) return arg_fail("n must be >= 0");
+  if (n == 0) return GB_OK;
+  if (!src || !dst || !aligned(src, 4) || !aligned(dst, 2)) return arg_fail("NULL or misaligned");
+  GBB_TRY(launch_to_bf16(n, src, dst, reinterpret_cast<hipStream_t>(stream)), "to bf16");
+  return GB_OK;
+}
+
 gb_status gb_read_status(const void* ws, int64_t* K_out, int32_t* overflow_out, void* stream) {
   if (!ws || !K_out || !overflow_out) return arg_fail("NULL argument");
   hipStream_t hs = reinterpret_cast<hipStream_t>(stream);

@@ -194,6 +194,20 @@ hipError_t launch_blend_bwd(const Plan& pl, const gb_splats& sp, const gb_option
                             const PairList& first, const PairList& rest,
                             const uint32_t* open_bits, const float* T_final, const float* d_rgb,
                             float* d_rec, float* d_tex, hipStream_t s);
+// Training glue (train.hip).
+hipError_t launch_activate_fwd(int P, const float* quats, const float* log_scales,
+                               const float* logits, float* tan_u, float* tan_v, float* scales,
+                               float* opacity, hipStream_t s);
+hipError_t launch_activate_bwd(int P, const float* quats, const float* log_scales,
+                               const float* logits, const float* d_tan_u, const float* d_tan_v,
+                               const float* d_scales, const float* d_opacity, float* d_quats,
+                               float* d_log_scales, float* d_logits, hipStream_t s);
+hipError_t launch_l1_loss(int64_t n, const float* rgb, const float* target, float scale,
+                          float* loss, float* d_rgb, hipStream_t s);
+hipError_t launch_to_bf16(int64_t n, const float* src, uint16_t* dst, hipStream_t s);
+hipError_t launch_adam(int64_t n, float* theta, const float* grad, float* m, float* v, float lr,
+                       float b1, float b2, float c1, float c2, float eps, uint16_t* bf16,
+                       hipStream_t s);
 hipError_t launch_preprocess_bwd(const gb_splats& sp, const ViewDev* d_views, int n_views,
                                  const uint32_t* count, const float* d_rec,
                                  const gb_grads& g, hipStream_t s);

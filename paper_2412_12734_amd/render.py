@@ -177,6 +177,19 @@ class Rasterizer:
                 "gb_render_bwd")
         return grads
 
+    def set_views(self, views: Sequence) -> None:
+        """Renders into another set of views from now on. If the views have the same sizes as
+        before, the workspace layout is unchanged and is kept (the capacity is re-planned on
+        overflow when check_overflow is set); otherwise the next forward plans again."""
+        views = list(views)
+        same = [(v.width, v.height) for v in views] == [(v.width, v.height) for v in self.views]
+        self.views = views
+        self.cviews = L.make_views(views)
+        self.nv = len(views)
+        if not same:
+            self.total_pixels = sum(v.width * v.height for v in views)
+            self.ws, self.capacity, self._plan_key = None, 0, None
+
     def capture_step(self, sp: Splats, rgb: torch.Tensor, T_final: torch.Tensor,
                      d_rgb: torch.Tensor, grads: dict) -> "torch.cuda.CUDAGraph":
         """Records one forward + backward over the given preallocated tensors into a HIP graph

@@ -1,0 +1,135 @@
+"""Training step around the rasterizer: activations, L1 image loss and Adam.
+
+The paper optimises the splats' positions, rotations, scales, opacities and colour grids
+against images (Sec. 3.3). This module keeps raw float32 parameters with their Adam moments
+on the device, activates them (quaternion -> tangents, exp scales, sigmoid opacity), renders a
+batch of views, takes the L1 loss against target images, backpropagates through the
+rasterizer and the activations and applies Adam to every parameter group. With bfloat16
+textures the Adam step also rewrites the bfloat16 render copy of the float32 master textures.
+Every step runs in libgbb kernels; torch supplies memory and the stream. Densification,
+pruning and the SSIM term are not part of it.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, Optional, Sequence
+
+import torch
+
+from . import _lib as L
+from .render import Options, Rasterizer, Splats, _stream
+
+# learning rates per parameter group (not given by the paper; only their cost matters here)
+DEFAULT_LR = dict(means=1.6e-4, quats=1e-3, log_scales=5e-3, opacity_logits=5e-2,
+                  textures=2.5e-3)
+GROUPS = ("means", "quats", "log_scales", "opacity_logits", "textures")
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+class TrainState:
+    """Raw parameters (float32 masters), Adam moments and activated copies on the device."""
+
+    def __init__(self, raw, bf16: bool = True, device="cuda",
+                 lr: Optional[Dict[str, float]] = None, betas=(0.9, 0.999), eps: float = 1e-15):
+        self.lib = L.load()
+        self.device = torch.device(device)
+        f = lambda a: torch.from_numpy(a).to(self.device).contiguous()
+        self.params = {g: f(getattr(raw, g)) for g in GROUPS}
+        self.m = {g: torch.zeros_like(t) for g, t in self.params.items()}
+        self.v = {g: torch.zeros_like(t) for g, t in self.params.items()}
+        self.raw_grads = {g: torch.zeros_like(t) for g, t in self.params.items()}
+        P = self.P = int(self.params["means"].shape[0])
+        self.N = int(self.params["textures"].shape[1])
+        z = lambda *s: torch.empty(s, dtype=torch.float32, device=self.device)
+        self.tan_u, self.tan_v, self.scales, self.opacity = z(P, 3), z(P, 3), z(P, 2), z(P)
+        self.bf16 = bf16
+        self.tex_bits = None
+        if bf16:
+            tex = self.params["textures"]
+            self.tex_bits = torch.empty(tex.shape, dtype=torch.int16, device=self.device)
+            L.check(self.lib.gb_to_bf16(tex.numel(), _p(tex), _p(self.tex_bits),
+                                        self.stream()), "gb_to_bf16")
+        self.lr = dict(DEFAULT_LR, **(lr or {}))
+        self.betas, self.eps = betas, eps
+        self.step_count = 0
+
+    def stream(self) -> int:
+        return _stream(self.device)
+
+    def activate(self) -> Splats:
+        p = self.params
+        L.check(self.lib.gb_activate_fwd(self.P, _p(p["quats"]), _p(p["log_scales"]),
+                                         _p(p["opacity_logits"]), _p(self.tan_u),
+                                         _p(self.tan_v), _p(self.scales), _p(self.opacity),
+                                         self.stream()), "gb_activate_fwd")
+        tex = self.tex_bits.view(torch.bfloat16) if self.bf16 else p["textures"]
+        return Splats(p["means"], self.tan_u, self.tan_v, self.scales, self.opacity, tex)
+
+    def backward_activations(self, grads: Dict[str, torch.Tensor]) -> Dict[str, torch.Tensor]:
+        """Rasterizer gradients (activated parameters) -> gradients of the raw parameters."""
+        p, r = self.params, self.raw_grads
+        L.check(self.lib.gb_activate_bwd(self.P, _p(p["quats"]), _p(p["log_scales"]),
+                                         _p(p["opacity_logits"]), _p(grads["tan_u"]),
+                                         _p(grads["tan_v"]), _p(grads["scales"]),
+                                         _p(grads["opacity"]), _p(r["quats"]),
+                                         _p(r["log_scales"]), _p(r["opacity_logits"]),
+                                         self.stream()), "gb_activate_bwd")
+        r["means"] = grads["means"]
+        r["textures"] = grads["textures"]
+        return r
+
+    def adam(self, raw_grads: Dict[str, torch.Tensor]) -> None:
+        self.step_count += 1
+        b1, b2 = self.betas
+        for g in GROUPS:
+            t = self.params[g]
+            bits = self.tex_bits if (g == "textures" and self.bf16) else None
+            L.check(self.lib.gb_adam_step(t.numel(), _p(t), _p(raw_grads[g]), _p(self.m[g]),
+                                          _p(self.v[g]), self.step_count, self.lr[g], b1, b2,
+                                          self.eps, _p(bits), self.stream()), "gb_adam_step")
+
+
+def l1_loss(rgb: torch.Tensor, target: torch.Tensor, scale: float, loss: torch.Tensor,
+            d_rgb: torch.Tensor) -> None:
+    """loss[0] = scale * sum |rgb - target|, d_rgb = scale * sign(rgb - target)."""
+    lib = L.load()
+    L.check(lib.gb_l1_loss(rgb.numel(), _p(rgb), _p(target), float(scale), _p(loss), _p(d_rgb),
+                           _stream(rgb.device)), "gb_l1_loss")
+
+
+class Trainer:
+    """One optimisation step per call on a batch of views with target images.
+
+    targets: [n_views, H * W, 3] float32 on the device (all views the same size)."""
+
+    def __init__(self, state: TrainState, views: Sequence, targets: torch.Tensor,
+                 options: Optional[Options] = None):
+        self.state, self.views, self.targets = state, list(views), targets
+        self.rast: Optional[Rasterizer] = None
+        self.options = options or Options()
+        self.loss = torch.zeros(1, dtype=torch.float32, device=state.device)
+        self.bufs = None
+
+    def step(self, batch: Sequence[int]) -> torch.Tensor:
+        st = self.state
+        views = [self.views[i] for i in batch]
+        if self.rast is None:
+            self.rast = Rasterizer(views, self.options, device=st.device, headroom=1.5)
+        else:
+            self.rast.set_views(views)
+        sp = st.activate()
+        n_px = sum(v.width * v.height for v in views)
+        if self.bufs is None or self.bufs[0].shape[0] != n_px:
+            z = lambda *s: torch.empty(s, dtype=torch.float32, device=st.device)
+            self.bufs = (z(n_px, 3), z(n_px), z(n_px, 3), z(n_px, 3))
+        rgb, T, target, d_rgb = self.bufs
+        rgb, T = self.rast.forward(sp, rgb, T)
+        torch.index_select(self.targets, 0, torch.tensor(batch, device=st.device),
+                           out=target.view(len(batch), -1, 3))
+        l1_loss(rgb, target, 1.0 / (3 * n_px), self.loss, d_rgb)
+        grads = self.rast.backward(sp, T, d_rgb)
+        st.adam(st.backward_activations(grads))
+        return self.loss

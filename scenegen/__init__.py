@@ -213,3 +213,95 @@ def config(name: str, seed: int = 0, P: Optional[int] = None) -> Tuple[Scene, Li
     else:
         views = orbit_views(seed, nv, dist, res, pick_resolution=len(res) > 1)
     return scene, views
+
+
+# ---- training workload (raw parameters) ------------------------------------------------------
+@dataclasses.dataclass
+class RawScene:
+    """Raw (pre-activation) splat parameters, float32: means [P][3], quats [P][4] (w, x, y, z,
+    not normalised), log_scales [P][2], opacity_logits [P], textures [P][N][N][3] in [0, 1]."""
+    means: np.ndarray
+    quats: np.ndarray
+    log_scales: np.ndarray
+    opacity_logits: np.ndarray
+    textures: np.ndarray
+
+    @property
+    def P(self) -> int:
+        return self.means.shape[0]
+
+    @property
+    def N(self) -> int:
+        return self.textures.shape[1]
+
+
+def make_raw_scene(seed: int, P: int, lo: float, hi: float, s_lo: float, s_hi: float, N: int,
+                   op_lo: float = 0.05, op_hi: float = 0.95) -> RawScene:
+    """The draws of ``make_scene`` (same order and stream) kept as raw parameters: the quaternion
+    draws, the log-scales, the logits of the opacities and float32 textures."""
+    rng = np.random.default_rng(seed)
+    means = rng.uniform(lo, hi, (P, 3))
+    q = rng.standard_normal((P, 4))
+    log_s = rng.uniform(math.log(s_lo), math.log(s_hi), (P, 2))
+    o = rng.uniform(op_lo, op_hi, P)
+    tex = np.empty((P, N, N, 3), dtype=np.float32)
+    flat = tex.reshape(P, N * N * 3)
+    step = max(1, (1 << 22) // (N * N * 3))
+    for i in range(0, P, step):
+        part = flat[i:i + step]
+        part[...] = rng.uniform(0.0, 1.0, part.shape)
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    return RawScene(f32(means), f32(q), f32(log_s), f32(np.log(o / (1.0 - o))), tex)
+
+
+def perturb_raw(raw: RawScene, seed: int) -> RawScene:
+    """Target scene of the training workload: means + N(0, 0.02), log-scales + N(0, 0.1),
+    quaternions + N(0, 0.05) then renormalised, logits + N(0, 0.2), textures + N(0, 0.05)
+    clipped to [0, 1]; one stream, in that order."""
+    rng = np.random.default_rng(seed)
+    P = raw.P
+    means = raw.means + rng.normal(0.0, 0.02, (P, 3))
+    log_s = raw.log_scales + rng.normal(0.0, 0.1, (P, 2))
+    q = raw.quats + rng.normal(0.0, 0.05, (P, 4))
+    q = q / np.linalg.norm(q, axis=1, keepdims=True)
+    logits = raw.opacity_logits + rng.normal(0.0, 0.2, P)
+    tex = np.empty_like(raw.textures)
+    src, dst = raw.textures.reshape(P, -1), tex.reshape(P, -1)
+    step = max(1, (1 << 22) // src.shape[1])
+    for i in range(0, P, step):
+        dst[i:i + step] = np.clip(src[i:i + step] + rng.normal(0.0, 0.05, src[i:i + step].shape),
+                                  0.0, 1.0)
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    return RawScene(f32(means), f32(q), f32(log_s), f32(logits), tex)
+
+
+# 500k splats, 8x8 textures (BF16 render copy of FP32 masters), 32 views 1280x720 on a radius-8
+# sphere, batches of 4 views per iteration, targets from a perturbed copy of the scene
+TRAIN_CONFIG = dict(P=500_000, lo=-4.0, hi=4.0, s_lo=0.02, s_hi=0.2, N=8, n_views=32,
+                    res=(1280, 720), radius=8.0, batch=4)
+
+
+def train_config(seed: int = 0, P: Optional[int] = None, n_views: Optional[int] = None,
+                 res: Optional[Tuple[int, int]] = None):
+    """Raw scene, raw target scene, views and a batch schedule generator of the training
+    workload. ``batches(k)`` gives k batches of view indices: each a slice of a fresh
+    permutation of the views (seed + 4 stream), batch size TRAIN_CONFIG['batch']."""
+    c = TRAIN_CONFIG
+    P = P if P is not None else c["P"]
+    nv = n_views if n_views is not None else c["n_views"]
+    res = res if res is not None else c["res"]
+    raw = make_raw_scene(seed, P, c["lo"], c["hi"], c["s_lo"], c["s_hi"], c["N"])
+    target = perturb_raw(raw, seed + 3)
+    views = orbit_views(seed, nv, c["radius"], [res])
+    rng = np.random.default_rng(seed + 4)
+    b = c["batch"]
+
+    def batches(k: int) -> List[List[int]]:
+        out: List[List[int]] = []
+        while len(out) < k:
+            perm = rng.permutation(nv)
+            out.extend([list(map(int, perm[i:i + b])) for i in range(0, nv - b + 1, b)])
+        return out[:k]
+
+    return raw, target, views, batches
+

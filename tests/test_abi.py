@@ -24,7 +24,7 @@ def _lib():
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "gbb.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(gb_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(gb_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_the_binding_exports():
@@ -113,3 +113,24 @@ def test_render_rejects_null_pointers_before_launching():
                            None, None)
     assert st == L.GB_ERR_ARG
     assert b"NULL" in lib.gb_last_error()
+
+
+def test_training_glue_rejects_invalid_arguments_before_any_launch():
+    lib = _lib()
+    assert lib.gb_activate_fwd(-1, *([None] * 7), None) == L.GB_ERR_ARG
+    assert lib.gb_activate_fwd(0, *([None] * 7), None) == L.GB_OK  # nothing to do
+    assert lib.gb_activate_bwd(5, *([None] * 10), None) == L.GB_ERR_ARG
+    assert lib.gb_l1_loss(10, None, None, 1.0, None, None, None) == L.GB_ERR_ARG
+    buf = ctypes.create_string_buffer(64)
+    base = ctypes.addressof(buf)
+    p16 = base + (-base) % 16
+    # misaligned (4 bytes past a 16-byte boundary) arrays are refused
+    assert lib.gb_l1_loss(4, p16 + 4, p16, 1.0, p16, p16, None) == L.GB_ERR_ARG
+    assert lib.gb_adam_step(4, p16, p16, p16, p16, 0, 0.1, 0.9, 0.999, 1e-15, None,
+                            None) == L.GB_ERR_ARG  # step must be >= 1
+    assert lib.gb_adam_step(4, p16, p16, p16, p16, 1, 0.1, 1.0, 0.999, 1e-15, None,
+                            None) == L.GB_ERR_ARG  # beta1 must be < 1
+    assert lib.gb_adam_step(0, None, None, None, None, 1, 0.1, 0.9, 0.999, 1e-15, None,
+                            None) == L.GB_OK  # empty
+    assert lib.gb_to_bf16(-1, None, None, None) == L.GB_ERR_ARG
+
