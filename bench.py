@@ -8,7 +8,8 @@ inputs are resident in device memory before the timed region starts.
 
 Prints one JSON line: whole-job throughput in Mpixels/s (fwd+bwd), the roofline of the dominant
 kernel (blend backward, measured with HIP events on its launch stream), variants (bfloat16
-textures; four 1080p views in one batched call) and the FP64 oracle's rate on a bounded crop of
+textures; four 1080p views in one batched call; a full optimisation step with L1 loss and Adam
+over batches of four 1280x720 views) and the FP64 oracle's rate on a bounded crop of
 the same workload on the host CPU.
 """
 from __future__ import annotations
@@ -112,15 +113,65 @@ def setup(gb, sg, torch, name, views=None):
     return scene, views, sp, rast, g, rgb, T, grads, K
 
 
+def train_variant(gb, sg, torch, warmup=20, iters=200):
+    """Full optimisation step: activations, render of a batch of 4 of 32 views, L1 loss,
+    backward through the rasterizer and the activations, Adam on every parameter group with
+    the bfloat16 texture copy rewritten. Per-iteration durations from HIP events on the
+    launch stream; the targets are the perturbed scene rendered once by the FP32 path."""
+    from paper_2412_12734_amd import train as TR
+    raw, tgt, views, batches = sg.train_config()
+    hw = views[0].width * views[0].height
+    targets = torch.empty((len(views), hw, 3), dtype=torch.float32, device="cuda")
+    tst = TR.TrainState(tgt, bf16=False)
+    sp_t = tst.activate()
+    rt = gb.Rasterizer(views[:4])
+    for i in range(0, len(views), 4):
+        rt.set_views(views[i:i + 4])
+        rgb_t, _ = rt.forward(sp_t)
+        targets[i:i + 4].copy_(rgb_t.view(4, hw, 3))
+    del rt, tst, sp_t, rgb_t
+    st = TR.TrainState(raw, bf16=True)
+    trainer = TR.Trainer(st, views, targets)
+    sched = batches(warmup + iters)
+    cap = trainer.plan(sched)
+    for b in sched[:warmup]:
+        trainer.step(b)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(iters + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record()
+    for i, b in enumerate(sched[warmup:]):
+        trainer.step(b)
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / iters
+    ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(iters))
+    q = lambda f: ms[min(iters - 1, int(round(f * (iters - 1))))]
+    loss = float(trainer.loss)
+    over = trainer.overflowed()
+    n_par = sum(t.numel() for t in st.params.values())
+    out = {"ms_per_iter_median": round(q(0.5), 3), "ms_per_iter_p10": round(q(0.1), 3),
+           "ms_per_iter_p90": round(q(0.9), 3), "ms_per_iter_wall": round(wall * 1e3, 3),
+           "iters": iters, "warmup": warmup, "parameters": n_par, "pair_capacity": cap,
+           "final_l1": round(loss, 6), "overflow_last_step": over,
+           "workload": "500k splats, 8x8 BF16 textures (FP32 master), batch of 4 of 32 "
+                       "1280x720 views, L1 + Adam"}
+    del trainer, st, targets
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(scene, view, crop):
     """FP64 oracle (one process) on a crop of the workload: forward + analytic backward."""
     import numpy as np
     from oracle import gb_oracle as O
-    t0 = time.perf_counter()
-    r = O.render(scene, view, O.Options(), crop=crop, keep_saved=True)
-    g = np.random.default_rng(0).standard_normal((crop[2] * crop[3], 3))
-    O.render_backward(scene, view, O.Options(), r, g)
-    dt = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):  # one core: BLAS and OpenMP pools held to one thread
+        t0 = time.perf_counter()
+        r = O.render(scene, view, O.Options(), crop=crop, keep_saved=True)
+        g = np.random.default_rng(0).standard_normal((crop[2] * crop[3], 3))
+        O.render_backward(scene, view, O.Options(), r, g)
+        dt = time.perf_counter() - t0
     return crop[2] * crop[3] / dt / 1e6, dt
 
 
@@ -131,6 +182,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--train-iters", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the rasterizer has no "
@@ -248,14 +300,18 @@ def main():
             (px4 / s_t) / (pixels / sec), 3)
         del rast_t, rgb_t, T_t, grads_t
         torch.cuda.empty_cache()
+        log("variant: full optimisation step (500k splats, batch of 4 of 32 views at 1280x720)")
+        variants["train_step_500k_4x720p"] = train_variant(gb, sg, torch,
+                                                           iters=args.train_iters)
+        log(f"train step: {variants['train_step_500k_4x720p']}")
 
     cpu = None
     if not args.no_cpu_baseline:
-        crop = (896, 476, 128, 128)
-        log("cpu baseline: FP64 oracle on a 128x128 centre crop (fwd + bwd)")
+        crop = (832, 412, 256, 256)
+        log("cpu baseline: FP64 oracle on a 256x256 centre crop (fwd + bwd)")
         mpx, dt = cpu_baseline(scene, views[0], crop)
         cpu = {"value": round(mpx, 6), "unit": "Mpixels/s", "cores": 1, "kind": "oracle",
-               "sample": "128x128 centre crop of the 1920x1080 view, forward + analytic "
+               "sample": "256x256 centre crop of the 1920x1080 view, forward + analytic "
                          f"backward, one process ({dt:.1f} s)"}
 
     out = {

@@ -103,7 +103,8 @@ def l1_loss(rgb: torch.Tensor, target: torch.Tensor, scale: float, loss: torch.T
 class Trainer:
     """One optimisation step per call on a batch of views with target images.
 
-    targets: [n_views, H * W, 3] float32 on the device (all views the same size)."""
+    targets: [n_views, H * W, 3] float32 on the device, one image per view (views of
+    different sizes use the first width * height rows of theirs)."""
 
     def __init__(self, state: TrainState, views: Sequence, targets: torch.Tensor,
                  options: Optional[Options] = None):
@@ -112,24 +113,48 @@ class Trainer:
         self.options = options or Options()
         self.loss = torch.zeros(1, dtype=torch.float32, device=state.device)
         self.bufs = None
+        self.grads = None
+
+    def _use(self, batch: Sequence[int]) -> None:
+        views = [self.views[i] for i in batch]
+        if self.rast is None:
+            self.rast = Rasterizer(views, self.options, device=self.state.device, headroom=1.5)
+        else:
+            self.rast.set_views(views)
+
+    def plan(self, batches: Sequence[Sequence[int]], headroom: float = 1.5) -> int:
+        """Sizes the pair capacity for the largest of the given batches at the current
+        parameters (one device count per distinct batch) and turns the per-step overflow
+        check off, so that steps never wait on the host. The headroom covers the drift of the
+        parameters during training; ``overflowed()`` tells whether the last step fitted."""
+        sp = self.state.activate()
+        K = 0
+        for b in sorted({tuple(b) for b in batches}):
+            self._use(b)
+            K = max(K, self.rast.count_pairs(sp))
+        cap = self.rast.plan(sp, int(K * headroom) + 4096)
+        self.rast.check_overflow = False
+        return cap
+
+    def overflowed(self) -> bool:
+        return self.rast is not None and self.rast.status()[1]
 
     def step(self, batch: Sequence[int]) -> torch.Tensor:
         st = self.state
-        views = [self.views[i] for i in batch]
-        if self.rast is None:
-            self.rast = Rasterizer(views, self.options, device=st.device, headroom=1.5)
-        else:
-            self.rast.set_views(views)
+        self._use(batch)
         sp = st.activate()
-        n_px = sum(v.width * v.height for v in views)
+        n_px = sum(self.views[i].width * self.views[i].height for i in batch)
         if self.bufs is None or self.bufs[0].shape[0] != n_px:
             z = lambda *s: torch.empty(s, dtype=torch.float32, device=st.device)
             self.bufs = (z(n_px, 3), z(n_px), z(n_px, 3), z(n_px, 3))
         rgb, T, target, d_rgb = self.bufs
         rgb, T = self.rast.forward(sp, rgb, T)
-        torch.index_select(self.targets, 0, torch.tensor(batch, device=st.device),
-                           out=target.view(len(batch), -1, 3))
+        at = 0
+        for i in batch:  # device-to-device copies of the batch's target images
+            hw = self.views[i].width * self.views[i].height
+            target[at:at + hw].copy_(self.targets[i].view(-1, 3)[:hw])
+            at += hw
         l1_loss(rgb, target, 1.0 / (3 * n_px), self.loss, d_rgb)
-        grads = self.rast.backward(sp, T, d_rgb)
-        st.adam(st.backward_activations(grads))
+        self.grads = self.rast.backward(sp, T, d_rgb, self.grads)
+        st.adam(st.backward_activations(self.grads))
         return self.loss

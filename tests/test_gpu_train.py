@@ -175,3 +175,22 @@ def test_trainer_steps_run_and_move_the_parameters(gb):
     np.testing.assert_array_equal(
         st.tex_bits.cpu().numpy().view(np.uint16).reshape(-1),
         TO.bf16_round(st.params["textures"].cpu().numpy().reshape(-1)))
+
+
+def test_planned_trainer_matches_the_checked_one(gb):
+    """Trainer.plan sizes the capacity up front and drops the per-step host check; the
+    losses must follow those of the trainer that checks (and re-plans) every step."""
+    from paper_2412_12734_amd import train as T
+    raw, tgt, views, batches = sg.train_config(seed=2, P=4000, n_views=8, res=(80, 48))
+    tst = T.TrainState(tgt, bf16=False)
+    rast = gb.Rasterizer(views)
+    targets = rast.forward(tst.activate())[0].view(len(views), -1, 3).clone()
+    sched = batches(5)
+    runs = []
+    for planned in (False, True):
+        tr = T.Trainer(T.TrainState(raw, bf16=True), views, targets)
+        if planned:
+            assert tr.plan(sched) > 0 and not tr.rast.check_overflow
+        runs.append([float(tr.step(b)) for b in sched])
+        assert not tr.overflowed()
+    np.testing.assert_allclose(runs[1], runs[0], rtol=1e-5)
