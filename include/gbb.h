@@ -90,10 +90,15 @@ typedef struct {
                          else 32), or 8, 16, 32 */
   int32_t prefix_pairs_per_tile;
                       /* depth-prefix split. The first pass renders the longest prefix of the
-                         depth order whose pairs fit this many pairs per tile (0 = default 512);
+                         depth order whose pairs fit this many pairs per tile (0 = default 1024);
                          a second pass renders the remaining records on the tiles where some
                          pixel is still open (not stopped by t_min). Results are those of one
                          pass over all pairs. -1 = a single pass over all pairs. */
+  int32_t tile_order; /* order in which workgroups take tiles in the blend backward: 0 = default
+                         (1), 1 = most work first (ranked on the device by the pair span each
+                         tile blended in the forward), -1 = fixed bands of neighbouring tiles
+                         per XCD (the forward always uses these). Results are the same either
+                         way, up to the order of the backward's float atomics. */
 } gb_options;
 
 /* Output gradients (device, float32, overwritten -- not accumulated). */
@@ -133,6 +138,10 @@ typedef struct {
   size_t n_last_rest;
   size_t open_tiles;        /* uint32[ceil(tiles / 32)]: bit t set if tile t had an open pixel
                                after the first pass */
+  size_t tile_order;        /* with work-ordered tiles (else 0): uint32[total tiles], the tile
+                               taken by each workgroup of the backward */
+  size_t tile_work;         /* with work-ordered tiles (else 0): uint32[total tiles], the
+                               tile's blended span over both passes (the backward's cost) */
 } gb_layout;
 
 /* Workspace layout for P splats of texture side N over n_views views with room for

@@ -41,7 +41,8 @@ class GbOptions(ctypes.Structure):
     _fields_ = [("sigma", c_float), ("alpha_min", c_float), ("alpha_max", c_float),
                 ("t_min", c_float), ("lowpass_var", c_float), ("bg", c_float * 3),
                 ("tile_w", c_int32), ("tile_h", c_int32), ("batch", c_int32),
-                ("batch_bwd", c_int32), ("prefix_pairs_per_tile", c_int32)]
+                ("batch_bwd", c_int32), ("prefix_pairs_per_tile", c_int32),
+                ("tile_order", c_int32)]
 
 
 class GbGrads(ctypes.Structure):
@@ -56,7 +57,8 @@ class GbLayout(ctypes.Structure):
                 ("n_last", c_size_t), ("pair_capacity", c_int64), ("total_tiles", c_int64),
                 ("prefix_capacity", c_int64), ("pair_keys_rest", c_size_t),
                 ("pair_vals_rest", c_size_t), ("ranges_rest", c_size_t),
-                ("n_last_rest", c_size_t), ("open_tiles", c_size_t)]
+                ("n_last_rest", c_size_t), ("open_tiles", c_size_t), ("tile_order", c_size_t),
+                ("tile_work", c_size_t)]
 
 
 class GbbError(RuntimeError):
@@ -137,6 +139,6 @@ def make_views(views) -> ctypes.Array:
 
 def make_options(sigma=0.5, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4,
                  lowpass_var=0.5, bg=(0.0, 0.0, 0.0), tile_w=16, tile_h=16, batch=0,
-                 batch_bwd=0, prefix_pairs_per_tile=0) -> GbOptions:
+                 batch_bwd=0, prefix_pairs_per_tile=0, tile_order=0) -> GbOptions:
     return GbOptions(sigma, alpha_min, alpha_max, t_min, lowpass_var, (c_float * 3)(*bg),
-                     tile_w, tile_h, batch, batch_bwd, prefix_pairs_per_tile)
+                     tile_w, tile_h, batch, batch_bwd, prefix_pairs_per_tile, tile_order)

@@ -25,18 +25,21 @@ KNOBS: Dict[str, List] = {
     "tile": [(16, 16), (16, 8), (8, 8)],
     "batch": [8, 16, 32, 64],
     "batch_bwd": [8, 16, 32],
-    "prefix_pairs_per_tile": [256, 512, 1024, -1],
+    "prefix_pairs_per_tile": [256, 512, 1024, 2048, -1],
+    "tile_order": [1, -1],
 }
 
 
 def resolve_defaults(opts, N: int):
     """The options with the library's defaults written out (batch 0 -> 16 or 64, batch_bwd 0 ->
-    8 or 32, prefix budget 0 -> 512 pairs per tile), so that search results are explicit."""
+    8 or 32, prefix budget 0 -> 1024 pairs per tile, tile order 0 -> 1), so that search
+    results are explicit."""
     return dataclasses.replace(
         opts,
         batch=opts.batch or (16 if N >= 8 else 64),
         batch_bwd=opts.batch_bwd or (8 if N >= 8 else 32),
-        prefix_pairs_per_tile=opts.prefix_pairs_per_tile or 512)
+        prefix_pairs_per_tile=opts.prefix_pairs_per_tile or 1024,
+        tile_order=opts.tile_order or 1)
 
 
 def workload_key(N: int, bf16: bool, P: int, view_sizes: Iterable[Tuple[int, int]]) -> str:

@@ -383,7 +383,8 @@ hipError_t launch_np(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
                      const ViewDev* views, const SplatRec* rec, const PairList& first,
                      const PairList& rest, const uint32_t* open_bits, const float* T_final,
                      const float* d_rgb, float* d_rec, float* d_tex, hipStream_t s) {
-  const dim3 grid((unsigned)(8 * (int64_t)bp.tiles_per_xcd));
+  const dim3 grid((unsigned)(bp.tile_order ? (int64_t)bp.total_tiles
+                                           : 8 * (int64_t)bp.tiles_per_xcd));
   const dim3 block((unsigned)(pl.tile_w * pl.tile_h / PIX));
 #define GBB_BWD_B(BB)                                                                         \
   hipLaunchKernelGGL((blend_bwd_kernel<N, BF16, BB, PIX>), grid, block, 0, s, views, rec, first, \
@@ -402,9 +403,11 @@ hipError_t launch_np(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
 hipError_t launch_blend_bwd(const Plan& pl, const gb_splats& sp, const gb_options& o,
                             const ViewDev* views, int n_views, const SplatRec* rec,
                             const PairList& first, const PairList& rest,
-                            const uint32_t* open_bits, const float* T_final, const float* d_rgb,
-                            float* d_rec, float* d_tex, hipStream_t s) {
-  const BlendParams bp = make_blend_params(pl, o, n_views);
+                            const uint32_t* open_bits, const uint32_t* tile_order,
+                            const float* T_final, const float* d_rgb, float* d_rec,
+                            float* d_tex, hipStream_t s) {
+  BlendParams bp = make_blend_params(pl, o, n_views);
+  bp.tile_order = tile_order;
   const bool bf = sp.tex_dtype == GB_BF16;
   // One pixel per lane. Two pixels per lane (8 x 16 wave blocks) measured slower on the
   // 1M-splat 1080p workload (3.0 vs 2.3 ms): LDS limits such blocks to two waves per SIMD and

@@ -20,14 +20,19 @@ struct BlendParams {
   int32_t n_views;
   int32_t total_tiles;
   int32_t tiles_per_xcd;
+  const uint32_t* tile_order;  // nullable: workgroup b takes tile tile_order[b]
+  uint32_t* tile_work;         // nullable: per-tile blended span written by the forward
 };
 
 BlendParams make_blend_params(const Plan& pl, const gb_options& o, int n_views);
 
-// Workgroups are handed to the 8 XCDs round-robin; give each XCD one contiguous band of
-// tiles so that neighbouring tiles (which share splats) hit the same L2.
+// Without a work order, workgroups (handed to the 8 XCDs round-robin) take one contiguous
+// band of tiles per XCD, so that neighbouring tiles (which share splats) hit the same L2.
+// With one, the tiles with the most work start first, round-robin over the XCDs, which
+// shortens the tail of the launch and balances the XCDs.
 __device__ __forceinline__ int tile_of_block(const BlendParams& p) {
   const int b = blockIdx.x;
+  if (p.tile_order) return b < p.total_tiles ? (int)p.tile_order[b] : p.total_tiles;
   return (b & 7) * p.tiles_per_xcd + (b >> 3);
 }
 

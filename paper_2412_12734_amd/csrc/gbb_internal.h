@@ -91,6 +91,7 @@ struct Plan {
   int32_t tile_w, tile_h, batch_fwd, batch_bwd;
   int32_t tile_bits;
   bool split;            // depth-prefix split enabled
+  bool ordered;          // blend workgroups take tiles in work order (else fixed XCD bands)
   int64_t prefix_cap;    // pair slots of the prefix pass (0 without the split)
   int64_t nb_vp;      // radix blocks over V*P records
   int64_t nb_pairs;   // radix blocks over the pair capacity
@@ -100,7 +101,8 @@ struct Plan {
       off_pair_keys_alt, off_pair_vals_alt, off_ranges, off_n_last, off_drec, off_stats,
       off_partials64,
       off_ranges_rest, off_n_last_rest, off_fwd_state, off_open_bits,
-      off_count_rest, off_offsets_rest, off_chunk_owner, off_sat, total;
+      off_count_rest, off_offsets_rest, off_chunk_owner, off_sat, off_tile_order,
+      off_tile_work, total;
   int64_t n_chunks;  // entries of the chunk-owner table
   int64_t sat_len;   // entries of the open-tile summed-area tables of all views
   int64_t partials_len, hist_len;
@@ -181,19 +183,29 @@ hipError_t launch_duplicate_rest(const uint32_t* order, const uint32_t* count_re
 // Tile ranges of the first *d_n sorted keys.
 hipError_t launch_ranges(const uint32_t* pair_keys, const uint32_t* d_n, int64_t n_cap,
                          uint32_t* ranges, hipStream_t s);
+// Work order of the tiles: order[0..n_tiles) is a permutation of the tiles by decreasing
+// cost work[t]. Costs are compared in buckets (exact below 16, then 1/16 of the cost wide);
+// the order inside a bucket is unspecified. One workgroup; n_tiles <= kMaxOrderedTiles.
+constexpr int64_t kMaxOrderedTiles = (int64_t)1 << 20;
+hipError_t launch_order_tiles(const uint32_t* work, int64_t n_tiles, uint32_t* order,
+                              hipStream_t s);
 // Forward blend of one pass (mode in split.mode). REST launches the open-tile kernel.
+// tile_work (nullable): per tile, the span of pairs (first pair to one past the last pair any
+// pixel blended) is written by the first pass and added to by the rest pass.
 hipError_t launch_blend_fwd(const Plan& pl, const gb_splats& sp, const gb_options& o,
                             const ViewDev* views, int n_views, const SplatRec* rec,
                             const uint32_t* pair_vals, const uint32_t* ranges, float* rgb,
                             float* T_final, uint32_t* n_last, const SplitState& split,
-                            unsigned long long* stats, hipStream_t s);
+                            uint32_t* tile_work, unsigned long long* stats, hipStream_t s);
 // Backward blend over the prefix (or only) pass's pairs `first`; with open_bits != null the
-// tiles marked there first walk `rest` (the rest pass's pairs).
+// tiles marked there first walk `rest` (the rest pass's pairs). tile_order (nullable):
+// workgroup b takes tile tile_order[b].
 hipError_t launch_blend_bwd(const Plan& pl, const gb_splats& sp, const gb_options& o,
                             const ViewDev* views, int n_views, const SplatRec* rec,
                             const PairList& first, const PairList& rest,
-                            const uint32_t* open_bits, const float* T_final, const float* d_rgb,
-                            float* d_rec, float* d_tex, hipStream_t s);
+                            const uint32_t* open_bits, const uint32_t* tile_order,
+                            const float* T_final, const float* d_rgb, float* d_rec,
+                            float* d_tex, hipStream_t s);
 // Training glue (train.hip).
 hipError_t launch_activate_fwd(int P, const float* quats, const float* log_scales,
                                const float* logits, float* tan_u, float* tan_v, float* scales,

@@ -365,7 +365,87 @@ __global__ void ranges_kernel(const uint32_t* __restrict__ keys, const uint32_t*
   }
 }
 
+// Work order of the tiles for the backward launch: a counting sort of the tiles by a
+// bucketed cost, most work first, in one workgroup (two passes over the tiles with four
+// loads in flight per thread, and a scan of the bucket counts in between).
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBuckets = 512;
+constexpr int kOrderUnroll = 4;
+
+// Monotone bucket of a cost: exact below 16, then 16 buckets per octave (steps of at most
+// 1/16 of the cost); at most 463 for 32-bit costs.
+__device__ __forceinline__ uint32_t cost_bucket(uint32_t c) {
+  if (c < 16u) return c;
+  const uint32_t e = 31u - (uint32_t)__clz(c);  // >= 4
+  return 16u * (e - 3u) + ((c >> (e - 4u)) & 15u);
+}
+
+__global__ void __launch_bounds__(kOrderThreads)
+order_tiles_kernel(const uint32_t* __restrict__ work, int n, uint32_t* __restrict__ order) {
+  __shared__ uint32_t s_next[kOrderBuckets];
+  __shared__ uint32_t s_wave[kOrderBuckets / 64];
+  const int tid = threadIdx.x, lane = tid & 63;
+  // slot of tile t: buckets reversed, so that the most work comes first
+  auto slots = [&](int t0, uint32_t (&sl)[kOrderUnroll]) {
+    uint32_t c[kOrderUnroll];
+#pragma unroll
+    for (int k = 0; k < kOrderUnroll; ++k) {
+      const int t = t0 + k * kOrderThreads;
+      c[k] = t < n ? work[t] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kOrderUnroll; ++k)
+      sl[k] = (uint32_t)(kOrderBuckets - 1) - cost_bucket(c[k]);
+  };
+  for (int i = tid; i < kOrderBuckets; i += kOrderThreads) s_next[i] = 0u;
+  __syncthreads();
+  for (int t0 = tid; t0 < n; t0 += kOrderUnroll * kOrderThreads) {
+    uint32_t sl[kOrderUnroll];
+    slots(t0, sl);
+#pragma unroll
+    for (int k = 0; k < kOrderUnroll; ++k)
+      if (t0 + k * kOrderThreads < n) atomicAdd(&s_next[sl[k]], 1u);
+  }
+  __syncthreads();
+  // exclusive scan of the bucket counts: threads 0..511 are eight whole waves
+  uint32_t v = 0u, incl = 0u;
+  if (tid < kOrderBuckets) {
+    v = s_next[tid];
+    incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t u = (uint32_t)__shfl_up((int)incl, d, 64);
+      if (lane >= d) incl += u;
+    }
+    if (lane == 63) s_wave[tid >> 6] = incl;
+  }
+  __syncthreads();
+  if (tid < kOrderBuckets) {
+    uint32_t base = 0u;
+    for (int w = 0; w < (tid >> 6); ++w) base += s_wave[w];
+    s_next[tid] = base + incl - v;
+  }
+  __syncthreads();
+  for (int t0 = tid; t0 < n; t0 += kOrderUnroll * kOrderThreads) {
+    uint32_t sl[kOrderUnroll];
+    slots(t0, sl);
+#pragma unroll
+    for (int k = 0; k < kOrderUnroll; ++k) {
+      const int t = t0 + k * kOrderThreads;
+      if (t < n) order[atomicAdd(&s_next[sl[k]], 1u)] = (uint32_t)t;
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_order_tiles(const uint32_t* work, int64_t n_tiles, uint32_t* order,
+                              hipStream_t s) {
+  if (n_tiles < 1 || n_tiles > kMaxOrderedTiles || !work || !order) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(order_tiles_kernel, dim3(1), dim3(kOrderThreads), 0, s, work, (int)n_tiles,
+                     order);
+  return hipGetLastError();
+}
 
 hipError_t launch_finalize_count(const uint32_t* offsets, int64_t VP, Status* st,
                                  int64_t capacity, hipStream_t s) {

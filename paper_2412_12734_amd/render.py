@@ -28,11 +28,15 @@ class Options:
     batch_bwd: int = 0
     # depth-prefix split: pairs per tile of the first pass (0 = default), -1 = one pass
     prefix_pairs_per_tile: int = 0
+    # order of the tiles over the blend workgroups: 0 = default, 1 = most work first,
+    # -1 = fixed bands of neighbouring tiles per XCD
+    tile_order: int = 0
 
     def c(self) -> L.GbOptions:
         return L.make_options(self.sigma, self.alpha_min, self.alpha_max, self.t_min,
                               self.lowpass_var, tuple(self.bg), self.tile_w, self.tile_h,
-                              self.batch, self.batch_bwd, self.prefix_pairs_per_tile)
+                              self.batch, self.batch_bwd, self.prefix_pairs_per_tile,
+                              self.tile_order)
 
 
 def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:

@@ -40,9 +40,9 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_header_layout():
     # gb_view: 2 ints + 4 floats + 9 + 3 + 1 floats
     assert ctypes.sizeof(L.GbView) == 4 * (2 + 4 + 9 + 3 + 1)
-    assert ctypes.sizeof(L.GbOptions) == 4 * (5 + 3 + 5)
+    assert ctypes.sizeof(L.GbOptions) == 4 * (5 + 3 + 6)
     assert ctypes.sizeof(L.GbSplats) == 16 + 6 * 8
-    assert ctypes.sizeof(L.GbLayout) == 8 * 18
+    assert ctypes.sizeof(L.GbLayout) == 8 * 20
 
 
 def test_default_options():
@@ -53,7 +53,8 @@ def test_default_options():
     assert o.alpha_min == np.float32(1 / 255)
     assert o.alpha_max == pytest.approx(0.99)
     assert o.t_min == pytest.approx(1e-4)
-    assert (o.tile_w, o.tile_h, o.batch, o.batch_bwd, o.prefix_pairs_per_tile) == (16, 16, 0, 0, 0)
+    assert (o.tile_w, o.tile_h, o.batch, o.batch_bwd, o.prefix_pairs_per_tile,
+            o.tile_order) == (16, 16, 0, 0, 0, 0)
 
 
 def _layout(P=100, N=4, views=None, opts=None, cap=1000):
@@ -71,20 +72,21 @@ def test_layout_sections_are_aligned_and_disjoint():
     assert st == L.GB_OK
     offs = [lay.status, lay.depth_key, lay.tile_count, lay.records, lay.order, lay.pair_keys,
             lay.pair_vals, lay.ranges, lay.n_last, lay.pair_keys_rest, lay.pair_vals_rest,
-            lay.ranges_rest, lay.n_last_rest, lay.open_tiles]
+            lay.ranges_rest, lay.n_last_rest, lay.open_tiles, lay.tile_order, lay.tile_work]
     assert all(o % 256 == 0 for o in offs)
     assert len(set(offs)) == len(offs)
     assert max(offs) < lay.total_bytes
     assert lay.pair_capacity == 12345
     assert lay.total_tiles == 4 * 3 + 3 * 2
-    # the depth-prefix pass gets 512 pairs per tile by default, rounded up to 1024 slots
-    assert lay.prefix_capacity == 9216
+    # the depth-prefix pass gets 1024 pairs per tile by default, rounded up to 1024 slots
+    assert lay.prefix_capacity == 18 * 1024
     assert lay.pair_keys_rest == lay.pair_keys + 4 * lay.prefix_capacity
 
 
 @pytest.mark.parametrize("field,value,status", [
     ("tile_w", 12, L.GB_ERR_ARG), ("tile_h", 64, L.GB_ERR_ARG), ("batch", 7, L.GB_ERR_ARG),
     ("batch_bwd", 64, L.GB_ERR_ARG), ("prefix_pairs_per_tile", -2, L.GB_ERR_ARG),
+    ("tile_order", 2, L.GB_ERR_ARG), ("tile_order", -2, L.GB_ERR_ARG),
     ("sigma", 0.0, L.GB_ERR_ARG), ("alpha_max", 1.5, L.GB_ERR_ARG), ("t_min", -1.0, L.GB_ERR_ARG),
     ("lowpass_var", 0.0, L.GB_ERR_ARG),
 ])

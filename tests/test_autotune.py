@@ -11,20 +11,23 @@ from paper_2412_12734_amd.render import Options
 
 
 def synthetic_cost(o):
-    # separable bowl with its minimum at tile 16x8, batch 16, batch_bwd 8, prefix 1024
+    # separable bowl with its minimum at tile 16x8, batch 16, batch_bwd 8, prefix 2048,
+    # work-ordered tiles
     c = {(16, 16): 1.0, (16, 8): 0.5, (8, 8): 2.0}[(o.tile_w, o.tile_h)]
     c += {8: 0.3, 16: 0.0, 32: 0.2, 64: 0.9}[o.batch if o.batch else 16]
     c += {8: 0.0, 16: 0.4, 32: 1.5}[o.batch_bwd if o.batch_bwd else 8]
-    c += {256: 0.6, 512: 0.1, 1024: 0.0, -1: 3.0}[o.prefix_pairs_per_tile or 512]
+    c += {256: 0.6, 512: 0.1, 1024: 0.05, 2048: 0.0, -1: 3.0}[o.prefix_pairs_per_tile or 1024]
+    c += {1: 0.0, -1: 0.2}[o.tile_order or 1]
     return c
 
 
 def test_search_finds_the_separable_minimum():
     base = at.resolve_defaults(Options(), 8)
-    assert (base.batch, base.batch_bwd, base.prefix_pairs_per_tile) == (16, 8, 512)
+    assert (base.batch, base.batch_bwd, base.prefix_pairs_per_tile, base.tile_order) == \
+        (16, 8, 1024, 1)
     best, cost, log = at.search(base, synthetic_cost)
     assert (best.tile_w, best.tile_h, best.batch, best.batch_bwd,
-            best.prefix_pairs_per_tile) == (16, 8, 16, 8, 1024)
+            best.prefix_pairs_per_tile, best.tile_order) == (16, 8, 16, 8, 2048, 1)
     assert cost == pytest.approx(0.5)
     # the base is measured first and no candidate twice
     assert log[0][0] == base.__dict__

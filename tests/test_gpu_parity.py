@@ -388,6 +388,71 @@ def test_split_image_matches_oracle(gb):
     assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 128, 96)
 
 
+# --- work order of the tiles: a schedule, not a change of any result -------------------------
+def tile_spans(n_last, ranges, views, tw=16, th=16):
+    """Per tile: one past the last pair any of its pixels blended, minus the tile's first pair
+    (tiles numbered view by view, row-major)."""
+    out, base = [], 0
+    for v in views:
+        W, H = v.width, v.height
+        tx, ty = -(-W // tw), -(-H // th)
+        pad = np.zeros((ty * th, tx * tw), np.int64)
+        pad[:H, :W] = n_last[base:base + W * H].reshape(H, W)
+        out.append(pad.reshape(ty, th, tx, tw).max(axis=(1, 3)).reshape(-1))
+        base += W * H
+    top = np.concatenate(out)
+    return np.maximum(top - ranges[:, 0], 0)
+
+
+def assert_decreasing_in_buckets(cost):
+    # buckets are exact below 16 and 1/16 of the cost wide above: a later tile never costs
+    # more than 17/16 of an earlier one
+    prev_min = np.minimum.accumulate(cost)[:-1]
+    assert np.all(cost[1:] <= prev_min * 17 // 16 + 1)
+
+
+@pytest.mark.parametrize("prefix", [8, -1])
+def test_tile_order_changes_no_result(gb, prefix):
+    scene, view = dense_scene(N=8)
+    views = [view, sg.look_at_view((0.5, 0.3, -3.0), 72, 50)]
+    g = torch.from_numpy(sg.make_dl_drgb(3, views)).cuda()
+    runs = {}
+    for order in (-1, 1):
+        o = gpu_opts(O.Options(), prefix=prefix)
+        o.tile_order = order
+        sp = gb.Splats.from_numpy(scene)
+        rast = gb.Rasterizer(views, o)
+        rast.plan(sp)
+        rgb, T = rast.forward(sp)
+        grads = rast.backward(sp, T, g)
+        torch.cuda.synchronize()
+        runs[order] = (rast, rgb, T, rast.section("n_last", rast.total_pixels).clone(), grads)
+    (r0, rgb0, T0, nl0, g0), (r1, rgb1, T1, nl1, g1) = runs[-1], runs[1]
+    assert torch.equal(rgb0, rgb1) and torch.equal(T0, T1) and torch.equal(nl0, nl1)
+    for k in g0:  # only the order of the float atomics differs
+        assert rel_l2(g1[k].cpu().numpy().astype(np.float64),
+                      g0[k].cpu().numpy().astype(np.float64)) <= 1e-5, k
+    lay = r1.layout
+    n = lay.total_tiles
+    assert r0.layout.tile_order == 0 and lay.tile_order != 0
+    order = r1.section("tile_order", n).cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(np.sort(order), np.arange(n))
+    ranges = r1.section("ranges", 2 * n).cpu().numpy().view(np.uint32).reshape(n, 2)
+    ranges = ranges.astype(np.int64)
+    # the backward's cost: the blended span of the first pass plus, on open tiles, the rest's
+    work = r1.section("tile_work", n).cpu().numpy().view(np.uint32).astype(np.int64)
+    want = tile_spans(nl1.cpu().numpy().view(np.uint32), ranges, views)
+    if prefix >= 0:
+        bits = r1.section("open_tiles", (n + 31) // 32).cpu().numpy().view(np.uint32)
+        t = np.arange(n)
+        is_open = ((bits[t >> 5] >> (t & 31)) & 1).astype(bool)
+        rr = r1.section("ranges_rest", 2 * n).cpu().numpy().view(np.uint32).reshape(n, 2)
+        nlr = r1.section("n_last_rest", r1.total_pixels).cpu().numpy().view(np.uint32)
+        want = want + np.where(is_open, tile_spans(nlr, rr.astype(np.int64), views), 0)
+    np.testing.assert_array_equal(work, want)
+    assert_decreasing_in_buckets(work[order])
+
+
 # --- autotuner: whatever it picks keeps oracle parity ---------------------------------------
 def test_autotuned_options_keep_parity(gb, tmp_path):
     from paper_2412_12734_amd import autotune as at
