@@ -183,6 +183,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--train-iters", type=int, default=200)
+    ap.add_argument("--train-only", action="store_true",
+                    help="time only the optimisation-step variant (for kernel traces of it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the rasterizer has no "
@@ -194,6 +196,10 @@ def main():
     import scenegen as sg
 
     gb.load()
+    if args.train_only:
+        tr = train_variant(gb, sg, torch, warmup=args.warmup, iters=args.train_iters)
+        print(json.dumps({"train_step_500k_4x720p": tr}), flush=True)
+        return
     copy_gbs = copy_probe(torch)
     log(f"plain device copy of {COPY_BYTES >> 20} MiB: {copy_gbs:.0f} GB/s (read + write)")
     log("setting up T0 (1M splats, 8x8 FP32 textures, 1920x1080)")
