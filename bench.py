@@ -161,6 +161,61 @@ def train_variant(gb, sg, torch, warmup=20, iters=200):
     return out
 
 
+def c3_variant(gb, sg, torch, warmup, steps):
+    """1M splats with 4x4 FP32 textures, 16 views of uneven size on a radius-8 sphere: forward
+    + backward of all views as one batched step replayed from a HIP graph, against the same
+    views rendered one view per call (16 rasterizers, launched back to back)."""
+    scene, views = sg.config("C3")
+    sp = gb.Splats.from_numpy(scene)
+    g = torch.from_numpy(sg.make_dl_drgb(0, views)).cuda()
+    px = sum(v.width * v.height for v in views)
+    rast = gb.Rasterizer(views, gb.Options(), check_overflow=False)
+    rast.plan(sp)
+    rgb, T = rast.forward(sp)
+    grads = rast.backward(sp, T, g)
+    K, over = rast.status()
+    if over:
+        raise RuntimeError("pair capacity exceeded after planning")
+    graph = rast.capture_step(sp, rgb, T, g, grads)
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    s_batch = (time.perf_counter() - t0) / steps
+    del graph, rast
+    torch.cuda.empty_cache()
+    singles, at = [], 0
+    for v in views:  # one rasterizer per view; the gradient buffers are shared (overwritten)
+        r = gb.Rasterizer([v], gb.Options(), check_overflow=False)
+        r.plan(sp)
+        hw = v.width * v.height
+        singles.append((r, rgb[at:at + hw], T[at:at + hw], g[at:at + hw]))
+        at += hw
+
+    def single_step():
+        for r, rgb_i, T_i, g_i in singles:
+            r.forward(sp, rgb_i, T_i)
+            r.backward(sp, T_i, g_i, grads)
+
+    for _ in range(warmup):
+        single_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        single_step()
+    torch.cuda.synchronize()
+    s_single = (time.perf_counter() - t0) / steps
+    del singles, grads, rgb, T, g, sp
+    torch.cuda.empty_cache()
+    return {"batched_graph_ms": round(s_batch * 1e3, 3),
+            "single_view_calls_ms": round(s_single * 1e3, 3),
+            "speedup_batched": round(s_single / s_batch, 3),
+            "mpix_per_s_batched": round(px / s_batch / 1e6, 1), "pixels": px, "pairs": K}
+
+
 def cpu_baseline(scene, view, crop):
     """FP64 oracle (one process) on a crop of the workload: forward + analytic backward."""
     import numpy as np
@@ -238,6 +293,12 @@ def main():
     log("stages (ms): " + ", ".join(f"{k}={v:.3f}" for k, v in stages.items()))
 
     st = rast.blend_stats(sp, rgb, T)
+    # tiling overhead: pixel slots of the staged (tile, splat) pairs over the (pixel, splat)
+    # pairs the method needs (blended ones plus the one that stops each terminated pixel)
+    tile_px = rast.opts.tile_w * rast.opts.tile_h
+    st["e_contrib"] = st["blended"] + st["terminated"]
+    st["e_tile"] = st["staged"] * tile_px
+    st["tiling_overhead"] = round(st["e_tile"] / max(st["e_contrib"], 1), 3)
     # the dominant kernel is the blend backward: one launch walks the pairs of both passes of
     # the depth-prefix split, so its units are all blended pairs
     e_eval, e_blend = st["lane_evals"], st["blended"]
@@ -267,8 +328,16 @@ def main():
             rast_b.forward(sp_b, rgb_b, T_b)
             rast_b.backward(sp_b, T_b, g_b, grads_b)
         s_b = time_steps(rast_b, sp_b, rgb_b, T_b, g_b, grads_b, args.steps, torch)
-        variants["bf16_single_view"] = {"ms_per_step": round(s_b * 1e3, 3),
-                                        "mpix_per_s": round(pixels / s_b / 1e6, 1)}
+        # storage error of bfloat16 textures: the same scene rendered from FP32 textures
+        rgb_b, T_b = rast_b.forward(sp_b, rgb_b, T_b)
+        grads_b = rast_b.backward(sp_b, T_b, g_b, grads_b)
+        d_img = (rgb_b - rgb).abs()
+        rel = lambda a, b: float((a - b).double().norm() / b.double().norm().clamp_min(1e-30))
+        variants["bf16_single_view"] = {
+            "ms_per_step": round(s_b * 1e3, 3), "mpix_per_s": round(pixels / s_b / 1e6, 1),
+            "storage_error_vs_fp32_textures": {
+                "image_max_abs": float(d_img.max()), "image_rms": float(d_img.pow(2).mean().sqrt()),
+                "grad_rel_l2": {k: round(rel(grads_b[k], grads[k]), 7) for k in grads}}}
         del rast_b
         torch.cuda.empty_cache()
         log("variant: bf16 textures, four 1080p views batched in one call")
@@ -304,8 +373,11 @@ def main():
             "candidates_timed": len(rec["candidates"])}
         variants["speedup_autotuned_bf16_batched_vs_fp32_single"] = round(
             (px4 / s_t) / (pixels / sec), 3)
-        del rast_t, rgb_t, T_t, grads_t
+        del rast_t, rgb_t, T_t, grads_t, sp4, g4
         torch.cuda.empty_cache()
+        log("variant: 16 uneven views (1M splats, 4x4 textures) in one graph vs one at a time")
+        variants["c3_16_views"] = c3_variant(gb, sg, torch, args.warmup, args.steps)
+        log(f"c3: {variants['c3_16_views']}")
         log("variant: full optimisation step (500k splats, batch of 4 of 32 views at 1280x720)")
         variants["train_step_500k_4x720p"] = train_variant(gb, sg, torch,
                                                            iters=args.train_iters)

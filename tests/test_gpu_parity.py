@@ -295,6 +295,58 @@ def test_full_size_crop_parity(gb, name, vi):
     check_full_size_crop(gb, name, vi)
 
 
+# --- full-size invariants: properties that hold at any size, checked at 1M splats, 1080p ------
+def pixel_tile_index(views, tw=16, th=16):
+    """Global tile index of every packed pixel (views in order, row-major)."""
+    out, base = [], 0
+    for v in views:
+        tx = -(-v.width // tw)
+        j, i = np.divmod(np.arange(v.width * v.height), v.width)
+        out.append(base + (j // th) * tx + i // tw)
+        base += tx * -(-v.height // th)
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_full_size_weights_telescope(gb, bf16):
+    """Weights plus transmittance sum to one at every pixel whatever was skipped or stopped
+    (the weights telescope). With white textures and a black background a pixel shows the sum
+    of its weights, so rgb + T_final = 1; and because the bilinear weights of every pixel sum
+    to one, the texture gradients of dL/drgb = g summed over all splats and texels equal
+    sum_p (1 - T_p) g_p per channel. Checked on the 1M-splat 1920x1080 workload."""
+    scene, views = sg.config("T0")
+    white = sg.Scene(scene.means, scene.tan_u, scene.tan_v, scene.scales, scene.opacity,
+                     np.ones_like(scene.textures))
+    sp = gb.Splats.from_numpy(white, tex_bf16=bf16)
+    rast = gb.Rasterizer(views)
+    rast.plan(sp)
+    rgb, T = rast.forward(sp)
+    g = torch.from_numpy(sg.make_dl_drgb(0, views)).cuda()
+    grads = rast.backward(sp, T, g)
+    torch.cuda.synchronize()
+    rgb_h = rgb.cpu().numpy().astype(np.float64)
+    T_h = T.cpu().numpy().astype(np.float64)
+    # pairs each pixel walked (an upper bound of its blended splats); a blended step rounds
+    # the weight, the sum, 1 - alpha and T once each: at most 4 units of 2^-24 of acc + T ~ 1
+    n = rast.total_pixels
+    tiles = rast.layout.total_tiles
+    pt = pixel_tile_index(views)
+    r1 = rast.section("ranges", 2 * tiles).cpu().numpy().view(np.uint32).reshape(-1, 2)
+    steps = rast.section("n_last", n).cpu().numpy().view(np.uint32).astype(np.int64) - r1[pt, 0]
+    bits = rast.section("open_tiles", (tiles + 31) // 32).cpu().numpy().view(np.uint32)
+    is_open = ((bits[pt >> 5] >> (pt & 31)) & 1).astype(bool)
+    r2 = rast.section("ranges_rest", 2 * tiles).cpu().numpy().view(np.uint32).reshape(-1, 2)
+    nl2 = rast.section("n_last_rest", n).cpu().numpy().view(np.uint32).astype(np.int64)
+    steps = steps + np.where(is_open, nl2 - r2[pt, 0], 0)
+    bound = 4.0 * 2.0 ** -24 * (steps + 2)
+    err = np.abs(rgb_h + T_h[:, None] - 1.0)
+    print(f"max |rgb + T - 1| = {err.max():.3g}, max steps {steps.max()}")
+    assert np.all(err <= bound[:, None])
+    want = ((1.0 - T_h)[:, None] * sg.make_dl_drgb(0, views).astype(np.float64)).sum(0)
+    got = grads["textures"].double().sum(dim=(0, 1, 2)).cpu().numpy()
+    np.testing.assert_allclose(got, want, rtol=1e-5)
+
+
 # --- LDS batch sizes: same images, gradients within tolerance -------------------------------
 @pytest.mark.parametrize("batch,batch_bwd", [(8, 8), (16, 32), (64, 16), (32, 8)])
 def test_batch_sizes(gb, batch, batch_bwd):
