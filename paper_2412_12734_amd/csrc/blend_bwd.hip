@@ -38,25 +38,23 @@ struct PixOut {
   float gh[7], gc2x, gc2y, go;   // record gradients
 };
 
+// One (pixel, splat) step of the reverse walk. `act`: the pixel blended this splat. A lane
+// that did not runs the same arithmetic with a zero weight and adjoint and a unit
+// transmittance factor, so that all of its outputs are zero and its state is unchanged
+// without a branch or zeroed outputs; its u, v and 1 / rho2 are replaced by 0 (they are
+// infinite where rho2 = 0). Its cell and corner weights are left unspecified.
 template <int N>
-__device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex, float lx,
-                                           float ly, uint32_t jg, PixState& ps,
+__device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex,
+                                           const PixelEval& e, bool act, PixState& ps,
                                            const BlendParams& p, PixOut& o) {
-  o.act = false;
-  o.k00 = 0;
-  o.w[0] = o.w[1] = o.w[2] = o.w[3] = 0.f;
-  o.dc0 = o.dc1 = o.dc2 = 0.f;
-#pragma unroll
-  for (int k = 0; k < 7; ++k) o.gh[k] = 0.f;
-  o.gc2x = o.gc2y = o.go = 0.f;
-  const PixelEval e = eval_splat(g, lx, ly, p);
-  if (!((jg < ps.last) && e.hit)) return;
-  o.act = true;
-  const float inv1m = __builtin_amdgcn_rcpf(1.0f - e.alpha);
+  o.act = act;
+  const float inv = act ? e.inv : 0.f;
+  const float u = act ? e.u : 0.f, v = act ? e.v : 0.f;
+  const float inv1m = act ? __builtin_amdgcn_rcpf(1.0f - e.alpha) : 1.0f;
   ps.T = ps.T * inv1m;  // transmittance in front of this splat
   float c0, c1, c2;
   float du = 0.f, dv = 0.f;
-  const float wgt = e.alpha * ps.T;
+  const float wgt = act ? e.alpha * ps.T : 0.f;
   o.dc0 = wgt * ps.g0;
   o.dc1 = wgt * ps.g1;
   o.dc2 = wgt * ps.g2;
@@ -65,12 +63,14 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
     c0 = t.x;
     c1 = t.y;
     c2 = t.z;
+    o.k00 = 0;
     o.w[0] = 1.f;
+    o.w[1] = o.w[2] = o.w[3] = 0.f;
   } else {
     int iu, iv;
     float fu, fv;
-    grid_coord<N>(e.u, p, iu, fu);
-    grid_coord<N>(e.v, p, iv, fv);
+    grid_coord<N>(u, p, iu, fu);
+    grid_coord<N>(v, p, iv, fv);
     o.k00 = iu * N + iv;
     const int l00 = TexLayout<N>::at(iu, iv), kr = TexLayout<N>::kRow;
     const float4 t00 = tex[l00], t01 = tex[l00 + 1], t10 = tex[l00 + kr], t11 = tex[l00 + kr + 1];
@@ -90,11 +90,12 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
     const float fv1 = (t01.y - t00.y) * (1.f - fu) + (t11.y - t10.y) * fu;
     const float fv2 = (t01.z - t00.z) * (1.f - fu) + (t11.z - t10.z) * fu;
     const float dfv = o.dc0 * fv0 + o.dc1 * fv1 + o.dc2 * fv2;
-    du = (e.u > -p.sigma && e.u < p.sigma) ? p.tex_scale * dfu : 0.f;
-    dv = (e.v > -p.sigma && e.v < p.sigma) ? p.tex_scale * dfv : 0.f;
+    du = (u > -p.sigma && u < p.sigma) ? p.tex_scale * dfu : 0.f;
+    dv = (v > -p.sigma && v < p.sigma) ? p.tex_scale * dfv : 0.f;
   }
-  const float dalpha = ps.g0 * (c0 * ps.T - ps.S0 * inv1m) + ps.g1 * (c1 * ps.T - ps.S1 * inv1m) +
-                       ps.g2 * (c2 * ps.T - ps.S2 * inv1m);
+  const float dalpha_act = ps.g0 * (c0 * ps.T - ps.S0 * inv1m) +
+                           ps.g1 * (c1 * ps.T - ps.S1 * inv1m) + ps.g2 * (c2 * ps.T - ps.S2 * inv1m);
+  const float dalpha = act ? dalpha_act : 0.f;
   ps.S0 += wgt * c0;
   ps.S1 += wgt * c1;
   ps.S2 += wgt * c2;
@@ -103,14 +104,14 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
   const float dq = unclamped ? -e.G * g.g0.w * dalpha : 0.f;
   float ddx = 0.f, ddy = 0.f;
   if (e.uv_branch) {
-    du += dq * e.u;
-    dv += dq * e.v;
+    du += dq * u;
+    dv += dq * v;
   } else {
     ddx = dq * 2.f * p.lp_scale * e.dx;
     ddy = dq * 2.f * p.lp_scale * e.dy;
   }
-  const float dr0 = du * e.inv, dr1 = dv * e.inv;
-  const float dr2 = -(du * e.u + dv * e.v) * e.inv;
+  const float dr0 = du * inv, dr1 = dv * inv;
+  const float dr2 = -(du * u + dv * v) * inv;
   o.gh[0] = dr0 * e.dx;
   o.gh[1] = dr0 * e.dy;
   o.gh[2] = dr1 * e.dx;
@@ -264,13 +265,18 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
         g.g1 = s_geo[j][1];
         g.g2 = s_geo[j][2];
         const float4* tex = s_tex + j * TexLayout<N>::kPerSplat;
+        PixelEval e[PIX];
+        bool act[PIX], wave_act = false;
+#pragma unroll
+        for (int s = 0; s < PIX; ++s) {
+          e[s] = eval_splat(g, lx, ly[s], p);
+          act[s] = (jg < ps[s].last) && e[s].hit;
+          wave_act = wave_act || act[s];
+        }
+        if (!__any(wave_act)) continue;  // no pixel of the wave blended this splat
         PixOut po[PIX];
 #pragma unroll
-        for (int s = 0; s < PIX; ++s) pixel_step<N>(g, tex, lx, ly[s], jg, ps[s], p, po[s]);
-        bool wave_act = false;
-#pragma unroll
-        for (int s = 0; s < PIX; ++s) wave_act = wave_act || po[s].act;
-        if (!__any(wave_act)) continue;  // no pixel of the wave blended this splat
+        for (int s = 0; s < PIX; ++s) pixel_step<N>(g, tex, e[s], act[s], ps[s], p, po[s]);
 
         // Row sums of the per-splat scalars (a lane first adds its own pixels); each total lands
         // in one lane of the row, which adds it to the row's LDS slot.

@@ -75,7 +75,8 @@ template <int N>
 struct TexLayout {
   static constexpr int kRow = N + 1;
   static constexpr int kPerSplat = N * (N + 1);
-  __device__ static constexpr int at(int iu, int iv) { return iu * kRow + iv; }
+  // a 24-bit multiply (full rate; a 32-bit integer multiply is quarter rate): iu < N
+  __device__ static int at(int iu, int iv) { return (int)__umul24((unsigned)iu, kRow) + iv; }
 };
 
 // Copies the texels of `nb` staged splats into LDS as float4 (RGB + pad) per texel. For even
@@ -205,7 +206,7 @@ __device__ __forceinline__ bool block_may_contribute(const StagedGeo& s, float c
 template <int N>
 __device__ __forceinline__ void grid_coord(float u, const BlendParams& p, int& i, float& f) {
   const float up = fminf(fmaxf(__builtin_fmaf(u, p.tex_scale, p.tex_offset), 0.0f), (float)(N - 1));
-  const int fi = (int)floorf(up);
+  const int fi = (int)up;  // up >= 0, so truncation is the floor
   i = fi < N - 2 ? fi : N - 2;
   f = up - (float)i;
 }
