@@ -83,6 +83,19 @@ def test_layout_sections_are_aligned_and_disjoint():
     assert lay.pair_keys_rest == lay.pair_keys + 4 * lay.prefix_capacity
 
 
+def test_tile_order_sections_follow_the_option():
+    views = [sg.look_at_view((0, 0, -3), 64, 48)]
+    st, lay = _layout(P=1000, views=views, cap=5000)
+    assert st == L.GB_OK
+    # default: work-ordered backward, with its order and the forward's spans in the workspace
+    assert lay.tile_order % 256 == 0 and lay.tile_work % 256 == 0
+    assert 0 < lay.tile_order < lay.tile_work < lay.total_bytes
+    o = L.make_options(tile_order=-1)
+    st, lay2 = _layout(P=1000, views=views, opts=o, cap=5000)
+    assert st == L.GB_OK and lay2.tile_order == 0 and lay2.tile_work == 0
+    assert lay2.total_bytes <= lay.total_bytes
+
+
 @pytest.mark.parametrize("field,value,status", [
     ("tile_w", 12, L.GB_ERR_ARG), ("tile_h", 64, L.GB_ERR_ARG), ("batch", 7, L.GB_ERR_ARG),
     ("batch_bwd", 64, L.GB_ERR_ARG), ("prefix_pairs_per_tile", -2, L.GB_ERR_ARG),
