@@ -423,11 +423,12 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   uint32_t* tile_work = pl.ordered ? at<uint32_t>(ws, pl.off_tile_work) : nullptr;
   if (stats)
     GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_stats), 0u, 16, hs), "clear stats");
-  SplitState split{kSinglePass, nullptr, nullptr};
+  SplitState split{kSinglePass, nullptr, nullptr, nullptr};
   if (pl.split) {
     split.mode = kPrefixPass;
     split.open_bits = at<uint32_t>(ws, pl.off_open_bits);
     split.fwd_state = at<float4>(ws, pl.off_fwd_state);
+    split.any_open = &d_st->any_open;  // cleared by the count's finalisation
     GBB_TRY(launch_fill_u32(split.open_bits, 0u, (pl.total_tiles + 31) / 32, hs), "clear bits");
   }
   GBB_TRY(stage_mark(kStBlendFwd, 0, hs), "timing");

@@ -182,7 +182,10 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   if (!REST && split.mode == kPrefixPass) {
     // a tile with an open pixel takes part in the rest pass
     if (!__syncthreads_and(done)) {
-      if (tid == 0) atomicOr(&split.open_bits[tile >> 5], 1u << (tile & 31));
+      if (tid == 0) {
+        atomicOr(&split.open_bits[tile >> 5], 1u << (tile & 31));
+        atomicOr(split.any_open, 1u);
+      }
       if (inside) split.fwd_state[pix] = make_float4(acc0, acc1, acc2, done ? 1.f : 0.f);
     }
   }

@@ -59,6 +59,7 @@ struct Status {
   unsigned long long K_rest64;  // exact total of the second pass
   uint32_t last_first; // depth rank of the record owning the first pass's last pair slot
   uint32_t last_rest;  // the same for the second pass
+  uint32_t any_open;   // nonzero if the prefix pass left some tile open
 };
 
 // Depth-prefix split. The first pass renders the records of a prefix of the depth order
@@ -72,6 +73,7 @@ struct SplitState {
   int32_t mode;
   uint32_t* open_bits;  // one bit per global tile: set if the prefix left a pixel open
   float4* fwd_state;    // per pixel after the prefix: accumulated colour, done flag (0 / 1)
+  uint32_t* any_open;   // Status::any_open (prefix pass)
 };
 
 // The sorted pairs of one pass as the backward reads them.

@@ -42,6 +42,7 @@ __global__ void finalize_count_kernel(const uint32_t* __restrict__ offsets, int6
     st->n_sorted = over ? 0u : (uint32_t)K;
     st->cut = (uint32_t)VP;
     st->last_first = (!over && K > 0) ? (uint32_t)last_at_or_below(offsets, VP, K - 1) : 0u;
+    st->any_open = 0u;
   }
 }
 
@@ -256,7 +257,8 @@ count_rest_kernel(const uint32_t* __restrict__ order, const uint32_t* __restrict
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= VP) return;
   uint32_t c = 0;
-  if (!st->overflow && r >= (int64_t)st->cut) {
+  // with no open tile (the common case when the prefix budget suffices) no record is read
+  if (!st->overflow && st->any_open != 0u && r >= (int64_t)st->cut) {
     const uint32_t id = order[r];
     if (count[id] > 0) {
       const SplatRec& R = rec[id];
