@@ -157,6 +157,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   const bool tile_open = open_bits && ((open_bits[tile >> 5] >> (tile & 31)) & 1u) != 0;
   const int vi = view_of_tile(views, p.n_views, tile);
   const ViewDev& V = views[vi];
+  const uint32_t rec_base = (uint32_t)vi * (uint32_t)p.P;  // first record of the tile's view
   const int lt = tile - V.tile_base;
   const int tile_x0 = (lt % V.tiles_x) * p.tile_w;
   const int tile_y0 = (lt / V.tiles_x) * p.tile_h;
@@ -240,8 +241,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
       }
       for (int e = tid; e < nb * TEXG; e += nthr) s_gtex[e] = 0.f;
       for (int e = tid; e < nb * 4 * kRecGrad; e += nthr) s_grec[e] = 0.f;
-      __syncthreads();
-      stage_texels<N, BF16>(textures, s_splat, nb, s_tex);
+      stage_texels<N, BF16>(textures, pair_vals + bstart, rec_base, nb, s_tex);
       __syncthreads();
 
       // splats of this batch that can reach the wave's block, walked back to front

@@ -18,6 +18,7 @@ struct BlendParams {
   float bg[3];
   int32_t tile_w, tile_h;
   int32_t n_views;
+  int32_t P;          // splats per view: record v P + k is splat k seen from view v
   int32_t total_tiles;
   int32_t tiles_per_xcd;
   const uint32_t* tile_order;  // nullable: workgroup b takes tile tile_order[b]
@@ -79,19 +80,23 @@ struct TexLayout {
   __device__ static int at(int iu, int iv) { return (int)__umul24((unsigned)iu, kRow) + iv; }
 };
 
-// Copies the texels of `nb` staged splats into LDS as float4 (RGB + pad) per texel. For even
-// N a splat's 3 N^2 channel values split into groups of 12 (four texels): each thread moves
-// whole groups, three 16-byte (float32) or 8-byte (bfloat16) loads in, four LDS stores out.
+// Copies the texels of `nb` staged splats into LDS as float4 (RGB + pad) per texel. The j-th
+// splat is pairs[j] - rec_base: a tile's pairs all hold records of the tile's view, so the
+// splat follows from the pair list alone and the texel loads need not wait for the staged
+// records. For even N a splat's 3 N^2 channel values split into groups of 12 (four texels):
+// each thread moves whole groups, three 16-byte (float32) or 8-byte (bfloat16) loads in, four
+// LDS stores out.
 template <int N, bool BF16>
 __device__ __forceinline__ void stage_texels(const void* __restrict__ textures,
-                                             const int32_t* s_splat, int nb, float4* s_tex) {
+                                             const uint32_t* __restrict__ pairs,
+                                             uint32_t rec_base, int nb, float4* s_tex) {
   constexpr int per = 3 * N * N;  // channel values per splat
   const int tid = threadIdx.x, nthr = blockDim.x;
   if constexpr ((per % 12) == 0) {
     constexpr int groups = per / 12;  // = N^2 / 4
     for (int gi = tid; gi < nb * groups; gi += nthr) {
       const int j = gi / groups, a = gi - j * groups;
-      const int64_t src = ((int64_t)s_splat[j] * groups + a) * 3;
+      const int64_t src = ((int64_t)(pairs[j] - rec_base) * groups + a) * 3;
       float v[12];
       if constexpr (BF16) {
         const uint2* t = reinterpret_cast<const uint2*>(textures) + src;
@@ -124,11 +129,12 @@ __device__ __forceinline__ void stage_texels(const void* __restrict__ textures,
   } else {
     for (int e = tid; e < nb * per; e += nthr) {
       const int j = e / per, r = e - j * per;
+      const int64_t k = (int64_t)(pairs[j] - rec_base);
       float x;
       if constexpr (BF16)
-        x = bf16_to_f32(reinterpret_cast<const uint16_t*>(textures)[(int64_t)s_splat[j] * per + r]);
+        x = bf16_to_f32(reinterpret_cast<const uint16_t*>(textures)[k * per + r]);
       else
-        x = reinterpret_cast<const float*>(textures)[(int64_t)s_splat[j] * per + r];
+        x = reinterpret_cast<const float*>(textures)[k * per + r];
       const int t = r / 3, iu = t / N, iv = t - iu * N;
       reinterpret_cast<float*>(s_tex + j * TexLayout<N>::kPerSplat + TexLayout<N>::at(iu, iv))[r % 3] = x;
     }

@@ -30,7 +30,6 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
                  float* __restrict__ T_final, uint32_t* __restrict__ n_last, SplitState split,
                  unsigned long long* __restrict__ stats) {
   __shared__ float4 s_geo[B][4];
-  __shared__ int32_t s_splat[B];
   __shared__ float4 s_tex[B * TexLayout<N>::kPerSplat];
 
   const int tile = tile_of_block(p);
@@ -58,6 +57,7 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   const float bcx = (float)bx + 3.5f - 0.5f * (float)(p.tile_w - 1);
   const float bcy = (float)by + 3.5f - 0.5f * (float)(p.tile_h - 1);
 
+  const uint32_t rec_base = (uint32_t)vi * (uint32_t)p.P;  // first record of the tile's view
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
   const int64_t pix = (int64_t)V.pix_base + (int64_t)py * V.W + px;  // valid if inside
   float T = 1.0f;
@@ -86,10 +86,8 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
       s_geo[tid][1] = g.g1;
       s_geo[tid][2] = g.g2;
       s_geo[tid][3] = g.g3;
-      s_splat[tid] = R.splat;
     }
-    __syncthreads();
-    stage_texels<N, BF16>(textures, s_splat, nb, s_tex);
+    stage_texels<N, BF16>(textures, pair_vals + b0, rec_base, nb, s_tex);
     __syncthreads();
 
     if (!__all(done)) {
@@ -260,6 +258,7 @@ BlendParams make_blend_params(const Plan& pl, const gb_options& o, int n_views) 
   bp.tile_w = pl.tile_w;
   bp.tile_h = pl.tile_h;
   bp.n_views = n_views;
+  bp.P = pl.P;
   bp.total_tiles = (int32_t)pl.total_tiles;
   bp.tiles_per_xcd = (int32_t)((pl.total_tiles + 7) / 8);
   bp.tile_order = nullptr;
