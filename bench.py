@@ -340,6 +340,17 @@ def main():
                 "grad_rel_l2": {k: round(rel(grads_b[k], grads[k]), 7) for k in grads}}}
         del rast_b
         torch.cuda.empty_cache()
+        log("variant: 16 x 16 colour grids, one view")
+        _, _, sp_16, rast_16, g_16, rgb_16, T_16, grads_16, _ = setup(gb, sg, torch, "T0_N16")
+        for _ in range(args.warmup):
+            rast_16.forward(sp_16, rgb_16, T_16)
+            rast_16.backward(sp_16, T_16, g_16, grads_16)
+        s_16 = time_steps(rast_16, sp_16, rgb_16, T_16, g_16, grads_16, args.steps, torch)
+        variants["n16_single_view"] = {"ms_per_step": round(s_16 * 1e3, 3),
+                                       "mpix_per_s": round(pixels / s_16 / 1e6, 1),
+                                       "texels_per_splat": 256}
+        del rast_16, sp_16, rgb_16, T_16, grads_16, g_16
+        torch.cuda.empty_cache()
         log("variant: bf16 textures, four 1080p views batched in one call")
         views4 = sg.orbit_views(0, 4, 8.0, [(1920, 1080)])
         _, _, sp4, rast4, g4, rgb4, T4, grads4, K4 = setup(gb, sg, torch, "T0_BF16", views=views4)

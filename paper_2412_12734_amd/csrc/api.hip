@@ -83,8 +83,8 @@ gb_status validate_views(const gb_view* views, int32_t n_views) {
 gb_status validate_splats(const gb_splats* s) {
   if (!s) return arg_fail("splats is NULL");
   if (s->P < 1) return arg_fail("P must be >= 1");
-  if (!(s->N == 1 || s->N == 2 || s->N == 4 || s->N == 8)) {
-    g_last_error = "texture side N must be 1, 2, 4 or 8";
+  if (!(s->N == 1 || s->N == 2 || s->N == 4 || s->N == 8 || s->N == 16)) {
+    g_last_error = "texture side N must be 1, 2, 4, 8 or 16";
     return GB_ERR_UNSUPPORTED;
   }
   if (s->tex_dtype != GB_F32 && s->tex_dtype != GB_BF16) {
@@ -113,8 +113,14 @@ gb_status make_plan(int32_t P, int32_t N, const gb_view* views, int32_t n_views,
   // defaults: at N = 8 the smaller batches measured faster on the 1M-splat 1080p workload
   // (forward 16 vs 32: 0.50 vs 0.60 ms; backward 8 vs 16: 2.21 vs 2.31 ms), because less LDS
   // per block lets more blocks share a CU
-  pl->batch_fwd = o->batch != 0 ? o->batch : (N >= 8 ? 16 : 64);
+  pl->batch_fwd = o->batch != 0 ? o->batch : (N >= 16 ? 8 : N >= 8 ? 16 : 64);
   pl->batch_bwd = o->batch_bwd != 0 ? o->batch_bwd : (N >= 8 ? 8 : 32);
+  // N = 16: 4.3 KB of staged texels per splat; batches of 8 keep the backward's LDS (texels
+  // plus their gradient sums) near 61 KB per workgroup
+  if (N >= 16 && (pl->batch_fwd != 8 || pl->batch_bwd != 8)) {
+    g_last_error = "N = 16 takes batch and batch_bwd 8 (or 0)";
+    return GB_ERR_UNSUPPORTED;
+  }
   int64_t tiles = 0, pixels = 0, sat = 0;
   for (int i = 0; i < n_views; ++i) {
     const int64_t tx = (views[i].width + pl->tile_w - 1) / pl->tile_w;
@@ -304,8 +310,8 @@ gb_status gb_workspace_layout(int32_t P, int32_t N, const gb_view* views, int32_
                               const gb_options* opts, int64_t pair_capacity, gb_layout* out) {
   if (!out) return arg_fail("out is NULL");
   if (P < 1) return arg_fail("P must be >= 1");
-  if (!(N == 1 || N == 2 || N == 4 || N == 8)) {
-    g_last_error = "texture side N must be 1, 2, 4 or 8";
+  if (!(N == 1 || N == 2 || N == 4 || N == 8 || N == 16)) {
+    g_last_error = "texture side N must be 1, 2, 4, 8 or 16";
     return GB_ERR_UNSUPPORTED;
   }
   gb_status st;

@@ -395,10 +395,14 @@ hipError_t launch_np(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
 #define GBB_BWD_B(BB)                                                                         \
   hipLaunchKernelGGL((blend_bwd_kernel<N, BF16, BB, PIX>), grid, block, 0, s, views, rec, first, \
                      rest, open_bits, sp.textures, bp, T_final, d_rgb, d_rec, d_tex)
-  switch (pl.batch_bwd) {
-    case 8: GBB_BWD_B(8); break;
-    case 32: GBB_BWD_B(32); break;
-    default: GBB_BWD_B(16); break;
+  if constexpr (N >= 16) {
+    GBB_BWD_B(8);  // the only batch built for N = 16 (LDS)
+  } else {
+    switch (pl.batch_bwd) {
+      case 8: GBB_BWD_B(8); break;
+      case 32: GBB_BWD_B(32); break;
+      default: GBB_BWD_B(16); break;
+    }
   }
 #undef GBB_BWD_B
   return hipGetLastError();
@@ -428,6 +432,7 @@ hipError_t launch_blend_bwd(const Plan& pl, const gb_splats& sp, const gb_option
     case 2: GBB_BWD(2);
     case 4: GBB_BWD(4);
     case 8: GBB_BWD(8);
+    case 16: GBB_BWD(16);
     default: return hipErrorInvalidValue;
   }
 #undef GBB_BWD

@@ -212,11 +212,15 @@ hipError_t launch_n(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
   hipLaunchKernelGGL((blend_fwd_kernel<N, BF16, BB, STATS, REST>), grid, block, 0, s, views, \
                      rec, pair_vals, ranges, sp.textures, bp, rgb, T_final, n_last, split,    \
                      stats)
-  switch (pl.batch_fwd) {
-    case 8: GBB_FWD_B(8); break;
-    case 16: GBB_FWD_B(16); break;
-    case 32: GBB_FWD_B(32); break;
-    default: GBB_FWD_B(64); break;
+  if constexpr (N >= 16) {
+    GBB_FWD_B(8);  // the only batch built for N = 16 (LDS)
+  } else {
+    switch (pl.batch_fwd) {
+      case 8: GBB_FWD_B(8); break;
+      case 16: GBB_FWD_B(16); break;
+      case 32: GBB_FWD_B(32); break;
+      default: GBB_FWD_B(64); break;
+    }
   }
 #undef GBB_FWD_B
   return hipGetLastError();
@@ -286,6 +290,7 @@ hipError_t launch_blend_fwd(const Plan& pl, const gb_splats& sp, const gb_option
     case 2: GBB_FWD(2);
     case 4: GBB_FWD(4);
     case 8: GBB_FWD(8);
+    case 16: GBB_FWD(16);
     default: return hipErrorInvalidValue;
   }
 #undef GBB_FWD

@@ -199,6 +199,9 @@ CONFIGS = {
                views=("front", 8.0, [(1920, 1080)], 1)),
     "T0_BF16": dict(P=1_000_000, lo=-4.0, hi=4.0, s_lo=0.02, s_hi=0.2, N=8, bf16=True,
                     views=("front", 8.0, [(1920, 1080)], 1)),
+    # the same with 16 x 16 colour grids (FP32)
+    "T0_N16": dict(P=1_000_000, lo=-4.0, hi=4.0, s_lo=0.02, s_hi=0.2, N=16, bf16=False,
+                   views=("front", 8.0, [(1920, 1080)], 1)),
 }
 
 

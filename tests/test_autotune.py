@@ -35,6 +35,21 @@ def test_search_finds_the_separable_minimum():
     assert len(set(keys)) == len(keys)
 
 
+def test_n16_defaults_and_search_space_use_batches_of_8(tmp_path):
+    assert at.resolve_defaults(Options(), 16).batch == 8
+    assert at.resolve_defaults(Options(), 16).batch_bwd == 8
+    splats = types.SimpleNamespace(P=100, N=16, textures=torch.zeros(1))
+    views = [types.SimpleNamespace(width=32, height=32)]
+    seen = []
+
+    def cost(o):
+        seen.append((o.batch, o.batch_bwd))
+        return 1.0
+
+    at.autotune(splats, views, cost=cost)
+    assert set(seen) == {(8, 8)}
+
+
 def test_search_keeps_the_base_when_it_is_best():
     best, cost, log = at.search(Options(), lambda o: 0.0 if o == Options() else 1.0)
     assert best == Options() and cost == 0.0

@@ -347,6 +347,18 @@ def test_full_size_weights_telescope(gb, bf16):
     np.testing.assert_allclose(got, want, rtol=1e-5)
 
 
+# --- 16 x 16 colour grids (beyond the paper's 8 x 8 shared-memory limit) ----------------------
+@pytest.mark.parametrize("bf16", [False, True])
+def test_n16_image_and_gradients_match_oracle(gb, bf16):
+    scene = sg.make_scene(41, 3000, -1.0, 1.0, 0.05, 0.4, 16, tex_bf16=bf16)
+    view = sg.look_at_view((0.2, -0.1, -3.0), 96, 80)
+    opts = O.Options()
+    rast, sp, rgb, T = run_gpu(gb, scene, [view], opts, tex_bf16=bf16)
+    ref = O.render(scene, view, opts, crop=(24, 16, 48, 40))
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 96, 80)
+    check_grads(gb, scene, view, opts, (32, 24, 32, 32), seed=7, tex_bf16=bf16)
+
+
 # --- LDS batch sizes: same images, gradients within tolerance -------------------------------
 @pytest.mark.parametrize("batch,batch_bwd", [(8, 8), (16, 32), (64, 16), (32, 8)])
 def test_batch_sizes(gb, batch, batch_bwd):

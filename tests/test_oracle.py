@@ -112,7 +112,7 @@ def test_grid_border_isolines_match_paper():
 
 
 # --- P4: a linear texel field is reproduced exactly (Alg. 2, pins the floor reading) ------
-@pytest.mark.parametrize("N", [2, 3, 4, 8])
+@pytest.mark.parametrize("N", [2, 3, 4, 8, 16])
 def test_bilinear_reproduces_linear_fields(N):
     rng = np.random.default_rng(N)
     sig = 0.5
@@ -141,7 +141,7 @@ def test_bilinear_N1_is_constant():
 
 
 # --- P10: adj-bilinear against central differences of bilinear (Alg. 2) -------------------
-@pytest.mark.parametrize("N", [2, 4, 8])
+@pytest.mark.parametrize("N", [2, 4, 8, 16])
 def test_adj_bilinear_matches_finite_differences(N):
     rng = np.random.default_rng(10 + N)
     sig = 0.5
