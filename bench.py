@@ -216,6 +216,34 @@ def c3_variant(gb, sg, torch, warmup, steps):
             "mpix_per_s_batched": round(px / s_batch / 1e6, 1), "pixels": px, "pairs": K}
 
 
+def config_times(gb, sg, torch, warmup, steps):
+    """Step times of the smaller named workloads (their parity is checked by the tests):
+    1k splats at 128x128 forward only, 100k splats at 800x800 forward + backward, 3M splats
+    with bfloat16 textures at 4 x 1080p forward + backward."""
+    out = {}
+    for name, bwd in (("C1", False), ("C2", True), ("C4", True)):
+        scene, views, sp, rast, g, rgb, T, grads, K = setup(gb, sg, torch, name)
+        px = sum(v.width * v.height for v in views)
+        for _ in range(warmup):
+            rast.forward(sp, rgb, T)
+            if bwd:
+                rast.backward(sp, T, g, grads)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rast.forward(sp, rgb, T)
+            if bwd:
+                rast.backward(sp, T, g, grads)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        out[name] = {"ms_per_step": round(sec * 1e3, 3), "mpix_per_s": round(px / sec / 1e6, 1),
+                     "pass": "fwd+bwd" if bwd else "fwd", "splats": scene.P, "pixels": px,
+                     "pairs": K}
+        del scene, sp, rast, g, rgb, T, grads
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(scene, view, crop):
     """FP64 oracle (one process) on a crop of the workload: forward + analytic backward."""
     import numpy as np
@@ -389,6 +417,9 @@ def main():
         log("variant: 16 uneven views (1M splats, 4x4 textures) in one graph vs one at a time")
         variants["c3_16_views"] = c3_variant(gb, sg, torch, args.warmup, args.steps)
         log(f"c3: {variants['c3_16_views']}")
+        log("variant: the smaller named workloads (1k, 100k and 3M splats)")
+        variants["configs"] = config_times(gb, sg, torch, args.warmup, args.steps)
+        log(f"configs: {variants['configs']}")
         log("variant: full optimisation step (500k splats, batch of 4 of 32 views at 1280x720)")
         variants["train_step_500k_4x720p"] = train_variant(gb, sg, torch,
                                                            iters=args.train_iters)

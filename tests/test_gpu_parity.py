@@ -347,6 +347,41 @@ def test_full_size_weights_telescope(gb, bf16):
     np.testing.assert_allclose(got, want, rtol=1e-5)
 
 
+# --- constant grids: a box-filtered (single-colour) grid renders as one texel -----------------
+@pytest.mark.parametrize("N", [4, 8, 16])
+def test_constant_grid_renders_as_one_texel(gb, N):
+    """A colour grid filled with one colour (the grid box-filtered to 1 x 1, as the paper does
+    to show that the grid carries the image) renders exactly like N = 1 with that colour:
+    the bilinear lerps of equal values are exact, so images are bit-equal; the grid's
+    gradients sum to the single texel's (bilinear weights sum to one), and the geometry
+    gradients agree (the uv adjoint from a constant grid is zero)."""
+    base = sg.make_scene(23, 2000, -1.0, 1.0, 0.05, 0.4, N)
+    mean = base.textures.mean(axis=(1, 2), dtype=np.float64).astype(np.float32)  # [P, 3]
+    grid = sg.Scene(base.means, base.tan_u, base.tan_v, base.scales, base.opacity,
+                    np.ascontiguousarray(np.broadcast_to(mean[:, None, None, :],
+                                                         base.textures.shape)))
+    one = sg.Scene(base.means, base.tan_u, base.tan_v, base.scales, base.opacity,
+                   np.ascontiguousarray(mean[:, None, None, :]))
+    view = sg.look_at_view((0.1, 0.2, -3.0), 80, 64)
+    g = torch.from_numpy(sg.make_dl_drgb(4, [view])).cuda()
+    out = []
+    for sc in (grid, one):
+        rast, sp, rgb, T = run_gpu(gb, sc, [view], O.Options())
+        out.append((rgb, T, rast.backward(sp, T, g)))
+    (rgb_n, T_n, g_n), (rgb_1, T_1, g_1) = out
+    assert torch.equal(rgb_n, rgb_1) and torch.equal(T_n, T_1)
+    summed = g_n["textures"].double().sum(dim=(1, 2)).cpu().numpy()
+    want = g_1["textures"].double().cpu().numpy().reshape(-1, 3)
+    # both are float32 sums of terms of both signs: bound the difference by the magnitude of
+    # the terms, taken from the same backward with |dL/drgb|
+    rast_1, sp_1, _, T_1b = run_gpu(gb, one, [view], O.Options())
+    mag = rast_1.backward(sp_1, T_1b, g.abs())["textures"].double().cpu().numpy().reshape(-1, 3)
+    assert np.all(np.abs(summed - want) <= 1e-5 * mag + 1e-12)
+    for k in ("means", "tan_u", "tan_v", "scales", "opacity"):
+        assert rel_l2(g_n[k].cpu().numpy().astype(np.float64),
+                      g_1[k].cpu().numpy().astype(np.float64)) <= 1e-5, k
+
+
 # --- 16 x 16 colour grids (beyond the paper's 8 x 8 shared-memory limit) ----------------------
 @pytest.mark.parametrize("bf16", [False, True])
 def test_n16_image_and_gradients_match_oracle(gb, bf16):
