@@ -129,14 +129,15 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
 // With batches of 8 the LDS would allow more than 6 waves per SIMD, but the register
 // allocation (77 VGPRs) stops there; asking for 7 (at most 72 VGPRs, two dwords spilled)
 // measured 4 % faster on the 1M-splat 1080p workload, 8 (64 VGPRs) slower.
-template <int B>
-constexpr int bwd_min_waves() { return B <= 8 ? 7 : 1; }
+// (N = 16 blocks hold 61 KB of LDS, two per CU, so no register target applies there.)
+template <int N, int B>
+constexpr int bwd_min_waves() { return (B <= 8 && N <= 8) ? 7 : 1; }
 
 // Depth-prefix split: on a tile that the prefix left open the block first walks the rest
 // pass's list (the later splats) and then, with each pixel's T and S carried over in
 // registers, the prefix pass's list; other tiles only walk the prefix list.
 template <int N, bool BF16, int B, int PIX>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(bwd_min_waves<B>())))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(bwd_min_waves<N, B>())))
 blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__ rec,
                  PairList first, PairList rest, const uint32_t* __restrict__ open_bits,
                  const void* __restrict__ textures, BlendParams p,
