@@ -48,6 +48,8 @@ __global__ void finalize_count_kernel(const uint32_t* __restrict__ offsets, int6
 
 constexpr int kDupThreads = 256;
 constexpr int kDupGrid = 4096;  // workgroups of the duplicate kernels (they loop over chunks)
+// Rest pass: a chunk whose owners lie more ranks apart than this searches per slot.
+constexpr int64_t kSparseChunkRecords = 4 * kChunkSlots;
 static_assert(kChunkSlots == 4 * kDupThreads, "four slots per thread and round");
 
 // Prefix pass: the largest record count (in depth order) whose pairs fit the budget; single
@@ -95,8 +97,19 @@ __device__ __forceinline__ uint32_t nth_open(const uint32_t* __restrict__ bits, 
     if (w == wb) m &= ~0u >> (31 - (b & 31));
     const uint32_t c = (uint32_t)__popc(m);
     if (k < c) {
-      for (uint32_t i = 0; i < k; ++i) m &= m - 1;  // drop the k lowest set bits
-      return (w << 5) + (uint32_t)__builtin_ctz(m);
+      // position of the k-th set bit: halve the word five times, keeping the half that
+      // holds it (popcount of the low half decides)
+      uint32_t pos = 0;
+#pragma unroll
+      for (int width = 16; width >= 1; width >>= 1) {
+        const uint32_t lo = (uint32_t)__popc(m & ((1u << width) - 1u));
+        if (k >= lo) {
+          k -= lo;
+          m >>= width;
+          pos += (uint32_t)width;
+        }
+      }
+      return (w << 5) + pos;
     }
     k -= c;
   }
@@ -153,6 +166,42 @@ expand_kernel(const uint32_t* __restrict__ order, const uint32_t* __restrict__ c
     const int64_t c1 = (c0 + C < total) ? c0 + C : total;
     const int64_t r0 = chunk_owner[c];
     const int64_t r1 = (c + 1 < n_chunks) ? (int64_t)chunk_owner[c + 1] : last;
+    if (REST && r1 - r0 > kSparseChunkRecords) {
+      // After the depth cut most records meet no open tile, so a chunk's owners can lie far
+      // apart. Such a chunk finds each slot's record by a binary search over the offsets
+      // instead of walking every record in between: the last rank whose offset is at or
+      // below the slot is its owner (records without slots start where their successor
+      // does). The branch is uniform over the workgroup.
+      const int64_t q0 = c0 + 4 * t;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int64_t q = q0 + k;
+        if (q >= c1) break;
+        const int64_t r = r0 + last_at_or_below(offsets + r0, r1 - r0 + 1, (uint64_t)q);
+        const uint32_t id = order[r];
+        const SplatRec& R = rec[id];
+        const int i0 = R.rect_x & 0xffff, i1 = R.rect_x >> 16;
+        const int j0 = R.rect_y & 0xffff, j1 = R.rect_y >> 16;
+        const ViewDev& V = views[R.view];
+        const uint32_t wt = (uint32_t)(i1 / tile_w - i0 / tile_w + 1);
+        const uint32_t ht = (uint32_t)(j1 / tile_h - j0 / tile_h + 1);
+        const uint32_t step = (uint32_t)V.tiles_x;
+        const uint32_t at = (uint32_t)(V.sat_base + (j0 / tile_h) * (V.tiles_x + 1) + i0 / tile_w);
+        uint32_t local = (uint32_t)(q - (int64_t)offsets[r]);
+        uint32_t lo = 0, hi = ht - 1;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (open_rows(sat, at, step + 1, wt, mid) > local) hi = mid;
+          else lo = mid + 1;
+        }
+        if (lo > 0) local -= open_rows(sat, at, step + 1, wt, lo - 1);
+        const uint32_t a = (uint32_t)(V.tile_base + (j0 / tile_h) * V.tiles_x + i0 / tile_w) +
+                           lo * step;
+        pair_keys[q] = nth_open(open_bits, a, a + wt - 1, local);
+        pair_vals[q] = id;
+      }
+      continue;
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) s_own[4 * t + k] = -1;
     __syncthreads();
