@@ -23,7 +23,7 @@ namespace {
 // by t_min, lane evaluations (64 per wave and evaluated splat) and staged (tile, splat) pairs;
 // the rest pass also adds its blended pairs to stats[4].
 template <int N, bool BF16, int B, bool STATS, bool REST>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__ rec,
                  const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ ranges,
                  const void* __restrict__ textures, BlendParams p, float* __restrict__ rgb,
@@ -31,6 +31,8 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
                  unsigned long long* __restrict__ stats) {
   __shared__ float4 s_geo[B][4];
   __shared__ float4 s_tex[B * TexLayout<N>::kPerSplat];
+  __shared__ uint8_t s_reach[4][B];  // [wave block][staged splat]: may reach the block
+  static_assert((B & (B - 1)) == 0, "batch sizes are powers of two");
 
   const int tile = tile_of_block(p);
   if (tile >= p.total_tiles) return;
@@ -45,6 +47,7 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   // the wave index is uniform: keep it (and the wave block's geometry) in scalar registers
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int waves_x = p.tile_w >> 3;
+  const int n_waves = (int)(blockDim.x >> 6);
   const int bx = (w % waves_x) * 8, by = (w / waves_x) * 8;
   const int lxi = bx + (lane & 7), lyi = by + (lane >> 3);
   const int px = tile_x0 + lxi, py = tile_y0 + lyi;
@@ -52,10 +55,6 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   // pixel centre relative to the tile centre (exact half-integers)
   const float lx = (float)lxi - 0.5f * (float)(p.tile_w - 1);
   const float ly = (float)lyi - 0.5f * (float)(p.tile_h - 1);
-  // wave block: first pixel, and centre relative to the tile centre
-  const int wx0 = tile_x0 + bx, wy0 = tile_y0 + by;
-  const float bcx = (float)bx + 3.5f - 0.5f * (float)(p.tile_w - 1);
-  const float bcy = (float)by + 3.5f - 0.5f * (float)(p.tile_h - 1);
 
   const uint32_t rec_base = (uint32_t)vi * (uint32_t)p.P;  // first record of the tile's view
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
@@ -78,29 +77,35 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   for (uint32_t b0 = start; b0 < end; b0 += B) {
     const int nb = (int)((end - b0) < (uint32_t)B ? (end - b0) : (uint32_t)B);
     if (STATS && tid == 0) atomicAdd(&stats[3], (unsigned long long)nb);
-    if (tid < nb) {
-      const uint32_t r = pair_vals[b0 + tid];
-      const SplatRec R = rec[r];
-      const StagedGeo g = stage_geo(R, tile_x0, tile_y0, p.tile_w, p.tile_h);
-      s_geo[tid][0] = g.g0;
-      s_geo[tid][1] = g.g1;
-      s_geo[tid][2] = g.g2;
-      s_geo[tid][3] = g.g3;
+    {
+      // thread c stages splat c mod B and tests it against wave block c / B: for a batch of
+      // 16 and four waves that is one wave doing every (splat, block) test once, instead of
+      // every wave testing every splat; the block-0 threads also store the geometry
+      const int j = tid & (B - 1), b = tid / B;
+      if (b < n_waves && j < nb) {
+        const uint32_t r = pair_vals[b0 + j];
+        const SplatRec R = rec[r];
+        const StagedGeo g = stage_geo(R, tile_x0, tile_y0, p.tile_w, p.tile_h);
+        if (b == 0) {
+          s_geo[j][0] = g.g0;
+          s_geo[j][1] = g.g1;
+          s_geo[j][2] = g.g2;
+          s_geo[j][3] = g.g3;
+        }
+        const int kbx = (b % waves_x) * 8, kby = (b / waves_x) * 8;
+        s_reach[b][j] = block_may_contribute(
+            g, (float)kbx + 3.5f - 0.5f * (float)(p.tile_w - 1),
+            (float)kby + 3.5f - 0.5f * (float)(p.tile_h - 1), tile_x0 + kbx, tile_y0 + kby, p)
+                            ? 1
+                            : 0;
+      }
     }
     stage_texels<N, BF16>(textures, pair_vals + b0, rec_base, nb, s_tex);
     __syncthreads();
 
     if (!__all(done)) {
       // splats of this batch that can reach the wave's 8 x 8 block (one lane per splat)
-      bool may = false;
-      if (lane < nb) {
-        StagedGeo c;
-        c.g0 = s_geo[lane][0];
-        c.g1 = s_geo[lane][1];
-        c.g2 = s_geo[lane][2];
-        c.g3 = s_geo[lane][3];
-        may = block_may_contribute(c, bcx, bcy, wx0, wy0, p);
-      }
+      const bool may = lane < nb && s_reach[w][lane] != 0;
       uint64_t todo = ballot(may);
       while (todo != 0) {
         const int j = (int)__builtin_ctzll(todo);
