@@ -206,12 +206,16 @@ def check_grads(gb, scene, view, opts, crop, seed=0, tex_bf16=False, batch=0, ba
     d_rgb = torch.from_numpy(g_full.reshape(-1, 3)).cuda()
     grads = rast.backward(sp, T, d_rgb)
     torch.cuda.synchronize()
-    errs = {}
+    errs, p999 = {}, {}
     for name in ("means", "tan_u", "tan_v", "scales", "opacity", "textures"):
         got = grads[name].cpu().numpy().astype(np.float64)
         want = getattr(ref_g, name)
         errs[name] = rel_l2(got, want)
+        # element-wise error against the tensor's scale, 99.9th percentile (reported only)
+        scale = np.abs(want) + np.sqrt(np.mean(want * want))
+        p999[name] = float(np.percentile(np.abs(got - want) / np.maximum(scale, 1e-30), 99.9))
     print("gradient rel L2:", {k: f"{v:.2e}" for k, v in errs.items()})
+    print("gradient p99.9 |d|/(|g| + rms g):", {k: f"{v:.2e}" for k, v in p999.items()})
     for k, v in errs.items():
         assert v <= GRAD_TOL, (k, v)
     return errs
