@@ -166,6 +166,19 @@ def test_image_parity_tiny_scenes(gb, seed):
     assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, W, H)
 
 
+@pytest.mark.parametrize("W,H", [(1, 1), (1, 37), (41, 2), (7, 5), (17, 9)])
+def test_degenerate_view_sizes(gb, W, H):
+    """Views narrower or lower than one tile, down to a single pixel: partial tiles, ragged
+    wave blocks and lanes outside the view."""
+    scene = sg.make_scene(77, 60, -0.4, 0.4, 0.05, 0.5, 4)
+    view = sg.look_at_view((0.05, -0.02, -2.0), W, H)
+    opts = O.Options()
+    rast, sp, rgb, T = run_gpu(gb, scene, [view], opts)
+    ref = O.render(scene, view, opts)
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, W, H)
+    check_grads(gb, scene, view, opts, (0, 0, W, H), seed=W * 100 + H)
+
+
 def test_image_parity_thresholds_off(gb):
     scene = sg.make_scene(9, 6, -0.4, 0.4, 0.05, 0.3, 4)
     view = sg.look_at_view((0.1, 0.2, -2.0), 40, 30)
