@@ -324,15 +324,11 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
           }
           if (lead_cell < 0) break;
           bool in[PIX];
-          uint64_t grp_any = 0;
 #pragma unroll
           for (int s = 0; s < PIX; ++s) {
             in[s] = ((pend[s] >> lane) & 1ull) && po[s].k00 == lead_cell;
-            const uint64_t grp = ballot(in[s]);
-            pend[s] &= ~grp;
-            grp_any |= grp;
+            pend[s] &= ~ballot(in[s]);
           }
-          const bool row_in = ((grp_any >> (16 * row)) & 0xffffull) != 0;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             if (N == 1 && q > 0) break;
@@ -347,8 +343,20 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
               red[2] += wv * po[s].dc2;
             }
             if (!__any(nz)) continue;
-            const float tot = row_reduce_scatter<3>(red);
-            if (tex_owner && row_in) atomicAdd(gt + 3 * (lead_cell + offq[q]) + tex_slot, tot);
+            // row totals, then the four rows summed (rows outside the group add zeros), so
+            // that one lane per channel adds to LDS instead of four lanes on one address
+            float tot = row_reduce_scatter<3>(red);
+            {
+              const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(tot),
+                                                              __float_as_uint(tot), false, false);
+              tot = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+            }
+            {
+              const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(tot),
+                                                              __float_as_uint(tot), false, false);
+              tot = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+            }
+            if (tex_owner && row == 0) atomicAdd(gt + 3 * (lead_cell + offq[q]) + tex_slot, tot);
           }
         }
       }
