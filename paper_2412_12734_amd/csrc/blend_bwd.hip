@@ -150,7 +150,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   __shared__ uint32_t s_recid[B];
   __shared__ float4 s_tex[B * TexLayout<N>::kPerSplat];
   __shared__ float s_gtex[B * TEXG];
-  __shared__ float s_grec[B * 4 * kRecGrad];  // per splat, per 16-lane row of a wave
+  __shared__ float s_grec[B * kRecGrad];  // per splat
   __shared__ uint32_t s_tile_last;
 
   const int tile = tile_of_block(p);
@@ -241,7 +241,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
         s_recid[tid] = r;
       }
       for (int e = tid; e < nb * TEXG; e += nthr) s_gtex[e] = 0.f;
-      for (int e = tid; e < nb * 4 * kRecGrad; e += nthr) s_grec[e] = 0.f;
+      for (int e = tid; e < nb * kRecGrad; e += nthr) s_grec[e] = 0.f;
       stage_texels<N, BF16>(textures, pair_vals + bstart, rec_base, nb, s_tex);
       __syncthreads();
 
@@ -279,8 +279,9 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
 #pragma unroll
         for (int s = 0; s < PIX; ++s) pixel_step<N>(g, tex, e[s], act[s], ps[s], p, po[s]);
 
-        // Row sums of the per-splat scalars (a lane first adds its own pixels); each total lands
-        // in one lane of the row, which adds it to the row's LDS slot.
+        // Sums of the per-splat scalars (a lane first adds its own pixels): each row total lands
+        // in one lane of the row, the four rows are summed, and one lane per scalar adds it to
+        // the splat's LDS slot.
         {
           float red[kRecGrad];
 #pragma unroll
@@ -288,7 +289,6 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
           red[7] = po[0].gc2x;
           red[8] = po[0].gc2y;
           red[9] = po[0].go;
-          bool any_act = po[0].act;
 #pragma unroll
           for (int s = 1; s < PIX; ++s) {
 #pragma unroll
@@ -296,12 +296,19 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
             red[7] += po[s].gc2x;
             red[8] += po[s].gc2y;
             red[9] += po[s].go;
-            any_act = any_act || po[s].act;
           }
-          const float tot = row_reduce_scatter<kRecGrad>(red);
-          // ballot taken by the whole wave (not inside the lane condition)
-          const bool row_act = ((ballot(any_act) >> (16 * row)) & 0xffffull) != 0;
-          if (rec_owner && row_act) atomicAdd(&s_grec[(j * 4 + row) * kRecGrad + rec_slot], tot);
+          float tot = row_reduce_scatter<kRecGrad>(red);
+          {
+            const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(tot),
+                                                            __float_as_uint(tot), false, false);
+            tot = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+          }
+          {
+            const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(tot),
+                                                            __float_as_uint(tot), false, false);
+            tot = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+          }
+          if (rec_owner && row == 0) atomicAdd(&s_grec[j * kRecGrad + rec_slot], tot);
         }
 
         // Texel gradients, grouped by cell over all pixels of the wave.
@@ -371,8 +378,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
       }
       for (int e = tid; e < nb * kRecGrad; e += nthr) {
         const int j = e / kRecGrad, r = e - j * kRecGrad;
-        const float* g4 = s_grec + j * 4 * kRecGrad + r;
-        const float x = (g4[0] + g4[kRecGrad]) + (g4[2 * kRecGrad] + g4[3 * kRecGrad]);
+        const float x = s_grec[e];
         if (x != 0.f) atomicAdd(&d_rec[(int64_t)s_recid[j] * kRecGrad + r], x);
       }
       __syncthreads();
