@@ -22,8 +22,16 @@ namespace {
 // With STATS the kernel also counts its work into stats[0..3]: blended pairs, pixels stopped
 // by t_min, lane evaluations (64 per wave and evaluated splat) and staged (tile, splat) pairs;
 // the rest pass also adds its blended pairs to stats[4].
+// Occupancy target: eight waves per SIMD, or what the 160 KB of LDS per CU allows (a
+// workgroup puts one wave on each of the CU's four SIMDs).
+template <int N, int B>
+constexpr int fwd_min_waves() {
+  constexpr int lds = B * (4 * 16 + 4 + TexLayout<N>::kPerSplat * 16);
+  return 160 * 1024 / lds < 8 ? 160 * 1024 / lds : 8;
+}
+
 template <int N, bool BF16, int B, bool STATS, bool REST>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fwd_min_waves<N, B>())))
 blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__ rec,
                  const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ ranges,
                  const void* __restrict__ textures, BlendParams p, float* __restrict__ rgb,
