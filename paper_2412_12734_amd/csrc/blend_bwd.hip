@@ -203,7 +203,11 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   int rec_slot, tex_slot;
   bool rec_owner, tex_owner;
   row_scatter_slot<kRecGrad>(rec_slot, rec_owner);
-  row_scatter_slot<3>(tex_slot, tex_owner);
+  // texel sums: the three channels of each of the four cell corners (one corner when N = 1);
+  // tex_off is the lane's value's offset from the cell's first channel
+  constexpr int KT = N == 1 ? 3 : 12;
+  row_scatter_slot<KT>(tex_slot, tex_owner);
+  const int tex_off = 3 * ((tex_slot / 3 & 1) + (tex_slot / 6) * N) + tex_slot % 3;
 
 #pragma unroll 1
   for (int li = tile_open ? 0 : 1; li < 2; ++li) {
@@ -316,7 +320,6 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
         uint64_t pend[PIX];
 #pragma unroll
         for (int s = 0; s < PIX; ++s) pend[s] = ballot(po[s].act);
-        const int offq[4] = {0, 1, N, N + 1};
         // Every group takes at least its lead lane, so the loop ends within 64 passes. A bound
         // of four passes with per-lane LDS adds for the remaining lanes measured 1.80 ms at
         // 1M splats and 1080p (10 % of wave steps have more than four cells), eight passes
@@ -336,35 +339,34 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
             in[s] = ((pend[s] >> lane) & 1ull) && po[s].k00 == lead_cell;
             pend[s] &= ~ballot(in[s]);
           }
+          // all corners and channels in one transposing row reduction, then the four rows
+          // summed (rows outside the group add zeros), so that one lane per value adds it to
+          // LDS: one add instruction per group
+          float red[KT];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            if (N == 1 && q > 0) break;
-            float red[3] = {0.f, 0.f, 0.f};
-            bool nz = false;
+          for (int k = 0; k < KT; ++k) red[k] = 0.f;
 #pragma unroll
-            for (int s = 0; s < PIX; ++s) {
+          for (int s = 0; s < PIX; ++s) {
+#pragma unroll
+            for (int q = 0; q < KT / 3; ++q) {
               const float wv = in[s] ? po[s].w[q] : 0.f;
-              nz = nz || wv != 0.f;
-              red[0] += wv * po[s].dc0;
-              red[1] += wv * po[s].dc1;
-              red[2] += wv * po[s].dc2;
+              red[3 * q] += wv * po[s].dc0;
+              red[3 * q + 1] += wv * po[s].dc1;
+              red[3 * q + 2] += wv * po[s].dc2;
             }
-            if (!__any(nz)) continue;
-            // row totals, then the four rows summed (rows outside the group add zeros), so
-            // that one lane per channel adds to LDS instead of four lanes on one address
-            float tot = row_reduce_scatter<3>(red);
-            {
-              const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(tot),
-                                                              __float_as_uint(tot), false, false);
-              tot = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-            }
-            {
-              const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(tot),
-                                                              __float_as_uint(tot), false, false);
-              tot = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-            }
-            if (tex_owner && row == 0) atomicAdd(gt + 3 * (lead_cell + offq[q]) + tex_slot, tot);
           }
+          float tot = row_reduce_scatter<KT>(red);
+          {
+            const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(tot),
+                                                            __float_as_uint(tot), false, false);
+            tot = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+          }
+          {
+            const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(tot),
+                                                            __float_as_uint(tot), false, false);
+            tot = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+          }
+          if (tex_owner && row == 0) atomicAdd(gt + 3 * lead_cell + tex_off, tot);
         }
       }
       __syncthreads();
