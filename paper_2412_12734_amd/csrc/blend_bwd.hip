@@ -12,9 +12,10 @@
 // A lane owns PIX vertically adjacent pixels (the launch uses PIX = 1: waves of 8 x 8 pixels).
 // Per splat, a lane first adds up its pixels' contributions; the ten per-splat scalars are
 // then summed over each 16-lane row with a transposing DPP butterfly that leaves each total
-// in one lane, which adds it to the row's LDS slot. Texel gradients are grouped by grid cell
-// (with sigma = 0.5 the grid covers only the splat's core, so most blended pixels are
-// border-clamped and share a few cells), summed per row the same way and added to LDS, one
+// in one lane, the four rows' totals are added with permlane swaps, and one lane per scalar
+// adds it to the splat's LDS slot. Texel gradients are grouped by grid cell (with sigma = 0.5
+// the grid covers only the splat's core, so most blended pixels are border-clamped and share
+// a few cells); each group's four corners and three channels are reduced the same way, one
 // group after another until every pixel's cell has been taken. A splat that no pixel of the
 // wave blended is skipped after evaluation. After each batch the non-zero LDS sums go to
 // global memory with one float atomic each.
