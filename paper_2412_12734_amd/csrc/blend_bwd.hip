@@ -11,13 +11,13 @@
 //
 // A lane owns PIX vertically adjacent pixels (the launch uses PIX = 1: waves of 8 x 8 pixels).
 // Per splat, a lane first adds up its pixels' contributions; the ten per-splat scalars are
-// then summed over each 16-lane row with a transposing DPP butterfly that leaves each total
-// in one lane, the four rows' totals are added with permlane swaps, and one lane per scalar
-// adds it to the splat's LDS slot. Texel gradients are grouped by grid cell (with sigma = 0.5
-// the grid covers only the splat's core, so most blended pixels are border-clamped and share
-// a few cells); each group's four corners and three channels are reduced the same way, one
-// group after another until every pixel's cell has been taken. A splat that no pixel of the
-// wave blended is skipped after evaluation. After each batch the non-zero LDS sums go to
+// then summed over the wave by a transposing reduction (permlane swaps across the wave's
+// halves and row pairs, then a DPP butterfly inside each row) that leaves each total in one
+// lane, which adds it to the splat's LDS slot. Texel gradients are grouped by grid cell (with
+// sigma = 0.5 the grid covers only the splat's core, so most blended pixels are border-clamped
+// and share a few cells); each group's four corners and three channels are reduced the same
+// way, one group after another until every pixel's cell has been taken. A splat that no pixel
+// of the wave blended is skipped after evaluation. After each batch the non-zero LDS sums go to
 // global memory with one float atomic each.
 #include "blend_common.h"
 
@@ -199,15 +199,15 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
     ps[s].S1 = ps[s].T * p.bg[1];
     ps[s].S2 = ps[s].T * p.bg[2];
   }
-  const int row = lane >> 4;
-  // which row total each lane receives from the row reductions below
+  // which wave total each lane receives from the reductions below
   int rec_slot, tex_slot;
   bool rec_owner, tex_owner;
-  row_scatter_slot<kRecGrad>(rec_slot, rec_owner);
+  const SwapSides sides = swap_sides();
+  wave_scatter_slot<kRecGrad>(sides, rec_slot, rec_owner);
   // texel sums: the three channels of each of the four cell corners (one corner when N = 1);
   // tex_off is the lane's value's offset from the cell's first channel
   constexpr int KT = N == 1 ? 3 : 12;
-  row_scatter_slot<KT>(tex_slot, tex_owner);
+  wave_scatter_slot<KT>(sides, tex_slot, tex_owner);
   const int tex_off = 3 * ((tex_slot / 3 & 1) + (tex_slot / 6) * N) + tex_slot % 3;
 
 #pragma unroll 1
@@ -284,9 +284,8 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
 #pragma unroll
         for (int s = 0; s < PIX; ++s) pixel_step<N>(g, tex, e[s], act[s], ps[s], p, po[s]);
 
-        // Sums of the per-splat scalars (a lane first adds its own pixels): each row total lands
-        // in one lane of the row, the four rows are summed, and one lane per scalar adds it to
-        // the splat's LDS slot.
+        // Wave sums of the per-splat scalars (a lane first adds its own pixels); the one lane
+        // that owns each total adds it to the splat's LDS slot.
         {
           float red[kRecGrad];
 #pragma unroll
@@ -302,22 +301,12 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
             red[8] += po[s].gc2y;
             red[9] += po[s].go;
           }
-          float tot = row_reduce_scatter<kRecGrad>(red);
-          {
-            const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(tot),
-                                                            __float_as_uint(tot), false, false);
-            tot = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-          }
-          {
-            const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(tot),
-                                                            __float_as_uint(tot), false, false);
-            tot = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-          }
-          if (rec_owner && row == 0) atomicAdd(&s_grec[j * kRecGrad + rec_slot], tot);
+          const float tot = wave_reduce_scatter<kRecGrad>(red);
+          if (rec_owner) atomicAdd(&s_grec[j * kRecGrad + rec_slot], tot);
         }
 
         // Texel gradients, grouped by cell over all pixels of the wave.
-        float* gt = s_gtex + j * TEXG;
+        float* gt = s_gtex + j * TEXG + tex_off;  // this lane's value in cell 0
         uint64_t pend[PIX];
 #pragma unroll
         for (int s = 0; s < PIX; ++s) pend[s] = ballot(po[s].act);
@@ -340,9 +329,8 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
             in[s] = ((pend[s] >> lane) & 1ull) && po[s].k00 == lead_cell;
             pend[s] &= ~ballot(in[s]);
           }
-          // all corners and channels in one transposing row reduction, then the four rows
-          // summed (rows outside the group add zeros), so that one lane per value adds it to
-          // LDS: one add instruction per group
+          // all corners and channels in one transposing wave reduction, so that one lane per
+          // value adds it to LDS: one add instruction per group
           float red[KT];
 #pragma unroll
           for (int k = 0; k < KT; ++k) red[k] = 0.f;
@@ -356,18 +344,8 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
               red[3 * q + 2] += wv * po[s].dc2;
             }
           }
-          float tot = row_reduce_scatter<KT>(red);
-          {
-            const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(tot),
-                                                            __float_as_uint(tot), false, false);
-            tot = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-          }
-          {
-            const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(tot),
-                                                            __float_as_uint(tot), false, false);
-            tot = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-          }
-          if (tex_owner && row == 0) atomicAdd(gt + 3 * lead_cell + tex_off, tot);
+          const float tot = wave_reduce_scatter<KT>(red);
+          if (tex_owner) atomicAdd(gt + 3 * lead_cell, tot);
         }
       }
       __syncthreads();

@@ -190,12 +190,63 @@ __device__ __forceinline__ float row_reduce_scatter(const float (&v)[K]) {
   return d[0];
 }
 
-// The value index that row_reduce_scatter<K> leaves in this lane, and whether the lane owns
-// it (a value that went unpaired at some step is held by several lanes; only the one on the
-// low side of every such step owns it).
+// One swap step across lane groups: v_permlane32_swap pairs each lane of the wave's lower half
+// with one of the upper half, v_permlane16_swap each lane of an even row with one of the next
+// row. Swapping a value pair (a, b) and adding the two results leaves one side of every lane
+// pair with a summed over the pair and the other side with b summed: a transposing step at one
+// swap and one add per pair. A value without a pair is summed on both sides.
+template <bool HALVES>
+__device__ __forceinline__ float swap_sum(float a, float b) {
+  if constexpr (HALVES) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b),
+                                                    false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  } else {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b),
+                                                    false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+}
+
+template <bool HALVES, int KI>
+__device__ __forceinline__ void swap_step(const float (&in)[KI], float (&out)[(KI + 1) / 2]) {
+#pragma unroll
+  for (int i = 0; i < KI / 2; ++i) out[i] = swap_sum<HALVES>(in[2 * i], in[2 * i + 1]);
+  if (KI & 1) out[KI / 2] = swap_sum<HALVES>(in[KI - 1], in[KI - 1]);
+}
+
+// Wave sums of K values (K <= 16): two swap steps (wave halves, then row pairs) and the
+// transposing row butterfly leave each of the K totals in lanes of one row, at about
+// 2 K / 2 + 2 K / 4 + 3 K / 8 + 4 instructions. wave_scatter_slot gives each lane's total.
 template <int K>
-__device__ __forceinline__ void row_scatter_slot(int& idx, bool& owner) {
+__device__ __forceinline__ float wave_reduce_scatter(const float (&v)[K]) {
+  static_assert(K >= 1 && K <= 16, "at most 16 values per wave");
+  constexpr int K1 = (K + 1) / 2, K2 = (K1 + 1) / 2;
+  float a[K1], b[K2];
+  swap_step<true>(v, a);
+  swap_step<false>(a, b);
+  return row_reduce_scatter<K2>(b);
+}
+
+// The side of each swap step a lane is on: true where it receives the second value of a pair.
+// Taken from the swap itself once per kernel, so that the mapping below holds whichever way
+// the hardware orders the exchange.
+struct SwapSides {
+  bool halves, rows;
+};
+
+__device__ __forceinline__ SwapSides swap_sides() {
+  return {swap_sum<true>(0.f, 1.f) != 0.f, swap_sum<false>(0.f, 1.f) != 0.f};
+}
+
+// The value index that wave_reduce_scatter<K> leaves in this lane, and whether the lane owns
+// it (a value that went unpaired at some step is held on both sides; only the lane on the low
+// side of every such step owns it, so each of the K totals has exactly one owner).
+template <int K>
+__device__ __forceinline__ void wave_scatter_slot(SwapSides sides, int& idx, bool& owner) {
   const int l = threadIdx.x & 15;
+  const bool hi[6] = {sides.halves, sides.rows, (l & 8) != 0, (l & 4) != 0, (l & 2) != 0,
+                      (l & 1) != 0};
   int ids[16];
   bool dup[16];
 #pragma unroll
@@ -205,13 +256,12 @@ __device__ __forceinline__ void row_scatter_slot(int& idx, bool& owner) {
   }
   int n = K;
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const bool hi = ((l >> (3 - s)) & 1) != 0;
+  for (int s = 0; s < 6; ++s) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       if (i < n / 2) {
-        ids[i] = hi ? ids[2 * i + 1] : ids[2 * i];
-        dup[i] = hi ? dup[2 * i + 1] : dup[2 * i];
+        ids[i] = hi[s] ? ids[2 * i + 1] : ids[2 * i];
+        dup[i] = hi[s] ? dup[2 * i + 1] : dup[2 * i];
       }
     }
     if (n & 1) {
@@ -219,7 +269,7 @@ __device__ __forceinline__ void row_scatter_slot(int& idx, bool& owner) {
       for (int i = 0; i < 8; ++i)
         if (i == n / 2) {
           ids[i] = ids[n - 1];
-          dup[i] = dup[n - 1] || hi;
+          dup[i] = dup[n - 1] || hi[s];
         }
     }
     n = (n + 1) / 2;
