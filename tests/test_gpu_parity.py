@@ -682,3 +682,20 @@ def test_all_splats_culled_gives_background(gb):
     assert rast.status() == (0, False)
     np.testing.assert_array_equal(rgb.cpu().numpy(), np.broadcast_to([0.25, 0.5, 0.75], (32 * 24, 3)).astype(np.float32))
     assert float(T.min()) == 1.0
+
+
+# --- gradient buffers are cleared by the backward (odd sizes: the fill's tail words) ---------
+@pytest.mark.parametrize("N", [1, 2])
+def test_backward_overwrites_stale_gradient_buffers(gb, N):
+    scene = sg.make_scene(13, 1001, -1.0, 1.0, 0.05, 0.3, N)  # 3 x 1001 texel words for N = 1
+    view = sg.look_at_view((0.0, 0.0, -3.0), 67, 45)
+    rast, sp, rgb, T = run_gpu(gb, scene, [view], O.Options())
+    g = torch.from_numpy(sg.make_dl_drgb(5, [view])).cuda()
+    fresh = {k: v.clone() for k, v in rast.backward(sp, T, g).items()}
+    stale = {k: torch.full_like(v, 123.0) for k, v in fresh.items()}
+    got = rast.backward(sp, T, g, stale)
+    torch.cuda.synchronize()
+    for k, v in fresh.items():
+        assert not bool((got[k] == 123.0).any()), k
+        err = float((got[k].double() - v.double()).norm() / v.double().norm().clamp_min(1e-30))
+        assert err <= 1e-5, (k, err)
