@@ -15,6 +15,8 @@ below are those definitions written out:
 * ``l1_loss``: scale * sum |I - I*| and its gradient scale * sign(I - I*).
 * ``adam_step``: the Adam update with bias correction, as published (Kingma and Ba, Alg. 1).
 * ``bf16_round``: float32 -> nearest bfloat16, ties to even, from the bit pattern.
+* ``mse_loss``, ``box_filter``, ``rotz_only``: the single-image fitting set-up of Sec. 4
+  (MSE loss; colour grids box-filtered to fewer texels; rotation about Z only).
 """
 from __future__ import annotations
 
@@ -69,6 +71,37 @@ def activate_backward(quats, log_scales, opacity_logits, d_tan_u, d_tan_v, d_sca
 def l1_loss(rgb, target, scale):
     d = np.asarray(rgb, dtype=np.float64) - np.asarray(target, dtype=np.float64)
     return scale * np.abs(d).sum(), scale * np.sign(d)
+
+
+def mse_loss(rgb, target, scale):
+    """Squared-error image loss (Sec. 4 fits single images with an MSE loss): the loss
+    scale * sum (rgb - target)^2 and its gradient 2 scale (rgb - target)."""
+    d = np.asarray(rgb, dtype=np.float64) - np.asarray(target, dtype=np.float64)
+    return scale * (d * d).sum(), 2.0 * scale * d
+
+
+def box_filter(textures, M):
+    """Box filter of colour grids to M x M (Sec. 4 renders fitted grids downsampled to 2 x 2
+    and to one colour): each output texel is the mean of the (N / M)^2 texels it covers.
+    textures [P][N][N][3] -> [P][M][M][3], float64."""
+    t = np.asarray(textures, dtype=np.float64)
+    P, N = t.shape[0], t.shape[1]
+    if N % M:
+        raise ValueError("M must divide N")
+    k = N // M
+    out = np.zeros((P, M, M, 3))
+    for i in range(M):
+        for j in range(M):
+            out[:, i, j, :] = t[:, i * k:(i + 1) * k, j * k:(j + 1) * k, :].mean(axis=(1, 2))
+    return out
+
+
+def rotz_only(d_quats):
+    """Rotation about the Z axis only (Sec. 4, single-image fitting): the x and y components
+    of the quaternion gradient are dropped, so quaternions (w, 0, 0, z) keep that form."""
+    d = np.array(d_quats, dtype=np.float64, copy=True)
+    d[:, 1:3] = 0.0
+    return d
 
 
 def adam_step(theta, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-15):

@@ -308,3 +308,47 @@ def train_config(seed: int = 0, P: Optional[int] = None, n_views: Optional[int] 
 
     return raw, target, views, batches
 
+
+
+def synthetic_image(seed: int, width: int, height: int) -> np.ndarray:
+    """A seeded RGB image [H * W, 3] in [0, 1] standing in for the paper's photographs: smooth
+    colour gradients, a few sinusoidal stripes (fine texture) and 24 flat-coloured discs (sharp
+    edges)."""
+    rng = np.random.default_rng(seed)
+    y, x = np.mgrid[0:height, 0:width].astype(np.float64)
+    u, v = x / max(width - 1, 1), y / max(height - 1, 1)
+    img = np.stack([0.2 + 0.6 * u, 0.3 + 0.5 * v, 0.5 + 0.3 * (1.0 - u) * v], axis=-1)
+    for _ in range(3):
+        k = rng.uniform(20.0, 120.0, 2)
+        ph = rng.uniform(0.0, 2.0 * math.pi)
+        img += 0.08 * np.sin(k[0] * u + k[1] * v + ph)[..., None] * rng.uniform(-1.0, 1.0, 3)
+    for _ in range(24):
+        cx, cy = rng.uniform(0, width), rng.uniform(0, height)
+        r = rng.uniform(0.02, 0.12) * min(width, height)
+        img[(x - cx) ** 2 + (y - cy) ** 2 < r * r] = rng.uniform(0.0, 1.0, 3)
+    return np.ascontiguousarray(np.clip(img, 0.0, 1.0).reshape(-1, 3), dtype=np.float32)
+
+
+def image_fit_config(seed: int, P: int, width: int, height: int, N: int,
+                     depth: float = 1.0, fov_deg: float = 60.0):
+    """The single-image fitting set-up (Sec. 4): one camera at the origin looking down +z, the
+    splats on the plane z = depth inside the view, rotated about z only (quaternions
+    (cos a/2, 0, 0, sin a/2), a uniform), scales of 0.5 to 1.5 times sqrt(W H / P) pixels at
+    that depth (so the splats together cover the image about once),
+    opacities uniform in [0.3, 0.9], colour grids uniform in [0, 1], and a synthetic target
+    image. Returns (raw scene, view, target [H * W, 3])."""
+    view = frontal_view(width, height, fov_deg)
+    rng = np.random.default_rng(seed)
+    half_w = (width / 2.0) / float(view.fx) * depth
+    half_h = (height / 2.0) / float(view.fy) * depth
+    means = np.stack([rng.uniform(-half_w, half_w, P), rng.uniform(-half_h, half_h, P),
+                      np.full(P, depth)], axis=1)
+    a = rng.uniform(0.0, 2.0 * math.pi, P)
+    q = np.stack([np.cos(a / 2), np.zeros(P), np.zeros(P), np.sin(a / 2)], axis=1)
+    px = depth / float(view.fx)  # world size of one pixel at that depth
+    log_s = np.log(rng.uniform(0.5, 1.5, (P, 2)) * math.sqrt(width * height / P) * px)
+    o = rng.uniform(0.3, 0.9, P)
+    tex = rng.uniform(0.0, 1.0, (P, N, N, 3))
+    f32 = lambda arr: np.ascontiguousarray(arr, dtype=np.float32)
+    raw = RawScene(f32(means), f32(q), f32(log_s), f32(np.log(o / (1.0 - o))), f32(tex))
+    return raw, view, synthetic_image(seed + 1, width, height)

@@ -117,3 +117,61 @@ def test_adam_zero_gradient_keeps_the_parameter_at_zero_moments():
 ])
 def test_bf16_round_to_nearest_even(x, bits):
     assert int(T.bf16_round(np.array([x], dtype=np.float32))[0]) == bits
+
+
+# --- single-image fitting set-up (Sec. 4): MSE loss, box-filtered grids, rotation about z ---
+def test_mse_loss_hand_example():
+    loss, d = T.mse_loss([1.0, 2.0, 3.0], [0.0, 4.0, 3.0], 0.5)
+    assert loss == pytest.approx(0.5 * (1.0 + 4.0 + 0.0))
+    np.testing.assert_allclose(d, [1.0, -2.0, 0.0])
+
+
+def test_mse_gradient_matches_central_differences():
+    rng = np.random.default_rng(4)
+    a, b = rng.uniform(0, 1, 12), rng.uniform(0, 1, 12)
+    _, d = T.mse_loss(a, b, 0.25)
+    h = 1e-6
+    for i in range(12):
+        e = np.zeros(12)
+        e[i] = h
+        fd = (T.mse_loss(a + e, b, 0.25)[0] - T.mse_loss(a - e, b, 0.25)[0]) / (2 * h)
+        assert fd == pytest.approx(d[i], rel=1e-6, abs=1e-9)
+
+
+def test_box_filter_hand_example_and_special_cases():
+    t = np.arange(4 * 4 * 3, dtype=np.float64).reshape(1, 4, 4, 3)
+    out = T.box_filter(t, 2)
+    # top-left 2 x 2 block of channel 0 holds 0, 3, 12, 15
+    assert out[0, 0, 0, 0] == pytest.approx((0 + 3 + 12 + 15) / 4)
+    # bottom-right block of channel 2 holds 32, 35, 44, 47
+    assert out[0, 1, 1, 2] == pytest.approx((32 + 35 + 44 + 47) / 4)
+    np.testing.assert_array_equal(T.box_filter(t, 4), t)  # M = N: identity
+    np.testing.assert_allclose(T.box_filter(t, 1)[0, 0, 0], t[0].mean(axis=(0, 1)))
+    const = np.broadcast_to(np.array([0.2, 0.5, 0.9]), (3, 8, 8, 3))
+    np.testing.assert_allclose(T.box_filter(const, 2), np.broadcast_to([0.2, 0.5, 0.9],
+                                                                       (3, 2, 2, 3)))
+    rng = np.random.default_rng(2)
+    r = rng.uniform(0, 1, (5, 8, 8, 3))
+    # the mean colour of every grid is kept, and filtering in steps equals filtering at once
+    np.testing.assert_allclose(T.box_filter(r, 2).mean(axis=(1, 2)), r.mean(axis=(1, 2)))
+    np.testing.assert_allclose(T.box_filter(T.box_filter(r, 4), 2), T.box_filter(r, 2))
+    with pytest.raises(ValueError):
+        T.box_filter(r, 3)
+
+
+def test_rotz_only_keeps_quaternions_about_z_and_tangents_in_plane():
+    rng = np.random.default_rng(6)
+    P = 40
+    a = rng.uniform(0, 2 * np.pi, P)
+    q = np.stack([np.cos(a / 2), np.zeros(P), np.zeros(P), np.sin(a / 2)], axis=1)
+    m, v = np.zeros_like(q), np.zeros_like(q)
+    for step in range(1, 6):
+        g = T.rotz_only(rng.standard_normal((P, 4)))
+        assert np.all(g[:, 1:3] == 0.0)
+        q, m, v = T.adam_step(q, g, m, v, step, 1e-2)
+    assert np.all(q[:, 1:3] == 0.0)
+    t_u, t_v, _, _ = T.activate(q, np.zeros((P, 2)), np.zeros(P))
+    # a rotation about z by angle b = 2 atan2(z, w): t_u = (cos b, sin b, 0), t_v = (-sin b, cos b, 0)
+    b = 2.0 * np.arctan2(q[:, 3], q[:, 0])
+    np.testing.assert_allclose(t_u, np.stack([np.cos(b), np.sin(b), np.zeros(P)], 1), atol=1e-12)
+    np.testing.assert_allclose(t_v, np.stack([-np.sin(b), np.cos(b), np.zeros(P)], 1), atol=1e-12)
