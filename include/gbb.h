@@ -226,6 +226,25 @@ gb_status gb_activate_bwd(int32_t P, const float* quats, const float* log_scales
 gb_status gb_l1_loss(int64_t n, const float* rgb, const float* target, float scale,
                      float* loss, float* d_rgb, void* stream);
 
+/* Squared-error image loss over n values (Sec. 4: single images are fitted with an MSE loss):
+ * *loss (one device float) = scale * sum (rgb - target)^2 and d_rgb = 2 scale (rgb - target);
+ * scale = 1 / n gives the mean. rgb, target and d_rgb 16-byte aligned. */
+gb_status gb_mse_loss(int64_t n, const float* rgb, const float* target, float scale,
+                      float* loss, float* d_rgb, void* stream);
+
+/* Box filter of colour grids (Sec. 4: the fitted grids are rendered downsampled to 2 x 2 or to
+ * one colour to show that the image lives in them): textures [P][N][N][3] -> out [P][M][M][3],
+ * each output texel the mean of the (N / M) x (N / M) input texels it covers. M divides N,
+ * 1 <= M <= N <= 64. `out` must not overlap `textures`. */
+gb_status gb_box_filter_textures(int32_t P, int32_t N, int32_t M, const float* textures,
+                                 float* out, void* stream);
+
+/* Restricts splat rotations to the Z axis (Sec. 4: for single-image fitting the splats only
+ * rotate about the camera axis, so that they stay in the image plane): zeroes the x and y
+ * components of d_quats [P][4] = d(w, x, y, z) in place. With quaternions initialised as
+ * (w, 0, 0, z), Adam then keeps them in that form. */
+gb_status gb_rotz_only(int32_t P, float* d_quats, void* stream);
+
 /* One Adam step (Kingma and Ba) on n parameters: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
  * param -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps), in place; step >= 1.
  * With bf16_copy != NULL the updated parameters are also written rounded to bfloat16 (nearest,

@@ -22,6 +22,7 @@ EXPORTS = (
     "gb_read_status", "gb_blend_stats", "gb_timing_enable", "gb_timing_read",
     "gb_timing_stage_name", "gb_default_options", "gb_status_string", "gb_last_error",
     "gb_activate_fwd", "gb_activate_bwd", "gb_l1_loss", "gb_adam_step", "gb_to_bf16",
+    "gb_mse_loss", "gb_box_filter_textures", "gb_rotz_only",
 )
 
 
@@ -110,10 +111,14 @@ def load() -> ctypes.CDLL:
     lib.gb_adam_step.argtypes = [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
                                  c_float, c_float, c_float, c_float, c_void_p, c_void_p]
     lib.gb_to_bf16.argtypes = [c_int64, c_void_p, c_void_p, c_void_p]
+    lib.gb_mse_loss.argtypes = [c_int64, c_void_p, c_void_p, c_float, c_void_p, c_void_p, c_void_p]
+    lib.gb_box_filter_textures.argtypes = [c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                                           c_void_p]
+    lib.gb_rotz_only.argtypes = [c_int32, c_void_p, c_void_p]
     for name in ("gb_workspace_layout", "gb_count_pairs", "gb_render_fwd", "gb_render_bwd",
                  "gb_read_status", "gb_blend_stats", "gb_timing_enable", "gb_timing_read",
                  "gb_activate_fwd", "gb_activate_bwd", "gb_l1_loss", "gb_adam_step",
-                 "gb_to_bf16"):
+                 "gb_to_bf16", "gb_mse_loss", "gb_box_filter_textures", "gb_rotz_only"):
         getattr(lib, name).restype = c_int32
     _lib = lib
     return lib

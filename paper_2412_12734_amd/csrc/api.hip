@@ -626,6 +626,40 @@ gb_status gb_l1_loss(int64_t n, const float* rgb, const float* target, float sca
   return GB_OK;
 }
 
+gb_status gb_mse_loss(int64_t n, const float* rgb, const float* target, float scale,
+                      float* loss, float* d_rgb, void* stream) {
+  if (n < 0) return arg_fail("n must be >= 0");
+  if (!loss || !aligned(loss, 4)) return arg_fail("loss NULL or misaligned");
+  const void* ptrs[] = {rgb, target, d_rgb};
+  for (const void* p : ptrs)
+    if (!p || !aligned(p, 16)) return arg_fail("loss array NULL or not 16-byte aligned");
+  GBB_TRY(launch_mse_loss(n, rgb, target, scale, loss, d_rgb,
+                          reinterpret_cast<hipStream_t>(stream)),
+          "mse loss");
+  return GB_OK;
+}
+
+gb_status gb_box_filter_textures(int32_t P, int32_t N, int32_t M, const float* textures,
+                                 float* out, void* stream) {
+  if (P < 0) return arg_fail("P must be >= 0");
+  if (N < 1 || N > 64 || M < 1 || M > N || N % M != 0)
+    return arg_fail("need 1 <= M <= N <= 64 with M dividing N");
+  if (P == 0) return GB_OK;
+  if (!textures || !out || !aligned(textures, 4) || !aligned(out, 4))
+    return arg_fail("texture arrays NULL or misaligned");
+  GBB_TRY(launch_box_filter(P, N, M, textures, out, reinterpret_cast<hipStream_t>(stream)),
+          "box filter");
+  return GB_OK;
+}
+
+gb_status gb_rotz_only(int32_t P, float* d_quats, void* stream) {
+  if (P < 0) return arg_fail("P must be >= 0");
+  if (P == 0) return GB_OK;
+  if (!d_quats || !aligned(d_quats, 4)) return arg_fail("d_quats NULL or misaligned");
+  GBB_TRY(launch_rotz_only(P, d_quats, reinterpret_cast<hipStream_t>(stream)), "rotz only");
+  return GB_OK;
+}
+
 gb_status gb_adam_step(int64_t n, float* param, const float* grad, float* m, float* v,
                        int32_t step, float lr, float beta1, float beta2, float eps,
                        uint16_t* bf16_copy, void* stream) {

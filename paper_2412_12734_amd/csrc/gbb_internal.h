@@ -218,6 +218,11 @@ hipError_t launch_activate_bwd(int P, const float* quats, const float* log_scale
                                float* d_log_scales, float* d_logits, hipStream_t s);
 hipError_t launch_l1_loss(int64_t n, const float* rgb, const float* target, float scale,
                           float* loss, float* d_rgb, hipStream_t s);
+hipError_t launch_mse_loss(int64_t n, const float* rgb, const float* target, float scale,
+                           float* loss, float* d_rgb, hipStream_t s);
+hipError_t launch_box_filter(int64_t P, int N, int M, const float* in, float* out,
+                             hipStream_t s);
+hipError_t launch_rotz_only(int64_t P, float* d_quats, hipStream_t s);
 hipError_t launch_to_bf16(int64_t n, const float* src, uint16_t* dst, hipStream_t s);
 hipError_t launch_adam(int64_t n, float* theta, const float* grad, float* m, float* v, float lr,
                        float b1, float b2, float c1, float c2, float eps, uint16_t* bf16,

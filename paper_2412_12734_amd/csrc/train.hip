@@ -91,11 +91,24 @@ __device__ __forceinline__ float l1_term(float r, float t, float scale, float& d
   return fabsf(diff);
 }
 
-// L1 loss: d_rgb = scale sign(rgb - target); the block's sum of |rgb - target| goes to *loss
-// with one float atomic (the order of those additions is free).
+__device__ __forceinline__ float mse_term(float r, float t, float scale, float& d) {
+  const float diff = r - t;
+  d = 2.0f * scale * diff;
+  return diff * diff;
+}
+
+template <bool MSE>
+__device__ __forceinline__ float loss_term(float r, float t, float scale, float& d) {
+  return MSE ? mse_term(r, t, scale, d) : l1_term(r, t, scale, d);
+}
+
+// Image loss (L1, or squared error with MSE): d_rgb = scale sign(rgb - target), or
+// 2 scale (rgb - target); the block's sum of the terms goes to *loss with one float atomic
+// (the order of those additions is free).
+template <bool MSE>
 __global__ void __launch_bounds__(kThreads)
-l1_kernel(int64_t n, const float* __restrict__ rgb, const float* __restrict__ target,
-          float scale, float* __restrict__ loss, float* __restrict__ d_rgb) {
+loss_kernel(int64_t n, const float* __restrict__ rgb, const float* __restrict__ target,
+            float scale, float* __restrict__ loss, float* __restrict__ d_rgb) {
   __shared__ float wave_sum[kThreads / 64];
   float acc = 0.0f;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -104,13 +117,13 @@ l1_kernel(int64_t n, const float* __restrict__ rgb, const float* __restrict__ ta
       const float4 r = reinterpret_cast<const float4*>(rgb)[i];
       const float4 t = reinterpret_cast<const float4*>(target)[i];
       float4 d;
-      acc += l1_term(r.x, t.x, scale, d.x) + l1_term(r.y, t.y, scale, d.y) +
-             l1_term(r.z, t.z, scale, d.z) + l1_term(r.w, t.w, scale, d.w);
+      acc += loss_term<MSE>(r.x, t.x, scale, d.x) + loss_term<MSE>(r.y, t.y, scale, d.y) +
+             loss_term<MSE>(r.z, t.z, scale, d.z) + loss_term<MSE>(r.w, t.w, scale, d.w);
       reinterpret_cast<float4*>(d_rgb)[i] = d;
     } else {
       for (int64_t j = 4 * i; j < n; ++j) {
         float d;
-        acc += l1_term(rgb[j], target[j], scale, d);
+        acc += loss_term<MSE>(rgb[j], target[j], scale, d);
         d_rgb[j] = d;
       }
     }
@@ -208,6 +221,60 @@ hipError_t launch_activate_bwd(int P, const float* quats, const float* log_scale
   return hipGetLastError();
 }
 
+// Box filter of colour grids (the paper's check that the optimised grids carry the image):
+// each output texel of the M x M grid is the mean of the k x k input texels it covers, k = N / M.
+__global__ void __launch_bounds__(kThreads)
+box_filter_kernel(int64_t P, int N, int M, const float* __restrict__ in, float* __restrict__ out) {
+  const int64_t total = P * M * M * 3;
+  const int k = N / M;
+  const float inv = 1.0f / (float)(k * k);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % 3);
+    const int64_t t = e / 3;
+    const int j = (int)(t % M), i = (int)((t / M) % M);
+    const int64_t p = t / ((int64_t)M * M);
+    const float* src = in + ((p * N + (int64_t)i * k) * N + (int64_t)j * k) * 3 + c;
+    float acc = 0.0f;
+    for (int a = 0; a < k; ++a)
+      for (int b = 0; b < k; ++b) acc += src[((int64_t)a * N + b) * 3];
+    out[e] = acc * inv;
+  }
+}
+
+// Rotation about the Z axis only: the x and y components of each quaternion's gradient are
+// zeroed, so that Adam leaves quaternions of the form (w, 0, 0, z) in that form.
+__global__ void __launch_bounds__(kThreads)
+rotz_only_kernel(int64_t P, float* __restrict__ d_quats) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    d_quats[4 * k + 1] = 0.0f;
+    d_quats[4 * k + 2] = 0.0f;
+  }
+}
+
+hipError_t launch_mse_loss(int64_t n, const float* rgb, const float* target, float scale,
+                           float* loss, float* d_rgb, hipStream_t s) {
+  unsigned blocks = grid_for(n, 4);
+  if (blocks > kL1MaxBlocks) blocks = kL1MaxBlocks;
+  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s, loss);
+  hipLaunchKernelGGL(loss_kernel<true>, dim3(blocks), dim3(kThreads), 0, s, n, rgb, target,
+                     scale, loss, d_rgb);
+  return hipGetLastError();
+}
+
+hipError_t launch_box_filter(int64_t P, int N, int M, const float* in, float* out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(box_filter_kernel, dim3(grid_for(P * M * M * 3, 1)), dim3(kThreads), 0, s,
+                     P, N, M, in, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rotz_only(int64_t P, float* d_quats, hipStream_t s) {
+  hipLaunchKernelGGL(rotz_only_kernel, dim3(grid_for(P, 1)), dim3(kThreads), 0, s, P, d_quats);
+  return hipGetLastError();
+}
+
 hipError_t launch_l1_loss(int64_t n, const float* rgb, const float* target, float scale,
                           float* loss, float* d_rgb, hipStream_t s) {
   // each block ends with one float atomic on the single loss value, and those serialise:
@@ -216,8 +283,8 @@ hipError_t launch_l1_loss(int64_t n, const float* rgb, const float* target, floa
   unsigned blocks = grid_for(n, 4);
   if (blocks > kL1MaxBlocks) blocks = kL1MaxBlocks;
   hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s, loss);
-  hipLaunchKernelGGL(l1_kernel, dim3(blocks), dim3(kThreads), 0, s, n, rgb, target, scale, loss,
-                     d_rgb);
+  hipLaunchKernelGGL(loss_kernel<false>, dim3(blocks), dim3(kThreads), 0, s, n, rgb, target,
+                     scale, loss, d_rgb);
   return hipGetLastError();
 }
 

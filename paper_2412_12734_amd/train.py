@@ -1,4 +1,4 @@
-"""Training step around the rasterizer: activations, L1 image loss and Adam.
+"""Training step around the rasterizer: activations, image loss (L1 or MSE) and Adam.
 
 The paper optimises the splats' positions, rotations, scales, opacities and colour grids
 against images (Sec. 3.3). This module keeps raw float32 parameters with their Adam moments
@@ -6,8 +6,11 @@ on the device, activates them (quaternion -> tangents, exp scales, sigmoid opaci
 batch of views, takes the L1 loss against target images, backpropagates through the
 rasterizer and the activations and applies Adam to every parameter group. With bfloat16
 textures the Adam step also rewrites the bfloat16 render copy of the float32 master textures.
-Every step runs in libgbb kernels; torch supplies memory and the stream. Densification,
-pruning and the SSIM term are not part of it.
+For fitting a single image (Sec. 4) the loss is the mean squared error and the splats rotate
+about the camera's Z axis only (``rotz_only``); ``box_filter_textures`` downsamples fitted
+colour grids as the paper does to show that they carry the image. Every step runs in libgbb
+kernels; torch supplies memory and the stream. Densification, pruning and the SSIM term are
+not part of it.
 """
 from __future__ import annotations
 
@@ -33,8 +36,10 @@ class TrainState:
     """Raw parameters (float32 masters), Adam moments and activated copies on the device."""
 
     def __init__(self, raw, bf16: bool = True, device="cuda",
-                 lr: Optional[Dict[str, float]] = None, betas=(0.9, 0.999), eps: float = 1e-15):
+                 lr: Optional[Dict[str, float]] = None, betas=(0.9, 0.999), eps: float = 1e-15,
+                 rotz_only: bool = False):
         self.lib = L.load()
+        self.rotz_only = rotz_only
         self.device = torch.device(device)
         f = lambda a: torch.from_numpy(a).to(self.device).contiguous()
         self.params = {g: f(getattr(raw, g)) for g in GROUPS}
@@ -77,6 +82,8 @@ class TrainState:
                                          _p(grads["opacity"]), _p(r["quats"]),
                                          _p(r["log_scales"]), _p(r["opacity_logits"]),
                                          self.stream()), "gb_activate_bwd")
+        if self.rotz_only:
+            L.check(self.lib.gb_rotz_only(self.P, _p(r["quats"]), self.stream()), "gb_rotz_only")
         r["means"] = grads["means"]
         r["textures"] = grads["textures"]
         return r
@@ -100,6 +107,26 @@ def l1_loss(rgb: torch.Tensor, target: torch.Tensor, scale: float, loss: torch.T
                            _stream(rgb.device)), "gb_l1_loss")
 
 
+def mse_loss(rgb: torch.Tensor, target: torch.Tensor, scale: float, loss: torch.Tensor,
+             d_rgb: torch.Tensor) -> None:
+    """loss[0] = scale * sum (rgb - target)^2, d_rgb = 2 scale (rgb - target)."""
+    lib = L.load()
+    L.check(lib.gb_mse_loss(rgb.numel(), _p(rgb), _p(target), float(scale), _p(loss),
+                            _p(d_rgb), _stream(rgb.device)), "gb_mse_loss")
+
+
+def box_filter_textures(textures: torch.Tensor, M: int) -> torch.Tensor:
+    """[P, N, N, 3] float32 colour grids -> [P, M, M, 3], each texel the mean of the N / M
+    square of texels it covers (M divides N)."""
+    lib = L.load()
+    textures = textures.contiguous()
+    P, N = int(textures.shape[0]), int(textures.shape[1])
+    out = torch.empty((P, M, M, 3), dtype=torch.float32, device=textures.device)
+    L.check(lib.gb_box_filter_textures(P, N, M, _p(textures), _p(out), _stream(textures.device)),
+            "gb_box_filter_textures")
+    return out
+
+
 class Trainer:
     """One optimisation step per call on a batch of views with target images.
 
@@ -107,7 +134,10 @@ class Trainer:
     different sizes use the first width * height rows of theirs)."""
 
     def __init__(self, state: TrainState, views: Sequence, targets: torch.Tensor,
-                 options: Optional[Options] = None):
+                 options: Optional[Options] = None, loss: str = "l1"):
+        if loss not in ("l1", "mse"):
+            raise ValueError("loss must be 'l1' or 'mse'")
+        self.loss_fn = l1_loss if loss == "l1" else mse_loss
         self.state, self.views, self.targets = state, list(views), targets
         self.rast: Optional[Rasterizer] = None
         self.options = options or Options()
@@ -154,7 +184,7 @@ class Trainer:
             hw = self.views[i].width * self.views[i].height
             target[at:at + hw].copy_(self.targets[i].view(-1, 3)[:hw])
             at += hw
-        l1_loss(rgb, target, 1.0 / (3 * n_px), self.loss, d_rgb)
+        self.loss_fn(rgb, target, 1.0 / (3 * n_px), self.loss, d_rgb)
         self.grads = self.rast.backward(sp, T, d_rgb, self.grads)
         st.adam(st.backward_activations(self.grads))
         return self.loss

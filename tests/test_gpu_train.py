@@ -194,3 +194,85 @@ def test_planned_trainer_matches_the_checked_one(gb):
         runs.append([float(tr.step(b)) for b in sched])
         assert not tr.overflowed()
     np.testing.assert_allclose(runs[1], runs[0], rtol=1e-5)
+
+
+# --- single-image fitting set-up (Sec. 4): MSE loss, box-filtered grids, rotation about z ---
+@pytest.mark.parametrize("n", [1, 7, 4096, 100003])
+def test_mse_loss_matches_the_oracle(gb, n):
+    from paper_2412_12734_amd import train as T
+    rng = np.random.default_rng(n + 7)
+    a, b = rng.uniform(0, 1, n).astype(np.float32), rng.uniform(0, 1, n).astype(np.float32)
+    loss = torch.zeros(1, device="cuda")
+    d = torch.empty(n, device="cuda")
+    T.mse_loss(cuda(a), cuda(b), 1.0 / n, loss, d)
+    wl, wd = TO.mse_loss(a, b, np.float32(1.0 / n))
+    assert float(loss) == pytest.approx(wl, rel=1e-5)
+    # d = 2 scale (a - b): two float32 roundings (the difference, the product)
+    np.testing.assert_allclose(d.cpu().numpy(), wd, rtol=3 * 2.0 ** -24, atol=1e-30)
+
+
+@pytest.mark.parametrize("N,M", [(8, 2), (8, 1), (4, 4), (16, 4), (2, 1)])
+def test_box_filter_matches_the_oracle(gb, N, M):
+    from paper_2412_12734_amd import train as T
+    rng = np.random.default_rng(N * 10 + M)
+    tex = rng.uniform(0, 1, (1001, N, N, 3)).astype(np.float32)
+    got = T.box_filter_textures(cuda(tex), M).cpu().numpy()
+    want = TO.box_filter(tex, M)
+    k = N // M
+    # k^2 float32 additions of values in [0, 1], then an exact scaling by 1 / k^2
+    np.testing.assert_allclose(got, want, rtol=0, atol=k * k * 2.0 ** -24)
+
+
+def test_image_fit_gradients_with_mse_and_rotation_about_z(gb):
+    from paper_2412_12734_amd import train as T
+    raw, view, target = sg.image_fit_config(21, 600, 80, 56, 4)
+    n_px = view.width * view.height
+    scale = 1.0 / (3 * n_px)
+    st = T.TrainState(raw, bf16=False, rotz_only=True)
+    sp = st.activate()
+    rast = gb.Rasterizer([view])
+    rast.plan(sp)
+    rgb, Tf = rast.forward(sp)
+    loss = torch.zeros(1, device="cuda")
+    d_rgb = torch.empty_like(rgb)
+    T.mse_loss(rgb, cuda(target), scale, loss, d_rgb)
+    t_u, t_v, s, o = TO.activate(raw.quats, raw.log_scales, raw.opacity_logits)
+    scene = sg.Scene(raw.means, t_u.astype(np.float32), t_v.astype(np.float32),
+                     s.astype(np.float32), o.astype(np.float32), raw.textures)
+    ref = O.render(scene, view, O.Options(), keep_saved=True)
+    wl, wd = TO.mse_loss(ref.rgb.reshape(-1, 3), target, scale)
+    assert float(loss) == pytest.approx(wl, rel=1e-4)
+    keep = ~O.grad_flags(ref).reshape(-1)
+    # both sides take the oracle's pixel adjoint, so that the comparison is of the chain
+    d_rgb.copy_(cuda(np.where(keep[:, None], wd, 0.0)))
+    raw_g = st.backward_activations(rast.backward(sp, Tf, d_rgb))
+    ref_g = O.render_backward(scene, view, O.Options(), ref, np.where(keep[:, None], wd, 0.0))
+    wq, wls, wol = TO.activate_backward(raw.quats, raw.log_scales, raw.opacity_logits,
+                                        ref_g.tan_u, ref_g.tan_v, ref_g.scales, ref_g.opacity)
+    wq = TO.rotz_only(wq)
+    got_q = raw_g["quats"].cpu().numpy()
+    assert np.all(got_q[:, 1:3] == 0.0)
+    for name, want in (("means", ref_g.means), ("textures", ref_g.textures), ("quats", wq),
+                       ("log_scales", wls), ("opacity_logits", wol)):
+        err = rel(raw_g[name].cpu().numpy(), want)
+        assert err <= 1e-3, (name, err)
+
+
+def test_image_fit_trainer_keeps_rotations_about_z_and_lowers_the_loss(gb):
+    from paper_2412_12734_amd import train as T
+    raw, view, target = sg.image_fit_config(3, 3000, 128, 96, 4)
+    st = T.TrainState(raw, bf16=False, rotz_only=True)
+    tr = T.Trainer(st, [view], cuda(target).view(1, -1, 3), loss="mse")
+    losses = [float(tr.step([0])) for _ in range(12)]
+    assert all(np.isfinite(losses)) and losses[-1] < losses[0]
+    q = st.params["quats"].cpu().numpy()
+    assert np.all(q[:, 1:3] == 0.0)
+    # the box-filtered grids render with N = 2 and N = 1 (the paper's check of the grids)
+    for M in (2, 1):
+        small = T.box_filter_textures(st.params["textures"], M)
+        sp = st.activate()
+        sp2 = gb.Splats(sp.means, sp.tan_u, sp.tan_v, sp.scales, sp.opacity, small)
+        rast = gb.Rasterizer([view])
+        rast.plan(sp2)
+        rgb, _ = rast.forward(sp2)
+        assert bool(torch.isfinite(rgb).all())
