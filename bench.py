@@ -161,6 +161,37 @@ def train_variant(gb, sg, torch, warmup=20, iters=200):
     return out
 
 
+def image_fit_variant(gb, sg, torch, P, N, warmup=10, iters=100):
+    """Single-image fitting (Sec. 4): P splats with N x N FP32 colour grids in the plane of a
+    1920 x 871 synthetic image (the size of the paper's first test image), rotation about Z
+    only, MSE loss, Adam. Per-iteration durations from HIP events on the launch stream."""
+    from paper_2412_12734_amd import train as TR
+    raw, view, target = sg.image_fit_config(0, P, 1920, 871, N)
+    st = TR.TrainState(raw, bf16=False, rotz_only=True)
+    trainer = TR.Trainer(st, [view], torch.from_numpy(target).cuda().view(1, -1, 3), loss="mse")
+    sched = [[0]] * (warmup + iters)
+    trainer.plan(sched[:1], headroom=2.0)
+    first = float(trainer.step([0]))
+    for b in sched[1:warmup]:
+        trainer.step(b)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(iters + 1)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for i, b in enumerate(sched[warmup:]):
+        trainer.step(b)
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(iters))
+    out = {"ms_per_iter_median": round(ms[iters // 2], 3), "iters": iters, "warmup": warmup,
+           "mse_first": round(first, 6), "mse_last": round(float(trainer.loss), 6),
+           "overflow_last_step": trainer.overflowed(),
+           "workload": f"{P} splats, {N}x{N} FP32 grids, 1920x871 synthetic image, MSE, "
+                       "rotation about Z, Adam"}
+    del trainer, st
+    torch.cuda.empty_cache()
+    return out
+
+
 def c3_variant(gb, sg, torch, warmup, steps):
     """1M splats with 4x4 FP32 textures, 16 views of uneven size on a radius-8 sphere: forward
     + backward of all views as one batched step replayed from a HIP graph, against the same
@@ -424,6 +455,10 @@ def main():
         variants["train_step_500k_4x720p"] = train_variant(gb, sg, torch,
                                                            iters=args.train_iters)
         log(f"train step: {variants['train_step_500k_4x720p']}")
+        for P in (10_000, 100_000):
+            log(f"variant: single-image fitting, {P} splats, 4x4 grids, 1920x871")
+            variants[f"image_fit_{P // 1000}k"] = image_fit_variant(gb, sg, torch, P, 4)
+            log(f"image fit: {variants[f'image_fit_{P // 1000}k']}")
 
     cpu = None
     if not args.no_cpu_baseline:
