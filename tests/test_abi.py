@@ -154,3 +154,21 @@ def test_training_glue_rejects_invalid_arguments_before_any_launch():
                             None) == L.GB_OK  # empty
     assert lib.gb_to_bf16(-1, None, None, None) == L.GB_ERR_ARG
 
+
+
+def test_image_fitting_glue_rejects_invalid_arguments_before_any_launch():
+    lib = _lib()
+    buf = ctypes.create_string_buffer(64)
+    base = ctypes.addressof(buf)
+    p16 = base + (-base) % 16
+    assert lib.gb_mse_loss(-1, p16, p16, 1.0, p16, p16, None) == L.GB_ERR_ARG
+    assert lib.gb_mse_loss(4, p16 + 4, p16, 1.0, p16, p16, None) == L.GB_ERR_ARG  # misaligned
+    assert lib.gb_mse_loss(4, None, p16, 1.0, p16, p16, None) == L.GB_ERR_ARG
+    for N, M in ((8, 3), (4, 8), (128, 2), (0, 1), (8, 0)):
+        assert lib.gb_box_filter_textures(2, N, M, p16, p16, None) == L.GB_ERR_ARG, (N, M)
+    assert lib.gb_box_filter_textures(-1, 8, 2, p16, p16, None) == L.GB_ERR_ARG
+    assert lib.gb_box_filter_textures(2, 8, 2, None, p16, None) == L.GB_ERR_ARG
+    assert lib.gb_box_filter_textures(0, 8, 2, None, None, None) == L.GB_OK  # nothing to do
+    assert lib.gb_rotz_only(-1, p16, None) == L.GB_ERR_ARG
+    assert lib.gb_rotz_only(3, None, None) == L.GB_ERR_ARG
+    assert lib.gb_rotz_only(0, None, None) == L.GB_OK
