@@ -39,7 +39,7 @@ def pixel_to_world(view, x, y, Z):
     return (Z * (x - view.cx) / view.fx, Z * (y - view.cy) / view.fy, Z)
 
 
-# --- P1: alpha at the splat centre equals opacity (the benchmark spec) -------------------------
+# --- P1: alpha at the splat centre equals opacity ---------------------------------------
 def test_alpha_at_center_equals_opacity():
     view = sg.frontal_view(16, 16)
     X, Y, Z = pixel_to_world(view, 8.5, 7.5, 4.0)
