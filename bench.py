@@ -299,6 +299,8 @@ def main():
     ap.add_argument("--train-iters", type=int, default=200)
     ap.add_argument("--train-only", action="store_true",
                     help="time only the optimisation-step variant (for kernel traces of it)")
+    ap.add_argument("--image-fit-only", action="store_true",
+                    help="time only the 100k-splat single-image fitting variant")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the rasterizer has no "
@@ -313,6 +315,11 @@ def main():
     if args.train_only:
         tr = train_variant(gb, sg, torch, warmup=args.warmup, iters=args.train_iters)
         print(json.dumps({"train_step_500k_4x720p": tr}), flush=True)
+        return
+    if args.image_fit_only:
+        fit = image_fit_variant(gb, sg, torch, 100_000, 4, warmup=args.warmup,
+                                iters=args.train_iters)
+        print(json.dumps({"image_fit_100k": fit}), flush=True)
         return
     copy_gbs = copy_probe(torch)
     log(f"plain device copy of {COPY_BYTES >> 20} MiB: {copy_gbs:.0f} GB/s (read + write)")
