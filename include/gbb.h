@@ -86,7 +86,8 @@ typedef struct {
   int32_t tile_w;     /* tile width in px: 8, 16 or 32 */
   int32_t tile_h;     /* tile height in px: 8, 16 or 32; tile_w * tile_h <= 256 */
   int32_t batch;      /* splats staged in LDS per forward batch: 0 = default (8 for N = 16,
-                         16 for N = 8, else 64), or 8, 16, 32, 64 (N = 16: 8 only) */
+                         16 for N = 8, 32 for N = 4, else 64), or 8, 16, 32, 64 (N = 16: 8
+                         only) */
   int32_t batch_bwd;  /* splats staged in LDS per backward batch: 0 = default (8 for N >= 8,
                          else 32), or 8, 16, 32 (N = 16: 8 only) */
   int32_t prefix_pairs_per_tile;

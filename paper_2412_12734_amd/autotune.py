@@ -31,12 +31,12 @@ KNOBS: Dict[str, List] = {
 
 
 def resolve_defaults(opts, N: int):
-    """The options with the library's defaults written out (batch 0 -> 8, 16 or 64, batch_bwd 0 ->
-    8 or 32, prefix budget 0 -> 1024 pairs per tile, tile order 0 -> 1), so that search
-    results are explicit."""
+    """The options with the library's defaults written out (batch 0 -> 8, 16, 32 or 64,
+    batch_bwd 0 -> 8 or 32, prefix budget 0 -> 1024 pairs per tile, tile order 0 -> 1), so that
+    search results are explicit."""
     return dataclasses.replace(
         opts,
-        batch=opts.batch or (8 if N >= 16 else 16 if N >= 8 else 64),
+        batch=opts.batch or (8 if N >= 16 else 16 if N >= 8 else 32 if N >= 4 else 64),
         batch_bwd=opts.batch_bwd or (8 if N >= 8 else 32),
         prefix_pairs_per_tile=opts.prefix_pairs_per_tile or 1024,
         tile_order=opts.tile_order or 1)

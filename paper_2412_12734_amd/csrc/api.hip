@@ -112,8 +112,10 @@ gb_status make_plan(int32_t P, int32_t N, const gb_view* views, int32_t n_views,
   pl->tile_h = o->tile_h == 0 ? 16 : o->tile_h;
   // defaults: at N = 8 the smaller batches measured faster on the 1M-splat 1080p workload
   // (forward 16 vs 32: 0.50 vs 0.60 ms; backward 8 vs 16: 2.21 vs 2.31 ms), because less LDS
-  // per block lets more blocks share a CU
-  pl->batch_fwd = o->batch != 0 ? o->batch : (N >= 16 ? 8 : N >= 8 ? 16 : 64);
+  // per block lets more blocks share a CU; at N = 4 a forward batch of 32 beat 64 and 16 (1M
+  // splats at 1080p, forward + backward: 2.06 vs 2.13 ms) and a backward batch of 32 beat
+  // 16 and 8 (2.13 vs 2.19 and 2.28 ms)
+  pl->batch_fwd = o->batch != 0 ? o->batch : (N >= 16 ? 8 : N >= 8 ? 16 : N >= 4 ? 32 : 64);
   pl->batch_bwd = o->batch_bwd != 0 ? o->batch_bwd : (N >= 8 ? 8 : 32);
   // N = 16: 4.3 KB of staged texels per splat; batches of 8 keep the backward's LDS (texels
   // plus their gradient sums) near 61 KB per workgroup
