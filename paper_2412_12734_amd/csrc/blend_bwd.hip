@@ -16,8 +16,9 @@
 // lane, which adds it to the splat's LDS slot. Texel gradients are grouped by grid cell (with
 // sigma = 0.5 the grid covers only the splat's core, so most blended pixels are border-clamped
 // and share a few cells); each group's four corners and three channels are reduced the same
-// way, one group after another until every pixel's cell has been taken. A splat that no pixel
-// of the wave blended is skipped after evaluation. After each batch the non-zero LDS sums go to
+// way, one group after another until every pixel's cell has been taken (a step that blended
+// at most 16 pixels adds each pixel's corners directly instead). A splat that no pixel of the
+// wave blended is skipped after evaluation. After each batch the non-zero LDS sums go to
 // global memory with one float atomic each.
 #include "blend_common.h"
 
@@ -131,6 +132,12 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
 // allocation (77 VGPRs) stops there; asking for 7 (at most 72 VGPRs, two dwords spilled)
 // measured 4 % faster on the 1M-splat 1080p workload, 8 (64 VGPRs) slower.
 // (N = 16 blocks hold 61 KB of LDS, two per CU, so no register target applies there.)
+// Wave steps that blended at most this many pixels skip the cell grouping (measured at 1M
+// splats and 1080p: unchanged time; 100k splats at 800x800 and 3M splats at 4 x 1080p, where
+// fewer lanes blend per step: 5 and 6 % faster; 32 lanes gained more there but cost the 1M
+// splat workload).
+constexpr int kLaneAddMax = 16;
+
 template <int N, int B>
 constexpr int bwd_min_waves() { return (B <= 8 && N <= 8) ? 7 : 1; }
 
@@ -310,42 +317,66 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
         uint64_t pend[PIX];
 #pragma unroll
         for (int s = 0; s < PIX; ++s) pend[s] = ballot(po[s].act);
-        // Every group takes at least its lead lane, so the loop ends within 64 passes. A bound
-        // of four passes with per-lane LDS adds for the remaining lanes measured 1.80 ms at
-        // 1M splats and 1080p (10 % of wave steps have more than four cells), eight passes
-        // 1.73 ms: the per-lane adds, serialised on shared addresses, cost more than passes.
-#pragma unroll 1
-        for (;;) {
-          int lead_cell = -1;
+        // A wave step that blended few pixels (small or distant splats) adds each pixel's
+        // bilinear corners to LDS directly; up to 16 lanes this costs less than group passes.
+        int n_act = 0;
+#pragma unroll
+        for (int s = 0; s < PIX; ++s) n_act += __builtin_popcountll(pend[s]);
+        if (n_act <= kLaneAddMax) {
+          float* gb = s_gtex + j * TEXG;
 #pragma unroll
           for (int s = 0; s < PIX; ++s) {
-            if (lead_cell < 0 && pend[s] != 0)
-              lead_cell = __builtin_amdgcn_readlane(po[s].k00, (int)__builtin_ctzll(pend[s]));
-          }
-          if (lead_cell < 0) break;
-          bool in[PIX];
+            if ((pend[s] >> lane) & 1ull) {
 #pragma unroll
-          for (int s = 0; s < PIX; ++s) {
-            in[s] = ((pend[s] >> lane) & 1ull) && po[s].k00 == lead_cell;
-            pend[s] &= ~ballot(in[s]);
-          }
-          // all corners and channels in one transposing wave reduction, so that one lane per
-          // value adds it to LDS: one add instruction per group
-          float red[KT];
-#pragma unroll
-          for (int k = 0; k < KT; ++k) red[k] = 0.f;
-#pragma unroll
-          for (int s = 0; s < PIX; ++s) {
-#pragma unroll
-            for (int q = 0; q < KT / 3; ++q) {
-              const float wv = in[s] ? po[s].w[q] : 0.f;
-              red[3 * q] += wv * po[s].dc0;
-              red[3 * q + 1] += wv * po[s].dc1;
-              red[3 * q + 2] += wv * po[s].dc2;
+              for (int q = 0; q < KT / 3; ++q) {
+                const float wq = po[s].w[q];
+                if (wq != 0.f) {
+                  float* dst = gb + 3 * (po[s].k00 + (q & 1) + (q >> 1) * N);
+                  atomicAdd(dst + 0, wq * po[s].dc0);
+                  atomicAdd(dst + 1, wq * po[s].dc1);
+                  atomicAdd(dst + 2, wq * po[s].dc2);
+                }
+              }
             }
           }
-          const float tot = wave_reduce_scatter<KT>(red);
-          if (tex_owner) atomicAdd(gt + 3 * lead_cell, tot);
+        } else {
+          // Every group takes at least its lead lane, so the loop ends within 64 passes. A bound
+          // of four passes with per-lane LDS adds for the remaining lanes measured 1.80 ms at
+          // 1M splats and 1080p (10 % of wave steps have more than four cells), eight passes
+          // 1.73 ms: the per-lane adds, serialised on shared addresses, cost more than passes.
+  #pragma unroll 1
+          for (;;) {
+            int lead_cell = -1;
+  #pragma unroll
+            for (int s = 0; s < PIX; ++s) {
+              if (lead_cell < 0 && pend[s] != 0)
+                lead_cell = __builtin_amdgcn_readlane(po[s].k00, (int)__builtin_ctzll(pend[s]));
+            }
+            if (lead_cell < 0) break;
+            bool in[PIX];
+  #pragma unroll
+            for (int s = 0; s < PIX; ++s) {
+              in[s] = ((pend[s] >> lane) & 1ull) && po[s].k00 == lead_cell;
+              pend[s] &= ~ballot(in[s]);
+            }
+            // all corners and channels in one transposing wave reduction, so that one lane per
+            // value adds it to LDS: one add instruction per group
+            float red[KT];
+  #pragma unroll
+            for (int k = 0; k < KT; ++k) red[k] = 0.f;
+  #pragma unroll
+            for (int s = 0; s < PIX; ++s) {
+  #pragma unroll
+              for (int q = 0; q < KT / 3; ++q) {
+                const float wv = in[s] ? po[s].w[q] : 0.f;
+                red[3 * q] += wv * po[s].dc0;
+                red[3 * q + 1] += wv * po[s].dc1;
+                red[3 * q + 2] += wv * po[s].dc2;
+              }
+            }
+            const float tot = wave_reduce_scatter<KT>(red);
+            if (tex_owner) atomicAdd(gt + 3 * lead_cell, tot);
+          }
         }
       }
       __syncthreads();
