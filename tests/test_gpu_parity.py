@@ -699,3 +699,12 @@ def test_backward_overwrites_stale_gradient_buffers(gb, N):
         assert not bool((got[k] == 123.0).any()), k
         err = float((got[k].double() - v.double()).norm() / v.double().norm().clamp_min(1e-30))
         assert err <= 1e-5, (k, err)
+
+
+# --- both texel-scatter paths of the backward: few blended lanes per wave step (small splats,
+#     direct per-lane adds) and many (large splats, grouped by cell) ---------------------------
+@pytest.mark.parametrize("s_lo,s_hi", [(0.004, 0.015), (0.15, 0.5)])
+def test_gradients_with_small_and_large_splats(gb, s_lo, s_hi):
+    scene = sg.make_scene(41, 3000, -1.0, 1.0, s_lo, s_hi, 8)
+    view = sg.look_at_view((0.0, 0.0, -3.0), 96, 80)
+    check_grads(gb, scene, view, O.Options(), (0, 0, 96, 80), seed=3)
