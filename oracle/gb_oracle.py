@@ -25,9 +25,9 @@ Readings where the paper is silent or garbled (each one is also listed in the de
 * The ray-splat intersection is the homogeneous solve (u, v, 1) ~ h_x x h_y with
   M = K [R s_u t_u | R s_v t_v | R p + t], h_x = x M_2 - M_0, h_y = y M_2 - M_1. rho_2 = 0 means
   no hit; there is no test on the side of the camera.
-* A screen-space low-pass of variance 1/2 px^2 bounds the falloff from below:
-  G_hat = exp(-min(q_uv, q_lp)), q_uv = (u^2 + v^2)/2, q_lp = |x - c2|^2, c2 the projected centre
-  (ties go to the uv branch). The colour still uses the ray's (u, v).
+* A screen-space low-pass of variance var (default 1/2 px^2) bounds the falloff from below:
+  G_hat = exp(-min(q_uv, q_lp)), q_uv = (u^2 + v^2)/2, q_lp = |x - c2|^2 / (2 var), c2 the
+  projected centre (ties go to the uv branch). The colour still uses the ray's (u, v).
 * alpha = min(alpha_max, o * G_hat); alpha < alpha_min is skipped; a splat that would bring the
   transmittance below t_min is not blended and ends the pixel (Alg. 1 is marked simplified;
   these are the conventions of the splatting line of work it extends).
@@ -38,8 +38,8 @@ Readings where the paper is silent or garbled (each one is also listed in the de
 The key stage (screen rectangle, tile counts, depth key) is defined in float32 with a fixed
 operation order so that the tiling is reproducible bit for bit; everything after it is fp64.
 Its constants: 3.33 >= sqrt(2 ln 255) bounds the uv radius where o*G >= 1/255 for o <= 1, and
-2.36 >= sqrt(ln 255) px bounds the low-pass disk; with them the rectangle contains every pixel
-where alpha >= alpha_min.
+2.36 >= sqrt(ln 255) px bounds the low-pass disk at variance 1/2 (3.34 sqrt(var) above that);
+with them the rectangle contains every pixel where alpha >= alpha_min.
 """
 from __future__ import annotations
 
@@ -70,9 +70,23 @@ class Options:
 KS_RADIUS_UV = F32(3.33)
 KS_RADIUS_LP = F32(2.36)
 KS_MARGIN = F32(0.01)
+
 # The rectangle bound above holds for alpha_min >= 1/255; below it the rectangle is the
 # whole image (no culling by extent) so that thresholds can be switched off.
 KS_ALPHA_FLOOR = F32(1.0 / 255.0)
+
+
+def ks_lowpass_radius(lowpass_var: float) -> np.float32:
+    """Screen radius (px) beyond which the low-pass term alone gives o*G < 1/255 for o <= 1.
+
+    The term is exp(-r^2 / (2 var)), so the bound is sqrt(2 var ln 255) = 3.3290 sqrt(var):
+    2.36 covers every variance up to 1/2 (the default); above it the radius is
+    3.34 sqrt(var), evaluated in double precision and rounded once to float32.
+    """
+    var = float(F32(lowpass_var))
+    if var <= 0.5:
+        return KS_RADIUS_LP
+    return F32(3.34 * math.sqrt(var))
 
 
 def _f(x):
@@ -120,6 +134,7 @@ def key_stage(scene, view, opts: Options) -> Dict[str, np.ndarray]:
     zn = F32(view.z_near)
     fx, fy, cx, cy = F32(view.fx), F32(view.fy), F32(view.cx), F32(view.cy)
     W, H = int(view.width), int(view.height)
+    r_lp = ks_lowpass_radius(opts.lowpass_var)
     with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
         behind = np.zeros(p.shape[0], dtype=bool)
         for q in corners:
@@ -130,10 +145,10 @@ def key_stage(scene, view, opts: Options) -> Dict[str, np.ndarray]:
         ys = [fy * (q[1] / q[2]) + cy for q in corners]
         c2x = fx * (pc[0] / d) + cx
         c2y = fy * (pc[1] / d) + cy
-        xmin = _fmin(_fmin(_fmin(_fmin(xs[0], xs[1]), xs[2]), xs[3]), c2x - KS_RADIUS_LP) - KS_MARGIN
-        xmax = _fmax(_fmax(_fmax(_fmax(xs[0], xs[1]), xs[2]), xs[3]), c2x + KS_RADIUS_LP) + KS_MARGIN
-        ymin = _fmin(_fmin(_fmin(_fmin(ys[0], ys[1]), ys[2]), ys[3]), c2y - KS_RADIUS_LP) - KS_MARGIN
-        ymax = _fmax(_fmax(_fmax(_fmax(ys[0], ys[1]), ys[2]), ys[3]), c2y + KS_RADIUS_LP) + KS_MARGIN
+        xmin = _fmin(_fmin(_fmin(_fmin(xs[0], xs[1]), xs[2]), xs[3]), c2x - r_lp) - KS_MARGIN
+        xmax = _fmax(_fmax(_fmax(_fmax(xs[0], xs[1]), xs[2]), xs[3]), c2x + r_lp) + KS_MARGIN
+        ymin = _fmin(_fmin(_fmin(_fmin(ys[0], ys[1]), ys[2]), ys[3]), c2y - r_lp) - KS_MARGIN
+        ymax = _fmax(_fmax(_fmax(_fmax(ys[0], ys[1]), ys[2]), ys[3]), c2y + r_lp) + KS_MARGIN
         half = F32(0.5)
         i0 = np.ceil(xmin - half)
         i1 = np.floor(xmax - half)
@@ -314,7 +329,8 @@ def prune_for_crop(scene, view, opts: Options, cand: np.ndarray, crop) -> np.nda
 
     Bounding sphere of the 3.33-radius uv square: centre p, radius 3.33 (s_u|t_u| + s_v|t_v|).
     A splat is dropped only if that sphere lies beyond z_near, misses the crop's pixel-centre
-    frustum, and the 2.36 px low-pass disk around the projected centre misses the crop.
+    frustum, and the low-pass disk around the projected centre (the key stage's radius) misses
+    the crop.
     """
     if cand.size == 0 or F32(opts.alpha_min) < KS_ALPHA_FLOOR:
         return cand
@@ -340,7 +356,8 @@ def prune_for_crop(scene, view, opts: Options, cand: np.ndarray, crop) -> np.nda
         c2y = view.fy * c[:, 1] / c[:, 2] + view.cy
     dx = np.maximum(np.maximum((x0 + 0.5) - c2x, c2x - (x0 + w - 0.5)), 0.0)
     dy = np.maximum(np.maximum((y0 + 0.5) - c2y, c2y - (y0 + h - 0.5)), 0.0)
-    lp_out = dx * dx + dy * dy > 2.36 ** 2
+    r_lp = float(ks_lowpass_radius(opts.lowpass_var))
+    lp_out = dx * dx + dy * dy > r_lp * r_lp
     drop = in_front & outside & lp_out
     return cand[~drop]
 
@@ -363,6 +380,12 @@ class RenderResult:
     saved: List[Tuple[int, np.ndarray, np.ndarray, np.ndarray]] = dataclasses.field(repr=False,
                                                                                   default_factory=list)
     eval_count: int = 0        # number of (pixel, splat) evaluations (visited pairs)
+    # the depth order walked (after pruning) and, per pixel id of the crop, the decisions that
+    # fell inside the flag bands: (splat, 'a') for alpha vs alpha_min, (splat, 't') for the
+    # t_min stop, with the transmittance in front of the splat and its alpha
+    order: List[int] = dataclasses.field(repr=False, default_factory=list)
+    straddles: Dict[int, List[Tuple[int, str, float, float]]] = dataclasses.field(
+        repr=False, default_factory=dict)
 
 
 def _pixel_grid(crop):
@@ -389,16 +412,37 @@ def _rel_gap(value, threshold):
     return np.abs(value - threshold) / threshold
 
 
-def render(scene, view, opts: Options, crop=None, keep_saved: bool = False) -> RenderResult:
-    """Composite every key-stage-visible splat at every pixel of ``crop`` (x0, y0, w, h)."""
+# Default flag thresholds: a float32 renderer reproduces alpha to ~1e-6 relative and the
+# transmittance after ~100 blends to ~1e-5 relative; decisions closer than these to their
+# threshold may legitimately go either way.
+TAU_ALPHA = 1e-5
+TAU_T = 1e-4
+TAU_KINK = 1e-4
+
+
+def render(scene, view, opts: Options, crop=None, keep_saved: bool = False, prune: bool = True,
+           order: Optional[Sequence[int]] = None, flip=None) -> RenderResult:
+    """Composite every key-stage-visible splat at every pixel of ``crop`` (x0, y0, w, h).
+
+    ``prune=False`` walks every visible splat (no exact pruning). ``order`` replaces the
+    depth order (it must be the depth order of a superset of the splats that can reach the
+    crop, e.g. the ``order`` of a render of an enclosing crop). ``flip`` is a set of
+    (splat, kind) decisions taken the other way at every pixel of the crop: kind 'a' inverts
+    the alpha >= alpha_min test, 't' inverts the t_min stop (for enumerating the outcomes of
+    flagged pixels).
+    """
     W, H = view.width, view.height
     crop = tuple(crop) if crop is not None else (0, 0, W, H)
     x, y = _pixel_grid(crop)
     npx = x.size
-    ks = key_stage(scene, view, opts)
-    order = depth_order(ks)
-    keep = set(prune_for_crop(scene, view, opts, order, crop).tolist())
-    order = [int(k) for k in order if int(k) in keep]
+    if order is None:
+        ks = key_stage(scene, view, opts)
+        order = depth_order(ks)
+        if prune:
+            keep = set(prune_for_crop(scene, view, opts, order, crop).tolist())
+            order = [int(k) for k in order if int(k) in keep]
+    order = [int(k) for k in order]
+    flip = set(flip or ())
     T = np.ones(npx)
     acc = np.zeros((npx, 3))
     done = np.zeros(npx, dtype=bool)
@@ -406,6 +450,7 @@ def render(scene, view, opts: Options, crop=None, keep_saved: bool = False) -> R
     a_gap = np.full(npx, np.inf)
     t_gap = np.full(npx, np.inf)
     k_gap = np.full(npx, np.inf)
+    straddles: Dict[int, List[Tuple[int, str, float, float]]] = {}
     saved = []
     evals = 0
     a_min, a_max, t_min = opts.alpha_min, opts.alpha_max, opts.t_min
@@ -420,7 +465,10 @@ def render(scene, view, opts: Options, crop=None, keep_saved: bool = False) -> R
         alpha = np.minimum(a_max, o * G)
         live = active & valid
         m = _rel_gap(alpha, a_min)
-        contrib = live & (alpha >= a_min)
+        contrib = alpha >= a_min
+        if (k, "a") in flip:
+            contrib = ~contrib
+        contrib &= live
         Tn = T * (1.0 - alpha)
         m_t = _rel_gap(Tn, t_min)
         m_c = _rel_gap(o * G, a_max)
@@ -428,7 +476,14 @@ def render(scene, view, opts: Options, crop=None, keep_saved: bool = False) -> R
         a_gap = np.where(live, np.minimum(a_gap, m), a_gap)
         t_gap = np.where(contrib, np.minimum(t_gap, m_t), t_gap)
         k_gap = np.where(contrib, np.minimum(k_gap, np.minimum(m_c, m_b)), k_gap)
-        term = contrib & (Tn < t_min)
+        for pid in np.nonzero(live & (m < TAU_ALPHA))[0]:
+            straddles.setdefault(int(pid), []).append((k, "a", float(T[pid]), float(alpha[pid])))
+        for pid in np.nonzero(contrib & (m_t < TAU_T))[0]:
+            straddles.setdefault(int(pid), []).append((k, "t", float(T[pid]), float(alpha[pid])))
+        stop = Tn < t_min
+        if (k, "t") in flip:
+            stop = ~stop
+        term = contrib & stop
         blend = contrib & ~term
         if blend.any():
             ids = np.nonzero(blend)[0]
@@ -445,15 +500,7 @@ def render(scene, view, opts: Options, crop=None, keep_saved: bool = False) -> R
     h, w = crop[3], crop[2]
     return RenderResult(rgb.reshape(h, w, 3), T.reshape(h, w), nbl.reshape(h, w),
                         done.reshape(h, w), a_gap.reshape(h, w), t_gap.reshape(h, w),
-                        k_gap.reshape(h, w), crop, saved, evals)
-
-
-# Default flag thresholds: a float32 renderer reproduces alpha to ~1e-6 relative and the
-# transmittance after ~100 blends to ~1e-5 relative; decisions closer than these to their
-# threshold may legitimately go either way.
-TAU_ALPHA = 1e-5
-TAU_T = 1e-4
-TAU_KINK = 1e-4
+                        k_gap.reshape(h, w), crop, saved, evals, order, straddles)
 
 
 def image_flags(r: RenderResult, tau_alpha=TAU_ALPHA, tau_t=TAU_T) -> np.ndarray:
@@ -465,6 +512,41 @@ def image_flags(r: RenderResult, tau_alpha=TAU_ALPHA, tau_t=TAU_T) -> np.ndarray
 def grad_flags(r: RenderResult, tau_alpha=TAU_ALPHA, tau_t=TAU_T, tau_kink=TAU_KINK) -> np.ndarray:
     """Image flags plus pixels near a kink of the gradient (alpha_max clamp, branch tie)."""
     return image_flags(r, tau_alpha, tau_t) | (r.kink_gap < tau_kink)
+
+
+def flagged_outcomes(scene, view, opts: Options, r: RenderResult, row: int, col: int,
+                     max_decisions: int = 4):
+    """Every admissible result of a flagged pixel (row, col of the crop of ``r``).
+
+    Each decision of the pixel that fell inside a flag band may go either way in a float32
+    renderer. The pixel is re-rendered for every subset of those decisions taken the other
+    way (2^m renders for m decisions); returns a list of (rgb [3], T) pairs, the first being
+    ``r``'s own result. With more than ``max_decisions`` such decisions returns None.
+    """
+    pid = row * r.crop[2] + col
+    dec = sorted({(k, kind) for k, kind, _, _ in r.straddles.get(pid, [])})
+    if len(dec) > max_decisions:
+        return None
+    x0, y0 = r.crop[0] + col, r.crop[1] + row
+    out = [(r.rgb[row, col].copy(), float(r.T_final[row, col]))]
+    for mask in range(1, 1 << len(dec)):
+        fl = {dec[i] for i in range(len(dec)) if (mask >> i) & 1}
+        rr = render(scene, view, opts, crop=(x0, y0, 1, 1), order=r.order, flip=fl)
+        out.append((rr.rgb[0, 0].copy(), float(rr.T_final[0, 0])))
+    return out
+
+
+def flagged_bound(scene, r: RenderResult, row: int, col: int, bg=(0.0, 0.0, 0.0)) -> float:
+    """Bound on how far a flagged pixel's colour can move when its in-band decisions go the
+    other way: a skipped or blended splat changes the colour by at most alpha T (|c| + |S|)
+    <= 2 alpha T c_max, a stop taken or not by at most T c_max (what lies behind), with
+    c_max the largest texel or background magnitude of the scene."""
+    pid = row * r.crop[2] + col
+    cmax = max(float(np.abs(scene.textures).max()), float(np.abs(np.asarray(bg)).max()), 1e-30)
+    b = 0.0
+    for k, kind, T_before, alpha in r.straddles.get(pid, []):
+        b += (2.0 * alpha * T_before if kind == "a" else T_before) * cmax
+    return b
 
 
 @dataclasses.dataclass

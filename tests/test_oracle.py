@@ -396,3 +396,146 @@ def test_oracle_gradient_matches_central_differences(thresholds):
             assert a == pytest.approx(fd, rel=2e-5, abs=2e-6 * max(1.0, abs(fd))), (name, idx)
             checked += 1
     assert checked >= 40
+
+
+# --- Screen-space low-pass: closed form at a known offset from a sub-pixel splat -----------
+@pytest.mark.parametrize("var", [0.5, 1.0, 0.25])
+def test_lowpass_falloff_closed_form(var):
+    """A splat far smaller than a pixel covers no pixel centre in uv (u, v are in the
+    thousands there), so only the low-pass acts: at a pixel centre whose distance to the
+    projected centre is d, alpha = o exp(-d^2 / (2 var)). With the camera at the origin and the
+    splat at depth Z = fx, the projected centre is (X + cx, Y + cy), so d is set exactly."""
+    view = sg.frontal_view(48, 40)
+    Z = float(np.float32(view.fx))
+    o = 0.7
+    for dx, dy in [(0.3, 0.0), (1.1, -0.4), (0.0, 2.0), (-1.5, 1.25)]:
+        px, py = 20, 17
+        X = px + 0.5 + dx - view.cx
+        Y = py + 0.5 + dy - view.cy
+        sc = scene_of([frontal_splat(X, Y, Z, s=(1e-4, 1e-4), o=o, tex=np.ones((2, 2, 3)),
+                                     N=2)])
+        Xf, Yf, Zf = (float(c) for c in sc.means[0])
+        d2 = (Xf * view.fx / Zf + view.cx - (px + 0.5)) ** 2 + \
+             (Yf * view.fy / Zf + view.cy - (py + 0.5)) ** 2
+        opts = O.Options(lowpass_var=var)
+        r = O.render(sc, view, opts)
+        want = float(sc.opacity[0]) * math.exp(-d2 / (2.0 * var))
+        if want >= opts.alpha_min:
+            assert 1.0 - r.T_final[py, px] == pytest.approx(want, rel=1e-9)
+            assert r.rgb[py, px, 0] == pytest.approx(want, rel=1e-9)
+        else:
+            assert r.T_final[py, px] == 1.0
+
+
+@pytest.mark.parametrize("var", [0.5, 1.0, 2.0])
+def test_key_stage_rect_contains_lowpass_disk(var):
+    """Sub-pixel splats contribute only through the low-pass; every pixel where alpha >=
+    alpha_min must lie in the key stage's rectangle, for any low-pass variance."""
+    rng = np.random.default_rng(int(var * 10))
+    view = sg.frontal_view(40, 32)
+    Z = 3.0
+    splats = []
+    for _ in range(20):
+        x, y = rng.uniform(2, 38), rng.uniform(2, 30)
+        X, Y, _ = pixel_to_world(view, x, y, Z)
+        splats.append(frontal_splat(X, Y, Z, s=(1e-4, 2e-4), theta=rng.uniform(0, 3), o=0.95,
+                                    tex=np.ones((2, 2, 3)), N=2))
+    sc = scene_of(splats)
+    opts = O.Options(lowpass_var=var)
+    ks = O.key_stage(sc, view, opts)
+    x, y = O._pixel_grid((0, 0, 40, 32))
+    ii, jj = (x - 0.5).astype(int), (y - 0.5).astype(int)
+    widest = 0
+    for k in range(len(splats)):
+        M = O.splat_M(sc, view, k)
+        *_, G, _, _, _ = O._falloff(M, x, y, var)
+        hit = np.minimum(opts.alpha_max, float(sc.opacity[k]) * G) >= opts.alpha_min
+        assert ks["visible"][k]
+        i0, i1, j0, j1 = ks["rect"][k]
+        inside = (ii >= i0) & (ii <= i1) & (jj >= j0) & (jj <= j1)
+        assert not (hit & ~inside).any()
+        widest = max(widest, int(np.ptp(ii[hit])) if hit.any() else 0)
+    # the disk really widens with the variance (radius sqrt(2 var ln(255 o)))
+    assert widest >= 2 * math.floor(math.sqrt(2 * var * math.log(255 * 0.95))) - 1
+
+
+# --- Exact pruning changes nothing: crop renders equal the same pixels of a full render -----
+@pytest.mark.parametrize("seed", [0, 1])
+def test_crop_render_equals_full_render(seed):
+    """Pruning is for speed only. Large, grazing and sub-pixel splats straddle the crop
+    edges; every crop must reproduce the full render's pixels, with pruning on and off."""
+    rng = np.random.default_rng(300 + seed)
+    big = sg.make_scene(seed, 40, -0.8, 0.8, 0.1, 0.7, 4)
+    tiny = sg.make_scene(seed + 9, 40, -0.8, 0.8, 3e-4, 2e-3, 2)
+    # sub-pixel splats keep a 4x4 grid shape (constant rows) so that both sets stack
+    tiny_tex = np.repeat(np.repeat(tiny.textures, 2, axis=1), 2, axis=2)
+    scene = sg.Scene(*(np.ascontiguousarray(np.concatenate([a, b])) for a, b in
+                       zip((big.means, big.tan_u, big.tan_v, big.scales, big.opacity, big.textures),
+                           (tiny.means, tiny.tan_u, tiny.tan_v, tiny.scales, tiny.opacity,
+                            tiny_tex))))
+    view = sg.look_at_view(np.array([0.4, -0.3, -2.4]) + 0.1 * rng.standard_normal(3), 60, 44)
+    opts = O.Options(bg=(0.2, 0.1, 0.3), lowpass_var=[0.5, 1.0][seed])
+    full = O.render(scene, view, opts)
+    for crop in [(0, 0, 13, 9), (17, 11, 20, 14), (41, 30, 19, 14), (29, 0, 3, 44)]:
+        x0, y0, w, h = crop
+        for prune in (True, False):
+            r = O.render(scene, view, opts, crop=crop, prune=prune)
+            np.testing.assert_allclose(r.rgb, full.rgb[y0:y0 + h, x0:x0 + w], rtol=0, atol=1e-13)
+            np.testing.assert_allclose(r.T_final, full.T_final[y0:y0 + h, x0:x0 + w], rtol=0,
+                                       atol=1e-13)
+    # pruning did drop splats here (so the test exercises it)
+    order = O.depth_order(O.key_stage(scene, view, opts))
+    kept = O.prune_for_crop(scene, view, opts, order, (0, 0, 13, 9))
+    assert kept.size < order.size
+
+
+# --- Flagged pixels: the admissible outcomes of a decision inside its flag band ------------
+def test_flagged_outcomes_cover_both_sides_of_alpha_min():
+    """A splat whose opacity is the float32 value nearest 1/255 is centred on a pixel, so its
+    alpha there is within 1e-7 of alpha_min and the pixel is flagged. Rendering with alpha_min
+    moved slightly down (the splat blends) and up (it is skipped) must give two of the
+    outcomes the oracle enumerates, and every outcome lies within the decision's bound."""
+    view = sg.frontal_view(16, 16)
+    X, Y, Z = pixel_to_world(view, 8.5, 6.5, 2.0)
+    Xb, Yb, Zb = pixel_to_world(view, 8.0, 6.0, 3.0)
+    sc = scene_of([frontal_splat(X, Y, Z, o=float(np.float32(1.0 / 255.0)),
+                                 tex=np.full((4, 4, 3), 0.9)),
+                   frontal_splat(Xb, Yb, Zb, o=0.8, s=(0.3, 0.3),
+                                 tex=np.full((4, 4, 3), 0.2))])
+    opts = O.Options()
+    r = O.render(sc, view, opts)
+    assert O.image_flags(r)[6, 8]
+    outs = O.flagged_outcomes(sc, view, opts, r, 6, 8)
+    assert outs is not None and len(outs) == 2
+    for am in (opts.alpha_min * (1 - 1e-6), opts.alpha_min * (1 + 1e-6)):
+        rr = O.render(sc, view, O.Options(alpha_min=am))
+        assert min(np.abs(rgb - rr.rgb[6, 8]).max() + abs(T - rr.T_final[6, 8])
+                   for rgb, T in outs) < 1e-12
+    b = O.flagged_bound(sc, r, 6, 8)
+    for rgb, T in outs:
+        assert np.abs(rgb - r.rgb[6, 8]).max() <= b + 1e-15
+
+
+def test_flagged_outcomes_cover_both_sides_of_t_min():
+    """Stacked layers whose transmittance after the third lands exactly on t_min: the stop
+    decision is flagged; t_min moved slightly either way gives two of the enumerated
+    outcomes."""
+    view = sg.frontal_view(17, 17)  # principal point at the centre of pixel (8, 8)
+    o = 0.9
+    layers = [frontal_splat(0.0, 0.0, 2.0 + 0.1 * i, o=o, tex=np.full((4, 4, 3), 0.1 * (i + 1)))
+              for i in range(5)]
+    sc = scene_of(layers)
+    of = float(sc.opacity[0])
+    t_star = (1.0 - of) ** 3
+    opts = O.Options(t_min=t_star)
+    r = O.render(sc, view, opts)
+    assert O.image_flags(r)[8, 8]
+    outs = O.flagged_outcomes(sc, view, opts, r, 8, 8)
+    assert outs is not None and len(outs) >= 2
+    for tm in (t_star * (1 - 1e-6), t_star * (1 + 1e-6)):
+        rr = O.render(sc, view, O.Options(t_min=tm))
+        assert min(np.abs(rgb - rr.rgb[8, 8]).max() + abs(T - rr.T_final[8, 8])
+                   for rgb, T in outs) < 1e-12
+    b = O.flagged_bound(sc, r, 8, 8)
+    for rgb, T in outs:
+        assert np.abs(rgb - r.rgb[8, 8]).max() <= b + 1e-15
