@@ -13,6 +13,8 @@ What it computes, and where the paper fixes it:
   [-sigma, sigma]^2 of the uv plane, coordinates border-clamped.
 * Compositing (Sec. 3.1, Eq. 2; Alg. 1): front-to-back over splats sorted by centre depth.
 * Backward (Alg. 1 backward, Alg. 2 adj-bilinear): hand-derived adjoints.
+* Diffuse-specular split (Sec. 4.2): optionally one set of spherical-harmonic coefficients
+  per splat adds a view-dependent colour, the same over the splat, to the grid's colour.
 
 Readings where the paper is silent or garbled (each one is also listed in the design notes):
 
@@ -218,6 +220,41 @@ def tile_pairs(scene, views: Sequence, opts: Options):
     return keys, vals, ranges
 
 
+def tile_pairs_vectorised(scene, views: Sequence, opts: Options):
+    """The same (tile, record) pairs and ranges as ``tile_pairs``, built with array operations
+    so that millions of splats finish in seconds: each visible record, in depth order, is
+    repeated once per tile of its rectangle (rows outer, columns inner); a stable sort by
+    tile then keeps the depth order inside every tile."""
+    P = scene.P
+    keys_v, vals_v = [], []
+    base = 0
+    for v, view in enumerate(views):
+        ks = key_stage(scene, view, opts)
+        order = depth_order(ks)
+        tr = ks["tile_rect"][order]
+        tw = tr[:, 1] - tr[:, 0] + 1
+        cnt = ks["count"][order]
+        rep = np.repeat(np.arange(order.size), cnt)
+        first = np.concatenate([[0], np.cumsum(cnt)[:-1]]) if order.size else np.zeros(0, np.int64)
+        local = np.arange(rep.size) - first[rep]
+        ty = tr[rep, 2] + local // tw[rep]
+        tx = tr[rep, 0] + local % tw[rep]
+        keys_v.append((base + ty * ks["tiles_x"] + tx).astype(np.int64))
+        vals_v.append((v * P + order[rep]).astype(np.int64))
+        base += ks["tiles_x"] * ks["tiles_y"]
+    keys = np.concatenate(keys_v) if keys_v else np.zeros(0, np.int64)
+    vals = np.concatenate(vals_v) if vals_v else np.zeros(0, np.int64)
+    srt = np.argsort(keys, kind="stable")
+    keys, vals = keys[srt].astype(np.uint32), vals[srt].astype(np.uint32)
+    ranges = np.zeros((base, 2), dtype=np.int64)
+    if keys.size:
+        starts = np.searchsorted(keys, np.arange(base), side="left")
+        ends = np.searchsorted(keys, np.arange(base), side="right")
+        ranges[:, 0] = np.where(ends > starts, starts, 0)
+        ranges[:, 1] = np.where(ends > starts, ends, 0)
+    return keys, vals, ranges
+
+
 # ---------------------------------------------------------------------------------------
 # Alg. 2: bilinear colour lookup and its adjoint (fp64, vectorised over lookups).
 # ---------------------------------------------------------------------------------------
@@ -322,6 +359,81 @@ def projected_center(M):
 
 
 # ---------------------------------------------------------------------------------------
+# View-dependent specular term (Sec. 4.2, diffuse-specular split): the colour grid is the
+# view-independent part; one set of spherical-harmonic coefficients per splat, the same over
+# the whole splat, adds a colour that depends on the direction from the camera to the centre.
+# ---------------------------------------------------------------------------------------
+def sh_basis(d, degree: int) -> np.ndarray:
+    """Real spherical harmonics of degree <= 3 at unit directions d [n, 3] (real or complex),
+    [n, (degree + 1)^2], index l^2 + l + m. Each is (-1)^m times the usual real harmonic
+    (for m > 0 the cosine part sqrt(2) Re Y_l^m, for m < 0 the sine part sqrt(2) Im Y_l^|m|,
+    of the complex harmonic with the Condon-Shortley phase): the sign convention of the
+    splatting line of work the paper extends. The polynomials in (x, y, z) and their
+    normalisations sqrt((2l + 1) (l - |m|)! / (4 pi (l + |m|)!)) are written out below."""
+    d = np.asarray(d)
+    x, y, z = d[:, 0], d[:, 1], d[:, 2]
+    pi = math.pi
+    out = [0.5 * math.sqrt(1.0 / pi) * np.ones_like(x)]
+    if degree >= 1:
+        c1 = math.sqrt(3.0 / (4.0 * pi))
+        out += [-c1 * y, c1 * z, -c1 * x]
+    if degree >= 2:
+        out += [0.5 * math.sqrt(15.0 / pi) * x * y,
+                -0.5 * math.sqrt(15.0 / pi) * y * z,
+                0.25 * math.sqrt(5.0 / pi) * (2.0 * z * z - x * x - y * y),
+                -0.5 * math.sqrt(15.0 / pi) * x * z,
+                0.25 * math.sqrt(15.0 / pi) * (x * x - y * y)]
+    if degree >= 3:
+        out += [-0.25 * math.sqrt(35.0 / (2.0 * pi)) * y * (3.0 * x * x - y * y),
+                0.5 * math.sqrt(105.0 / pi) * x * y * z,
+                -0.25 * math.sqrt(21.0 / (2.0 * pi)) * y * (4.0 * z * z - x * x - y * y),
+                0.25 * math.sqrt(7.0 / pi) * z * (2.0 * z * z - 3.0 * x * x - 3.0 * y * y),
+                -0.25 * math.sqrt(21.0 / (2.0 * pi)) * x * (4.0 * z * z - x * x - y * y),
+                0.25 * math.sqrt(105.0 / pi) * z * (x * x - y * y),
+                -0.25 * math.sqrt(35.0 / (2.0 * pi)) * x * (x * x - 3.0 * y * y)]
+    if degree > 3:
+        raise ValueError("spherical harmonics of degree <= 3 only")
+    return np.stack(out, axis=1)
+
+
+def camera_centre(view) -> np.ndarray:
+    """World position of the camera, -R^T t (fp64 from the float32 values)."""
+    R = np.asarray(view.R, dtype=np.float64)
+    t = np.asarray(view.t, dtype=np.float64)
+    return -R.T @ t
+
+
+def specular(scene, view, k: int, mean=None) -> np.ndarray:
+    """The view-dependent colour of splat k: sum_j Y_j(dir) sh[k, j], with dir the unit
+    vector from the camera centre to the splat centre (``mean`` overrides the centre; it may
+    be complex for complex-step derivatives). Zero without coefficients."""
+    if scene.sh is None:
+        return np.zeros(3)
+    p = scene.means[k].astype(np.float64) if mean is None else mean
+    v = p - camera_centre(view)
+    dvec = v / np.sqrt(np.sum(v * v))
+    Y = sh_basis(dvec[None, :], scene.sh_degree)[0]
+    return Y @ scene.sh[k].astype(np.float64)
+
+
+def specular_grads(scene, view, k: int, dspec) -> Tuple[np.ndarray, np.ndarray]:
+    """Adjoint of ``specular`` for the colour adjoint dspec [3]: (d sh [(D+1)^2, 3],
+    d mean [3]). The centre derivative is taken by the complex step, Im f(p + i h e) / h with
+    h = 1e-30, exact to rounding for this analytic map."""
+    p = scene.means[k].astype(np.float64)
+    v = p - camera_centre(view)
+    Y = sh_basis((v / np.linalg.norm(v))[None, :], scene.sh_degree)[0]
+    d_sh = np.outer(Y, dspec)
+    h = 1e-30
+    d_mean = np.zeros(3)
+    for i in range(3):
+        pc = p.astype(np.complex128)
+        pc[i] += 1j * h
+        d_mean[i] = float(np.imag(specular(scene, view, k, mean=pc) @ np.asarray(dspec)) / h)
+    return d_sh, d_mean
+
+
+# ---------------------------------------------------------------------------------------
 # Exact pruning (speed only): drop splats that provably have alpha < alpha_min on a crop.
 # ---------------------------------------------------------------------------------------
 def prune_for_crop(scene, view, opts: Options, cand: np.ndarray, crop) -> np.ndarray:
@@ -421,7 +533,7 @@ TAU_KINK = 1e-4
 
 
 def render(scene, view, opts: Options, crop=None, keep_saved: bool = False, prune: bool = True,
-           order: Optional[Sequence[int]] = None, flip=None) -> RenderResult:
+           order: Optional[Sequence[int]] = None, flip=None, shift=None) -> RenderResult:
     """Composite every key-stage-visible splat at every pixel of ``crop`` (x0, y0, w, h).
 
     ``prune=False`` walks every visible splat (no exact pruning). ``order`` replaces the
@@ -429,7 +541,8 @@ def render(scene, view, opts: Options, crop=None, keep_saved: bool = False, prun
     crop, e.g. the ``order`` of a render of an enclosing crop). ``flip`` is a set of
     (splat, kind) decisions taken the other way at every pixel of the crop: kind 'a' inverts
     the alpha >= alpha_min test, 't' inverts the t_min stop (for enumerating the outcomes of
-    flagged pixels).
+    flagged pixels). ``shift`` maps a splat index to an image translation (dx, dy) in pixels
+    of that splat's footprint (for checking the densification statistic; pruning is then off).
     """
     W, H = view.width, view.height
     crop = tuple(crop) if crop is not None else (0, 0, W, H)
@@ -438,7 +551,7 @@ def render(scene, view, opts: Options, crop=None, keep_saved: bool = False, prun
     if order is None:
         ks = key_stage(scene, view, opts)
         order = depth_order(ks)
-        if prune:
+        if prune and not shift:
             keep = set(prune_for_crop(scene, view, opts, order, crop).tolist())
             order = [int(k) for k in order if int(k) in keep]
     order = [int(k) for k in order]
@@ -460,6 +573,10 @@ def render(scene, view, opts: Options, crop=None, keep_saved: bool = False, prun
             break
         evals += int(active.sum())
         M = splat_M(scene, view, k)
+        if shift and k in shift:
+            M = M.copy()
+            M[0] += shift[k][0] * M[2]
+            M[1] += shift[k][1] * M[2]
         u, v, valid, q, use_uv, G, _, _, (q_uv, q_lp) = _falloff(M, x, y, opts.lowpass_var)
         o = float(scene.opacity[k])
         alpha = np.minimum(a_max, o * G)
@@ -488,6 +605,7 @@ def render(scene, view, opts: Options, crop=None, keep_saved: bool = False, prun
         if blend.any():
             ids = np.nonzero(blend)[0]
             col = bilinear(scene.textures[k].astype(np.float64), u[ids], v[ids], opts.sigma)
+            col = col + specular(scene, view, k)[None, :]
             w = alpha[ids] * T[ids]
             acc[ids] += w[:, None] * col
             if keep_saved:
@@ -557,6 +675,10 @@ class Grads:
     scales: np.ndarray
     opacity: np.ndarray
     textures: np.ndarray
+    sh: Optional[np.ndarray] = None
+    # per splat: gradient of the loss with respect to a translation of the splat's footprint
+    # in the image by (dx, dy) pixels (the densification statistic), [P, 2]
+    screen: Optional[np.ndarray] = None
 
 
 def render_backward(scene, view, opts: Options, fwd: RenderResult, dl_drgb) -> Grads:
@@ -576,7 +698,8 @@ def render_backward(scene, view, opts: Options, fwd: RenderResult, dl_drgb) -> G
     S = fwd.T_final.reshape(-1)[:, None] * bg[None, :]
     S = np.array(S)
     gr = Grads(np.zeros((P, 3)), np.zeros((P, 3)), np.zeros((P, 3)), np.zeros((P, 2)),
-               np.zeros(P), np.zeros((P, N, N, 3)))
+               np.zeros(P), np.zeros((P, N, N, 3)),
+               None if scene.sh is None else np.zeros(scene.sh.shape), np.zeros((P, 2)))
     Kmat = intrinsics(view)
     R = np.asarray(view.R, dtype=np.float64)
     for k, ids, Tk, alpha in reversed(fwd.saved):
@@ -586,11 +709,16 @@ def render_backward(scene, view, opts: Options, fwd: RenderResult, dl_drgb) -> G
                                                                            opts.lowpass_var)
         o = float(scene.opacity[k])
         C = scene.textures[k].astype(np.float64)
-        col = bilinear(C, u, v, opts.sigma)
+        col = bilinear(C, u, v, opts.sigma) + specular(scene, view, k)[None, :]
         w = alpha * Tk
         # colour -> grid and uv
         dC, du, dv = adj_bilinear(C, u, v, opts.sigma, w[:, None] * g)
         gr.textures[k] += dC
+        # colour -> view-dependent term -> coefficients and centre
+        if scene.sh is not None:
+            d_sh, d_mean = specular_grads(scene, view, k, np.sum(w[:, None] * g, axis=0))
+            gr.sh[k] += d_sh
+            gr.means[k] += d_mean
         # alpha
         Sk = S[ids]
         dalpha = np.sum(g * (col * Tk[:, None] - Sk / (1.0 - alpha)[:, None]), axis=1)
@@ -619,6 +747,8 @@ def render_backward(scene, view, opts: Options, fwd: RenderResult, dl_drgb) -> G
         dM[0, 2] += dc2x / M[2, 2]
         dM[1, 2] += dc2y / M[2, 2]
         dM[2, 2] -= (dc2x * M[0, 2] + dc2y * M[1, 2]) / (M[2, 2] ** 2)
+        # an image translation by (dx, dy) maps row 0 of M to M_0 + dx M_2 (row 1 likewise)
+        gr.screen[k] += np.array([dM[0] @ M[2], dM[1] @ M[2]])
         # M = K [a b pc]
         dA = Kmat.T @ dM
         da, db, dpc = dA[:, 0], dA[:, 1], dA[:, 2]

@@ -23,7 +23,7 @@ import numpy as np
 
 __all__ = [
     "Scene", "View", "make_scene", "look_at_view", "frontal_view", "orbit_views",
-    "make_dl_drgb", "to_bf16_bits", "bf16_bits_to_f32", "CONFIGS", "config",
+    "make_dl_drgb", "to_bf16_bits", "bf16_bits_to_f32", "CONFIGS", "config", "with_sh",
 ]
 
 
@@ -36,6 +36,9 @@ class Scene:
     scales: np.ndarray     # [P,2]  (s_u, s_v) > 0
     opacity: np.ndarray    # [P]    in (0, 1)
     textures: np.ndarray   # [P,N,N,3] indexed [k, i_u, i_v, c]
+    # optional per-splat spherical-harmonic coefficients of the view-dependent colour term,
+    # [P, (degree + 1)^2, 3] (None: no such term)
+    sh: Optional[np.ndarray] = None
 
     @property
     def P(self) -> int:
@@ -45,10 +48,16 @@ class Scene:
     def N(self) -> int:
         return int(self.textures.shape[1])
 
+    @property
+    def sh_degree(self) -> int:
+        """Degree of the spherical harmonics (-1 without them)."""
+        return -1 if self.sh is None else int(round(math.sqrt(self.sh.shape[1]))) - 1
+
     def subset(self, idx) -> "Scene":
+        sh = None if self.sh is None else np.ascontiguousarray(self.sh[idx])
         return Scene(*(np.ascontiguousarray(a[idx]) for a in
                        (self.means, self.tan_u, self.tan_v, self.scales, self.opacity,
-                        self.textures)))
+                        self.textures)), sh)
 
 
 @dataclasses.dataclass
@@ -151,6 +160,20 @@ def make_scene(seed: int, P: int, lo: float, hi: float, s_lo: float, s_hi: float
             part[...] = bf16_bits_to_f32(to_bf16_bits(part)).reshape(part.shape)
     f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
     return Scene(f32(means), f32(tu), f32(tv), f32(scales), f32(opacity), tex)
+
+
+def with_sh(scene: Scene, seed: int, degree: int, scale: float = 0.2) -> Scene:
+    """The scene with per-splat spherical-harmonic coefficients N(0, scale^2) of the given
+    degree, [P, (degree + 1)^2, 3] float32, drawn from their own stream."""
+    rng = np.random.default_rng(seed)
+    n = (degree + 1) ** 2
+    sh = np.empty((scene.P, n, 3), dtype=np.float32)
+    flat = sh.reshape(scene.P, n * 3)
+    step = max(1, (1 << 22) // (n * 3))
+    for i in range(0, scene.P, step):
+        part = flat[i:i + step]
+        part[...] = rng.normal(0.0, scale, part.shape)
+    return dataclasses.replace(scene, sh=sh)
 
 
 def orbit_views(seed: int, n: int, radius: float, resolutions: Sequence[Tuple[int, int]],

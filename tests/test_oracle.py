@@ -539,3 +539,146 @@ def test_flagged_outcomes_cover_both_sides_of_t_min():
     b = O.flagged_bound(sc, r, 8, 8)
     for rgb, T in outs:
         assert np.abs(rgb - r.rgb[8, 8]).max() <= b + 1e-15
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+def test_vectorised_tile_pairs_equal_the_plain_expansion(tile):
+    """The array-based pair expansion used at full size gives exactly the pairs of the plain
+    per-splat loop (several views, every tile shape)."""
+    scene, _ = sg.config("C1", P=600)
+    views = [sg.look_at_view((0, 0, -3.0), 70, 50), sg.look_at_view((2.0, 1.0, -2.0), 33, 47),
+             sg.look_at_view((0.3, -2.5, -0.4), 64, 64)]
+    opts = O.Options(tile_w=tile[0], tile_h=tile[1])
+    a = O.tile_pairs(scene, views, opts)
+    b = O.tile_pairs_vectorised(scene, views, opts)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+# --- Diffuse-specular split (Sec. 4.2): per-splat spherical harmonics -----------------------
+def _real_sh_from_scipy(d, degree):
+    """The basis built from scipy's complex harmonics (Condon-Shortley phase included):
+    sqrt(2) Re Y_l^m for m > 0, sqrt(2) Im Y_l^|m| for m < 0, Y_l^0 for m = 0."""
+    from scipy.special import sph_harm_y
+    theta = np.arccos(np.clip(d[:, 2], -1.0, 1.0))
+    phi = np.arctan2(d[:, 1], d[:, 0])
+    cols = []
+    for l in range(degree + 1):
+        for m in range(-l, l + 1):
+            Y = sph_harm_y(l, abs(m), theta, phi)
+            if m > 0:
+                cols.append(math.sqrt(2.0) * Y.real)
+            elif m < 0:
+                cols.append(math.sqrt(2.0) * Y.imag)
+            else:
+                cols.append(Y.real)
+    return np.stack(cols, axis=1)
+
+
+def _unit(n, seed):
+    d = np.random.default_rng(seed).standard_normal((n, 3))
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
+@pytest.mark.parametrize("degree", [0, 1, 2, 3])
+def test_sh_basis_matches_scipy_harmonics(degree):
+    d = _unit(200, degree)
+    np.testing.assert_allclose(O.sh_basis(d, degree), _real_sh_from_scipy(d, degree),
+                               rtol=1e-12, atol=1e-13)
+
+
+def test_sh_basis_is_orthonormal_on_the_sphere():
+    """Gauss-Legendre in cos(theta) times a uniform rule in phi integrates every product of
+    two degree-3 harmonics (degree 6 in x, y, z) exactly."""
+    xs, ws = np.polynomial.legendre.leggauss(8)
+    phis = 2.0 * math.pi * np.arange(16) / 16
+    ct, ph = np.meshgrid(xs, phis, indexing="ij")
+    w = (ws[:, None] * np.full(16, 2.0 * math.pi / 16)[None, :]).reshape(-1)
+    st = np.sqrt(1.0 - ct ** 2)
+    d = np.stack([st * np.cos(ph), st * np.sin(ph), ct], axis=-1).reshape(-1, 3)
+    Y = O.sh_basis(d, 3)
+    gram = (Y * w[:, None]).T @ Y
+    np.testing.assert_allclose(gram, np.eye(16), atol=1e-12)
+
+
+def test_sh_basis_on_the_axes():
+    """Closed forms on the coordinate axes: on +z only the zonal harmonics survive,
+    Y_00 = 1/(2 sqrt(pi)), Y_10 = sqrt(3/(4 pi)), Y_20 = sqrt(5/pi)/2, Y_30 = sqrt(7/pi)/2;
+    on +x the order-1 term is -sqrt(3/(4 pi)) (the (-1)^m sign) and Y_22 = sqrt(15/pi)/4."""
+    d = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0], [0.0, -1.0, 0.0]])
+    Y = O.sh_basis(d, 3)
+    pi = math.pi
+    want_z = np.zeros(16)
+    want_z[[0, 2, 6, 12]] = [0.5 / math.sqrt(pi), math.sqrt(3 / (4 * pi)), 0.5 * math.sqrt(5 / pi),
+                             0.5 * math.sqrt(7 / pi)]
+    np.testing.assert_allclose(Y[0], want_z, atol=1e-15)
+    assert Y[1, 3] == pytest.approx(-math.sqrt(3 / (4 * pi)), rel=1e-14)
+    assert Y[1, 8] == pytest.approx(0.25 * math.sqrt(15 / pi), rel=1e-14)
+    assert Y[1, 6] == pytest.approx(-0.25 * math.sqrt(5 / pi), rel=1e-14)
+    assert Y[2, 1] == pytest.approx(math.sqrt(3 / (4 * pi)), rel=1e-14)  # -c1 y at y = -1
+
+
+def test_sh_degree0_is_a_constant_colour_offset():
+    """Degree 0 adds sh_0 / (2 sqrt(pi)) to every texel's colour, whatever the view: the same
+    image as the grid shifted by that constant, from two viewpoints."""
+    base = sg.make_scene(12, 30, -0.5, 0.5, 0.05, 0.3, 4)
+    spec = sg.with_sh(base, 5, 0)
+    shifted = sg.Scene(base.means, base.tan_u, base.tan_v, base.scales, base.opacity,
+                       np.ascontiguousarray(base.textures.astype(np.float64)
+                                            + spec.sh[:, 0, None, None, :].astype(np.float64)
+                                            * 0.5 / math.sqrt(math.pi)))
+    for pos in ((0.2, 0.1, -2.5), (-1.5, 0.8, -1.5)):
+        view = sg.look_at_view(pos, 40, 32)
+        a = O.render(spec, view, O.Options())
+        b = O.render(shifted, view, O.Options())
+        np.testing.assert_allclose(a.rgb, b.rgb, atol=1e-12)
+
+
+def test_specular_term_depends_on_the_view_direction():
+    """A degree-1 term with coefficients along z only: a frontal splat seen from directions
+    d gets the colour shift -c1 (d . (0, 1, 0)) ... i.e. sum_j Y_j(d) sh_j; seen from straight
+    ahead (d = +z) the shift is sqrt(3/(4 pi)) sh_2."""
+    view = sg.frontal_view(17, 17)
+    sc = scene_of([frontal_splat(0.0, 0.0, 3.0, o=0.5, tex=np.zeros((2, 2, 3)), N=2)])
+    sh = np.zeros((1, 4, 3), dtype=np.float32)
+    sh[0, 2] = [0.4, -0.2, 0.1]
+    sc = sg.Scene(sc.means, sc.tan_u, sc.tan_v, sc.scales, sc.opacity, sc.textures, sh)
+    r = O.render(sc, view, O.Options())
+    shift = math.sqrt(3 / (4 * math.pi)) * sh[0, 2].astype(np.float64)
+    np.testing.assert_allclose(r.rgb[8, 8], float(sc.opacity[0]) * shift, atol=1e-12)
+
+
+@pytest.mark.parametrize("degree", [1, 3])
+def test_specular_gradients_match_central_differences(degree):
+    """The analytic gradient with respect to the SH coefficients and the centres (through the
+    view direction) against central differences of the render."""
+    rng = np.random.default_rng(90 + degree)
+    scene = sg.with_sh(sg.make_scene(31, 4, -0.3, 0.3, 0.08, 0.3, 3), 7, degree, scale=0.3)
+    view = sg.look_at_view((0.6, -0.4, -1.6), 24, 20)
+    opts = O.Options(bg=(0.1, 0.2, 0.3))
+    g = rng.standard_normal((24 * 20, 3))
+    r = O.render(scene, view, opts, keep_saved=True)
+    gr = O.render_backward(scene, view, opts, r, g)
+    checked = 0
+    for name in ("sh", "means"):
+        arr = getattr(scene, name)
+        for fi in rng.choice(arr.size, size=10, replace=False):
+            idx = np.unravel_index(fi, arr.shape)
+            h = 1e-4 * max(0.1, abs(float(arr[idx])))
+            vals, decs = [], []
+            for sgn in (1, -1):
+                parts = [a.astype(np.float64) for a in (scene.means, scene.tan_u, scene.tan_v,
+                                                         scene.scales, scene.opacity,
+                                                         scene.textures, scene.sh)]
+                target = parts[6] if name == "sh" else parts[0]
+                target[idx] += sgn * h
+                rr = O.render(sg.Scene(*parts), view, opts)
+                vals.append(float(np.sum(rr.rgb.reshape(-1, 3) * g)))
+                decs.append((rr.n_blended.copy(), rr.terminated.copy()))
+            if not all((a == b).all() for a, b in zip(decs[0], decs[1])):
+                continue
+            fd = (vals[0] - vals[1]) / (2 * h)
+            a = float(getattr(gr, name)[idx])
+            assert a == pytest.approx(fd, rel=2e-5, abs=2e-6 * max(1.0, abs(fd))), (name, idx)
+            checked += 1
+    assert checked >= 14
