@@ -88,14 +88,26 @@ def copy_probe(torch):
     return 2 * COPY_BYTES / (ms * 1e-3) / 1e9
 
 
+def assert_no_overflow(rast, what):
+    """Fails the run if any forward since the previous status read overflowed its pair
+    capacity (such a forward renders background and skips its stages, which would make the
+    timed steps faster)."""
+    K, over_last, over_any = rast.status_ex()
+    if over_last or over_any:
+        raise RuntimeError(f"{what}: a timed forward overflowed its pair capacity (K={K})")
+
+
 def time_steps(rast, sp, rgb, T, g, grads, steps, torch):
+    rast.status_ex()  # clears the sticky overflow flag of the warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         rast.forward(sp, rgb, T)
         rast.backward(sp, T, g, grads)
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
+    sec = (time.perf_counter() - t0) / steps
+    assert_no_overflow(rast, "timed steps")
+    return sec
 
 
 def setup(gb, sg, torch, name, views=None):
@@ -136,6 +148,7 @@ def train_variant(gb, sg, torch, warmup=20, iters=200):
     cap = trainer.plan(sched)
     for b in sched[:warmup]:
         trainer.step(b)
+    trainer.overflowed()  # clears the sticky overflow flag of the warm-up
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(iters + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -148,12 +161,14 @@ def train_variant(gb, sg, torch, warmup=20, iters=200):
     ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(iters))
     q = lambda f: ms[min(iters - 1, int(round(f * (iters - 1))))]
     loss = float(trainer.loss)
-    over = trainer.overflowed()
+    over = trainer.overflowed()  # any of the timed steps
+    if over:
+        raise RuntimeError("training step: a timed step overflowed its pair capacity")
     n_par = sum(t.numel() for t in st.params.values())
     out = {"ms_per_iter_median": round(q(0.5), 3), "ms_per_iter_p10": round(q(0.1), 3),
            "ms_per_iter_p90": round(q(0.9), 3), "ms_per_iter_wall": round(wall * 1e3, 3),
            "iters": iters, "warmup": warmup, "parameters": n_par, "pair_capacity": cap,
-           "final_l1": round(loss, 6), "overflow_last_step": over,
+           "final_l1": round(loss, 6), "overflow_any_timed_step": over,
            "workload": "500k splats, 8x8 BF16 textures (FP32 master), batch of 4 of 32 "
                        "1280x720 views, L1 + Adam"}
     del trainer, st, targets
@@ -174,6 +189,7 @@ def image_fit_variant(gb, sg, torch, P, N, warmup=10, iters=100):
     first = float(trainer.step([0]))
     for b in sched[1:warmup]:
         trainer.step(b)
+    trainer.overflowed()  # clears the sticky overflow flag of the warm-up
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(iters + 1)]
     torch.cuda.synchronize()
     ev[0].record()
@@ -184,7 +200,7 @@ def image_fit_variant(gb, sg, torch, P, N, warmup=10, iters=100):
     ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(iters))
     out = {"ms_per_iter_median": round(ms[iters // 2], 3), "iters": iters, "warmup": warmup,
            "mse_first": round(first, 6), "mse_last": round(float(trainer.loss), 6),
-           "overflow_last_step": trainer.overflowed(),
+           "overflow_any_timed_step": trainer.overflowed(),
            "workload": f"{P} splats, {N}x{N} FP32 grids, 1920x871 synthetic image, MSE, "
                        "rotation about Z, Adam"}
     del trainer, st
@@ -216,6 +232,7 @@ def c3_variant(gb, sg, torch, warmup, steps):
         graph.replay()
     torch.cuda.synchronize()
     s_batch = (time.perf_counter() - t0) / steps
+    assert_no_overflow(rast, "C3 graph replays")
     del graph, rast
     torch.cuda.empty_cache()
     singles, at = [], 0
@@ -259,6 +276,7 @@ def config_times(gb, sg, torch, warmup, steps):
             rast.forward(sp, rgb, T)
             if bwd:
                 rast.backward(sp, T, g, grads)
+        rast.status_ex()  # clears the sticky overflow flag of the warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -267,6 +285,7 @@ def config_times(gb, sg, torch, warmup, steps):
                 rast.backward(sp, T, g, grads)
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t0) / steps
+        assert_no_overflow(rast, name)
         out[name] = {"ms_per_step": round(sec * 1e3, 3), "mpix_per_s": round(px / sec / 1e6, 1),
                      "pass": "fwd+bwd" if bwd else "fwd", "splats": scene.P, "pixels": px,
                      "pairs": K}
@@ -343,6 +362,7 @@ def main():
         graph.replay()
     torch.cuda.synchronize()
     sec_graph = (time.perf_counter() - t0) / args.steps
+    assert_no_overflow(rast, "graph replays")
     del graph
     log(f"T0 fp32, HIP graph replay: {sec_graph * 1e3:.3f} ms/step")
 

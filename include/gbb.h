@@ -73,6 +73,14 @@ typedef struct {
   const float* scales;     /* [P][2] (s_u, s_v) */
   const float* opacity;    /* [P] */
   const void* textures;    /* [P][N][N][3], float32 or bfloat16 bit patterns */
+  int32_t sh_degree;       /* degree D in 0..3 of the view-dependent colour term (ignored when
+                              sh is NULL) */
+  const float* sh;         /* NULL, or [P][(D+1)^2][3] float32 spherical-harmonic coefficients:
+                              the diffuse-specular split of Sec. 4.2. Splat k's colour becomes
+                              bilinear(C_k, u, v) + sum_j Y_j(dir) sh[k][j], dir the unit vector
+                              from the camera centre -R^T t to p_k, Y_j the real harmonics of
+                              index j = l^2 + l + m, each (-1)^m times the usual real harmonic
+                              (sign convention of 3D Gaussian splatting). */
 } gb_splats;
 
 typedef struct {
@@ -81,7 +89,9 @@ typedef struct {
                          splat covers the whole image) */
   float alpha_max;    /* opacity clamp, e.g. 0.99; 1 switches it off */
   float t_min;        /* early-termination transmittance, e.g. 1e-4; 0 switches it off */
-  float lowpass_var;  /* variance of the screen-space low-pass in px^2, e.g. 0.5 */
+  float lowpass_var;  /* variance of the screen-space low-pass in px^2, e.g. 0.5; any value > 0 (the
+                         tile bound of the low-pass disk is 2.36 px up to 0.5, else
+                         3.34 sqrt(lowpass_var)) */
   float bg[3];        /* background colour composited with the final transmittance */
   int32_t tile_w;     /* tile width in px: 8, 16 or 32 */
   int32_t tile_h;     /* tile height in px: 8, 16 or 32; tile_w * tile_h <= 256 */
@@ -111,6 +121,8 @@ typedef struct {
   float* d_scales;    /* [P][2] */
   float* d_opacity;   /* [P] */
   float* d_textures;  /* [P][N][N][3] float32 */
+  float* d_sh;        /* [P][(D+1)^2][3] float32; required when splats->sh != NULL, else
+                         ignored */
 } gb_grads;
 
 /* Byte offsets of the workspace sections that tests and tools may read back. */
@@ -118,7 +130,8 @@ typedef struct {
   size_t total_bytes;
   size_t status;      /* uint32 pair count K (mod 2^32), pairs of the first pass, overflow flag,
                          records in the depth prefix; uint64 exact pair count; uint32 pairs of
-                         the rest pass, uint32 pad, uint64 exact pairs of the rest pass */
+                         the rest pass, uint32 32-bit total of the rest pass, uint64 exact pairs
+                         of the rest pass; then internal fields (see gb_read_status) */
   size_t depth_key;   /* uint32[V*P]: float bits of the centre depth, 0xFFFFFFFF if culled */
   size_t tile_count;  /* uint32[V*P]: tiles covered by record v*P+k */
   size_t records;     /* 96-byte record per (view, splat): 19 floats of blend geometry, then
@@ -154,7 +167,8 @@ gb_status gb_workspace_layout(int32_t P, int32_t N, const gb_view* views, int32_
 
 /* Runs the per-splat preprocess (key stage: depth, screen rectangle, tile count) for every
  * (view, splat) and returns the total pair count K in *K_out. The workspace must be laid out
- * for the same arguments (any capacity). Synchronises `stream`. */
+ * for the same arguments (any capacity). Synchronises `stream`. Forgets an earlier overflow
+ * on this workspace (see gb_render_fwd): the caller is re-planning with the exact count. */
 gb_status gb_count_pairs(const gb_splats* splats, const gb_view* views, int32_t n_views,
                          const gb_options* opts, void* workspace, size_t ws_bytes,
                          int64_t pair_capacity, int64_t* K_out, void* stream);
@@ -162,9 +176,15 @@ gb_status gb_count_pairs(const gb_splats* splats, const gb_view* views, int32_t 
 /* Forward render of all views (Alg. 1 forward):
  *   rgb     [sum HW][3] float32 (device)  composited colour, background included;
  *   T_final [sum HW]    float32 (device)  transmittance after the last blended splat.
- * The workspace keeps what gb_render_bwd needs until the next forward on it. If the pair
- * count exceeds `pair_capacity`, the overflow flag is set on the device, every later stage of
- * this call does nothing and the images are background; gb_read_status reports it. */
+ * The workspace keeps what gb_render_bwd needs until the next forward on it.
+ * Capacity: if the pair count exceeds `pair_capacity`, the overflow flag is set on the device,
+ * every later stage of this call does nothing and the images are background; gb_read_status
+ * reports it. The count and flag of every forward are also stored, without synchronising,
+ * in host-mapped memory kept per workspace address: a later gb_render_fwd on the same
+ * workspace whose `pair_capacity` is below the pair count of an earlier forward that
+ * overflowed (and has completed on the device) returns GB_ERR_CAPACITY before launching
+ * anything; with a capacity that fits that count (re-planned) it runs. The total number of
+ * pixels of all views must be below 2^31 (GB_ERR_ARG). */
 gb_status gb_render_fwd(const gb_splats* splats, const gb_view* views, int32_t n_views,
                         const gb_options* opts, void* workspace, size_t ws_bytes,
                         int64_t pair_capacity, float* rgb, float* T_final, void* stream);
@@ -178,10 +198,16 @@ gb_status gb_render_bwd(const gb_splats* splats, const gb_view* views, int32_t n
                         int64_t pair_capacity, const float* T_final, const float* d_rgb,
                         const gb_grads* grads, void* stream);
 
-/* Waits for `stream`, then reports the pair count of the last forward and its overflow
- * flag. */
+/* Waits for `stream`, then reports the last forward on `workspace`:
+ *   *K_out        exact (tile, splat) pair count of all views;
+ *   *overflow_out bit 0: the last forward overflowed its capacity; bit 1: some forward since
+ *                 the previous gb_read_status on this workspace overflowed (this sticky bit is
+ *                 cleared by the call, so each overflow is reported once);
+ *   K_per_view    (nullable) [n_views] pair count of each view; n_views must equal the last
+ *                 forward's (GB_ERR_ARG otherwise, and if no forward ran on the workspace).
+ * Launches one small reduction kernel when K_per_view is given. */
 gb_status gb_read_status(const void* workspace, int64_t* K_out, int32_t* overflow_out,
-                         void* stream);
+                         int64_t* K_per_view, int32_t n_views, void* stream);
 
 /* Work counts of one forward, for measurement: runs gb_render_fwd with counting enabled in the
  * blend kernels and waits for the stream. counts_out[0] = (pixel, splat) pairs blended,
@@ -259,7 +285,78 @@ gb_status gb_adam_step(int64_t n, float* param, const float* grad, float* m, flo
  * initial render copy of float32 textures. */
 gb_status gb_to_bf16(int64_t n, const float* src, uint16_t* dst, void* stream);
 
-/* Fills *out with the default options (sigma 0.5, alpha_min 1/255, alpha_max 0.99,
+/* ---- Densification and pruning (Sec. 4.2 trains with the default adaptive density control
+ * of Gaussian splatting; the colour grids are split as described at gb_densify_apply) ------ */
+
+typedef struct {
+  float grad_threshold;  /* a splat whose mean screen-translation gradient norm (below) is at
+                            least this is densified */
+  float dense_scale;     /* a densified splat with max(s_u, s_v) <= dense_scale is cloned,
+                            otherwise split */
+  float min_opacity;     /* outputs (kept splats, clone copies, split children) with opacity
+                            below this are pruned */
+  float max_scale;       /* > 0: outputs whose largest scale exceeds it are pruned; 0 = off */
+  float split_shrink;    /* scales of split children = parent's / split_shrink (e.g. 1.6), >= 1 */
+} gb_densify_options;
+
+/* Raw (pre-activation) training parameters, device float32, caller-owned. */
+typedef struct {
+  int32_t P;               /* splats */
+  int32_t N;               /* colour-grid side */
+  int32_t sh_coef;         /* spherical-harmonic coefficients per channel (0 = none) */
+  float* means;            /* [P][3] */
+  float* quats;            /* [P][4] (w, x, y, z), any non-zero length */
+  float* log_scales;       /* [P][2] */
+  float* opacity_logits;   /* [P] */
+  float* textures;         /* [P][N][N][3] float32 (the master copy) */
+  float* sh;               /* [P][sh_coef][3] or NULL */
+} gb_raw_splats;
+
+/* Per-splat rows of optimiser state (e.g. an Adam moment of one parameter group): `width`
+ * floats per splat; the rows of kept splats are copied, those of new splats are zero. */
+typedef struct {
+  const float* src;
+  float* dst;
+  int32_t width;
+} gb_row_state;
+
+/* Densification statistic of the last gb_render_bwd on `workspace` (same arguments as that
+ * call): for every splat k and every view where it is visible, grad_accum[k] += the norm of
+ * the gradient of the loss with respect to a translation of the splat's footprint in the
+ * image (pixels), and vis_count[k] += 1. Both [P] float32 device arrays accumulate across
+ * calls (the caller zeroes them). */
+gb_status gb_densify_stats(const gb_splats* splats, const gb_view* views, int32_t n_views,
+                           const gb_options* opts, const void* workspace, size_t ws_bytes,
+                           int64_t pair_capacity, float* grad_accum, float* vis_count,
+                           void* stream);
+
+/* Bytes of the work buffer (256-byte aligned device memory) of gb_densify_plan/apply. */
+size_t gb_densify_work_bytes(int32_t P);
+
+/* Decides, per splat of `src`, from max(exp(log_scales)), sigmoid(logit) and the mean
+ * statistic grad_accum / vis_count (0 where vis_count is 0): prune, keep, clone (the splat and
+ * an identical copy right after it) or split (two children in its place); outputs are pruned
+ * as described in gb_densify_options. Writes the outputs' parent map into `work` and returns
+ * their number in *P_new. Synchronises `stream`. */
+gb_status gb_densify_plan(const gb_raw_splats* src, const float* grad_accum,
+                          const float* vis_count, const gb_densify_options* opts, void* work,
+                          size_t work_bytes, int64_t* P_new, void* stream);
+
+/* Writes the planned outputs into `dst` (dst->P = the plan's P_new, same N and sh_coef as src;
+ * no overlap with src). Kept splats and clone copies copy their parent's parameters. Split
+ * child c in {0, 1} of parent k has centre p + s_u z0 t_u + s_v z1 t_v with (z0, z1) =
+ * noise[k][c][0..1] (noise: [src->P][2][2] float32 device, the caller's N(0, 1) draws; t_u, t_v
+ * the first two columns of the rotation of q / |q|), log-scales minus log(split_shrink), the
+ * parent's quaternion, logit and SH rows, and a colour grid resampled from the parent's: the
+ * child's texel (i, j) lies at child uv (u_i, v_j) = (-sigma + 2 sigma i / (N - 1), ...) (0 if
+ * N = 1), i.e. at parent uv (z0 + u_i / split_shrink, z1 + v_j / split_shrink), where it takes
+ * the parent's bilinear, border-clamped colour (Alg. 2). So a constant grid stays constant.
+ * `states` (n_states rows arrays) are carried along as gb_row_state describes. */
+gb_status gb_densify_apply(const gb_raw_splats* src, const void* work, const float* noise,
+                           float sigma, const gb_densify_options* opts, const gb_raw_splats* dst,
+                           const gb_row_state* states, int32_t n_states, void* stream);
+
+/* Fills *out with the default options/* Fills *out with the default options (sigma 0.5, alpha_min 1/255, alpha_max 0.99,
  * t_min 1e-4, lowpass_var 0.5, black background, 16 x 16 tiles, default batch). */
 void gb_default_options(gb_options* out);
 

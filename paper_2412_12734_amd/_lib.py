@@ -23,6 +23,7 @@ EXPORTS = (
     "gb_timing_stage_name", "gb_default_options", "gb_status_string", "gb_last_error",
     "gb_activate_fwd", "gb_activate_bwd", "gb_l1_loss", "gb_adam_step", "gb_to_bf16",
     "gb_mse_loss", "gb_box_filter_textures", "gb_rotz_only",
+    "gb_densify_stats", "gb_densify_work_bytes", "gb_densify_plan", "gb_densify_apply",
 )
 
 
@@ -35,7 +36,8 @@ class GbView(ctypes.Structure):
 class GbSplats(ctypes.Structure):
     _fields_ = [("P", c_int32), ("N", c_int32), ("tex_dtype", c_int32), ("means", c_void_p),
                 ("tan_u", c_void_p), ("tan_v", c_void_p), ("scales", c_void_p),
-                ("opacity", c_void_p), ("textures", c_void_p)]
+                ("opacity", c_void_p), ("textures", c_void_p), ("sh_degree", c_int32),
+                ("sh", c_void_p)]
 
 
 class GbOptions(ctypes.Structure):
@@ -48,7 +50,8 @@ class GbOptions(ctypes.Structure):
 
 class GbGrads(ctypes.Structure):
     _fields_ = [("d_means", c_void_p), ("d_tan_u", c_void_p), ("d_tan_v", c_void_p),
-                ("d_scales", c_void_p), ("d_opacity", c_void_p), ("d_textures", c_void_p)]
+                ("d_scales", c_void_p), ("d_opacity", c_void_p), ("d_textures", c_void_p),
+                ("d_sh", c_void_p)]
 
 
 class GbLayout(ctypes.Structure):
@@ -60,6 +63,21 @@ class GbLayout(ctypes.Structure):
                 ("pair_vals_rest", c_size_t), ("ranges_rest", c_size_t),
                 ("n_last_rest", c_size_t), ("open_tiles", c_size_t), ("tile_order", c_size_t),
                 ("tile_work", c_size_t)]
+
+
+class GbDensifyOptions(ctypes.Structure):
+    _fields_ = [("grad_threshold", c_float), ("dense_scale", c_float), ("min_opacity", c_float),
+                ("max_scale", c_float), ("split_shrink", c_float)]
+
+
+class GbRawSplats(ctypes.Structure):
+    _fields_ = [("P", c_int32), ("N", c_int32), ("sh_coef", c_int32), ("means", c_void_p),
+                ("quats", c_void_p), ("log_scales", c_void_p), ("opacity_logits", c_void_p),
+                ("textures", c_void_p), ("sh", c_void_p)]
+
+
+class GbRowState(ctypes.Structure):
+    _fields_ = [("src", c_void_p), ("dst", c_void_p), ("width", c_int32)]
 
 
 class GbbError(RuntimeError):
@@ -91,7 +109,8 @@ def load() -> ctypes.CDLL:
     lib.gb_render_bwd.argtypes = [POINTER(GbSplats), POINTER(GbView), c_int32,
                                   POINTER(GbOptions), c_void_p, c_size_t, c_int64, c_void_p,
                                   c_void_p, POINTER(GbGrads), c_void_p]
-    lib.gb_read_status.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_int32), c_void_p]
+    lib.gb_read_status.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_int32),
+                                   POINTER(c_int64), c_int32, c_void_p]
     lib.gb_blend_stats.argtypes = [POINTER(GbSplats), POINTER(GbView), c_int32,
                                    POINTER(GbOptions), c_void_p, c_size_t, c_int64, c_void_p,
                                    c_void_p, POINTER(c_int64), c_void_p]
@@ -115,10 +134,23 @@ def load() -> ctypes.CDLL:
     lib.gb_box_filter_textures.argtypes = [c_int32, c_int32, c_int32, c_void_p, c_void_p,
                                            c_void_p]
     lib.gb_rotz_only.argtypes = [c_int32, c_void_p, c_void_p]
+    lib.gb_densify_stats.argtypes = [POINTER(GbSplats), POINTER(GbView), c_int32,
+                                     POINTER(GbOptions), c_void_p, c_size_t, c_int64, c_void_p,
+                                     c_void_p, c_void_p]
+    lib.gb_densify_work_bytes.argtypes = [c_int32]
+    lib.gb_densify_work_bytes.restype = c_size_t
+    lib.gb_densify_plan.argtypes = [POINTER(GbRawSplats), c_void_p, c_void_p,
+                                    POINTER(GbDensifyOptions), c_void_p, c_size_t,
+                                    POINTER(c_int64), c_void_p]
+    lib.gb_densify_apply.argtypes = [POINTER(GbRawSplats), c_void_p, c_void_p, c_float,
+                                     POINTER(GbDensifyOptions), POINTER(GbRawSplats),
+                                     POINTER(GbRowState), c_int32, c_void_p]
     for name in ("gb_workspace_layout", "gb_count_pairs", "gb_render_fwd", "gb_render_bwd",
                  "gb_read_status", "gb_blend_stats", "gb_timing_enable", "gb_timing_read",
                  "gb_activate_fwd", "gb_activate_bwd", "gb_l1_loss", "gb_adam_step",
-                 "gb_to_bf16", "gb_mse_loss", "gb_box_filter_textures", "gb_rotz_only"):
+                 "gb_to_bf16", "gb_mse_loss", "gb_box_filter_textures", "gb_rotz_only",
+                 "gb_densify_stats", "gb_densify_plan",
+                 "gb_densify_apply"):
         getattr(lib, name).restype = c_int32
     _lib = lib
     return lib

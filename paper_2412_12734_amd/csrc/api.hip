@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "gbb_internal.h"
@@ -95,6 +96,13 @@ gb_status validate_splats(const gb_splats* s) {
   for (const void* p : ptrs)
     if (!p || !aligned(p, 4)) return arg_fail("splat array NULL or not 4-byte aligned");
   if (!s->textures || !aligned(s->textures, 16)) return arg_fail("textures NULL or not 16-byte aligned");
+  if (s->sh) {
+    if (s->sh_degree < 0 || s->sh_degree > 3) {
+      g_last_error = "sh_degree must be 0, 1, 2 or 3";
+      return GB_ERR_UNSUPPORTED;
+    }
+    if (!aligned(s->sh, 4)) return arg_fail("sh not 4-byte aligned");
+  }
   return GB_OK;
 }
 
@@ -132,6 +140,8 @@ gb_status make_plan(int32_t P, int32_t N, const gb_view* views, int32_t n_views,
     pixels += (int64_t)views[i].width * views[i].height;
   }
   if (sat >= ((int64_t)1 << 31)) return arg_fail("too many tiles");
+  // packed pixel and tile indices are int32 on the device
+  if (pixels >= ((int64_t)1 << 31)) return arg_fail("total pixels of all views must be < 2^31");
   pl->sat_len = sat;
   pl->total_tiles = tiles;
   pl->total_pixels = pixels;
@@ -201,6 +211,10 @@ gb_status make_plan(int32_t P, int32_t N, const gb_view* views, int32_t n_views,
   const size_t od = pl->ordered ? 1 : 0;
   pl->off_tile_order = take(od * 4 * (size_t)tiles);
   pl->off_tile_work = take(od * 4 * (size_t)tiles);
+  pl->off_view_pairs = take(8 * (size_t)n_views);
+  // view-dependent colour of each record and its adjoint (used with SH coefficients)
+  pl->off_spec = take(16 * (size_t)VP);
+  pl->off_dspec = take(16 * (size_t)VP);
   pl->total = off;
   return GB_OK;
 }
@@ -247,6 +261,57 @@ hipError_t stage_mark(int stage, int end, hipStream_t s) {
   return hipEventRecord(g_timing.ev[stage][end], s);
 }
 
+// ---- host-visible overflow state ---------------------------------------------------------
+// Every forward's count finalisation stores (overflow << 63) | K into a slot of host-mapped,
+// coherent memory chosen by the workspace address. A later gb_render_fwd on the same
+// workspace reads that slot without synchronising: if the last forward that has completed
+// overflowed and needed more pairs than the new call's capacity, it returns GB_ERR_CAPACITY
+// before launching anything. Slots are reused round-robin beyond kMirrorSlots workspaces.
+constexpr int kMirrorSlots = 64;
+struct Mirror {
+  std::mutex mu;
+  bool tried = false;
+  unsigned long long* host = nullptr;
+  unsigned long long* dev = nullptr;
+  const void* key[kMirrorSlots] = {};
+  int next = 0;
+} g_mirror;
+
+// Slot of `ws`: its host and device addresses (both null if host-mapped memory is
+// unavailable). `fresh` is set when the library has not seen this workspace before (or its
+// slot was recycled), so that the caller can clear the workspace's sticky overflow word.
+void mirror_slot(const void* ws, volatile unsigned long long** host, unsigned long long** dev,
+                 bool* fresh) {
+  std::lock_guard<std::mutex> lock(g_mirror.mu);
+  if (!g_mirror.tried) {
+    g_mirror.tried = true;
+    void* h = nullptr;
+    if (hipHostMalloc(&h, kMirrorSlots * sizeof(unsigned long long),
+                      hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess) {
+      memset(h, 0, kMirrorSlots * sizeof(unsigned long long));
+      void* d = nullptr;
+      if (hipHostGetDevicePointer(&d, h, 0) == hipSuccess) {
+        g_mirror.host = static_cast<unsigned long long*>(h);
+        g_mirror.dev = static_cast<unsigned long long*>(d);
+      } else {
+        (void)hipHostFree(h);
+      }
+    }
+    (void)hipGetLastError();  // a failure here must not surface in a later call
+  }
+  int i = 0;
+  while (i < kMirrorSlots && g_mirror.key[i] != ws) ++i;
+  *fresh = i == kMirrorSlots;
+  if (*fresh) {
+    i = g_mirror.next;
+    g_mirror.next = (g_mirror.next + 1) % kMirrorSlots;
+    g_mirror.key[i] = ws;
+    if (g_mirror.host) g_mirror.host[i] = 0;
+  }
+  *host = g_mirror.host ? g_mirror.host + i : nullptr;
+  *dev = g_mirror.dev ? g_mirror.dev + i : nullptr;
+}
+
 template <typename T>
 T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off);
@@ -266,12 +331,66 @@ gb_status run_preprocess(const gb_splats* s, const gb_view* views, int32_t n_vie
   GBB_TRY(launch_preprocess(*s, d_views, n_views, *o, pl.tile_w, pl.tile_h,
                             at<uint32_t>(ws, pl.off_depth_key),
                             at<uint32_t>(ws, pl.off_depth_key_alt), at<uint32_t>(ws, pl.off_count),
-                            at<SplatRec>(ws, pl.off_rec), st),
+                            at<SplatRec>(ws, pl.off_rec), at<float4>(ws, pl.off_spec), st),
           "preprocess");
   GBB_TRY(stage_mark(kStPreprocess, 1, st), "timing");
   return GB_OK;
 }
 
+}  // namespace
+}  // namespace gbb
+
+namespace gbb {
+namespace {
+struct DensifyWork {
+  size_t status, action, n_out, offsets, map, partials, partials64, total;
+};
+
+DensifyWork densify_work(int64_t P) {
+  DensifyWork w;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes, 256);
+    return at;
+  };
+  const int64_t parts = (P + kScanTile - 1) / kScanTile + 2;
+  w.status = take(256);
+  w.action = take(4 * (size_t)P);
+  w.n_out = take(4 * (size_t)P);
+  w.offsets = take(4 * (size_t)P);
+  w.map = take(8 * (size_t)P);
+  w.partials = take(4 * (size_t)parts);
+  w.partials64 = take(8 * (size_t)parts);
+  w.total = off;
+  return w;
+}
+
+gb_status check_raw(const gb_raw_splats* r, const char* what) {
+  if (!r) return arg_fail(what);
+  if (r->P < 0 || r->N < 1 || r->N > 64 || r->sh_coef < 0 || r->sh_coef > 64)
+    return arg_fail("raw splats: P >= 0, 1 <= N <= 64, 0 <= sh_coef <= 64");
+  if (r->P == 0) return GB_OK;
+  const void* ptrs[] = {r->means, r->quats, r->log_scales, r->opacity_logits, r->textures};
+  for (const void* p : ptrs)
+    if (!p || !aligned(p, 4)) return arg_fail("raw splat array NULL or misaligned");
+  if (r->sh_coef > 0 && (!r->sh || !aligned(r->sh, 4)))
+    return arg_fail("raw splats: sh NULL or misaligned with sh_coef > 0");
+  return GB_OK;
+}
+
+gb_status check_densify_options(const gb_densify_options* o) {
+  if (!o) return arg_fail("densify options NULL");
+  if (!(o->grad_threshold >= 0.f) || !std::isfinite(o->grad_threshold))
+    return arg_fail("grad_threshold must be >= 0");
+  if (!(o->dense_scale > 0.f) || !std::isfinite(o->dense_scale))
+    return arg_fail("dense_scale must be > 0");
+  if (!(o->min_opacity >= 0.f && o->min_opacity < 1.f)) return arg_fail("min_opacity in [0, 1)");
+  if (!(o->max_scale >= 0.f) || !std::isfinite(o->max_scale)) return arg_fail("max_scale >= 0");
+  if (!(o->split_shrink >= 1.f) || !std::isfinite(o->split_shrink))
+    return arg_fail("split_shrink must be >= 1");
+  return GB_OK;
+}
 }  // namespace
 }  // namespace gbb
 
@@ -362,21 +481,53 @@ gb_status gb_count_pairs(const gb_splats* s, const gb_view* views, int32_t n_vie
   GBB_TRY(hipMemcpyAsync(&h, d_st, sizeof(Status), hipMemcpyDeviceToHost, hs), "read count");
   GBB_TRY(hipStreamSynchronize(hs), "sync");
   *K_out = (int64_t)h.K64;
+  // a caller that counts is re-planning: forget an earlier overflow on this workspace
+  volatile unsigned long long* m_host = nullptr;
+  unsigned long long* m_dev = nullptr;
+  bool fresh = false;
+  mirror_slot(ws, &m_host, &m_dev, &fresh);
+  if (m_host) *m_host = 0ull;
+  GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(ws) +
+                                                      offsetof(Status, sticky_overflow)),
+                          0u, 1, hs),
+          "clear sticky overflow");
   return GB_OK;
 }
 
 static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32_t n_views,
                                  const gb_options* o, void* ws, size_t ws_bytes, int64_t cap,
-                                 float* rgb, float* T_final, bool stats, void* stream) {
+                                 float* rgb, float* T_final, bool stats, void* stream,
+                                 bool use_mirror = true, uint32_t* overflow_flag = nullptr) {
   Plan pl;
   gb_status st = check_common(s, views, n_views, o, ws, ws_bytes, cap, &pl);
   if (st != GB_OK) return st;
   if (!rgb || !T_final || !aligned(rgb, 4) || !aligned(T_final, 4))
     return arg_fail("rgb / T_final NULL or misaligned");
+  // a completed earlier forward on this workspace that did not fit this capacity
+  volatile unsigned long long* m_host = nullptr;
+  unsigned long long* m_dev = nullptr;
+  bool fresh = false;
+  if (use_mirror) mirror_slot(ws, &m_host, &m_dev, &fresh);
+  if (m_host) {
+    const unsigned long long m = *m_host;
+    const unsigned long long need = m & ~(1ull << 63);
+    if ((m >> 63) && need > (unsigned long long)cap) {
+      char buf[160];
+      snprintf(buf, sizeof(buf),
+               "an earlier forward on this workspace needed %llu pairs; pair_capacity is %lld",
+               need, (long long)cap);
+      g_last_error = buf;
+      return GB_ERR_CAPACITY;
+    }
+  }
   hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  Status* d_st = at<Status>(ws, pl.off_status);
+  // a workspace met for the first time holds whatever its memory held: its sticky
+  // overflow word starts at zero
+  if (fresh)
+    GBB_TRY(launch_fill_u32(&d_st->sticky_overflow, 0u, 1, hs), "clear sticky overflow");
   if ((st = run_preprocess(s, views, n_views, o, ws, pl, hs)) != GB_OK) return st;
 
-  Status* d_st = at<Status>(ws, pl.off_status);
   uint32_t* dk_a = at<uint32_t>(ws, pl.off_depth_key_alt);
   uint32_t* order = at<uint32_t>(ws, pl.off_order);
   uint32_t* order_alt = at<uint32_t>(ws, pl.off_order_alt);
@@ -407,7 +558,11 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   GBB_TRY(launch_scan_u32(count, order, offsets, pl.VP, partials, &d_st->K, &d_st->K64,
                           partials64, hs, chunk_owner, pl.n_chunks),
           "pair scan");
-  GBB_TRY(launch_finalize_count(offsets, pl.VP, d_st, pl.capacity, hs), "finalize count");
+  const StatusEcho echo{(uint32_t)n_views, (uint32_t)pl.P, (unsigned long long)pl.off_count,
+                        (unsigned long long)pl.off_view_pairs};
+  GBB_TRY(launch_finalize_count(offsets, pl.VP, d_st, pl.capacity, echo, m_dev, overflow_flag,
+                                hs),
+          "finalize count");
   if (pl.split)
     GBB_TRY(launch_prefix_cut(offsets, pl.VP, pl.prefix_cap, d_st, hs), "prefix cut");
   GBB_TRY(stage_mark(kStPairScan, 1, hs), "timing");
@@ -440,8 +595,9 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
     GBB_TRY(launch_fill_u32(split.open_bits, 0u, (pl.total_tiles + 31) / 32, hs), "clear bits");
   }
   GBB_TRY(stage_mark(kStBlendFwd, 0, hs), "timing");
+  const float4* spec = s->sh ? at<float4>(ws, pl.off_spec) : nullptr;
   GBB_TRY(launch_blend_fwd(pl, *s, *o, d_views, n_views, rec, pv, ranges, rgb, T_final,
-                           at<uint32_t>(ws, pl.off_n_last), split, tile_work,
+                           at<uint32_t>(ws, pl.off_n_last), split, tile_work, spec,
                            stats ? d_stats : nullptr, hs),
           "blend forward");
   GBB_TRY(stage_mark(kStBlendFwd, 1, hs), "timing");
@@ -478,7 +634,7 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   split.mode = kRestPass;
   GBB_TRY(stage_mark(kStBlendFwdRest, 0, hs), "timing");
   GBB_TRY(launch_blend_fwd(pl, *s, *o, d_views, n_views, rec, pv_r, ranges_rest, rgb, T_final,
-                           at<uint32_t>(ws, pl.off_n_last_rest), split, tile_work,
+                           at<uint32_t>(ws, pl.off_n_last_rest), split, tile_work, spec,
                            stats ? d_stats : nullptr, hs),
           "blend forward (rest)");
   GBB_TRY(stage_mark(kStBlendFwdRest, 1, hs), "timing");
@@ -544,10 +700,17 @@ gb_status gb_render_bwd(const gb_splats* s, const gb_view* views, int32_t n_view
   const void* gp[] = {g->d_means, g->d_tan_u, g->d_tan_v, g->d_scales, g->d_opacity, g->d_textures};
   for (const void* p : gp)
     if (!p || !aligned(p, 4)) return arg_fail("gradient array NULL or misaligned");
+  if (s->sh && (!g->d_sh || !aligned(g->d_sh, 4)))
+    return arg_fail("d_sh NULL or misaligned (the splats carry SH coefficients)");
   hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
   float* d_rec = at<float>(ws, pl.off_drec);
+  const float4* spec = s->sh ? at<float4>(ws, pl.off_spec) : nullptr;
+  float4* d_spec = s->sh ? at<float4>(ws, pl.off_dspec) : nullptr;
   GBB_TRY(stage_mark(kStBwdClear, 0, hs), "timing");
   GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_rec), 0u, kRecGrad * pl.VP, hs), "clear d_rec");
+  if (d_spec)
+    GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_spec), 0u, 4 * pl.VP, hs),
+            "clear d_spec");
   GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(g->d_textures), 0u,
                           (int64_t)s->P * 3 * s->N * s->N, hs),
           "clear d_textures");
@@ -573,14 +736,132 @@ gb_status gb_render_bwd(const gb_splats* s, const gb_view* views, int32_t n_view
   }
   GBB_TRY(stage_mark(kStBlendBwd, 0, hs), "timing");
   GBB_TRY(launch_blend_bwd(pl, *s, *o, d_views, n_views, rec, first, rest, open_bits,
-                           tile_order, T_final, d_rgb, d_rec, g->d_textures, hs),
+                           tile_order, T_final, d_rgb, d_rec, g->d_textures, spec,
+                           reinterpret_cast<float*>(d_spec), hs),
           "blend backward");
   GBB_TRY(stage_mark(kStBlendBwd, 1, hs), "timing");
   GBB_TRY(stage_mark(kStPreprocessBwd, 0, hs), "timing");
-  GBB_TRY(launch_preprocess_bwd(*s, d_views, n_views, at<uint32_t>(ws, pl.off_count), d_rec, *g,
-                                hs),
+  GBB_TRY(launch_preprocess_bwd(*s, d_views, n_views, at<uint32_t>(ws, pl.off_count), d_rec,
+                                d_spec, *g, hs),
           "preprocess backward");
   GBB_TRY(stage_mark(kStPreprocessBwd, 1, hs), "timing");
+  return GB_OK;
+}
+
+// ---- densification and pruning --------------------------------------------------------------
+
+size_t gb_densify_work_bytes(int32_t P) { return P < 0 ? 0 : densify_work(P).total; }
+
+gb_status gb_densify_stats(const gb_splats* s, const gb_view* views, int32_t n_views,
+                           const gb_options* o, const void* ws, size_t ws_bytes, int64_t cap,
+                           float* grad_accum, float* vis_count, void* stream) {
+  Plan pl;
+  gb_status st = check_common(s, views, n_views, o, const_cast<void*>(ws), ws_bytes, cap, &pl);
+  if (st != GB_OK) return st;
+  if (!grad_accum || !vis_count || !aligned(grad_accum, 4) || !aligned(vis_count, 4))
+    return arg_fail("grad_accum / vis_count NULL or misaligned");
+  char* base = const_cast<char*>(static_cast<const char*>(ws));
+  GBB_TRY(launch_densify_stats(reinterpret_cast<const uint32_t*>(base + pl.off_count),
+                               reinterpret_cast<const float*>(base + pl.off_drec), pl.P, n_views,
+                               grad_accum, vis_count, reinterpret_cast<hipStream_t>(stream)),
+          "densify stats");
+  return GB_OK;
+}
+
+gb_status gb_densify_plan(const gb_raw_splats* src, const float* grad_accum,
+                          const float* vis_count, const gb_densify_options* o, void* work,
+                          size_t work_bytes, int64_t* P_new, void* stream) {
+  gb_status st;
+  if ((st = check_raw(src, "src NULL")) != GB_OK) return st;
+  if ((st = check_densify_options(o)) != GB_OK) return st;
+  if (!P_new) return arg_fail("P_new NULL");
+  const DensifyWork w = densify_work(src->P);
+  if (!work || !aligned(work, 256) || work_bytes < w.total)
+    return arg_fail("densify work buffer NULL, misaligned or smaller than gb_densify_work_bytes");
+  if (src->P == 0) {
+    *P_new = 0;
+    return GB_OK;
+  }
+  if (!grad_accum || !vis_count || !aligned(grad_accum, 4) || !aligned(vis_count, 4))
+    return arg_fail("grad_accum / vis_count NULL or misaligned");
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  char* b = static_cast<char*>(work);
+  // thresholds in the domain of the raw parameters (double precision, rounded once)
+  const double shrink = o->split_shrink;
+  const float ls_dense = (float)std::log((double)o->dense_scale);
+  const float logit_min =
+      o->min_opacity > 0.f ? (float)std::log((double)o->min_opacity / (1.0 - o->min_opacity))
+                           : -INFINITY;
+  const bool use_max = o->max_scale > 0.f;
+  const float ls_max = use_max ? (float)std::log((double)o->max_scale) : 0.f;
+  const float ls_max_child = use_max ? (float)(std::log((double)o->max_scale) + std::log(shrink))
+                                     : 0.f;
+  uint32_t* action = reinterpret_cast<uint32_t*>(b + w.action);
+  uint32_t* n_out = reinterpret_cast<uint32_t*>(b + w.n_out);
+  uint32_t* offsets = reinterpret_cast<uint32_t*>(b + w.offsets);
+  uint32_t* d_total = reinterpret_cast<uint32_t*>(b + w.status);
+  unsigned long long* d_total64 = reinterpret_cast<unsigned long long*>(b + w.status + 8);
+  GBB_TRY(launch_densify_decide(src->P, src->log_scales, src->opacity_logits, grad_accum,
+                                vis_count, o->grad_threshold, ls_dense, logit_min, ls_max,
+                                ls_max_child, use_max, action, n_out, hs),
+          "densify decide");
+  GBB_TRY(launch_scan_u32(n_out, nullptr, offsets, src->P,
+                          reinterpret_cast<uint32_t*>(b + w.partials), d_total, d_total64,
+                          reinterpret_cast<unsigned long long*>(b + w.partials64), hs),
+          "densify scan");
+  GBB_TRY(launch_densify_map(src->P, action, n_out, offsets,
+                             reinterpret_cast<uint32_t*>(b + w.map), hs),
+          "densify map");
+  unsigned long long total = 0;
+  GBB_TRY(hipMemcpyAsync(&total, d_total64, sizeof(total), hipMemcpyDeviceToHost, hs),
+          "read densify count");
+  GBB_TRY(hipStreamSynchronize(hs), "sync");
+  *P_new = (int64_t)total;
+  return GB_OK;
+}
+
+gb_status gb_densify_apply(const gb_raw_splats* src, const void* work, const float* noise,
+                           float sigma, const gb_densify_options* o, const gb_raw_splats* dst,
+                           const gb_row_state* states, int32_t n_states, void* stream) {
+  gb_status st;
+  if ((st = check_raw(src, "src NULL")) != GB_OK) return st;
+  if ((st = check_raw(dst, "dst NULL")) != GB_OK) return st;
+  if ((st = check_densify_options(o)) != GB_OK) return st;
+  if (dst->N != src->N || dst->sh_coef != src->sh_coef)
+    return arg_fail("dst must have the texture side and SH coefficients of src");
+  if (dst->P > 2 * (int64_t)src->P) return arg_fail("dst->P exceeds twice src->P");
+  if (!(sigma > 0.f) || !std::isfinite(sigma)) return arg_fail("sigma must be > 0");
+  if (!work || !aligned(work, 256)) return arg_fail("work NULL or misaligned");
+  if (n_states < 0 || (n_states > 0 && !states)) return arg_fail("states NULL");
+  for (int i = 0; i < n_states; ++i)
+    if (!states[i].src || !states[i].dst || states[i].width < 1 || !aligned(states[i].src, 4) ||
+        !aligned(states[i].dst, 4))
+      return arg_fail("state row arrays NULL, misaligned or of width < 1");
+  if (dst->P == 0) return GB_OK;
+  if (!noise || !aligned(noise, 4)) return arg_fail("noise NULL or misaligned");
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  const DensifyWork w = densify_work(src->P);
+  const char* b = static_cast<const char*>(work);
+  const uint32_t* map = reinterpret_cast<const uint32_t*>(b + w.map);
+  const uint32_t* d_n = reinterpret_cast<const uint32_t*>(b + w.status);
+  const int64_t n = dst->P;
+  const int N = src->N;
+  GBB_TRY(launch_child_geometry(map, d_n, n, src->means, src->quats, src->log_scales, noise,
+                                (float)std::log((double)o->split_shrink), dst->means,
+                                dst->log_scales, hs),
+          "densify geometry");
+  GBB_TRY(launch_gather_rows(map, d_n, n, 4, src->quats, dst->quats, false, hs), "quats");
+  GBB_TRY(launch_gather_rows(map, d_n, n, 1, src->opacity_logits, dst->opacity_logits, false, hs),
+          "logits");
+  if (src->sh_coef > 0)
+    GBB_TRY(launch_gather_rows(map, d_n, n, 3 * src->sh_coef, src->sh, dst->sh, false, hs), "sh");
+  GBB_TRY(launch_child_texture(map, d_n, n, N, src->textures, noise, sigma,
+                               (float)(1.0 / (double)o->split_shrink), dst->textures, hs),
+          "densify textures");
+  for (int i = 0; i < n_states; ++i)
+    GBB_TRY(launch_gather_rows(map, d_n, n, states[i].width, states[i].src, states[i].dst, true,
+                               hs),
+            "state rows");
   return GB_OK;
 }
 
@@ -691,14 +972,39 @@ gb_status gb_to_bf16(int64_t n, const float* src, uint16_t* dst, void* stream) {
   return GB_OK;
 }
 
-gb_status gb_read_status(const void* ws, int64_t* K_out, int32_t* overflow_out, void* stream) {
+gb_status gb_read_status(const void* ws, int64_t* K_out, int32_t* overflow_out,
+                         int64_t* K_per_view, int32_t n_views, void* stream) {
   if (!ws || !K_out || !overflow_out) return arg_fail("NULL argument");
+  if (!aligned(ws, 256)) return arg_fail("workspace not 256-byte aligned");
   hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
   Status h;
   GBB_TRY(hipMemcpyAsync(&h, ws, sizeof(Status), hipMemcpyDeviceToHost, hs), "read status");
   GBB_TRY(hipStreamSynchronize(hs), "sync");
+  if (K_per_view) {
+    if (h.n_views < 1 || h.n_views > GB_MAX_VIEWS) return arg_fail("no forward on this workspace");
+    if ((uint32_t)n_views != h.n_views)
+      return arg_fail("n_views differs from the last forward on this workspace");
+    char* base = const_cast<char*>(static_cast<const char*>(ws));
+    unsigned long long* d_kv = reinterpret_cast<unsigned long long*>(base + h.off_view_pairs);
+    GBB_TRY(launch_view_pairs(reinterpret_cast<const uint32_t*>(base + h.off_count), h.P,
+                              n_views, d_kv, hs),
+            "view pairs");
+    unsigned long long kv[GB_MAX_VIEWS];
+    GBB_TRY(hipMemcpyAsync(kv, d_kv, sizeof(unsigned long long) * (size_t)n_views,
+                           hipMemcpyDeviceToHost, hs),
+            "read view pairs");
+    GBB_TRY(hipStreamSynchronize(hs), "sync");
+    for (int v = 0; v < n_views; ++v) K_per_view[v] = (int64_t)kv[v];
+  }
   *K_out = (int64_t)h.K64;
-  *overflow_out = (int32_t)h.overflow;
+  *overflow_out = (int32_t)((h.overflow ? 1 : 0) | (h.sticky_overflow ? 2 : 0));
+  // the sticky flag reports every overflow once
+  if (h.sticky_overflow) {
+    char* base = const_cast<char*>(static_cast<const char*>(ws));
+    GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(base + offsetof(Status, sticky_overflow)),
+                            0u, 1, hs),
+            "clear sticky overflow");
+  }
   return GB_OK;
 }
 

@@ -254,7 +254,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
       }
       for (int e = tid; e < nb * TEXG; e += nthr) s_gtex[e] = 0.f;
       for (int e = tid; e < nb * kRecGrad; e += nthr) s_grec[e] = 0.f;
-      stage_texels<N, BF16>(textures, pair_vals + bstart, rec_base, nb, s_tex);
+      stage_texels<N, BF16>(textures, pair_vals + bstart, rec_base, nb, s_tex, p.spec);
       __syncthreads();
 
       // splats of this batch that can reach the wave's block, walked back to front
@@ -380,6 +380,18 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
         }
       }
       __syncthreads();
+      // the view-dependent colour of a record is added to every texel of its lookup, so its
+      // adjoint over the tile is the sum of the record's texel sums, one per channel: each
+      // wave sums the N^2 texels of a (splat, channel) pair at a time
+      if (p.d_spec) {
+        for (int jc = w; jc < 3 * nb; jc += nthr >> 6) {
+          const int j = jc / 3, c = jc - 3 * j;
+          float x = 0.f;
+          for (int t = lane; t < N * N; t += 64) x += s_gtex[j * TEXG + 3 * t + c];
+          x = wave_sum(x);
+          if (lane == 0 && x != 0.f) atomicAdd(&p.d_spec[4 * (int64_t)s_recid[j] + c], x);
+        }
+      }
       // flush the batch's sums
       for (int e = tid; e < nb * TEXG; e += nthr) {
         const float x = s_gtex[e];
@@ -430,9 +442,11 @@ hipError_t launch_blend_bwd(const Plan& pl, const gb_splats& sp, const gb_option
                             const PairList& first, const PairList& rest,
                             const uint32_t* open_bits, const uint32_t* tile_order,
                             const float* T_final, const float* d_rgb, float* d_rec,
-                            float* d_tex, hipStream_t s) {
+                            float* d_tex, const float4* spec, float* d_spec, hipStream_t s) {
   BlendParams bp = make_blend_params(pl, o, n_views);
   bp.tile_order = tile_order;
+  bp.spec = spec;
+  bp.d_spec = d_spec;
   const bool bf = sp.tex_dtype == GB_BF16;
   // One pixel per lane. Two pixels per lane (8 x 16 wave blocks) measured slower on the
   // 1M-splat 1080p workload (3.0 vs 2.3 ms): LDS limits such blocks to two waves per SIMD and

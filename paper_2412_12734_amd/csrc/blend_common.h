@@ -23,6 +23,10 @@ struct BlendParams {
   int32_t tiles_per_xcd;
   const uint32_t* tile_order;  // nullable: workgroup b takes tile tile_order[b]
   uint32_t* tile_work;         // nullable: per-tile blended span written by the forward
+  // view-dependent colour of each record, added to every texel on staging (nullable), and
+  // the backward's adjoint of it (nullable; xyz summed over the record's blended pixels)
+  const float4* spec;
+  float* d_spec;
 };
 
 BlendParams make_blend_params(const Plan& pl, const gb_options& o, int n_views);
@@ -86,10 +90,13 @@ struct TexLayout {
 // records. For even N a splat's 3 N^2 channel values split into groups of 12 (four texels):
 // each thread moves whole groups, three 16-byte (float32) or 8-byte (bfloat16) loads in, four
 // LDS stores out.
+// With spec != null each texel also gets the record's view-dependent colour spec[pairs[j]]
+// (the bilinear weights sum to one, so this adds that colour to the lookup).
 template <int N, bool BF16>
 __device__ __forceinline__ void stage_texels(const void* __restrict__ textures,
                                              const uint32_t* __restrict__ pairs,
-                                             uint32_t rec_base, int nb, float4* s_tex) {
+                                             uint32_t rec_base, int nb, float4* s_tex,
+                                             const float4* __restrict__ spec) {
   constexpr int per = 3 * N * N;  // channel values per splat
   const int tid = threadIdx.x, nthr = blockDim.x;
   if constexpr ((per % 12) == 0) {
@@ -97,6 +104,7 @@ __device__ __forceinline__ void stage_texels(const void* __restrict__ textures,
     for (int gi = tid; gi < nb * groups; gi += nthr) {
       const int j = gi / groups, a = gi - j * groups;
       const int64_t src = ((int64_t)(pairs[j] - rec_base) * groups + a) * 3;
+      const float4 sc = spec ? spec[pairs[j]] : make_float4(0.f, 0.f, 0.f, 0.f);
       float v[12];
       if constexpr (BF16) {
         const uint2* t = reinterpret_cast<const uint2*>(textures) + src;
@@ -123,7 +131,9 @@ __device__ __forceinline__ void stage_texels(const void* __restrict__ textures,
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int t = 4 * a + k, iu = t / N, iv = t - iu * N;
-        dst[TexLayout<N>::at(iu, iv)] = make_float4(v[3 * k], v[3 * k + 1], v[3 * k + 2], 0.f);
+        dst[TexLayout<N>::at(iu, iv)] =
+            spec ? make_float4(v[3 * k] + sc.x, v[3 * k + 1] + sc.y, v[3 * k + 2] + sc.z, 0.f)
+                 : make_float4(v[3 * k], v[3 * k + 1], v[3 * k + 2], 0.f);
       }
     }
   } else {
@@ -135,6 +145,10 @@ __device__ __forceinline__ void stage_texels(const void* __restrict__ textures,
         x = bf16_to_f32(reinterpret_cast<const uint16_t*>(textures)[k * per + r]);
       else
         x = reinterpret_cast<const float*>(textures)[k * per + r];
+      if (spec) {
+        const float4 sc = spec[pairs[j]];
+        x += (r % 3) == 0 ? sc.x : (r % 3) == 1 ? sc.y : sc.z;
+      }
       const int t = r / 3, iu = t / N, iv = t - iu * N;
       reinterpret_cast<float*>(s_tex + j * TexLayout<N>::kPerSplat + TexLayout<N>::at(iu, iv))[r % 3] = x;
     }

@@ -108,7 +108,7 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
                             : 0;
       }
     }
-    stage_texels<N, BF16>(textures, pair_vals + b0, rec_base, nb, s_tex);
+    stage_texels<N, BF16>(textures, pair_vals + b0, rec_base, nb, s_tex, p.spec);
     __syncthreads();
 
     if (!__all(done)) {
@@ -280,6 +280,8 @@ BlendParams make_blend_params(const Plan& pl, const gb_options& o, int n_views) 
   bp.tiles_per_xcd = (int32_t)((pl.total_tiles + 7) / 8);
   bp.tile_order = nullptr;
   bp.tile_work = nullptr;
+  bp.spec = nullptr;
+  bp.d_spec = nullptr;
   return bp;
 }
 
@@ -287,11 +289,13 @@ hipError_t launch_blend_fwd(const Plan& pl, const gb_splats& sp, const gb_option
                             const ViewDev* views, int n_views, const SplatRec* rec,
                             const uint32_t* pair_vals, const uint32_t* ranges, float* rgb,
                             float* T_final, uint32_t* n_last, const SplitState& split,
-                            uint32_t* tile_work, unsigned long long* stats, hipStream_t s) {
+                            uint32_t* tile_work, const float4* spec, unsigned long long* stats,
+                            hipStream_t s) {
   // the forward keeps the fixed tile bands: ranking its tiles by list length measured no
   // faster on the 1M-splat 1080p workload (0.50 ms either way)
   BlendParams bp = make_blend_params(pl, o, n_views);
   bp.tile_work = tile_work;
+  bp.spec = spec;
   const bool bf = sp.tex_dtype == GB_BF16;
 #define GBB_FWD(NN)                                                                          \
   return bf ? launch_nb<NN, true>(pl, sp, bp, views, rec, pair_vals, ranges, rgb, T_final,   \

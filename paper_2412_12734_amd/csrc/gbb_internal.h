@@ -60,7 +60,13 @@ struct Status {
   uint32_t last_first; // depth rank of the record owning the first pass's last pair slot
   uint32_t last_rest;  // the same for the second pass
   uint32_t any_open;   // nonzero if the prefix pass left some tile open
+  uint32_t sticky_overflow;  // ORed by every forward's overflow flag; cleared by gb_read_status
+  uint32_t n_views;    // views and splats of the last forward, and the byte offsets of its
+  uint32_t P;          // per-record tile counts and per-view pair totals in the workspace
+  unsigned long long off_count;
+  unsigned long long off_view_pairs;
 };
+static_assert(sizeof(Status) <= 256, "status section");
 
 // Depth-prefix split. The first pass renders the records of a prefix of the depth order
 // (as many as fit a pair budget); tiles where some pixel is still open afterwards get a
@@ -101,7 +107,7 @@ struct Plan {
   size_t off_status, off_views, off_depth_key, off_depth_key_alt, off_order, off_order_alt,
       off_count, off_offsets, off_rec, off_partials, off_hist, off_pair_keys, off_pair_vals,
       off_pair_keys_alt, off_pair_vals_alt, off_ranges, off_n_last, off_drec, off_stats,
-      off_partials64,
+      off_partials64, off_view_pairs, off_spec, off_dspec,
       off_ranges_rest, off_n_last_rest, off_fwd_state, off_open_bits,
       off_count_rest, off_offsets_rest, off_chunk_owner, off_sat, off_tile_order,
       off_tile_work, total;
@@ -115,12 +121,19 @@ constexpr int kRadixThreads = 256;
 constexpr int kRadixTile = kRadixItems * kRadixThreads;  // 4096 elements per block
 constexpr int kScanTile = 4096;
 
+// Key-stage radius (px) of the screen-space low-pass disk: 2.36 for variances up to 1/2, else
+// 3.34 sqrt(var) (>= sqrt(2 var ln 255)), computed in double and rounded once to float32.
+float lowpass_radius(float lowpass_var);
+
 // ---- launchers (all stream-ordered, no synchronisation) --------------------------------
 hipError_t launch_upload_views(const gb_view* views, int n_views, int tile_w, int tile_h,
                                ViewDev* d_views, hipStream_t s);
+// With sp.sh != null it also writes spec[v P + k] = (view-dependent colour of splat k seen
+// from view v, 0) for every visible record.
 hipError_t launch_preprocess(const gb_splats& sp, const ViewDev* d_views, int n_views,
                              const gb_options& o, int tile_w, int tile_h, uint32_t* depth_key,
-                             uint32_t* sort_key, uint32_t* count, SplatRec* rec, hipStream_t s);
+                             uint32_t* sort_key, uint32_t* count, SplatRec* rec, float4* spec,
+                             hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
 hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t s);
 // Pair slots per chunk of the duplicate kernels (one workgroup round).
@@ -151,8 +164,22 @@ hipError_t launch_scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t*
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                              uint32_t* vals_alt, const uint32_t* d_n, int64_t n_cap, int bits,
                              uint32_t* hist, uint32_t* partials, hipStream_t s);
+// Overflow decision of a forward: st->overflow from the exact pair count against the capacity,
+// ORed into st->sticky_overflow; records the plan echo (views, splats, section offsets) for
+// gb_read_status. With mirror != null (host-mapped memory) it also stores
+// (overflow << 63) | K64 there, so that the host sees an overflow without synchronising;
+// with overflow_flag != null (device memory) it sets *overflow_flag = 1 on overflow.
+struct StatusEcho {
+  uint32_t n_views, P;
+  unsigned long long off_count, off_view_pairs;
+};
 hipError_t launch_finalize_count(const uint32_t* offsets, int64_t VP, Status* st,
-                                 int64_t capacity, hipStream_t s);
+                                 int64_t capacity, StatusEcho echo,
+                                 unsigned long long* mirror, uint32_t* overflow_flag,
+                                 hipStream_t s);
+// Per-view pair totals: out[v] = sum of count[v P .. (v + 1) P) (one workgroup per view).
+hipError_t launch_view_pairs(const uint32_t* count, int64_t P, int n_views,
+                             unsigned long long* out, hipStream_t s);
 // Depth-prefix cut: the largest record count (in depth order) whose pairs fit `budget`.
 // Writes st->cut and st->n_sorted (the prefix's pairs); nothing on overflow.
 hipError_t launch_prefix_cut(const uint32_t* offsets, int64_t VP, int64_t budget, Status* st,
@@ -198,16 +225,18 @@ hipError_t launch_blend_fwd(const Plan& pl, const gb_splats& sp, const gb_option
                             const ViewDev* views, int n_views, const SplatRec* rec,
                             const uint32_t* pair_vals, const uint32_t* ranges, float* rgb,
                             float* T_final, uint32_t* n_last, const SplitState& split,
-                            uint32_t* tile_work, unsigned long long* stats, hipStream_t s);
+                            uint32_t* tile_work, const float4* spec, unsigned long long* stats,
+                            hipStream_t s);
 // Backward blend over the prefix (or only) pass's pairs `first`; with open_bits != null the
 // tiles marked there first walk `rest` (the rest pass's pairs). tile_order (nullable):
-// workgroup b takes tile tile_order[b].
+// workgroup b takes tile tile_order[b]. With spec != null the records' view-dependent colours
+// are part of the colour and d_spec[4 r + c] (zeroed by the caller) receives their adjoints.
 hipError_t launch_blend_bwd(const Plan& pl, const gb_splats& sp, const gb_options& o,
                             const ViewDev* views, int n_views, const SplatRec* rec,
                             const PairList& first, const PairList& rest,
                             const uint32_t* open_bits, const uint32_t* tile_order,
                             const float* T_final, const float* d_rgb, float* d_rec,
-                            float* d_tex, hipStream_t s);
+                            float* d_tex, const float4* spec, float* d_spec, hipStream_t s);
 // Training glue (train.hip).
 hipError_t launch_activate_fwd(int P, const float* quats, const float* log_scales,
                                const float* logits, float* tan_u, float* tan_v, float* scales,
@@ -227,8 +256,32 @@ hipError_t launch_to_bf16(int64_t n, const float* src, uint16_t* dst, hipStream_
 hipError_t launch_adam(int64_t n, float* theta, const float* grad, float* m, float* v, float lr,
                        float b1, float b2, float c1, float c2, float eps, uint16_t* bf16,
                        hipStream_t s);
+// With sp.sh != null, d_spec[v P + k] holds the adjoint of record v P + k's view-dependent
+// colour; g.d_sh receives the coefficients' gradient and the centres' gradient includes the
+// term through the view direction.
 hipError_t launch_preprocess_bwd(const gb_splats& sp, const ViewDev* d_views, int n_views,
                                  const uint32_t* count, const float* d_rec,
-                                 const gb_grads& g, hipStream_t s);
+                                 const float4* d_spec, const gb_grads& g, hipStream_t s);
+
+// Densification and pruning (densify.hip). The apply launchers are sized by n_new (the
+// host's count) and bounded on the device by *d_n (the planned count).
+hipError_t launch_densify_stats(const uint32_t* count, const float* d_rec, int64_t P,
+                                int n_views, float* accum, float* vis, hipStream_t s);
+hipError_t launch_densify_decide(int64_t P, const float* log_scales, const float* logits,
+                                 const float* accum, const float* vis, float grad_threshold,
+                                 float ls_dense, float logit_min, float ls_max,
+                                 float ls_max_child, bool use_max_scale, uint32_t* action,
+                                 uint32_t* n_out, hipStream_t s);
+hipError_t launch_densify_map(int64_t P, const uint32_t* action, const uint32_t* n_out,
+                              const uint32_t* offsets, uint32_t* map, hipStream_t s);
+hipError_t launch_gather_rows(const uint32_t* map, const uint32_t* d_n, int64_t n_new, int width,
+                              const float* src, float* dst, bool zero_new, hipStream_t s);
+hipError_t launch_child_geometry(const uint32_t* map, const uint32_t* d_n, int64_t n_new,
+                                 const float* means, const float* quats, const float* log_scales,
+                                 const float* noise, float log_shrink, float* means_out,
+                                 float* log_scales_out, hipStream_t s);
+hipError_t launch_child_texture(const uint32_t* map, const uint32_t* d_n, int64_t n_new, int N,
+                                const float* tex, const float* noise, float sigma,
+                                float inv_shrink, float* tex_out, hipStream_t s);
 
 }  // namespace gbb

@@ -8,13 +8,18 @@
 //   corners q = (pc +- 3.33 a) +- 3.33 b in the order (-,-), (+,-), (-,+), (+,+)
 //   any corner with q_z <= z_near (or alpha_min < 1/255): rectangle = whole image; otherwise
 //   x = fx (q_x / q_z) + cx, y likewise, c2 = (fx (pc_x / d) + cx, fy (pc_y / d) + cy),
-//   xmin = min(x.., c2x - 2.36) - 0.01, xmax = max(x.., c2x + 2.36) + 0.01 (y likewise),
+//   xmin = min(x.., c2x - r_lp) - 0.01, xmax = max(x.., c2x + r_lp) + 0.01 (y likewise),
 //   i0 = ceil(xmin - 0.5), i1 = floor(xmax - 0.5), clamped to the image, empty -> culled.
-// 3.33 bounds the uv radius where o G >= 1/255 (sqrt(2 ln 255) = 3.329) and 2.36 the radius of
-// the low-pass disk with the same bound (sqrt(ln 255) = 2.354 px for variance 1/2), so every
-// pixel with alpha >= alpha_min lies inside (Eq. 3-4; the 0.01 px margin covers rounding).
+// 3.33 bounds the uv radius where o G >= 1/255 (sqrt(2 ln 255) = 3.329) and r_lp the radius of
+// the low-pass disk with the same bound, sqrt(2 var ln 255) = 3.329 sqrt(var) px: r_lp = 2.36
+// for variances up to 1/2 (the default), else 3.34 sqrt(var) rounded once to float32 (host
+// side, in double precision). Every pixel with alpha >= alpha_min then lies inside (Eq. 3-4;
+// the 0.01 px margin covers rounding).
+#include <cmath>
+
 #include "device_util.h"
 #include "gbb_internal.h"
+#include "sh_eval.h"
 
 namespace gbb {
 
@@ -51,6 +56,10 @@ __global__ void upload_views_kernel(ViewChunk c, int tile_w, int tile_h, ViewDev
   out[c.first + i] = d;
 }
 
+__device__ __forceinline__ float p_of(int i, float p0, float p1, float p2) {
+  return i == 0 ? p0 : i == 1 ? p1 : p2;
+}
+
 __device__ __forceinline__ float ks_min(float a, float b) { return a < b ? a : b; }
 __device__ __forceinline__ float ks_max(float a, float b) { return a > b ? a : b; }
 
@@ -68,14 +77,17 @@ __device__ __forceinline__ f2 rot_row_f2(const float* R, int i, float x0, float 
   return f2_add(s, t);
 }
 
+// SHD: degree of the view-dependent colour term (-1: none).
+template <int SHD>
 __global__ void __launch_bounds__(256)
 preprocess_kernel(const float* __restrict__ means, const float* __restrict__ tan_u,
                   const float* __restrict__ tan_v, const float* __restrict__ scales,
                   const float* __restrict__ opacity, const ViewDev* __restrict__ views,
-                  int64_t P, int64_t VP, float alpha_min, int tile_w, int tile_h,
+                  int64_t P, int64_t VP, float alpha_min, float r_lp, int tile_w, int tile_h,
                   uint32_t* __restrict__ depth_key, uint32_t* __restrict__ sort_key,
                   uint32_t* __restrict__ count,
-                  SplatRec* __restrict__ rec) {
+                  SplatRec* __restrict__ rec, const float* __restrict__ sh,
+                  float4* __restrict__ spec) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= VP) return;
   const int v = (int)(idx / P);
@@ -137,10 +149,10 @@ preprocess_kernel(const float* __restrict__ means, const float* __restrict__ tan
     } else {
       const float c2x = V.fx * (pc[0] / d) + V.cx;
       const float c2y = V.fy * (pc[1] / d) + V.cy;
-      xmin = ks_min(ks_min(ks_min(ks_min(xs[0], xs[1]), xs[2]), xs[3]), c2x - 2.36f) - 0.01f;
-      xmax = ks_max(ks_max(ks_max(ks_max(xs[0], xs[1]), xs[2]), xs[3]), c2x + 2.36f) + 0.01f;
-      ymin = ks_min(ks_min(ks_min(ks_min(ys[0], ys[1]), ys[2]), ys[3]), c2y - 2.36f) - 0.01f;
-      ymax = ks_max(ks_max(ks_max(ks_max(ys[0], ys[1]), ys[2]), ys[3]), c2y + 2.36f) + 0.01f;
+      xmin = ks_min(ks_min(ks_min(ks_min(xs[0], xs[1]), xs[2]), xs[3]), c2x - r_lp) - 0.01f;
+      xmax = ks_max(ks_max(ks_max(ks_max(xs[0], xs[1]), xs[2]), xs[3]), c2x + r_lp) + 0.01f;
+      ymin = ks_min(ks_min(ks_min(ks_min(ys[0], ys[1]), ys[2]), ys[3]), c2y - r_lp) - 0.01f;
+      ymax = ks_max(ks_max(ks_max(ks_max(ys[0], ys[1]), ys[2]), ys[3]), c2y + r_lp) + 0.01f;
       fi0 = ceilf(xmin - 0.5f);
       fi1 = floorf(xmax - 0.5f);
       fj0 = ceilf(ymin - 0.5f);
@@ -211,9 +223,36 @@ preprocess_kernel(const float* __restrict__ means, const float* __restrict__ tan
   r.view = v;
   r.pad = 0;
   rec[idx] = r;
+
+  // ---- view-dependent colour (diffuse-specular split): sum_j Y_j(dir) sh[k][j] ---------
+  if constexpr (SHD >= 0) {
+    if (n_tiles == 0) return;
+    // camera centre -R^T t; dir = (p - centre) / |p - centre|
+    float d[3];
+    for (int i = 0; i < 3; ++i)
+      d[i] = p_of(i, p0, p1, p2) + (R[i] * V.t[0] + R[3 + i] * V.t[1] + R[6 + i] * V.t[2]);
+    const float inv_len = 1.0f / sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    float Y[kShMaxCoef];
+    sh_basis(SHD, d[0] * inv_len, d[1] * inv_len, d[2] * inv_len, Y);
+    constexpr int n = (SHD + 1) * (SHD + 1);
+    const float* c = sh + (int64_t)k * n * 3;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+      s0 += Y[j] * c[3 * j + 0];
+      s1 += Y[j] * c[3 * j + 1];
+      s2 += Y[j] * c[3 * j + 2];
+    }
+    spec[idx] = make_float4(s0, s1, s2, 0.f);
+  }
 }
 
 }  // namespace
+
+float lowpass_radius(float lowpass_var) {
+  if (lowpass_var <= 0.5f) return 2.36f;
+  return (float)(3.34 * std::sqrt((double)lowpass_var));
+}
 
 hipError_t launch_upload_views(const gb_view* views, int n_views, int tile_w, int tile_h,
                                ViewDev* d_views, hipStream_t s) {
@@ -242,13 +281,26 @@ hipError_t launch_upload_views(const gb_view* views, int n_views, int tile_w, in
 
 hipError_t launch_preprocess(const gb_splats& sp, const ViewDev* d_views, int n_views,
                              const gb_options& o, int tile_w, int tile_h, uint32_t* depth_key,
-                             uint32_t* sort_key, uint32_t* count, SplatRec* rec, hipStream_t s) {
+                             uint32_t* sort_key, uint32_t* count, SplatRec* rec, float4* spec,
+                             hipStream_t s) {
   const int64_t VP = (int64_t)sp.P * n_views;
   const int threads = 256;
   const int64_t blocks = (VP + threads - 1) / threads;
-  hipLaunchKernelGGL(preprocess_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, sp.means,
-                     sp.tan_u, sp.tan_v, sp.scales, sp.opacity, d_views, (int64_t)sp.P, VP,
-                     o.alpha_min, tile_w, tile_h, depth_key, sort_key, count, rec);
+  const float r_lp = lowpass_radius(o.lowpass_var);
+  const int shd = sp.sh ? sp.sh_degree : -1;
+#define GBB_PRE(D)                                                                            \
+  hipLaunchKernelGGL(preprocess_kernel<D>, dim3((unsigned)blocks), dim3(threads), 0, s,        \
+                     sp.means, sp.tan_u, sp.tan_v, sp.scales, sp.opacity, d_views,            \
+                     (int64_t)sp.P, VP, o.alpha_min, r_lp, tile_w, tile_h, depth_key, sort_key, \
+                     count, rec, sp.sh, spec)
+  switch (shd) {
+    case 0: GBB_PRE(0); break;
+    case 1: GBB_PRE(1); break;
+    case 2: GBB_PRE(2); break;
+    case 3: GBB_PRE(3); break;
+    default: GBB_PRE(-1); break;
+  }
+#undef GBB_PRE
   return hipGetLastError();
 }
 

@@ -32,18 +32,40 @@ __device__ __forceinline__ int64_t last_at_or_below(const uint32_t* __restrict__
 }
 
 __global__ void finalize_count_kernel(const uint32_t* __restrict__ offsets, int64_t VP,
-                                      Status* st, int64_t capacity) {
+                                      Status* st, int64_t capacity, StatusEcho echo,
+                                      unsigned long long* mirror, uint32_t* overflow_flag) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     // the exact 64-bit total decides: the 32-bit offsets wrap only when it exceeds 2^32,
     // and the capacity is below that
     const unsigned long long K = st->K64;
     const bool over = K > (unsigned long long)capacity;
     st->overflow = over ? 1u : 0u;
+    st->sticky_overflow |= over ? 1u : 0u;
+    st->n_views = echo.n_views;
+    st->P = echo.P;
+    st->off_count = echo.off_count;
+    st->off_view_pairs = echo.off_view_pairs;
+    // one aligned 8-byte store, so that the host never reads a torn value
+    if (mirror) *reinterpret_cast<volatile unsigned long long*>(mirror) = (over ? 1ull << 63 : 0ull) | K;
+    if (overflow_flag && over) *overflow_flag = 1u;
     st->n_sorted = over ? 0u : (uint32_t)K;
     st->cut = (uint32_t)VP;
     st->last_first = (!over && K > 0) ? (uint32_t)last_at_or_below(offsets, VP, K - 1) : 0u;
     st->any_open = 0u;
   }
+}
+
+// Sum of one view's per-record tile counts (its pair total), one workgroup per view.
+__global__ void __launch_bounds__(256)
+view_pairs_kernel(const uint32_t* __restrict__ count, int64_t P, unsigned long long* out) {
+  __shared__ unsigned long long s_sum[4];
+  const uint32_t* c = count + (int64_t)blockIdx.x * P;
+  unsigned long long acc = 0;
+  for (int64_t i = threadIdx.x; i < P; i += blockDim.x) acc += c[i];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
 }
 
 constexpr int kDupThreads = 256;
@@ -499,8 +521,17 @@ hipError_t launch_order_tiles(const uint32_t* work, int64_t n_tiles, uint32_t* o
 }
 
 hipError_t launch_finalize_count(const uint32_t* offsets, int64_t VP, Status* st,
-                                 int64_t capacity, hipStream_t s) {
-  hipLaunchKernelGGL(finalize_count_kernel, dim3(1), dim3(64), 0, s, offsets, VP, st, capacity);
+                                 int64_t capacity, StatusEcho echo,
+                                 unsigned long long* mirror, uint32_t* overflow_flag,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(finalize_count_kernel, dim3(1), dim3(64), 0, s, offsets, VP, st, capacity,
+                     echo, mirror, overflow_flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_view_pairs(const uint32_t* count, int64_t P, int n_views,
+                             unsigned long long* out, hipStream_t s) {
+  hipLaunchKernelGGL(view_pairs_kernel, dim3((unsigned)n_views), dim3(256), 0, s, count, P, out);
   return hipGetLastError();
 }
 

@@ -48,11 +48,14 @@ def _stream(device) -> int:
 
 
 class Splats:
-    """Device views of the per-splat arrays in the layout the library expects."""
+    """Device views of the per-splat arrays in the layout the library expects. ``sh``
+    (optional, [P, (D+1)^2, 3] float32) holds the spherical-harmonic coefficients of the
+    view-dependent colour term."""
 
-    def __init__(self, means, tan_u, tan_v, scales, opacity, textures):
+    def __init__(self, means, tan_u, tan_v, scales, opacity, textures, sh=None):
         self.means, self.tan_u, self.tan_v = means, tan_u, tan_v
         self.scales, self.opacity, self.textures = scales, opacity, textures
+        self.sh = sh
         for name in ("means", "tan_u", "tan_v", "scales", "opacity"):
             t = getattr(self, name)
             if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
@@ -61,6 +64,14 @@ class Splats:
             raise ValueError("textures must be contiguous float32 or bfloat16 [P,N,N,3]")
         self.P = int(means.shape[0])
         self.N = int(textures.shape[1])
+        self.sh_degree = -1
+        if sh is not None:
+            n = int(sh.shape[1])
+            d = int(round(n ** 0.5)) - 1
+            if (sh.dtype != torch.float32 or not sh.is_contiguous() or sh.dim() != 3
+                    or (d + 1) ** 2 != n or not 0 <= d <= 3 or sh.shape[0] != self.P):
+                raise ValueError("sh must be contiguous float32 [P, (D+1)^2, 3] with D <= 3")
+            self.sh_degree = d
 
     @staticmethod
     def from_numpy(scene, device="cuda", tex_bf16: bool = False) -> "Splats":
@@ -68,14 +79,15 @@ class Splats:
         tex = torch.from_numpy(scene.textures).to(device)
         if tex_bf16:
             tex = tex.to(torch.bfloat16)
+        sh = getattr(scene, "sh", None)
         return Splats(f(scene.means), f(scene.tan_u), f(scene.tan_v), f(scene.scales),
-                      f(scene.opacity), tex)
+                      f(scene.opacity), tex, None if sh is None else f(sh))
 
     def c(self) -> L.GbSplats:
         dt = L.GB_BF16 if self.textures.dtype == torch.bfloat16 else L.GB_F32
         return L.GbSplats(self.P, self.N, dt, _ptr(self.means), _ptr(self.tan_u),
                           _ptr(self.tan_v), _ptr(self.scales), _ptr(self.opacity),
-                          _ptr(self.textures))
+                          _ptr(self.textures), max(self.sh_degree, 0), _ptr(self.sh))
 
 
 class Rasterizer:
@@ -102,6 +114,9 @@ class Rasterizer:
         self.ws: Optional[torch.Tensor] = None
         self.layout = L.GbLayout()
         self.total_pixels = sum(int(v.width) * int(v.height) for v in self.views)
+        # bumped by every forward and view change: a backward must follow the forward whose
+        # workspace contents it reads
+        self.generation = 0
 
     # -- workspace -------------------------------------------------------------------------
     def _layout(self, P: int, N: int, capacity: int) -> L.GbLayout:
@@ -136,11 +151,20 @@ class Rasterizer:
         return capacity
 
     def status(self) -> Tuple[int, bool]:
+        """(pair count, overflow) of the last forward (synchronises)."""
+        K, over, _ = self.status_ex()
+        return K, over
+
+    def status_ex(self, per_view: bool = False):
+        """(pair count, last forward overflowed, some forward since the previous status call
+        overflowed) and, with ``per_view``, the list of per-view pair counts."""
         K = ctypes.c_int64(0)
         ov = ctypes.c_int32(0)
+        kv = (ctypes.c_int64 * self.nv)() if per_view else None
         L.check(self.lib.gb_read_status(self.ws.data_ptr(), ctypes.byref(K), ctypes.byref(ov),
-                                        _stream(self.device)), "gb_read_status")
-        return int(K.value), bool(ov.value)
+                                        kv, self.nv, _stream(self.device)), "gb_read_status")
+        out = (int(K.value), bool(ov.value & 1), bool(ov.value & 2))
+        return out + (list(kv),) if per_view else out
 
     # -- raw calls -------------------------------------------------------------------------
     def forward(self, sp: Splats, rgb: Optional[torch.Tensor] = None,
@@ -151,12 +175,17 @@ class Rasterizer:
             rgb = torch.empty((self.total_pixels, 3), dtype=torch.float32, device=self.device)
         if T_final is None:
             T_final = torch.empty((self.total_pixels,), dtype=torch.float32, device=self.device)
+        self.generation += 1
         for _ in range(3):
-            L.check(self.lib.gb_render_fwd(ctypes.byref(sp.c()), self.cviews, self.nv,
-                                           ctypes.byref(self.copts), self.ws.data_ptr(),
-                                           self.ws.numel(), self.capacity, rgb.data_ptr(),
-                                           T_final.data_ptr(), _stream(self.device)),
-                    "gb_render_fwd")
+            st = self.lib.gb_render_fwd(ctypes.byref(sp.c()), self.cviews, self.nv,
+                                        ctypes.byref(self.copts), self.ws.data_ptr(),
+                                        self.ws.numel(), self.capacity, rgb.data_ptr(),
+                                        T_final.data_ptr(), _stream(self.device))
+            if st == L.GB_ERR_CAPACITY and self.check_overflow:
+                # an earlier forward on this workspace overflowed: count again and re-size
+                self.plan(sp)
+                continue
+            L.check(st, "gb_render_fwd")
             if not self.check_overflow:
                 break
             K, over = self.status()
@@ -171,9 +200,12 @@ class Rasterizer:
             grads = dict(means=z(sp.P, 3), tan_u=z(sp.P, 3), tan_v=z(sp.P, 3),
                          scales=z(sp.P, 2), opacity=z(sp.P),
                          textures=z(sp.P, sp.N, sp.N, 3))
+        if sp.sh is not None and grads.get("sh") is None:
+            grads["sh"] = torch.empty_like(sp.sh)
         d_rgb = d_rgb.contiguous().float()
         g = L.GbGrads(_ptr(grads["means"]), _ptr(grads["tan_u"]), _ptr(grads["tan_v"]),
-                      _ptr(grads["scales"]), _ptr(grads["opacity"]), _ptr(grads["textures"]))
+                      _ptr(grads["scales"]), _ptr(grads["opacity"]), _ptr(grads["textures"]),
+                      _ptr(grads.get("sh")) if sp.sh is not None else None)
         L.check(self.lib.gb_render_bwd(ctypes.byref(sp.c()), self.cviews, self.nv,
                                        ctypes.byref(self.copts), self.ws.data_ptr(),
                                        self.ws.numel(), self.capacity, T_final.data_ptr(),
@@ -186,6 +218,7 @@ class Rasterizer:
         before, the workspace layout is unchanged and is kept (the capacity is re-planned on
         overflow when check_overflow is set); otherwise the next forward plans again."""
         views = list(views)
+        self.generation += 1
         same = [(v.width, v.height) for v in views] == [(v.width, v.height) for v in self.views]
         self.views = views
         self.cviews = L.make_views(views)
@@ -254,11 +287,16 @@ class Rasterizer:
 
 class _RenderFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, rast: Rasterizer, means, tan_u, tan_v, scales, opacity, textures):
+    def forward(ctx, rast: Rasterizer, means, tan_u, tan_v, scales, opacity, textures, sh):
         sp = Splats(means.detach(), tan_u.detach(), tan_v.detach(), scales.detach(),
-                    opacity.detach(), textures.detach())
+                    opacity.detach(), textures.detach(), None if sh is None else sh.detach())
         rgb, T = rast.forward(sp)
         ctx.rast, ctx.sp = rast, sp
+        # the backward reads the pair lists and per-pixel state this forward left in the
+        # rasterizer's workspace: remember which forward that was
+        ctx.generation = rast.generation
+        ctx.ws_ptr = rast.ws.data_ptr()
+        ctx.total_pixels = rast.total_pixels
         ctx.save_for_backward(T)
         ctx.mark_non_differentiable(T)
         return rgb, T
@@ -266,13 +304,28 @@ class _RenderFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, d_rgb, d_T):
         (T,) = ctx.saved_tensors
-        g = ctx.rast.backward(ctx.sp, T, d_rgb)
+        rast = ctx.rast
+        if (rast.generation != ctx.generation or rast.ws is None
+                or rast.ws.data_ptr() != ctx.ws_ptr or rast.total_pixels != ctx.total_pixels):
+            raise RuntimeError(
+                "render(): the Rasterizer ran another forward (or changed views) after this "
+                "render and before its backward, so the workspace no longer holds this render's "
+                "state; call backward first or give each pending render its own Rasterizer")
+        if d_rgb is None:
+            d_rgb = torch.zeros((ctx.total_pixels, 3), dtype=torch.float32, device=T.device)
+        g = rast.backward(ctx.sp, T, d_rgb)
         dtex = g["textures"]
         if ctx.sp.textures.dtype != torch.float32:
             dtex = dtex.to(ctx.sp.textures.dtype)
-        return None, g["means"], g["tan_u"], g["tan_v"], g["scales"], g["opacity"], dtex
+        return (None, g["means"], g["tan_u"], g["tan_v"], g["scales"], g["opacity"], dtex,
+                g.get("sh"))
 
 
-def render(rast: Rasterizer, means, tan_u, tan_v, scales, opacity, textures):
-    """Differentiable render of all of ``rast``'s views: returns rgb [sum HW, 3] and T_final."""
-    return _RenderFn.apply(rast, means, tan_u, tan_v, scales, opacity, textures)
+def render(rast: Rasterizer, means, tan_u, tan_v, scales, opacity, textures, sh=None):
+    """Differentiable render of all of ``rast``'s views: returns rgb [sum HW, 3] and T_final.
+    ``sh`` (optional, [P, (D+1)^2, 3]) adds the per-splat view-dependent colour term.
+
+    The backward reads state that the forward leaves in ``rast``'s workspace, so each render
+    must be differentiated before ``rast`` renders again (a later forward raises in the
+    earlier render's backward)."""
+    return _RenderFn.apply(rast, means, tan_u, tan_v, scales, opacity, textures, sh)

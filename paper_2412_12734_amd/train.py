@@ -8,9 +8,11 @@ rasterizer and the activations and applies Adam to every parameter group. With b
 textures the Adam step also rewrites the bfloat16 render copy of the float32 master textures.
 For fitting a single image (Sec. 4) the loss is the mean squared error and the splats rotate
 about the camera's Z axis only (``rotz_only``); ``box_filter_textures`` downsamples fitted
-colour grids as the paper does to show that they carry the image. Every step runs in libgbb
-kernels; torch supplies memory and the stream. Densification, pruning and the SSIM term are
-not part of it.
+colour grids as the paper does to show that they carry the image. ``TrainState.densify``
+applies densification and pruning (clone, split with resampled colour grids, opacity and size
+pruning) from the screen-space gradient statistic the Trainer accumulates after each backward.
+Every step runs in libgbb kernels; torch supplies memory and the stream. The SSIM term is not
+part of it.
 """
 from __future__ import annotations
 
@@ -20,6 +22,7 @@ from typing import Dict, Optional, Sequence
 import torch
 
 from . import _lib as L
+from ._lib import GbbError
 from .render import Options, Rasterizer, Splats, _stream
 
 # learning rates per parameter group (not given by the paper; only their cost matters here)
@@ -88,6 +91,59 @@ class TrainState:
         r["textures"] = grads["textures"]
         return r
 
+    def raw(self, params: Optional[Dict[str, torch.Tensor]] = None) -> L.GbRawSplats:
+        p = params or self.params
+        P = int(p["means"].shape[0])
+        return L.GbRawSplats(P, self.N, 0, _p(p["means"]), _p(p["quats"]), _p(p["log_scales"]),
+                             _p(p["opacity_logits"]), _p(p["textures"]), None)
+
+    def densify(self, grad_accum: torch.Tensor, vis_count: torch.Tensor,
+                options: Optional["DensifyOptions"] = None, noise: Optional[torch.Tensor] = None,
+                sigma: float = 0.5, generator: Optional[torch.Generator] = None) -> int:
+        """Densification and pruning from the accumulated statistic (one host synchronisation
+        for the new count). Replaces the parameters, their Adam moments (kept rows copied, new
+        rows zero), the activated copies and the bfloat16 texture copy. ``noise`` ([P, 2, 2]
+        N(0, 1), the split children's offsets in units of the parent's scales) is drawn on the
+        device when not given. Returns the new number of splats."""
+        o = (options or DensifyOptions()).c()
+        P = self.P
+        work = torch.empty(int(self.lib.gb_densify_work_bytes(P)), dtype=torch.uint8,
+                           device=self.device)
+        P_new = ctypes.c_int64(0)
+        src = self.raw()
+        L.check(self.lib.gb_densify_plan(ctypes.byref(src), _p(grad_accum), _p(vis_count),
+                                         ctypes.byref(o), _p(work), work.numel(),
+                                         ctypes.byref(P_new), self.stream()), "gb_densify_plan")
+        n = int(P_new.value)
+        if noise is None:
+            noise = torch.randn((P, 2, 2), dtype=torch.float32, device=self.device,
+                                generator=generator)
+        new = {g: torch.empty((n,) + tuple(t.shape[1:]), dtype=torch.float32, device=self.device)
+               for g, t in self.params.items()}
+        new_m = {g: torch.empty_like(t) for g, t in new.items()}
+        new_v = {g: torch.empty_like(t) for g, t in new.items()}
+        rows = []
+        for g in GROUPS:
+            w = int(self.params[g][0].numel()) if P > 0 else 1
+            rows.append(L.GbRowState(_p(self.m[g]), _p(new_m[g]), w))
+            rows.append(L.GbRowState(_p(self.v[g]), _p(new_v[g]), w))
+        states = (L.GbRowState * len(rows))(*rows)
+        dst = self.raw(new)
+        L.check(self.lib.gb_densify_apply(ctypes.byref(src), _p(work), _p(noise.contiguous()),
+                                          float(sigma), ctypes.byref(o), ctypes.byref(dst),
+                                          states, len(rows), self.stream()), "gb_densify_apply")
+        self.params, self.m, self.v = new, new_m, new_v
+        self.raw_grads = {g: torch.zeros_like(t) for g, t in new.items()}
+        self.P = n
+        z = lambda *s: torch.empty(s, dtype=torch.float32, device=self.device)
+        self.tan_u, self.tan_v, self.scales, self.opacity = z(n, 3), z(n, 3), z(n, 2), z(n)
+        if self.bf16:
+            tex = self.params["textures"]
+            self.tex_bits = torch.empty(tex.shape, dtype=torch.int16, device=self.device)
+            L.check(self.lib.gb_to_bf16(tex.numel(), _p(tex), _p(self.tex_bits), self.stream()),
+                    "gb_to_bf16")
+        return n
+
     def adam(self, raw_grads: Dict[str, torch.Tensor]) -> None:
         self.step_count += 1
         b1, b2 = self.betas
@@ -127,6 +183,20 @@ def box_filter_textures(textures: torch.Tensor, M: int) -> torch.Tensor:
     return out
 
 
+class DensifyOptions:
+    """Densification and pruning thresholds (gb_densify_options): the statistic threshold,
+    the clone/split scale, the pruning opacity and scale (0: off) and the split shrink."""
+
+    def __init__(self, grad_threshold=0.0002, dense_scale=0.01, min_opacity=0.005,
+                 max_scale=0.0, split_shrink=1.6):
+        self.grad_threshold, self.dense_scale = grad_threshold, dense_scale
+        self.min_opacity, self.max_scale, self.split_shrink = min_opacity, max_scale, split_shrink
+
+    def c(self) -> L.GbDensifyOptions:
+        return L.GbDensifyOptions(self.grad_threshold, self.dense_scale, self.min_opacity,
+                                  self.max_scale, self.split_shrink)
+
+
 class Trainer:
     """One optimisation step per call on a batch of views with target images.
 
@@ -144,6 +214,30 @@ class Trainer:
         self.loss = torch.zeros(1, dtype=torch.float32, device=state.device)
         self.bufs = None
         self.grads = None
+        # densification statistic, accumulated after every backward once enabled
+        self.grad_accum: Optional[torch.Tensor] = None
+        self.vis_count: Optional[torch.Tensor] = None
+
+    def track_densify(self, on: bool = True) -> None:
+        """Start (or stop) accumulating the densification statistic of every step."""
+        if on:
+            self.grad_accum = torch.zeros(self.state.P, dtype=torch.float32,
+                                          device=self.state.device)
+            self.vis_count = torch.zeros_like(self.grad_accum)
+        else:
+            self.grad_accum = self.vis_count = None
+
+    def densify(self, options: Optional[DensifyOptions] = None,
+                noise: Optional[torch.Tensor] = None, generator=None) -> int:
+        """Densify and prune from the statistic accumulated since the last call, reset it and
+        drop the buffers sized for the old splat count. Returns the new count."""
+        if self.grad_accum is None:
+            raise RuntimeError("call track_densify() before training steps to densify")
+        n = self.state.densify(self.grad_accum, self.vis_count, options, noise,
+                               generator=generator)
+        self.grads = None
+        self.track_densify(True)
+        return n
 
     def _use(self, batch: Sequence[int]) -> None:
         views = [self.views[i] for i in batch]
@@ -167,7 +261,9 @@ class Trainer:
         return cap
 
     def overflowed(self) -> bool:
-        return self.rast is not None and self.rast.status()[1]
+        """Whether some step since the previous call overflowed its pair capacity (such a
+        step rendered background and took no gradient). Synchronises."""
+        return self.rast is not None and self.rast.status_ex()[2]
 
     def step(self, batch: Sequence[int]) -> torch.Tensor:
         st = self.state
@@ -178,7 +274,14 @@ class Trainer:
             z = lambda *s: torch.empty(s, dtype=torch.float32, device=st.device)
             self.bufs = (z(n_px, 3), z(n_px), z(n_px, 3), z(n_px, 3))
         rgb, T, target, d_rgb = self.bufs
-        rgb, T = self.rast.forward(sp, rgb, T)
+        try:
+            rgb, T = self.rast.forward(sp, rgb, T)
+        except GbbError as e:
+            if e.status != L.GB_ERR_CAPACITY:
+                raise
+            # a completed earlier step overflowed: re-size for this batch and render again
+            self.rast.plan(sp, int(self.rast.count_pairs(sp) * 1.5) + 4096)
+            rgb, T = self.rast.forward(sp, rgb, T)
         at = 0
         for i in batch:  # device-to-device copies of the batch's target images
             hw = self.views[i].width * self.views[i].height
@@ -186,5 +289,12 @@ class Trainer:
             at += hw
         self.loss_fn(rgb, target, 1.0 / (3 * n_px), self.loss, d_rgb)
         self.grads = self.rast.backward(sp, T, d_rgb, self.grads)
+        if self.grad_accum is not None:
+            r = self.rast
+            L.check(r.lib.gb_densify_stats(ctypes.byref(sp.c()), r.cviews, r.nv,
+                                           ctypes.byref(r.copts), r.ws.data_ptr(), r.ws.numel(),
+                                           r.capacity, self.grad_accum.data_ptr(),
+                                           self.vis_count.data_ptr(), st.stream()),
+                    "gb_densify_stats")
         st.adam(st.backward_activations(self.grads))
         return self.loss

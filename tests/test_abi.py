@@ -41,7 +41,10 @@ def test_struct_sizes_match_header_layout():
     # gb_view: 2 ints + 4 floats + 9 + 3 + 1 floats
     assert ctypes.sizeof(L.GbView) == 4 * (2 + 4 + 9 + 3 + 1)
     assert ctypes.sizeof(L.GbOptions) == 4 * (5 + 3 + 6)
-    assert ctypes.sizeof(L.GbSplats) == 16 + 6 * 8
+    # P, N, tex_dtype, pad, six pointers, sh_degree, pad, one pointer
+    assert ctypes.sizeof(L.GbSplats) == 16 + 6 * 8 + 8 + 8
+    assert L.GbSplats.sh.offset == 16 + 6 * 8 + 8
+    assert ctypes.sizeof(L.GbGrads) == 7 * 8
     assert ctypes.sizeof(L.GbLayout) == 8 * 20
 
 
@@ -172,3 +175,55 @@ def test_image_fitting_glue_rejects_invalid_arguments_before_any_launch():
     assert lib.gb_rotz_only(-1, p16, None) == L.GB_ERR_ARG
     assert lib.gb_rotz_only(3, None, None) == L.GB_ERR_ARG
     assert lib.gb_rotz_only(0, None, None) == L.GB_OK
+
+
+def test_total_pixels_must_stay_below_2_31():
+    """Packed pixel indices are int32 on the device: views whose pixels add up to 2^31 or more
+    are refused on the host (three 32767 x 32767 views hold 3.2e9 pixels)."""
+    big = [sg.look_at_view((0, 0, -3), 32767, 32767) for _ in range(3)]
+    st, _ = _layout(P=10, views=big, cap=0)
+    assert st == L.GB_ERR_ARG
+    assert b"2^31" in _lib().gb_last_error()
+    one_pass = L.make_options(prefix_pairs_per_tile=-1)  # (the prefix slots would not fit)
+    assert _layout(P=10, views=big[:2], opts=one_pass, cap=0)[0] == L.GB_OK  # 2.1e9 < 2^31
+
+
+def test_read_status_rejects_null_and_misaligned_arguments():
+    lib = _lib()
+    K = ctypes.c_int64(0)
+    ov = ctypes.c_int32(0)
+    assert lib.gb_read_status(None, ctypes.byref(K), ctypes.byref(ov), None, 1, None) == L.GB_ERR_ARG
+    buf = ctypes.create_string_buffer(1024)
+    base = ctypes.addressof(buf)
+    p256 = base + (-base) % 256
+    assert lib.gb_read_status(p256 + 4, ctypes.byref(K), ctypes.byref(ov), None, 1,
+                              None) == L.GB_ERR_ARG
+    assert lib.gb_read_status(p256, None, ctypes.byref(ov), None, 1, None) == L.GB_ERR_ARG
+
+
+def test_densify_entry_points_check_arguments_before_any_launch():
+    lib = _lib()
+    assert lib.gb_densify_work_bytes(1000) >= 4 * 5 * 1000
+    assert lib.gb_densify_work_bytes(-1) == 0
+    o = L.GbDensifyOptions(2e-4, 0.01, 0.005, 0.0, 1.6)
+    P = ctypes.c_int64(0)
+    buf = ctypes.create_string_buffer(1 << 16)
+    base = ctypes.addressof(buf)
+    p256 = base + (-base) % 256
+    raw = L.GbRawSplats(10, 4, 0, p256, p256, p256, p256, p256, None)
+    assert lib.gb_densify_plan(None, p256, p256, ctypes.byref(o), p256, 1 << 15,
+                               ctypes.byref(P), None) == L.GB_ERR_ARG
+    bad = L.GbDensifyOptions(2e-4, 0.01, 0.005, 0.0, 0.5)  # split_shrink < 1
+    assert lib.gb_densify_plan(ctypes.byref(raw), p256, p256, ctypes.byref(bad), p256, 1 << 15,
+                               ctypes.byref(P), None) == L.GB_ERR_ARG
+    assert lib.gb_densify_plan(ctypes.byref(raw), p256, p256, ctypes.byref(o), p256, 16,
+                               ctypes.byref(P), None) == L.GB_ERR_ARG  # work buffer too small
+    empty = L.GbRawSplats(0, 4, 0, None, None, None, None, None, None)
+    assert lib.gb_densify_plan(ctypes.byref(empty), None, None, ctypes.byref(o), p256, 1 << 15,
+                               ctypes.byref(P), None) == L.GB_OK and P.value == 0
+    big = L.GbRawSplats(21, 4, 0, p256, p256, p256, p256, p256, None)
+    assert lib.gb_densify_apply(ctypes.byref(raw), p256, p256, 0.5, ctypes.byref(o),
+                                ctypes.byref(big), None, 0, None) == L.GB_ERR_ARG
+    other_n = L.GbRawSplats(10, 8, 0, p256, p256, p256, p256, p256, None)
+    assert lib.gb_densify_apply(ctypes.byref(raw), p256, p256, 0.5, ctypes.byref(o),
+                                ctypes.byref(other_n), None, 0, None) == L.GB_ERR_ARG

@@ -66,7 +66,26 @@ def image_crop(arr, base, W, H, crop, ch=3):
     return a[y0:y0 + h, x0:x0 + w]
 
 
-def assert_image_parity(rgb_gpu, T_gpu, ref: O.RenderResult, base, W, H,
+def assert_flagged_pixels(g_rgb, g_T, ref: O.RenderResult, flagged, scene, view, opts):
+    """Every flagged pixel must equal, within the image bar, one of the outcomes the oracle
+    enumerates for its in-band decisions taken either way; with more in-band decisions than
+    the enumeration takes, its colour must stay within the oracle's bound for them."""
+    worst = 0.0
+    for j, i in zip(*np.nonzero(flagged)):
+        outs = O.flagged_outcomes(scene, view, opts, ref, int(j), int(i))
+        if outs is not None:
+            best = min(max(float(np.abs(g_rgb[j, i] - rgb).max()), abs(float(g_T[j, i]) - T))
+                       for rgb, T in outs)
+            assert best <= IMG_TOL, (f"flagged pixel (x={i + ref.crop[0]}, y={j + ref.crop[1]}) "
+                                     f"matches none of {len(outs)} outcomes: {best:.3g}")
+            worst = max(worst, best)
+        else:
+            b = O.flagged_bound(scene, ref, int(j), int(i), opts.bg)
+            assert float(np.abs(g_rgb[j, i] - ref.rgb[j, i]).max()) <= b + IMG_TOL
+    return worst
+
+
+def assert_image_parity(rgb_gpu, T_gpu, ref: O.RenderResult, base, W, H, scene, view, opts,
                         max_flagged=MAX_FLAGGED_FRACTION):
     crop = ref.crop
     g_rgb = image_crop(rgb_gpu, base, W, H, crop).astype(np.float64)
@@ -84,7 +103,8 @@ def assert_image_parity(rgb_gpu, T_gpu, ref: O.RenderResult, base, W, H,
               f"{ref.alpha_gap[j, i]:.3g} t_gap {ref.t_gap[j, i]:.3g}")
     assert d.max(initial=0) <= IMG_TOL, f"max image error {d.max()}"
     assert dT.max(initial=0) <= IMG_TOL, f"max transmittance error {dT.max()}"
-    return float(d.max(initial=0)), flagged
+    fl_err = assert_flagged_pixels(g_rgb, g_T, ref, ~ok, scene, view, opts)
+    return max(float(d.max(initial=0)), fl_err), flagged
 
 
 # --- key stage, pairs, ranges: bit-exact --------------------------------------------------
@@ -146,7 +166,8 @@ def test_image_parity_config1_full_frame(gb):
     opts = O.Options()
     rast, sp, rgb, T = run_gpu(gb, scene, views, opts)
     ref = O.render(scene, views[0], opts)
-    err, flagged = assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 128, 128)
+    err, flagged = assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 128, 128,
+                                       scene, views[0], opts)
     print(f"config1 image max err {err:.3g}, flagged {flagged}")
 
 
@@ -163,7 +184,7 @@ def test_image_parity_tiny_scenes(gb, seed):
     opts = O.Options(tile_w=tile[0], tile_h=tile[1], bg=bg)
     rast, sp, rgb, T = run_gpu(gb, scene, [view], opts)
     ref = O.render(scene, view, opts)
-    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, W, H)
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, W, H, scene, view, opts)
 
 
 @pytest.mark.parametrize("W,H", [(1, 1), (1, 37), (41, 2), (7, 5), (17, 9)])
@@ -175,7 +196,7 @@ def test_degenerate_view_sizes(gb, W, H):
     opts = O.Options()
     rast, sp, rgb, T = run_gpu(gb, scene, [view], opts)
     ref = O.render(scene, view, opts)
-    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, W, H)
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, W, H, scene, view, opts)
     check_grads(gb, scene, view, opts, (0, 0, W, H), seed=W * 100 + H)
 
 
@@ -185,7 +206,7 @@ def test_image_parity_thresholds_off(gb):
     opts = O.Options(alpha_min=0.0, t_min=0.0, alpha_max=1.0, bg=(0.3, 0.2, 0.1))
     rast, sp, rgb, T = run_gpu(gb, scene, [view], opts)
     ref = O.render(scene, view, opts)
-    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 40, 30)
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 40, 30, scene, view, opts)
 
 
 def test_image_parity_config2_crops(gb):
@@ -195,7 +216,7 @@ def test_image_parity_config2_crops(gb):
     rgb, T = rgb.cpu().numpy(), T.cpu().numpy()
     for crop in [(368, 368, 64, 64), (0, 0, 48, 40), (760, 750, 40, 50)]:
         ref = O.render(scene, views[0], opts, crop=crop)
-        assert_image_parity(rgb, T, ref, 0, 800, 800)
+        assert_image_parity(rgb, T, ref, 0, 800, 800, scene, views[0], opts)
 
 
 # --- gradients ------------------------------------------------------------------------------
@@ -220,7 +241,10 @@ def check_grads(gb, scene, view, opts, crop, seed=0, tex_bf16=False, batch=0, ba
     grads = rast.backward(sp, T, d_rgb)
     torch.cuda.synchronize()
     errs, p999 = {}, {}
-    for name in ("means", "tan_u", "tan_v", "scales", "opacity", "textures"):
+    names = ("means", "tan_u", "tan_v", "scales", "opacity", "textures")
+    if scene.sh is not None:
+        names = names + ("sh",)
+    for name in names:
         got = grads[name].cpu().numpy().astype(np.float64)
         want = getattr(ref_g, name)
         errs[name] = rel_l2(got, want)
@@ -263,9 +287,11 @@ def test_gradient_parity_config2_crop(gb):
 # (and at flagged pixels) on both sides, so every splat gradient is comparable: the splats the
 # oracle blended inside the crop are compared by relative L2, and the GPU gradient of every
 # other splat must carry no more than a 1e-6 share of the energy.
-def check_full_size_crop(gb, name, vi, seed=0):
+def check_full_size_crop(gb, name, vi, seed=0, sh_degree=None):
     import scenegen as sgm
     scene, views = sg.config(name)
+    if sh_degree is not None:
+        scene = sg.with_sh(scene, 99, sh_degree)
     bf16 = sgm.CONFIGS[name]["bf16"]
     opts = O.Options()
     sp = gb.Splats.from_numpy(scene, tex_bf16=bf16)
@@ -279,6 +305,7 @@ def check_full_size_crop(gb, name, vi, seed=0):
     crop = ((W - 64) // 2, (H - 64) // 2, 64, 64)
     ref = O.render(scene, view, opts, crop=crop, keep_saved=True)
     img_err, flagged = assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, base, W, H,
+                                           scene, view, opts,
                                            max_flagged=MAX_FLAGGED_FRACTION_DENSE)
     x0, y0, w, h = crop
     g_view = sg.make_dl_drgb(seed, [view]).reshape(H, W, 3)
@@ -294,7 +321,10 @@ def check_full_size_crop(gb, name, vi, seed=0):
     ks = np.unique(np.array([k for k, _, _, _ in ref.saved], dtype=np.int64))
     idx = torch.from_numpy(ks).cuda()
     errs = {}
-    for gname in ("means", "tan_u", "tan_v", "scales", "opacity", "textures"):
+    gnames = ("means", "tan_u", "tan_v", "scales", "opacity", "textures")
+    if scene.sh is not None:
+        gnames = gnames + ("sh",)
+    for gname in gnames:
         full = grads[gname]
         got = full[idx].double()
         want = getattr(ref_g, gname)[ks]
@@ -407,7 +437,7 @@ def test_n16_image_and_gradients_match_oracle(gb, bf16):
     opts = O.Options()
     rast, sp, rgb, T = run_gpu(gb, scene, [view], opts, tex_bf16=bf16)
     ref = O.render(scene, view, opts, crop=(24, 16, 48, 40))
-    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 96, 80)
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 96, 80, scene, view, opts)
     check_grads(gb, scene, view, opts, (32, 24, 32, 32), seed=7, tex_bf16=bf16)
 
 
@@ -501,7 +531,8 @@ def test_split_image_matches_oracle(gb):
     scene, view = dense_scene(N=8)
     rast, sp, rgb, T = run_gpu(gb, scene, [view], O.Options(), prefix=16)
     ref = O.render(scene, view, O.Options(), crop=(40, 32, 48, 32))
-    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 128, 96)
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 128, 96, scene, view,
+                        O.Options())
 
 
 # --- work order of the tiles: a schedule, not a change of any result -------------------------
@@ -585,7 +616,8 @@ def test_autotuned_options_keep_parity(gb, tmp_path):
     rast.plan(sp)
     rgb, T = rast.forward(sp)
     ref = O.render(scene, view, O.Options(), crop=(48, 36, 64, 48))
-    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 160, 120)
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 160, 120, scene, view,
+                        O.Options())
     opts2, rec2 = at.autotune(sp, [view], cache_path=path, knobs=knobs)
     assert opts2 == opts  # second call served from the cache
 
@@ -637,7 +669,8 @@ def test_bf16_textures_match_oracle_on_rounded_texels(gb):
     rounded = sg.bf16_bits_to_f32(sg.to_bf16_bits(scene.textures)).reshape(scene.textures.shape)
     s = sg.Scene(scene.means, scene.tan_u, scene.tan_v, scene.scales, scene.opacity, rounded)
     ref = O.render(s, views[0], O.Options())
-    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 128, 128)
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 128, 128, s, views[0],
+                        O.Options())
 
 
 # --- batching: many views in one launch sequence --------------------------------------------
@@ -671,7 +704,50 @@ def test_capacity_overflow_is_reported_then_replanned(gb):
     K2, over2 = rast.status()
     assert not over2 and K2 == K
     ref = O.render(scene, views[0], O.Options())
-    assert_image_parity(rgb2.cpu().numpy(), T2.cpu().numpy(), ref, 0, 128, 128)
+    assert_image_parity(rgb2.cpu().numpy(), T2.cpu().numpy(), ref, 0, 128, 128, scene, views[0],
+                        O.Options())
+
+
+def test_capacity_error_on_a_later_forward_and_per_view_counts(gb):
+    """Through the C ABI: a forward that overflows its capacity sets the overflow flag; once
+    it has completed, the next forward on the workspace with the same capacity returns
+    GB_ERR_CAPACITY without launching, and one with a capacity that fits runs. The status call
+    reports the sticky overflow once and the pair count of every view, which must equal the
+    oracle's key-stage counts."""
+    import ctypes
+    from paper_2412_12734_amd import _lib as L
+    scene = sg.make_scene(17, 2000, -1.0, 1.0, 0.02, 0.3, 4)
+    views = [sg.look_at_view((0.0, 0.0, -3.0), 80, 60), sg.look_at_view((1.5, 0.5, -2.5), 48, 64),
+             sg.look_at_view((-2.0, 1.0, -1.0), 33, 21)]
+    sp = gb.Splats.from_numpy(scene)
+    rast = gb.Rasterizer(views, gpu_opts(O.Options()), check_overflow=False)
+    rast.plan(sp, capacity=64)
+    lib = L.load()
+    rgb, T = rast.forward(sp)
+    torch.cuda.synchronize()
+
+    def fwd(cap):
+        return lib.gb_render_fwd(ctypes.byref(sp.c()), rast.cviews, rast.nv,
+                                 ctypes.byref(rast.copts), rast.ws.data_ptr(), rast.ws.numel(),
+                                 cap, rgb.data_ptr(), T.data_ptr(),
+                                 torch.cuda.current_stream().cuda_stream)
+
+    assert fwd(64) == L.GB_ERR_CAPACITY
+    assert b"needed" in lib.gb_last_error()
+    K, over_last, over_any, per_view = rast.status_ex(per_view=True)
+    want = [int(O.key_stage(scene, v, O.Options())["count"].sum()) for v in views]
+    assert per_view == want and K == sum(want) and over_last and over_any
+    # the sticky bit is reported once; the overflow of the last forward stays visible
+    assert rast.status_ex() == (K, True, False)
+    assert fwd(64) == L.GB_ERR_CAPACITY  # still too small (status calls do not clear it)
+    rast.plan(sp, capacity=K)  # fits exactly (same workspace or a larger one)
+    assert fwd(K) == L.GB_OK
+    torch.cuda.synchronize()
+    assert rast.status_ex() == (K, False, False)
+    ref = O.render(scene, views[2], O.Options())
+    base = 80 * 60 + 48 * 64
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, base, 33, 21, scene, views[2],
+                        O.Options())
 
 
 def test_all_splats_culled_gives_background(gb):
@@ -708,3 +784,125 @@ def test_gradients_with_small_and_large_splats(gb, s_lo, s_hi):
     scene = sg.make_scene(41, 3000, -1.0, 1.0, s_lo, s_hi, 8)
     view = sg.look_at_view((0.0, 0.0, -3.0), 96, 80)
     check_grads(gb, scene, view, O.Options(), (0, 0, 96, 80), seed=3)
+
+
+# --- full-size tiling: every record and every pair of the 1M-splat 1080p workload -------------
+def test_tiling_bit_exact_full_size_t0(gb):
+    """Depth keys, tile counts and rectangles of all 1M records, then all (tile, record) pairs
+    (one pass, about 43M) and every tile's range, against the oracle's key stage and its
+    vectorised pair expansion."""
+    scene, views = sg.config("T0")
+    opts = O.Options()
+    rast, sp, rgb, T = run_gpu(gb, scene, views, opts, prefix=-1)
+    P = scene.P
+    ks = O.key_stage(scene, views[0], opts)
+    vis = ks["visible"]
+    depth = rast.section("depth_key", P, torch.int32).cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(depth, np.where(vis, ks["depth"].view(np.uint32),
+                                                  np.uint32(0xFFFFFFFF)))
+    count = rast.section("tile_count", P, torch.int32).cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(count, ks["count"].astype(np.uint32))
+    recs = rast.section("records", P * 24, torch.int32).cpu().numpy().reshape(P, 24)
+    rx, ry = recs[:, 19], recs[:, 20]
+    got = np.stack([rx & 0xFFFF, rx >> 16, ry & 0xFFFF, ry >> 16], 1)[vis]
+    np.testing.assert_array_equal(got, ks["rect"][vis])
+    del recs, got
+    keys, vals, ranges = O.tile_pairs_vectorised(scene, views, opts)
+    K, over = rast.status()
+    print(f"T0: {int(vis.sum())} visible records, {K} pairs")
+    assert not over and K == keys.size
+    gk = rast.section("pair_keys", K, torch.int32).cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(gk, keys)
+    del gk
+    gv = rast.section("pair_vals", K, torch.int32).cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(gv, vals)
+    del gv
+    gr = rast.section("ranges", 2 * ranges.shape[0], torch.int32).cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(gr.reshape(-1, 2).astype(np.int64), ranges)
+
+
+# --- screen-space low-pass of any variance: tile bound, images and gradients ------------------
+@pytest.mark.parametrize("var", [1.0, 2.0])
+def test_lowpass_variance_parity(gb, var):
+    """Sub-pixel and ordinary splats with a wider low-pass than the default: the tile
+    rectangles (whose low-pass radius follows the variance) are bit-exact and the images and
+    gradients match the oracle."""
+    small = sg.make_scene(61, 1500, -1.0, 1.0, 5e-4, 4e-3, 4)
+    big = sg.make_scene(62, 300, -1.0, 1.0, 0.02, 0.2, 4)
+    scene = sg.Scene(*(np.ascontiguousarray(np.concatenate([a, b])) for a, b in
+                       zip((small.means, small.tan_u, small.tan_v, small.scales, small.opacity,
+                            small.textures),
+                           (big.means, big.tan_u, big.tan_v, big.scales, big.opacity,
+                            big.textures))))
+    view = sg.look_at_view((0.1, -0.2, -3.0), 96, 72)
+    opts = O.Options(lowpass_var=var)
+    check_tiling(gb, scene, [view], opts)
+    rast, sp, rgb, T = run_gpu(gb, scene, [view], opts)
+    ref = O.render(scene, view, opts)
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 96, 72, scene, view, opts)
+    check_grads(gb, scene, view, opts, (16, 8, 48, 40), seed=11)
+
+
+# --- wide and tall tiles (32 x 8, 8 x 32) -------------------------------------------------------
+@pytest.mark.parametrize("tile", [(32, 8), (8, 32)])
+def test_wide_and_tall_tiles(gb, tile):
+    scene = sg.make_scene(5, 3000, -1.5, 1.5, 0.01, 0.3, 8)
+    views = [sg.look_at_view((0.5, 0.3, -3.0), 97, 61), sg.look_at_view((-2.0, 1.0, -2.0), 64, 80)]
+    opts = O.Options(tile_w=tile[0], tile_h=tile[1])
+    check_tiling(gb, scene, views, opts)
+    rast, sp, rgb, T = run_gpu(gb, scene, views, opts)
+    ref = O.render(scene, views[1], opts)
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 97 * 61, 64, 80, scene, views[1],
+                        opts)
+    check_grads(gb, scene, views[0], opts, (20, 10, 50, 40), seed=13)
+
+
+# --- 16 x 16 colour grids at full size: a 64 x 64 crop of 1M splats at 1080p -------------------
+def test_n16_full_size_crop_parity(gb):
+    check_full_size_crop(gb, "T0_N16", 0)
+
+
+# --- diffuse-specular split (Sec. 4.2): per-splat spherical harmonics ---------------------------
+@pytest.mark.parametrize("degree,N", [(0, 4), (1, 2), (3, 8)])
+def test_specular_sh_image_and_gradients(gb, degree, N):
+    scene = sg.with_sh(sg.make_scene(71, 2000, -1.0, 1.0, 0.02, 0.3, N), 5, degree, scale=0.3)
+    view = sg.look_at_view((0.6, -0.4, -2.8), 96, 72)
+    opts = O.Options(bg=(0.1, 0.2, 0.3))
+    rast, sp, rgb, T = run_gpu(gb, scene, [view], opts)
+    ref = O.render(scene, view, opts)
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 96, 72, scene, view, opts)
+    check_grads(gb, scene, view, opts, (8, 8, 80, 56), seed=degree)
+
+
+def test_specular_sh_gradients_over_several_views(gb):
+    """The view-dependent colour differs per view: the coefficient and centre gradients of a
+    batched call must equal the sum of the oracle's per-view gradients."""
+    scene = sg.with_sh(sg.make_scene(72, 800, -0.8, 0.8, 0.03, 0.3, 4), 6, 2, scale=0.3)
+    views = [sg.look_at_view((0.3, 0.2, -2.6), 64, 48), sg.look_at_view((2.0, -0.6, -1.2), 48, 56)]
+    opts = O.Options()
+    rast, sp, rgb, T = run_gpu(gb, scene, views, opts)
+    g_all = sg.make_dl_drgb(8, views)
+    parts, base, total = [], 0, None
+    for v in views:
+        hw = v.width * v.height
+        ref = O.render(scene, v, opts, keep_saved=True)
+        ok = ~O.grad_flags(ref).reshape(-1)
+        g_all[base:base + hw] = np.where(ok[:, None], g_all[base:base + hw], 0.0)
+        gr = O.render_backward(scene, v, opts, ref, g_all[base:base + hw].astype(np.float64))
+        total = gr if total is None else O.Grads(*(a + b for a, b in zip(
+            (total.means, total.tan_u, total.tan_v, total.scales, total.opacity, total.textures,
+             total.sh),
+            (gr.means, gr.tan_u, gr.tan_v, gr.scales, gr.opacity, gr.textures, gr.sh))))
+        base += hw
+    grads = rast.backward(sp, T, torch.from_numpy(g_all).cuda())
+    torch.cuda.synchronize()
+    for name in ("means", "tan_u", "tan_v", "scales", "opacity", "textures", "sh"):
+        err = rel_l2(grads[name].cpu().numpy().astype(np.float64), getattr(total, name))
+        print(name, f"{err:.2e}")
+        assert err <= GRAD_TOL, (name, err)
+
+
+def test_specular_sh_full_size_crop(gb):
+    """Degree-3 coefficients on the 1M-splat 1080p workload: a 64 x 64 crop against the oracle
+    (image and every gradient, coefficients included)."""
+    check_full_size_crop(gb, "T0", 0, sh_degree=3)
