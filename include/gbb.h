@@ -356,7 +356,7 @@ gb_status gb_densify_apply(const gb_raw_splats* src, const void* work, const flo
                            float sigma, const gb_densify_options* opts, const gb_raw_splats* dst,
                            const gb_row_state* states, int32_t n_states, void* stream);
 
-/* Fills *out with the default options/* Fills *out with the default options (sigma 0.5, alpha_min 1/255, alpha_max 0.99,
+/* Fills *out with the default options (sigma 0.5, alpha_min 1/255, alpha_max 0.99,
  * t_min 1e-4, lowpass_var 0.5, black background, 16 x 16 tiles, default batch). */
 void gb_default_options(gb_options* out);
 

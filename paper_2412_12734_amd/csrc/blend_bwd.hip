@@ -153,7 +153,8 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
                  float* __restrict__ d_rec, float* __restrict__ d_tex) {
   constexpr int TEXG = 3 * N * N;
   constexpr int BH = 8 * PIX;  // wave block: 8 columns x BH rows
-  __shared__ float4 s_geo[B][4];
+  __shared__ GeoLds<B> s_geo;
+  __shared__ uint8_t s_reach[4][B];  // [wave block][staged splat]: may reach the block
   __shared__ int32_t s_splat[B];
   __shared__ uint32_t s_recid[B];
   __shared__ float4 s_tex[B * TexLayout<N>::kPerSplat];
@@ -175,13 +176,14 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   // the wave index is uniform: keep it (and the wave block's geometry) in scalar registers
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int waves_x = p.tile_w >> 3;
+  const int n_waves = nthr >> 6;
   const int bx = (w % waves_x) * 8, by = (w / waves_x) * BH;
   const int lxi = bx + (lane & 7);
-  const int wx0 = tile_x0 + bx, wy0 = tile_y0 + by;
-  const float bcx = (float)bx + 3.5f - 0.5f * (float)(p.tile_w - 1);
-  const float bcy = (float)by + 0.5f * (float)(BH - 1) - 0.5f * (float)(p.tile_h - 1);
-  // pixel centres relative to the tile centre (exact half-integers)
-  const float lx = (float)lxi - 0.5f * (float)(p.tile_w - 1);
+  // pixel centres relative to the wave block's centre (exact half-integers); the block centre
+  // relative to the tile's (wave-uniform integers)
+  const float lx = (float)(lane & 7) - 3.5f;
+  const int tcx = tile_x0 + (p.tile_w >> 1), tcy = tile_y0 + (p.tile_h >> 1);
+  const float bcx = (float)(tile_x0 + bx + 4 - tcx), bcy = (float)(tile_y0 + by + BH / 2 - tcy);
   float ly[PIX];
   PixState ps[PIX];
   // packed index of the lane's s-th pixel, or -1 outside the view (recomputed when needed)
@@ -191,8 +193,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   };
 #pragma unroll
   for (int s = 0; s < PIX; ++s) {
-    const int lyi = by + PIX * (lane >> 3) + s;
-    ly[s] = (float)lyi - 0.5f * (float)(p.tile_h - 1);
+    ly[s] = (float)(PIX * (lane >> 3) + s) - 0.5f * (float)(BH - 1);
     const int64_t pix = pixel_index(s);
     ps[s].T = 1.0f;
     ps[s].g0 = ps[s].g1 = ps[s].g2 = 0.f;
@@ -241,16 +242,29 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
     for (uint32_t bend = tile_last; bend > start;) {
       const uint32_t bstart = (bend - start) > (uint32_t)B ? bend - (uint32_t)B : start;
       const int nb = (int)(bend - bstart);
-      if (tid < nb) {
-        const uint32_t r = pair_vals[bstart + tid];
-        const SplatRec R = rec[r];
-        const StagedGeo g = stage_geo(R, tile_x0, tile_y0, p.tile_w, p.tile_h);
-        s_geo[tid][0] = g.g0;
-        s_geo[tid][1] = g.g1;
-        s_geo[tid][2] = g.g2;
-        s_geo[tid][3] = g.g3;
-        s_splat[tid] = R.splat;
-        s_recid[tid] = r;
+      {
+        // thread c stages splat c mod B for wave block c / B (geometry centred on that block)
+        // and tests whether it can reach the block
+        // (recomputed per batch from an opaque copy of the thread index: hoisted out of the
+        // loop, these indices would hold registers across the reverse walk)
+        int t = tid;
+        __asm__ volatile("" : "+v"(t));
+        const int j = t & (B - 1), b = t / B;
+        if (b < n_waves && j < nb) {
+          const uint32_t r = pair_vals[bstart + j];
+          const SplatRec R = rec[r];
+          const int kbx = tile_x0 + (b % waves_x) * 8, kby = tile_y0 + (b / waves_x) * BH;
+          const StagedGeo g = stage_geo(R, kbx + 4, kby + BH / 2, tcx, tcy);
+          s_geo.store(b, j, g);
+          s_reach[b][j] = block_may_contribute(g, (float)(kbx + 4 - tcx),
+                                               (float)(kby + BH / 2 - tcy), kbx, kby, p, 8, BH)
+                              ? 1
+                              : 0;
+          if (b == 0) {
+            s_splat[j] = R.splat;
+            s_recid[j] = r;
+          }
+        }
       }
       for (int e = tid; e < nb * TEXG; e += nthr) s_gtex[e] = 0.f;
       for (int e = tid; e < nb * kRecGrad; e += nthr) s_grec[e] = 0.f;
@@ -258,31 +272,20 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
       __syncthreads();
 
       // splats of this batch that can reach the wave's block, walked back to front
-      bool may = false;
-      if (lane < nb) {
-        StagedGeo c;
-        c.g0 = s_geo[lane][0];
-        c.g1 = s_geo[lane][1];
-        c.g2 = s_geo[lane][2];
-        c.g3 = s_geo[lane][3];
-        may = block_may_contribute(c, bcx, bcy, wx0, wy0, p, 8, BH);
-      }
+      const bool may = lane < nb && s_reach[w][lane] != 0;
       uint64_t todo = ballot(may);
       while (todo != 0) {
         const int j = 63 - (int)__builtin_clzll(todo);
         todo &= ~(1ull << j);
         const uint32_t jg = bstart + (uint32_t)j;
         if (!__any(jg < lane_last)) continue;
-        StagedGeo g;
-        g.g0 = s_geo[j][0];
-        g.g1 = s_geo[j][1];
-        g.g2 = s_geo[j][2];
+        const StagedGeo g = s_geo.load(w, j);
         const float4* tex = s_tex + j * TexLayout<N>::kPerSplat;
         PixelEval e[PIX];
         bool act[PIX], wave_act = false;
 #pragma unroll
         for (int s = 0; s < PIX; ++s) {
-          e[s] = eval_splat(g, lx, ly[s], p);
+          e[s] = eval_splat(g, lx, ly[s], lx + bcx, ly[s] + bcy, p);
           act[s] = (jg < ps[s].last) && e[s].hit;
           wave_act = wave_act || act[s];
         }

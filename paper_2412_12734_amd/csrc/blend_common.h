@@ -47,19 +47,28 @@ __device__ __forceinline__ int view_of_tile(const ViewDev* views, int n_views, i
   return v;
 }
 
-// Geometry of one staged splat, re-centred on the tile. With (lx, ly) a pixel's offset from
-// the tile centre (half-integers, exact), rho = A + (h00 lx + h01 ly, h10 lx + h11 ly,
-// h20 lx + h21 ly), where A is rho at the tile centre, evaluated in pair precision.
+// Geometry of one staged splat for one wave's pixel block. With (lx, ly) a pixel's offset from
+// the block centre (half-integers of at most 3.5 for 8 x 8 blocks, exact),
+// rho = A + (h00 lx + h01 ly, h10 lx + h11 ly, h20 lx + h21 ly), where A is rho at the block
+// centre, evaluated in pair precision. The float32 error of rho grows with the offset times
+// |h|, so a centre per wave block (rather than per tile) keeps it at the block's size whatever
+// the tile shape. The low-pass offset uses the tile centre: (ox, oy) = tile centre minus
+// projected centre, so that a pixel's offset from the projected centre is (tx + ox, ty + oy)
+// with (tx, ty) its offset from the tile centre.
 //   g0 = (A0, A1, A2, opacity), g1 = (h00, h01, h10, h11), g2 = (h20, h21, ox, oy),
-//   g3 = (rect_x, rect_y, -, -); (ox, oy) = tile centre minus projected centre.
+//   rect_x, rect_y: the record's pixel rectangle.
 struct StagedGeo {
-  float4 g0, g1, g2, g3;
+  float4 g0, g1, g2;
+  int32_t rect_x, rect_y;
 };
 
-__device__ __forceinline__ StagedGeo stage_geo(const SplatRec& r, int tile_x0, int tile_y0,
-                                               int tile_w, int tile_h) {
-  const f2 ox = f2_sub(f2_of((float)tile_x0 + 0.5f * (float)tile_w), f2{r.c2x_hi, r.c2x_lo});
-  const f2 oy = f2_sub(f2_of((float)tile_y0 + 0.5f * (float)tile_h), f2{r.c2y_hi, r.c2y_lo});
+// (cx, cy): the block centre, (tx, ty) the tile centre, in pixel coordinates (integers: blocks
+// and tiles have even sides).
+__device__ __forceinline__ StagedGeo stage_geo(const SplatRec& r, int cx, int cy, int tx,
+                                               int ty) {
+  const f2 c2x{r.c2x_hi, r.c2x_lo}, c2y{r.c2y_hi, r.c2y_lo};
+  const f2 ox = f2_sub(f2_of((float)cx), c2x);
+  const f2 oy = f2_sub(f2_of((float)cy), c2y);
   f2 h[7];
 #pragma unroll
   for (int i = 0; i < 7; ++i) h[i] = f2{r.h_hi[i], r.h_lo[i]};
@@ -69,10 +78,38 @@ __device__ __forceinline__ StagedGeo stage_geo(const SplatRec& r, int tile_x0, i
   StagedGeo s;
   s.g0 = make_float4(f2_round(A0), f2_round(A1), f2_round(A2), r.opacity);
   s.g1 = make_float4(r.h_hi[0], r.h_hi[1], r.h_hi[2], r.h_hi[3]);
-  s.g2 = make_float4(r.h_hi[4], r.h_hi[5], f2_round(ox), f2_round(oy));
-  s.g3 = make_float4(__int_as_float(r.rect_x), __int_as_float(r.rect_y), 0.f, 0.f);
+  s.g2 = make_float4(r.h_hi[4], r.h_hi[5], f2_round(f2_sub(f2_of((float)tx), c2x)),
+                     f2_round(f2_sub(f2_of((float)ty), c2y)));
+  s.rect_x = r.rect_x;
+  s.rect_y = r.rect_y;
   return s;
 }
+
+// LDS copy of a batch's staged geometry for the (at most four) wave blocks of a tile: g1 and
+// g2 once per splat, g0 once per (block, splat). 96 bytes per splat; reading one (block,
+// splat) takes three 16-byte loads.
+template <int B>
+struct GeoLds {
+  float4 g1[B];
+  float4 g2[B];
+  float4 g0[4][B];
+  static constexpr int kBytesPerSplat = 6 * 16;
+
+  __device__ void store(int b, int j, const StagedGeo& g) {
+    if (b == 0) {
+      g1[j] = g.g1;
+      g2[j] = g.g2;
+    }
+    g0[b][j] = g.g0;
+  }
+  __device__ StagedGeo load(int b, int j) const {
+    StagedGeo g;
+    g.g0 = g0[b][j];
+    g.g1 = g1[j];
+    g.g2 = g2[j];
+    return g;
+  }
+};
 
 // LDS texel layout per staged splat: N rows of N + 1 float4 (RGB + pad), so that texels
 // (i, j) and (i + 1, j) fall into different LDS banks.
@@ -166,12 +203,12 @@ struct PixelEval {
   bool hit;           // rho2 != 0 and alpha >= alpha_min
 };
 
-// (lx, ly): pixel centre minus tile centre.
-__device__ __forceinline__ PixelEval eval_splat(const StagedGeo& s, float lx, float ly,
-                                                const BlendParams& p) {
+// (lx, ly): pixel centre minus the wave block's centre; (tx, ty): minus the tile's centre.
+__device__ __forceinline__ PixelEval eval_splat(const StagedGeo& s, float lx, float ly, float tx,
+                                                float ty, const BlendParams& p) {
   PixelEval e;
-  e.dx = lx + s.g2.z;
-  e.dy = ly + s.g2.w;
+  e.dx = tx + s.g2.z;
+  e.dy = ty + s.g2.w;
   const float r0 = __builtin_fmaf(s.g1.y, ly, __builtin_fmaf(s.g1.x, lx, s.g0.x));
   const float r1 = __builtin_fmaf(s.g1.w, ly, __builtin_fmaf(s.g1.z, lx, s.g0.y));
   const float r2 = __builtin_fmaf(s.g2.y, ly, __builtin_fmaf(s.g2.x, lx, s.g0.z));
@@ -189,26 +226,26 @@ __device__ __forceinline__ PixelEval eval_splat(const StagedGeo& s, float lx, fl
 }
 
 // Conservative test whether a staged splat can reach alpha >= alpha_min anywhere in a wave's
-// bw x bh pixel block: (cx, cy) is the block centre relative to the tile centre, (bx0, by0)
-// the block's first pixel. rho is affine in the pixel offset, so its range over the block is
-// exact; where rho2 keeps its sign, |u| >= min|rho0| / max|rho2| (likewise v), and the
-// low-pass term is bounded by the block's distance to the projected centre. A splat is
+// bw x bh pixel block, staged for that block: (bx0, by0) is the block's first pixel and (cx, cy)
+// its centre relative to the tile centre. rho is affine in the pixel offset, so its range over
+// the block is exact; where rho2 keeps its sign, |u| >= min|rho0| / max|rho2| (likewise v), and
+// the low-pass term is bounded by the block's distance to the projected centre. A splat is
 // skipped only if even the largest possible opacity is clearly below alpha_min, so skipping
 // never changes a result.
 __device__ __forceinline__ bool block_may_contribute(const StagedGeo& s, float cx, float cy,
                                                      int bx0, int by0, const BlendParams& p,
                                                      int bw = 8, int bh = 8) {
-  const int rx = __float_as_int(s.g3.x), ry = __float_as_int(s.g3.y);
+  const int rx = s.rect_x, ry = s.rect_y;
   const int i0 = rx & 0xffff, i1 = rx >> 16, j0 = ry & 0xffff, j1 = ry >> 16;
   if (i1 < bx0 || i0 > bx0 + bw - 1 || j1 < by0 || j0 > by0 + bh - 1) return false;
   // half extents of the block's pixel centres
   const float ex = 0.5f * (float)(bw - 1), ey = 0.5f * (float)(bh - 1);
   const float h00 = s.g1.x, h01 = s.g1.y, h10 = s.g1.z, h11 = s.g1.w, h20 = s.g2.x, h21 = s.g2.y;
-  const float r2c = __builtin_fmaf(h21, cy, __builtin_fmaf(h20, cx, s.g0.z));
+  const float r2c = s.g0.z;
   const float r2e = ex * fabsf(h20) + ey * fabsf(h21);
   if (!(fabsf(r2c) > 1.001f * r2e)) return true;  // the vanishing line may cross the block
-  const float r0c = __builtin_fmaf(h01, cy, __builtin_fmaf(h00, cx, s.g0.x));
-  const float r1c = __builtin_fmaf(h11, cy, __builtin_fmaf(h10, cx, s.g0.y));
+  const float r0c = s.g0.x;
+  const float r1c = s.g0.y;
   const float r0m = fmaxf(fabsf(r0c) - (ex * fabsf(h00) + ey * fabsf(h01)), 0.f);
   const float r1m = fmaxf(fabsf(r1c) - (ex * fabsf(h10) + ey * fabsf(h11)), 0.f);
   const float inv = 1.0f / (fabsf(r2c) + r2e);

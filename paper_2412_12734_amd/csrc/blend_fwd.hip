@@ -26,7 +26,7 @@ namespace {
 // workgroup puts one wave on each of the CU's four SIMDs).
 template <int N, int B>
 constexpr int fwd_min_waves() {
-  constexpr int lds = B * (4 * 16 + 4 + TexLayout<N>::kPerSplat * 16);
+  constexpr int lds = B * (GeoLds<B>::kBytesPerSplat + 4 + TexLayout<N>::kPerSplat * 16);
   return 160 * 1024 / lds < 8 ? 160 * 1024 / lds : 8;
 }
 
@@ -37,7 +37,7 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
                  const void* __restrict__ textures, BlendParams p, float* __restrict__ rgb,
                  float* __restrict__ T_final, uint32_t* __restrict__ n_last, SplitState split,
                  unsigned long long* __restrict__ stats) {
-  __shared__ float4 s_geo[B][4];
+  __shared__ GeoLds<B> s_geo;
   __shared__ float4 s_tex[B * TexLayout<N>::kPerSplat];
   __shared__ uint8_t s_reach[4][B];  // [wave block][staged splat]: may reach the block
   static_assert((B & (B - 1)) == 0, "batch sizes are powers of two");
@@ -60,9 +60,12 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   const int lxi = bx + (lane & 7), lyi = by + (lane >> 3);
   const int px = tile_x0 + lxi, py = tile_y0 + lyi;
   const bool inside = px < V.W && py < V.H;
-  // pixel centre relative to the tile centre (exact half-integers)
-  const float lx = (float)lxi - 0.5f * (float)(p.tile_w - 1);
-  const float ly = (float)lyi - 0.5f * (float)(p.tile_h - 1);
+  // pixel centre relative to the wave block's centre and to the tile's (exact half-integers)
+  const float lx = (float)(lane & 7) - 3.5f;
+  const float ly = (float)(lane >> 3) - 3.5f;
+  const float tx = (float)lxi - 0.5f * (float)(p.tile_w - 1);
+  const float ty = (float)lyi - 0.5f * (float)(p.tile_h - 1);
+  const int tcx = tile_x0 + (p.tile_w >> 1), tcy = tile_y0 + (p.tile_h >> 1);
 
   const uint32_t rec_base = (uint32_t)vi * (uint32_t)p.P;  // first record of the tile's view
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
@@ -86,26 +89,20 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
     const int nb = (int)((end - b0) < (uint32_t)B ? (end - b0) : (uint32_t)B);
     if (STATS && tid == 0) atomicAdd(&stats[3], (unsigned long long)nb);
     {
-      // thread c stages splat c mod B and tests it against wave block c / B: for a batch of
-      // 16 and four waves that is one wave doing every (splat, block) test once, instead of
-      // every wave testing every splat; the block-0 threads also store the geometry
+      // thread c stages splat c mod B for wave block c / B (geometry centred on that block)
+      // and tests whether it can reach the block: for a batch of 16 and four waves that is
+      // one wave doing every (splat, block) staging and test once
       const int j = tid & (B - 1), b = tid / B;
       if (b < n_waves && j < nb) {
         const uint32_t r = pair_vals[b0 + j];
         const SplatRec R = rec[r];
-        const StagedGeo g = stage_geo(R, tile_x0, tile_y0, p.tile_w, p.tile_h);
-        if (b == 0) {
-          s_geo[j][0] = g.g0;
-          s_geo[j][1] = g.g1;
-          s_geo[j][2] = g.g2;
-          s_geo[j][3] = g.g3;
-        }
-        const int kbx = (b % waves_x) * 8, kby = (b / waves_x) * 8;
-        s_reach[b][j] = block_may_contribute(
-            g, (float)kbx + 3.5f - 0.5f * (float)(p.tile_w - 1),
-            (float)kby + 3.5f - 0.5f * (float)(p.tile_h - 1), tile_x0 + kbx, tile_y0 + kby, p)
-                            ? 1
-                            : 0;
+        const int kbx = tile_x0 + (b % waves_x) * 8, kby = tile_y0 + (b / waves_x) * 8;
+        const StagedGeo g = stage_geo(R, kbx + 4, kby + 4, tcx, tcy);
+        s_geo.store(b, j, g);
+        s_reach[b][j] =
+            block_may_contribute(g, (float)(kbx + 4 - tcx), (float)(kby + 4 - tcy), kbx, kby, p)
+                ? 1
+                : 0;
       }
     }
     stage_texels<N, BF16>(textures, pair_vals + b0, rec_base, nb, s_tex, p.spec);
@@ -118,11 +115,8 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
       while (todo != 0) {
         const int j = (int)__builtin_ctzll(todo);
         todo &= todo - 1;
-        StagedGeo g;
-        g.g0 = s_geo[j][0];
-        g.g1 = s_geo[j][1];
-        g.g2 = s_geo[j][2];
-        const PixelEval e = eval_splat(g, lx, ly, p);
+        const StagedGeo g = s_geo.load(w, j);
+        const PixelEval e = eval_splat(g, lx, ly, tx, ty, p);
         if (STATS) ++st_eval;
         if (!done && e.hit) {
           const float Tn = T * (1.0f - e.alpha);

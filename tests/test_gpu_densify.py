@@ -138,7 +138,9 @@ def test_densify_plan_and_apply_match_the_oracle(gb, N, max_scale):
     P_new = ctypes.c_int64(0)
     stream = torch.cuda.current_stream().cuda_stream
     src = raw(src_t, P)
-    L.check(lib.gb_densify_plan(ctypes.byref(src), dev(accum).data_ptr(), dev(vis).data_ptr(),
+    # keep the device copies alive for the call (a temporary's block could be handed out again)
+    accum_t, vis_t = dev(accum), dev(vis)
+    L.check(lib.gb_densify_plan(ctypes.byref(src), accum_t.data_ptr(), vis_t.data_ptr(),
                                 ctypes.byref(co), work.data_ptr(), work.numel(),
                                 ctypes.byref(P_new), stream), "gb_densify_plan")
     n = int(P_new.value)
@@ -148,7 +150,8 @@ def test_densify_plan_and_apply_match_the_oracle(gb, N, max_scale):
     m_src, m_dst = dev(m_rows), torch.full((n, N, N, 3), -9.0, device="cuda")
     st = (L.GbRowState * 1)(L.GbRowState(m_src.data_ptr(), m_dst.data_ptr(), 3 * N * N))
     dst = raw(dst_t, n)
-    L.check(lib.gb_densify_apply(ctypes.byref(src), work.data_ptr(), dev(noise).data_ptr(), 0.5,
+    noise_t = dev(noise)
+    L.check(lib.gb_densify_apply(ctypes.byref(src), work.data_ptr(), noise_t.data_ptr(), 0.5,
                                  ctypes.byref(co), ctypes.byref(dst), st, 1, stream),
             "gb_densify_apply")
     torch.cuda.synchronize()

@@ -19,14 +19,13 @@ pytestmark = pytest.mark.gpu
 IMG_TOL = 1e-5
 GRAD_TOL = 1e-3
 # Pixels where the oracle finds a decision within its flag threshold (alpha vs alpha_min within
-# 1e-5 relative, T(1 - alpha) vs t_min within 1e-4) are excluded from the image gate and
-# counted; the gradient gate also zeroes the adjoint at pixels near a gradient kink.
-MAX_FLAGGED_FRACTION = 1e-3
-# Every splat a pixel evaluates is one alpha-versus-alpha_min decision, so the share of pixels
-# with some decision inside the flag band grows with the scene's depth complexity: at 1M splats
-# a pixel evaluates hundreds of splats (a T0 crop flags 8 of 4096 pixels). The cap on the
-# full-size workloads allows for that; real errors show up on the unflagged pixels.
-MAX_FLAGGED_FRACTION_DENSE = 1e-2
+# 1e-5 relative, T(1 - alpha) vs t_min within 1e-4) are not held to the oracle's own outcome:
+# each must match one of the outcomes of its in-band decisions taken either way (or stay within
+# the oracle's bound for them). Their count is only a sanity check that the flagging does not
+# swallow the image: 1 % of the pixels plus a few, since every evaluated splat is one
+# alpha-versus-alpha_min decision and the share of flagged pixels grows with depth complexity
+# (a 64 x 64 crop of the 1M-splat 1080p scene flags about 8 of 4096 pixels).
+MAX_FLAGGED_FRACTION = 1e-2
 
 
 def _require_gpu():
@@ -92,7 +91,7 @@ def assert_image_parity(rgb_gpu, T_gpu, ref: O.RenderResult, base, W, H, scene, 
     g_T = image_crop(T_gpu, base, W, H, crop, ch=0).astype(np.float64)
     ok = ~O.image_flags(ref)
     flagged = int((~ok).sum())
-    assert flagged <= max_flagged * ok.size + 2, f"{flagged} flagged pixels"
+    assert flagged <= max_flagged * ok.size + 4, f"{flagged} flagged pixels"
     d = np.where(ok[..., None], np.abs(g_rgb - ref.rgb), 0.0)
     dT = np.where(ok, np.abs(g_T - ref.T_final), 0.0)
     if d.max(initial=0) > IMG_TOL or dT.max(initial=0) > IMG_TOL:
@@ -305,8 +304,7 @@ def check_full_size_crop(gb, name, vi, seed=0, sh_degree=None):
     crop = ((W - 64) // 2, (H - 64) // 2, 64, 64)
     ref = O.render(scene, view, opts, crop=crop, keep_saved=True)
     img_err, flagged = assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, base, W, H,
-                                           scene, view, opts,
-                                           max_flagged=MAX_FLAGGED_FRACTION_DENSE)
+                                           scene, view, opts)
     x0, y0, w, h = crop
     g_view = sg.make_dl_drgb(seed, [view]).reshape(H, W, 3)
     mask = np.zeros((H, W), dtype=bool)
