@@ -356,6 +356,28 @@ gb_status gb_densify_apply(const gb_raw_splats* src, const void* work, const flo
                            float sigma, const gb_densify_options* opts, const gb_raw_splats* dst,
                            const gb_row_state* states, int32_t n_states, void* stream);
 
+/* Most splats gb_densify_noalloc takes (its static work area holds about 21 MB per GPU). */
+#define GB_DENSIFY_NOALLOC_MAX_P (1 << 20)
+
+/* For callers that cannot allocate device memory (tight training loops, harnesses that forbid
+ * allocation): gb_densify_plan followed by gb_densify_apply in one call, with the plan's work
+ * buffer held in a library-owned static device array instead of a caller buffer. Each GPU the
+ * library runs on holds its own copy of that array (about 21 MB) until the process ends; the
+ * call allocates nothing.
+ *   src, grad_accum, vis_count, opts, noise, sigma, states: as for gb_densify_plan/apply;
+ *   dst: output arrays with room for dst->P rows (2 * src->P always suffice); the first
+ *        min(*P_new, dst->P) rows are written;
+ *   *P_new: the number of outputs.
+ * Errors: GB_ERR_ARG (nothing launched) for the argument errors of gb_densify_plan/apply and
+ * for src->P > GB_DENSIFY_NOALLOC_MAX_P; GB_ERR_CAPACITY if *P_new > dst->P (the rows that fit
+ * are written). Synchronises `stream`. All calls on one GPU share the work area: calls that
+ * overlap on one GPU (other streams or threads) race and must be serialised by the caller. */
+gb_status gb_densify_noalloc(const gb_raw_splats* src, const float* grad_accum,
+                             const float* vis_count, const gb_densify_options* opts,
+                             const float* noise, float sigma, const gb_raw_splats* dst,
+                             const gb_row_state* states, int32_t n_states, int64_t* P_new,
+                             void* stream);
+
 /* Fills *out with the default options (sigma 0.5, alpha_min 1/255, alpha_max 0.99,
  * t_min 1e-4, lowpass_var 0.5, black background, 16 x 16 tiles, default batch). */
 void gb_default_options(gb_options* out);

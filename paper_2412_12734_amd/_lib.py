@@ -24,7 +24,11 @@ EXPORTS = (
     "gb_activate_fwd", "gb_activate_bwd", "gb_l1_loss", "gb_adam_step", "gb_to_bf16",
     "gb_mse_loss", "gb_box_filter_textures", "gb_rotz_only",
     "gb_densify_stats", "gb_densify_work_bytes", "gb_densify_plan", "gb_densify_apply",
+    "gb_densify_noalloc",
 )
+
+# most splats gb_densify_noalloc takes (GB_DENSIFY_NOALLOC_MAX_P)
+DENSIFY_NOALLOC_MAX_P = 1 << 20
 
 
 class GbView(ctypes.Structure):
@@ -145,12 +149,16 @@ def load() -> ctypes.CDLL:
     lib.gb_densify_apply.argtypes = [POINTER(GbRawSplats), c_void_p, c_void_p, c_float,
                                      POINTER(GbDensifyOptions), POINTER(GbRawSplats),
                                      POINTER(GbRowState), c_int32, c_void_p]
+    lib.gb_densify_noalloc.argtypes = [POINTER(GbRawSplats), c_void_p, c_void_p,
+                                       POINTER(GbDensifyOptions), c_void_p, c_float,
+                                       POINTER(GbRawSplats), POINTER(GbRowState), c_int32,
+                                       POINTER(c_int64), c_void_p]
     for name in ("gb_workspace_layout", "gb_count_pairs", "gb_render_fwd", "gb_render_bwd",
                  "gb_read_status", "gb_blend_stats", "gb_timing_enable", "gb_timing_read",
                  "gb_activate_fwd", "gb_activate_bwd", "gb_l1_loss", "gb_adam_step",
                  "gb_to_bf16", "gb_mse_loss", "gb_box_filter_textures", "gb_rotz_only",
                  "gb_densify_stats", "gb_densify_plan",
-                 "gb_densify_apply"):
+                 "gb_densify_apply", "gb_densify_noalloc"):
         getattr(lib, name).restype = c_int32
     _lib = lib
     return lib

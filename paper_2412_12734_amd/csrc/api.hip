@@ -346,23 +346,21 @@ struct DensifyWork {
   size_t status, action, n_out, offsets, map, partials, partials64, total;
 };
 
-DensifyWork densify_work(int64_t P) {
-  DensifyWork w;
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    const size_t at = off;
-    off = align_up(off + bytes, 256);
-    return at;
-  };
-  const int64_t parts = (P + kScanTile - 1) / kScanTile + 2;
-  w.status = take(256);
-  w.action = take(4 * (size_t)P);
-  w.n_out = take(4 * (size_t)P);
-  w.offsets = take(4 * (size_t)P);
-  w.map = take(8 * (size_t)P);
-  w.partials = take(4 * (size_t)parts);
-  w.partials64 = take(8 * (size_t)parts);
-  w.total = off;
+constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Work buffer of the densification plan for P splats: per splat its action, output count,
+// output offset and two parent-map entries, plus the scan's partial sums.
+constexpr DensifyWork densify_work(int64_t P) {
+  const size_t parts = (size_t)((P + kScanTile - 1) / kScanTile + 2);
+  DensifyWork w{};
+  w.status = 0;
+  w.action = w.status + align256(256);
+  w.n_out = w.action + align256(4 * (size_t)P);
+  w.offsets = w.n_out + align256(4 * (size_t)P);
+  w.map = w.offsets + align256(4 * (size_t)P);
+  w.partials = w.map + align256(8 * (size_t)P);
+  w.partials64 = w.partials + align256(4 * parts);
+  w.total = w.partials64 + align256(8 * parts);
   return w;
 }
 
@@ -389,6 +387,140 @@ gb_status check_densify_options(const gb_densify_options* o) {
   if (!(o->max_scale >= 0.f) || !std::isfinite(o->max_scale)) return arg_fail("max_scale >= 0");
   if (!(o->split_shrink >= 1.f) || !std::isfinite(o->split_shrink))
     return arg_fail("split_shrink must be >= 1");
+  return GB_OK;
+}
+
+gb_status check_densify_plan_args(const gb_raw_splats* src, const float* grad_accum,
+                                  const float* vis_count, const gb_densify_options* o,
+                                  const int64_t* P_new) {
+  gb_status st;
+  if ((st = check_raw(src, "src NULL")) != GB_OK) return st;
+  if ((st = check_densify_options(o)) != GB_OK) return st;
+  if (!P_new) return arg_fail("P_new NULL");
+  if (src->P > 0 &&
+      (!grad_accum || !vis_count || !aligned(grad_accum, 4) || !aligned(vis_count, 4)))
+    return arg_fail("grad_accum / vis_count NULL or misaligned");
+  return GB_OK;
+}
+
+gb_status check_densify_apply_args(const gb_raw_splats* src, const float* noise, float sigma,
+                                   const gb_densify_options* o, const gb_raw_splats* dst,
+                                   const gb_row_state* states, int32_t n_states) {
+  gb_status st;
+  if ((st = check_raw(src, "src NULL")) != GB_OK) return st;
+  if ((st = check_raw(dst, "dst NULL")) != GB_OK) return st;
+  if ((st = check_densify_options(o)) != GB_OK) return st;
+  if (dst->N != src->N || dst->sh_coef != src->sh_coef)
+    return arg_fail("dst must have the texture side and SH coefficients of src");
+  if (!(sigma > 0.f) || !std::isfinite(sigma)) return arg_fail("sigma must be > 0");
+  if (n_states < 0 || (n_states > 0 && !states)) return arg_fail("states NULL");
+  for (int i = 0; i < n_states; ++i)
+    if (!states[i].src || !states[i].dst || states[i].width < 1 || !aligned(states[i].src, 4) ||
+        !aligned(states[i].dst, 4))
+      return arg_fail("state row arrays NULL, misaligned or of width < 1");
+  if (dst->P > 0 && (!noise || !aligned(noise, 4))) return arg_fail("noise NULL or misaligned");
+  return GB_OK;
+}
+
+// Decide, scan and map of the densification plan into `work` (laid out by densify_work),
+// stream-ordered, without waiting.
+gb_status densify_plan_launch(const gb_raw_splats* src, const float* grad_accum,
+                              const float* vis_count, const gb_densify_options* o, void* work,
+                              hipStream_t hs) {
+  const DensifyWork w = densify_work(src->P);
+  char* b = static_cast<char*>(work);
+  // thresholds in the domain of the raw parameters (double precision, rounded once)
+  const double shrink = o->split_shrink;
+  const float ls_dense = (float)std::log((double)o->dense_scale);
+  const float logit_min =
+      o->min_opacity > 0.f ? (float)std::log((double)o->min_opacity / (1.0 - o->min_opacity))
+                           : -INFINITY;
+  const bool use_max = o->max_scale > 0.f;
+  const float ls_max = use_max ? (float)std::log((double)o->max_scale) : 0.f;
+  const float ls_max_child = use_max ? (float)(std::log((double)o->max_scale) + std::log(shrink))
+                                     : 0.f;
+  uint32_t* action = reinterpret_cast<uint32_t*>(b + w.action);
+  uint32_t* n_out = reinterpret_cast<uint32_t*>(b + w.n_out);
+  uint32_t* offsets = reinterpret_cast<uint32_t*>(b + w.offsets);
+  uint32_t* d_total = reinterpret_cast<uint32_t*>(b + w.status);
+  unsigned long long* d_total64 = reinterpret_cast<unsigned long long*>(b + w.status + 8);
+  GBB_TRY(launch_densify_decide(src->P, src->log_scales, src->opacity_logits, grad_accum,
+                                vis_count, o->grad_threshold, ls_dense, logit_min, ls_max,
+                                ls_max_child, use_max, action, n_out, hs),
+          "densify decide");
+  GBB_TRY(launch_scan_u32(n_out, nullptr, offsets, src->P,
+                          reinterpret_cast<uint32_t*>(b + w.partials), d_total, d_total64,
+                          reinterpret_cast<unsigned long long*>(b + w.partials64), hs),
+          "densify scan");
+  GBB_TRY(launch_densify_map(src->P, action, n_out, offsets,
+                             reinterpret_cast<uint32_t*>(b + w.map), hs),
+          "densify map");
+  return GB_OK;
+}
+
+// Waits for the stream and reads the plan's output count from `work`.
+gb_status densify_read_count(const void* work, hipStream_t hs, int64_t* P_new) {
+  unsigned long long total = 0;
+  GBB_TRY(hipMemcpyAsync(&total, static_cast<const char*>(work) + 8, sizeof(total),
+                         hipMemcpyDeviceToHost, hs),
+          "read densify count");
+  GBB_TRY(hipStreamSynchronize(hs), "sync");
+  *P_new = (int64_t)total;
+  return GB_OK;
+}
+
+// Writes the planned outputs (at most n_cap rows, and no more than the plan's count) into dst.
+gb_status densify_apply_launch(const gb_raw_splats* src, const void* work, const float* noise,
+                               float sigma, const gb_densify_options* o,
+                               const gb_raw_splats* dst, int64_t n, const gb_row_state* states,
+                               int32_t n_states, hipStream_t hs) {
+  const DensifyWork w = densify_work(src->P);
+  const char* b = static_cast<const char*>(work);
+  const uint32_t* map = reinterpret_cast<const uint32_t*>(b + w.map);
+  const uint32_t* d_n = reinterpret_cast<const uint32_t*>(b + w.status);
+  const int N = src->N;
+  GBB_TRY(launch_child_geometry(map, d_n, n, src->means, src->quats, src->log_scales, noise,
+                                (float)std::log((double)o->split_shrink), dst->means,
+                                dst->log_scales, hs),
+          "densify geometry");
+  GBB_TRY(launch_gather_rows(map, d_n, n, 4, src->quats, dst->quats, false, hs), "quats");
+  GBB_TRY(launch_gather_rows(map, d_n, n, 1, src->opacity_logits, dst->opacity_logits, false, hs),
+          "logits");
+  if (src->sh_coef > 0)
+    GBB_TRY(launch_gather_rows(map, d_n, n, 3 * src->sh_coef, src->sh, dst->sh, false, hs), "sh");
+  GBB_TRY(launch_child_texture(map, d_n, n, N, src->textures, noise, sigma,
+                               (float)(1.0 / (double)o->split_shrink), dst->textures, hs),
+          "densify textures");
+  for (int i = 0; i < n_states; ++i)
+    GBB_TRY(launch_gather_rows(map, d_n, n, states[i].width, states[i].src, states[i].dst, true,
+                               hs),
+            "state rows");
+  return GB_OK;
+}
+
+// The work area of gb_densify_noalloc: a library-owned device array, one copy per GPU, held
+// until the process ends. In host code the array's name is only a host-side handle; its
+// device address comes from hipGetSymbolAddress, taken once per device with that device
+// current, and only that address is ever passed to kernels.
+constexpr size_t kNoallocWorkBytes = densify_work(GB_DENSIFY_NOALLOC_MAX_P).total;
+static __device__ __align__(256) unsigned char scratch[kNoallocWorkBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+gb_status static_densify_work(void** out) {
+  int dev = 0;
+  GBB_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return arg_fail("device index beyond the library's table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    GBB_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "address of the static work area");
+    if (!p) return hip_fail(hipErrorInvalidSymbol, "address of the static work area");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
   return GB_OK;
 }
 }  // namespace
@@ -772,9 +904,7 @@ gb_status gb_densify_plan(const gb_raw_splats* src, const float* grad_accum,
                           const float* vis_count, const gb_densify_options* o, void* work,
                           size_t work_bytes, int64_t* P_new, void* stream) {
   gb_status st;
-  if ((st = check_raw(src, "src NULL")) != GB_OK) return st;
-  if ((st = check_densify_options(o)) != GB_OK) return st;
-  if (!P_new) return arg_fail("P_new NULL");
+  if ((st = check_densify_plan_args(src, grad_accum, vis_count, o, P_new)) != GB_OK) return st;
   const DensifyWork w = densify_work(src->P);
   if (!work || !aligned(work, 256) || work_bytes < w.total)
     return arg_fail("densify work buffer NULL, misaligned or smaller than gb_densify_work_bytes");
@@ -782,86 +912,55 @@ gb_status gb_densify_plan(const gb_raw_splats* src, const float* grad_accum,
     *P_new = 0;
     return GB_OK;
   }
-  if (!grad_accum || !vis_count || !aligned(grad_accum, 4) || !aligned(vis_count, 4))
-    return arg_fail("grad_accum / vis_count NULL or misaligned");
   hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
-  char* b = static_cast<char*>(work);
-  // thresholds in the domain of the raw parameters (double precision, rounded once)
-  const double shrink = o->split_shrink;
-  const float ls_dense = (float)std::log((double)o->dense_scale);
-  const float logit_min =
-      o->min_opacity > 0.f ? (float)std::log((double)o->min_opacity / (1.0 - o->min_opacity))
-                           : -INFINITY;
-  const bool use_max = o->max_scale > 0.f;
-  const float ls_max = use_max ? (float)std::log((double)o->max_scale) : 0.f;
-  const float ls_max_child = use_max ? (float)(std::log((double)o->max_scale) + std::log(shrink))
-                                     : 0.f;
-  uint32_t* action = reinterpret_cast<uint32_t*>(b + w.action);
-  uint32_t* n_out = reinterpret_cast<uint32_t*>(b + w.n_out);
-  uint32_t* offsets = reinterpret_cast<uint32_t*>(b + w.offsets);
-  uint32_t* d_total = reinterpret_cast<uint32_t*>(b + w.status);
-  unsigned long long* d_total64 = reinterpret_cast<unsigned long long*>(b + w.status + 8);
-  GBB_TRY(launch_densify_decide(src->P, src->log_scales, src->opacity_logits, grad_accum,
-                                vis_count, o->grad_threshold, ls_dense, logit_min, ls_max,
-                                ls_max_child, use_max, action, n_out, hs),
-          "densify decide");
-  GBB_TRY(launch_scan_u32(n_out, nullptr, offsets, src->P,
-                          reinterpret_cast<uint32_t*>(b + w.partials), d_total, d_total64,
-                          reinterpret_cast<unsigned long long*>(b + w.partials64), hs),
-          "densify scan");
-  GBB_TRY(launch_densify_map(src->P, action, n_out, offsets,
-                             reinterpret_cast<uint32_t*>(b + w.map), hs),
-          "densify map");
-  unsigned long long total = 0;
-  GBB_TRY(hipMemcpyAsync(&total, d_total64, sizeof(total), hipMemcpyDeviceToHost, hs),
-          "read densify count");
-  GBB_TRY(hipStreamSynchronize(hs), "sync");
-  *P_new = (int64_t)total;
-  return GB_OK;
+  if ((st = densify_plan_launch(src, grad_accum, vis_count, o, work, hs)) != GB_OK) return st;
+  return densify_read_count(work, hs, P_new);
 }
 
 gb_status gb_densify_apply(const gb_raw_splats* src, const void* work, const float* noise,
                            float sigma, const gb_densify_options* o, const gb_raw_splats* dst,
                            const gb_row_state* states, int32_t n_states, void* stream) {
   gb_status st;
-  if ((st = check_raw(src, "src NULL")) != GB_OK) return st;
-  if ((st = check_raw(dst, "dst NULL")) != GB_OK) return st;
-  if ((st = check_densify_options(o)) != GB_OK) return st;
-  if (dst->N != src->N || dst->sh_coef != src->sh_coef)
-    return arg_fail("dst must have the texture side and SH coefficients of src");
+  if ((st = check_densify_apply_args(src, noise, sigma, o, dst, states, n_states)) != GB_OK)
+    return st;
   if (dst->P > 2 * (int64_t)src->P) return arg_fail("dst->P exceeds twice src->P");
-  if (!(sigma > 0.f) || !std::isfinite(sigma)) return arg_fail("sigma must be > 0");
   if (!work || !aligned(work, 256)) return arg_fail("work NULL or misaligned");
-  if (n_states < 0 || (n_states > 0 && !states)) return arg_fail("states NULL");
-  for (int i = 0; i < n_states; ++i)
-    if (!states[i].src || !states[i].dst || states[i].width < 1 || !aligned(states[i].src, 4) ||
-        !aligned(states[i].dst, 4))
-      return arg_fail("state row arrays NULL, misaligned or of width < 1");
   if (dst->P == 0) return GB_OK;
-  if (!noise || !aligned(noise, 4)) return arg_fail("noise NULL or misaligned");
+  return densify_apply_launch(src, work, noise, sigma, o, dst, dst->P, states, n_states,
+                              reinterpret_cast<hipStream_t>(stream));
+}
+
+gb_status gb_densify_noalloc(const gb_raw_splats* src, const float* grad_accum,
+                             const float* vis_count, const gb_densify_options* o,
+                             const float* noise, float sigma, const gb_raw_splats* dst,
+                             const gb_row_state* states, int32_t n_states, int64_t* P_new,
+                             void* stream) {
+  gb_status st;
+  if ((st = check_densify_plan_args(src, grad_accum, vis_count, o, P_new)) != GB_OK) return st;
+  if ((st = check_densify_apply_args(src, noise, sigma, o, dst, states, n_states)) != GB_OK)
+    return st;
+  if (src->P > GB_DENSIFY_NOALLOC_MAX_P)
+    return arg_fail("gb_densify_noalloc: src->P exceeds GB_DENSIFY_NOALLOC_MAX_P (use "
+                    "gb_densify_plan and gb_densify_apply with a work buffer)");
+  if (src->P == 0) {
+    *P_new = 0;
+    return GB_OK;
+  }
+  void* work = nullptr;
+  if ((st = static_densify_work(&work)) != GB_OK) return st;
   hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
-  const DensifyWork w = densify_work(src->P);
-  const char* b = static_cast<const char*>(work);
-  const uint32_t* map = reinterpret_cast<const uint32_t*>(b + w.map);
-  const uint32_t* d_n = reinterpret_cast<const uint32_t*>(b + w.status);
-  const int64_t n = dst->P;
-  const int N = src->N;
-  GBB_TRY(launch_child_geometry(map, d_n, n, src->means, src->quats, src->log_scales, noise,
-                                (float)std::log((double)o->split_shrink), dst->means,
-                                dst->log_scales, hs),
-          "densify geometry");
-  GBB_TRY(launch_gather_rows(map, d_n, n, 4, src->quats, dst->quats, false, hs), "quats");
-  GBB_TRY(launch_gather_rows(map, d_n, n, 1, src->opacity_logits, dst->opacity_logits, false, hs),
-          "logits");
-  if (src->sh_coef > 0)
-    GBB_TRY(launch_gather_rows(map, d_n, n, 3 * src->sh_coef, src->sh, dst->sh, false, hs), "sh");
-  GBB_TRY(launch_child_texture(map, d_n, n, N, src->textures, noise, sigma,
-                               (float)(1.0 / (double)o->split_shrink), dst->textures, hs),
-          "densify textures");
-  for (int i = 0; i < n_states; ++i)
-    GBB_TRY(launch_gather_rows(map, d_n, n, states[i].width, states[i].src, states[i].dst, true,
-                               hs),
-            "state rows");
+  if ((st = densify_plan_launch(src, grad_accum, vis_count, o, work, hs)) != GB_OK) return st;
+  // the apply kernels read the output count from the work area and write at most dst->P rows
+  const int64_t n_cap = dst->P < 2 * (int64_t)src->P ? dst->P : 2 * (int64_t)src->P;
+  if (n_cap > 0 &&
+      (st = densify_apply_launch(src, work, noise, sigma, o, dst, n_cap, states, n_states, hs)) !=
+          GB_OK)
+    return st;
+  if ((st = densify_read_count(work, hs, P_new)) != GB_OK) return st;
+  if (*P_new > dst->P) {
+    g_last_error = "gb_densify_noalloc: more outputs than dst->P rows (*P_new holds the count)";
+    return GB_ERR_CAPACITY;
+  }
   return GB_OK;
 }
 

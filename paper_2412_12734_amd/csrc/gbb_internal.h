@@ -33,8 +33,8 @@ static_assert(sizeof(ViewDev) == 96, "ViewDev layout");
 // projected centre onto homogeneous uv: (rho0, rho1, rho2) = H (dx, dy, 1) with
 // rho0 = h00 dx + h01 dy, rho1 = h10 dx + h11 dy, rho2 = h20 dx + h21 dy + h22,
 // u = rho0 / rho2, v = rho1 / rho2. The entries and the projected centre are unevaluated
-// float pairs (hi + lo): the blend re-centres the solve on each tile in pair precision, so
-// that float32 per-pixel arithmetic only spans offsets within one tile.
+// float pairs (hi + lo): the blend re-centres the solve on each wave's 8 x 8 pixel block in
+// pair precision, so that float32 per-pixel arithmetic only spans offsets within one block.
 struct SplatRec {
   float h_hi[7];
   float h_lo[7];

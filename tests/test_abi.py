@@ -227,3 +227,22 @@ def test_densify_entry_points_check_arguments_before_any_launch():
     other_n = L.GbRawSplats(10, 8, 0, p256, p256, p256, p256, p256, None)
     assert lib.gb_densify_apply(ctypes.byref(raw), p256, p256, 0.5, ctypes.byref(o),
                                 ctypes.byref(other_n), None, 0, None) == L.GB_ERR_ARG
+    # the allocation-free variant: the same checks, and its size limit, before any launch
+    dst = L.GbRawSplats(20, 4, 0, p256, p256, p256, p256, p256, None)
+    assert lib.gb_densify_noalloc(None, p256, p256, ctypes.byref(o), p256, 0.5, ctypes.byref(dst),
+                                  None, 0, ctypes.byref(P), None) == L.GB_ERR_ARG
+    assert lib.gb_densify_noalloc(ctypes.byref(raw), p256, p256, ctypes.byref(bad), p256, 0.5,
+                                  ctypes.byref(dst), None, 0, ctypes.byref(P), None) == L.GB_ERR_ARG
+    assert lib.gb_densify_noalloc(ctypes.byref(raw), p256, p256, ctypes.byref(o), p256, 0.5,
+                                  ctypes.byref(other_n), None, 0, ctypes.byref(P),
+                                  None) == L.GB_ERR_ARG
+    huge = L.GbRawSplats(L.DENSIFY_NOALLOC_MAX_P + 1, 4, 0, p256, p256, p256, p256, p256, None)
+    assert lib.gb_densify_noalloc(ctypes.byref(huge), p256, p256, ctypes.byref(o), p256, 0.5,
+                                  ctypes.byref(dst), None, 0, ctypes.byref(P),
+                                  None) == L.GB_ERR_ARG
+    assert b"GB_DENSIFY_NOALLOC_MAX_P" in lib.gb_last_error()
+    empty_dst = L.GbRawSplats(0, 4, 0, None, None, None, None, None, None)
+    P.value = 7
+    assert lib.gb_densify_noalloc(ctypes.byref(empty), None, None, ctypes.byref(o), None, 0.5,
+                                  ctypes.byref(empty_dst), None, 0, ctypes.byref(P),
+                                  None) == L.GB_OK and P.value == 0
