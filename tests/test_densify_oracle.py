@@ -135,6 +135,33 @@ def test_decisions_clone_split_prune_and_order():
                     (4, D.CHILD0), (4, D.CHILD1)]
 
 
+def test_decisions_at_the_thresholds():
+    """Each decision taken on both sides of its threshold, 1 % away: the split/clone size
+    (max scale against dense_scale), the gradient mean (accum / count against grad_threshold,
+    equality densifies), the opacity floor and the children's scale limit."""
+    sig = lambda o: math.log(o / (1 - o))
+    ds, gt, mo, ms, sh = 0.01, 2e-4, 0.005, 0.05, 1.6
+    rows = [  # (s_u, s_v, opacity, accum, count)
+        (1.01 * ds, 0.5 * ds, 0.5, 1e-3, 1.0),  # 0: just above dense_scale: split
+        (0.99 * ds, 0.5 * ds, 0.5, 1e-3, 1.0),  # 1: just below: clone
+        (0.5 * ds, 1.01 * ds, 0.5, 1e-3, 1.0),  # 2: the larger scale is s_v: split
+        (0.5 * ds, 0.5 * ds, 0.5, 2 * gt, 2.0),  # 3: mean exactly at the threshold: clone
+        (0.5 * ds, 0.5 * ds, 0.5, 0.99 * 2 * gt, 2.0),  # 4: mean just below: kept
+        (0.5 * ds, 0.5 * ds, 1.01 * mo, 0.0, 0.0),  # 5: opacity just above the floor: kept
+        (0.5 * ds, 0.5 * ds, 0.99 * mo, 0.0, 0.0),  # 6: just below: pruned
+        (0.99 * sh * ms, ds, 0.5, 1e-3, 1.0),  # 7: children just under max_scale: split
+        (1.01 * sh * ms, ds, 0.5, 1e-3, 1.0),  # 8: children just over: pruned
+        (1.01 * ms, ds, 0.5, 0.0, 1.0),  # 9: kept splat just over max_scale: pruned
+    ]
+    r = np.array(rows)
+    outs = D.plan(np.log(r[:, :2]), np.array([sig(o) for o in r[:, 2]]), r[:, 3], r[:, 4],
+                  D.DensifyOptions(grad_threshold=gt, dense_scale=ds, min_opacity=mo,
+                                   max_scale=ms, split_shrink=sh))
+    assert outs == [(0, D.CHILD0), (0, D.CHILD1), (1, D.KEEP), (1, D.CLONE_COPY),
+                    (2, D.CHILD0), (2, D.CHILD1), (3, D.KEEP), (3, D.CLONE_COPY), (4, D.KEEP),
+                    (5, D.KEEP), (7, D.CHILD0), (7, D.CHILD1)]
+
+
 def test_opacity_pruning_removes_exactly_the_chosen_splats():
     rng = np.random.default_rng(9)
     P = 50
