@@ -129,8 +129,9 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
 }
 
 // With batches of 8 the LDS would allow more than 6 waves per SIMD, but the register
-// allocation (77 VGPRs) stops there; asking for 7 (at most 72 VGPRs, two dwords spilled)
-// measured 4 % faster on the 1M-splat 1080p workload, 8 (64 VGPRs) slower.
+// allocation (75 VGPRs unconstrained) stops there; asking for 7 (at most 72 VGPRs; the
+// compiler's resource report gives 71 and no VGPR spills for 8 x 8 grids) measured 4 % faster
+// on the 1M-splat 1080p workload, 8 (64 VGPRs) slower.
 // (N = 16 blocks hold 61 KB of LDS, two per CU, so no register target applies there.)
 // Wave steps that blended at most this many pixels skip the cell grouping (measured at 1M
 // splats and 1080p: unchanged time; 100k splats at 800x800 and 3M splats at 4 x 1080p, where
