@@ -264,12 +264,18 @@ def c3_variant(gb, sg, torch, warmup, steps):
             "mpix_per_s_batched": round(px / s_batch / 1e6, 1), "pixels": px, "pairs": K}
 
 
-def config_times(gb, sg, torch, warmup, steps):
+CONFIG_PASSES = (("C1", False), ("C2", True), ("C4", True))
+
+
+def config_times(gb, sg, torch, warmup, steps, only=None):
     """Step times of the smaller named workloads (their parity is checked by the tests):
     1k splats at 128x128 forward only, 100k splats at 800x800 forward + backward, 3M splats
-    with bfloat16 textures at 4 x 1080p forward + backward."""
+    with bfloat16 textures at 4 x 1080p forward + backward. ``only`` names one of them; its
+    entry then also holds the per-stage times (HIP events) of one further step."""
     out = {}
-    for name, bwd in (("C1", False), ("C2", True), ("C4", True)):
+    for name, bwd in CONFIG_PASSES:
+        if only is not None and name != only:
+            continue
         scene, views, sp, rast, g, rgb, T, grads, K = setup(gb, sg, torch, name)
         px = sum(v.width * v.height for v in views)
         for _ in range(warmup):
@@ -289,6 +295,13 @@ def config_times(gb, sg, torch, warmup, steps):
         out[name] = {"ms_per_step": round(sec * 1e3, 3), "mpix_per_s": round(px / sec / 1e6, 1),
                      "pass": "fwd+bwd" if bwd else "fwd", "splats": scene.P, "pixels": px,
                      "pairs": K}
+        if only is not None:
+            rast.timing(True)
+            rast.forward(sp, rgb, T)
+            if bwd:
+                rast.backward(sp, T, g, grads)
+            out[name]["stage_ms"] = {k: round(v, 4) for k, v in rast.stage_times().items()}
+            rast.timing(False)
         del scene, sp, rast, g, rgb, T, grads
         torch.cuda.empty_cache()
     return out
@@ -320,6 +333,8 @@ def main():
                     help="time only the optimisation-step variant (for kernel traces of it)")
     ap.add_argument("--image-fit-only", action="store_true",
                     help="time only the 100k-splat single-image fitting variant")
+    ap.add_argument("--config-only", choices=[n for n, _ in CONFIG_PASSES],
+                    help="time only this named workload (for kernel traces of it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the rasterizer has no "
@@ -339,6 +354,10 @@ def main():
         fit = image_fit_variant(gb, sg, torch, 100_000, 4, warmup=args.warmup,
                                 iters=args.train_iters)
         print(json.dumps({"image_fit_100k": fit}), flush=True)
+        return
+    if args.config_only:
+        out = config_times(gb, sg, torch, args.warmup, args.steps, only=args.config_only)
+        print(json.dumps(out), flush=True)
         return
     copy_gbs = copy_probe(torch)
     log(f"plain device copy of {COPY_BYTES >> 20} MiB: {copy_gbs:.0f} GB/s (read + write)")
