@@ -65,7 +65,8 @@ typedef struct {
 
 typedef struct {
   int32_t P;               /* number of splats, >= 1 */
-  int32_t N;               /* texture side, one of 1, 2, 4, 8, 16 (16: batch and batch_bwd 8) */
+  int32_t N;               /* texture side, one of 1, 2, 4, 8, 16 (16: batch and batch_bwd 8);
+                              with tex_side: the largest side any splat may have, 8 or 16 */
   int32_t tex_dtype;       /* gb_dtype of `textures` */
   const float* means;      /* [P][3] */
   const float* tan_u;      /* [P][3] */
@@ -81,6 +82,16 @@ typedef struct {
                               from the camera centre -R^T t to p_k, Y_j the real harmonics of
                               index j = l^2 + l + m, each (-1)^m times the usual real harmonic
                               (sign convention of 3D Gaussian splatting). */
+  /* Colour grids of several sides in one call (NULL tex_side: every grid is N x N, packed as
+   * [P][N][N][3]). With tex_side, splat k's grid has its own side n_k = tex_side[k], any value
+   * in [1, N] (values outside are clamped to it), spans the same [-sigma, sigma]^2 of the uv
+   * plane with its texel centres corner-aligned (Sec. 3.2, Alg. 2 with n_k in place of N), and
+   * occupies texels [tex_offset[k], tex_offset[k] + n_k^2) of `textures`, each texel 3 values
+   * [i_u][i_v][c]; the grids may lie anywhere in the array, which holds n_texels texels (the
+   * gradient d_textures has the same layout and size and is written over all n_texels). */
+  const int32_t* tex_side;   /* NULL or [P] (device) */
+  const int64_t* tex_offset; /* [P] (device), required with tex_side */
+  int64_t n_texels;          /* texels in `textures` with tex_side (>= 1), else ignored */
 } gb_splats;
 
 typedef struct {
@@ -120,7 +131,8 @@ typedef struct {
   float* d_tan_v;     /* [P][3] */
   float* d_scales;    /* [P][2] */
   float* d_opacity;   /* [P] */
-  float* d_textures;  /* [P][N][N][3] float32 */
+  float* d_textures;  /* [P][N][N][3] float32, or with tex_side [n_texels][3] laid out as the
+                         splats' textures */
   float* d_sh;        /* [P][(D+1)^2][3] float32; required when splats->sh != NULL, else
                          ignored */
 } gb_grads;

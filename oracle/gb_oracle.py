@@ -660,7 +660,11 @@ def flagged_bound(scene, r: RenderResult, row: int, col: int, bg=(0.0, 0.0, 0.0)
     <= 2 alpha T c_max, a stop taken or not by at most T c_max (what lies behind), with
     c_max the largest texel or background magnitude of the scene."""
     pid = row * r.crop[2] + col
-    cmax = max(float(np.abs(scene.textures).max()), float(np.abs(np.asarray(bg)).max()), 1e-30)
+    if isinstance(scene.textures, np.ndarray):
+        tmax = float(np.abs(scene.textures).max())
+    else:  # grids of several sides
+        tmax = max(float(np.abs(np.asarray(g)).max()) for g in scene.textures)
+    cmax = max(tmax, float(np.abs(np.asarray(bg)).max()), 1e-30)
     b = 0.0
     for k, kind, T_before, alpha in r.straddles.get(pid, []):
         b += (2.0 * alpha * T_before if kind == "a" else T_before) * cmax
@@ -697,8 +701,11 @@ def render_backward(scene, view, opts: Options, fwd: RenderResult, dl_drgb) -> G
     bg = np.asarray(opts.bg, dtype=np.float64)
     S = fwd.T_final.reshape(-1)[:, None] * bg[None, :]
     S = np.array(S)
+    # grids of one side: one [P,N,N,3] array; of several sides: one [n_k,n_k,3] array each
+    dtex = (np.zeros((P, N, N, 3)) if isinstance(scene.textures, np.ndarray)
+            else [np.zeros(np.shape(g)) for g in scene.textures])
     gr = Grads(np.zeros((P, 3)), np.zeros((P, 3)), np.zeros((P, 3)), np.zeros((P, 2)),
-               np.zeros(P), np.zeros((P, N, N, 3)),
+               np.zeros(P), dtex,
                None if scene.sh is None else np.zeros(scene.sh.shape), np.zeros((P, 2)))
     Kmat = intrinsics(view)
     R = np.asarray(view.R, dtype=np.float64)

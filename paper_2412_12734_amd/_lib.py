@@ -41,7 +41,8 @@ class GbSplats(ctypes.Structure):
     _fields_ = [("P", c_int32), ("N", c_int32), ("tex_dtype", c_int32), ("means", c_void_p),
                 ("tan_u", c_void_p), ("tan_v", c_void_p), ("scales", c_void_p),
                 ("opacity", c_void_p), ("textures", c_void_p), ("sh_degree", c_int32),
-                ("sh", c_void_p)]
+                ("sh", c_void_p), ("tex_side", c_void_p), ("tex_offset", c_void_p),
+                ("n_texels", c_int64)]
 
 
 class GbOptions(ctypes.Structure):

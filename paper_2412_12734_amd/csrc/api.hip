@@ -96,6 +96,15 @@ gb_status validate_splats(const gb_splats* s) {
   for (const void* p : ptrs)
     if (!p || !aligned(p, 4)) return arg_fail("splat array NULL or not 4-byte aligned");
   if (!s->textures || !aligned(s->textures, 16)) return arg_fail("textures NULL or not 16-byte aligned");
+  if (s->tex_side) {
+    if (s->N != 8 && s->N != 16) {
+      g_last_error = "with tex_side the layout side N must be 8 or 16";
+      return GB_ERR_UNSUPPORTED;
+    }
+    if (!s->tex_offset || !aligned(s->tex_side, 4) || !aligned(s->tex_offset, 8))
+      return arg_fail("tex_offset NULL, or tex_side / tex_offset misaligned");
+    if (s->n_texels < 1) return arg_fail("n_texels must be >= 1 with tex_side");
+  }
   if (s->sh) {
     if (s->sh_degree < 0 || s->sh_degree > 3) {
       g_last_error = "sh_degree must be 0, 1, 2 or 3";
@@ -843,8 +852,8 @@ gb_status gb_render_bwd(const gb_splats* s, const gb_view* views, int32_t n_view
   if (d_spec)
     GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_spec), 0u, 4 * pl.VP, hs),
             "clear d_spec");
-  GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(g->d_textures), 0u,
-                          (int64_t)s->P * 3 * s->N * s->N, hs),
+  const int64_t tex_values = s->tex_side ? 3 * s->n_texels : (int64_t)s->P * 3 * s->N * s->N;
+  GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(g->d_textures), 0u, tex_values, hs),
           "clear d_textures");
   // the backward takes the tiles with the longest blended spans (saved by the forward) first
   const uint32_t* tile_order = nullptr;

@@ -45,10 +45,12 @@ struct PixOut {
 // transmittance factor, so that all of its outputs are zero and its state is unchanged
 // without a branch or zeroed outputs; its u, v and 1 / rho2 are replaced by 0 (they are
 // infinite where rho2 = 0). Its cell and corner weights are left unspecified.
-template <int N>
+// MIXED: the splat's grid has gn texels per side (at most N) and uv -> grid slope gscale.
+template <int N, bool MIXED = false>
 __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex,
                                            const PixelEval& e, bool act, PixState& ps,
-                                           const BlendParams& p, PixOut& o) {
+                                           const BlendParams& p, PixOut& o, int gn = N,
+                                           float gscale = 0.f) {
   o.act = act;
   const float inv = act ? e.inv : 0.f;
   const float u = act ? e.u : 0.f, v = act ? e.v : 0.f;
@@ -71,8 +73,13 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
   } else {
     int iu, iv;
     float fu, fv;
-    grid_coord<N>(u, p, iu, fu);
-    grid_coord<N>(v, p, iv, fv);
+    if constexpr (MIXED) {
+      grid_coord_n(u, gscale, gn, iu, fu);
+      grid_coord_n(v, gscale, gn, iv, fv);
+    } else {
+      grid_coord<N>(u, p, iu, fu);
+      grid_coord<N>(v, p, iv, fv);
+    }
     o.k00 = iu * N + iv;
     const int l00 = TexLayout<N>::at(iu, iv), kr = TexLayout<N>::kRow;
     const float4 t00 = tex[l00], t01 = tex[l00 + 1], t10 = tex[l00 + kr], t11 = tex[l00 + kr + 1];
@@ -92,8 +99,9 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
     const float fv1 = (t01.y - t00.y) * (1.f - fu) + (t11.y - t10.y) * fu;
     const float fv2 = (t01.z - t00.z) * (1.f - fu) + (t11.z - t10.z) * fu;
     const float dfv = o.dc0 * fv0 + o.dc1 * fv1 + o.dc2 * fv2;
-    du = (u > -p.sigma && u < p.sigma) ? p.tex_scale * dfu : 0.f;
-    dv = (v > -p.sigma && v < p.sigma) ? p.tex_scale * dfv : 0.f;
+    const float tsc = MIXED ? gscale : p.tex_scale;
+    du = (u > -p.sigma && u < p.sigma) ? tsc * dfu : 0.f;
+    dv = (v > -p.sigma && v < p.sigma) ? tsc * dfv : 0.f;
   }
   const float dalpha_act = ps.g0 * (c0 * ps.T - ps.S0 * inv1m) +
                            ps.g1 * (c1 * ps.T - ps.S1 * inv1m) + ps.g2 * (c2 * ps.T - ps.S2 * inv1m);
@@ -145,7 +153,9 @@ constexpr int bwd_min_waves() { return (B <= 8 && N <= 8) ? 7 : 1; }
 // Depth-prefix split: on a tile that the prefix left open the block first walks the rest
 // pass's list (the later splats) and then, with each pixel's T and S carried over in
 // registers, the prefix pass's list; other tiles only walk the prefix list.
-template <int N, bool BF16, int B, int PIX>
+// MIXED: each splat has a grid side of its own (at most N), read from p.grid_n; its texel
+// gradients go to its own n x n grid at p.grid_at.
+template <int N, bool BF16, int B, int PIX, bool MIXED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(bwd_min_waves<N, B>())))
 blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__ rec,
                  PairList first, PairList rest, const uint32_t* __restrict__ open_bits,
@@ -162,6 +172,9 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   __shared__ float s_gtex[B * TEXG];
   __shared__ float s_grec[B * kRecGrad];  // per splat
   __shared__ uint32_t s_tile_last;
+  __shared__ int32_t s_gn[MIXED ? B : 1];
+  __shared__ float s_gscale[MIXED ? B : 1];
+  __shared__ int64_t s_toff[MIXED ? B : 1];
 
   const int tile = tile_of_block(p);
   if (tile >= p.total_tiles) return;
@@ -264,12 +277,22 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
           if (b == 0) {
             s_splat[j] = R.splat;
             s_recid[j] = r;
+            if (MIXED) {
+              const int n = grid_side<N>(p, r - rec_base);
+              s_gn[j] = n;
+              s_gscale[j] = grid_scale(n, p.sigma);
+              s_toff[j] = p.grid_at[r - rec_base];
+            }
           }
         }
       }
       for (int e = tid; e < nb * TEXG; e += nthr) s_gtex[e] = 0.f;
       for (int e = tid; e < nb * kRecGrad; e += nthr) s_grec[e] = 0.f;
-      stage_texels<N, BF16>(textures, pair_vals + bstart, rec_base, nb, s_tex, p.spec);
+      if constexpr (MIXED)
+        stage_texels_mixed<N, BF16>(textures, pair_vals + bstart, rec_base, nb, s_tex, p.spec,
+                                    p.grid_n, p.grid_at);
+      else
+        stage_texels<N, BF16>(textures, pair_vals + bstart, rec_base, nb, s_tex, p.spec);
       __syncthreads();
 
       // splats of this batch that can reach the wave's block, walked back to front
@@ -292,8 +315,16 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
         }
         if (!__any(wave_act)) continue;  // no pixel of the wave blended this splat
         PixOut po[PIX];
+        if constexpr (MIXED) {
+          const int gn = s_gn[j];
+          const float gscale = s_gscale[j];
 #pragma unroll
-        for (int s = 0; s < PIX; ++s) pixel_step<N>(g, tex, e[s], act[s], ps[s], p, po[s]);
+          for (int s = 0; s < PIX; ++s)
+            pixel_step<N, true>(g, tex, e[s], act[s], ps[s], p, po[s], gn, gscale);
+        } else {
+#pragma unroll
+          for (int s = 0; s < PIX; ++s) pixel_step<N>(g, tex, e[s], act[s], ps[s], p, po[s]);
+        }
 
         // Wave sums of the per-splat scalars (a lane first adds its own pixels); the one lane
         // that owns each total adds it to the splat's LDS slot.
@@ -401,7 +432,13 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
         const float x = s_gtex[e];
         if (x != 0.f) {
           const int j = e / TEXG, r = e - j * TEXG;
-          atomicAdd(&d_tex[(int64_t)s_splat[j] * TEXG + r], x);
+          if constexpr (MIXED) {
+            // the N x N sums hold the splat's n x n grid in rows and columns [0, n)
+            const int t = r / 3, c = r - 3 * t, iu = t / N, iv = t - iu * N, n = s_gn[j];
+            if (iu < n && iv < n) atomicAdd(&d_tex[3 * (s_toff[j] + iu * n + iv) + c], x);
+          } else {
+            atomicAdd(&d_tex[(int64_t)s_splat[j] * TEXG + r], x);
+          }
         }
       }
       for (int e = tid; e < nb * kRecGrad; e += nthr) {
@@ -415,7 +452,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   }  // lists
 }
 
-template <int N, bool BF16, int PIX>
+template <int N, bool BF16, int PIX, bool MIXED = false>
 hipError_t launch_np(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
                      const ViewDev* views, const SplatRec* rec, const PairList& first,
                      const PairList& rest, const uint32_t* open_bits, const float* T_final,
@@ -424,8 +461,8 @@ hipError_t launch_np(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
                                            : 8 * (int64_t)bp.tiles_per_xcd));
   const dim3 block((unsigned)(pl.tile_w * pl.tile_h / PIX));
 #define GBB_BWD_B(BB)                                                                         \
-  hipLaunchKernelGGL((blend_bwd_kernel<N, BF16, BB, PIX>), grid, block, 0, s, views, rec, first, \
-                     rest, open_bits, sp.textures, bp, T_final, d_rgb, d_rec, d_tex)
+  hipLaunchKernelGGL((blend_bwd_kernel<N, BF16, BB, PIX, MIXED>), grid, block, 0, s, views, rec, \
+                     first, rest, open_bits, sp.textures, bp, T_final, d_rgb, d_rec, d_tex)
   if constexpr (N >= 16) {
     GBB_BWD_B(8);  // the only batch built for N = 16 (LDS)
   } else {
@@ -452,6 +489,20 @@ hipError_t launch_blend_bwd(const Plan& pl, const gb_splats& sp, const gb_option
   bp.spec = spec;
   bp.d_spec = d_spec;
   const bool bf = sp.tex_dtype == GB_BF16;
+  if (sp.tex_side) {
+    // grids of several sides in the N x N layout (N = 8 or 16, checked by the API)
+    bp.grid_n = sp.tex_side;
+    bp.grid_at = sp.tex_offset;
+    if (pl.N == 16)
+      return bf ? launch_np<16, true, 1, true>(pl, sp, bp, views, rec, first, rest, open_bits,
+                                               T_final, d_rgb, d_rec, d_tex, s)
+                : launch_np<16, false, 1, true>(pl, sp, bp, views, rec, first, rest, open_bits,
+                                                T_final, d_rgb, d_rec, d_tex, s);
+    return bf ? launch_np<8, true, 1, true>(pl, sp, bp, views, rec, first, rest, open_bits,
+                                            T_final, d_rgb, d_rec, d_tex, s)
+              : launch_np<8, false, 1, true>(pl, sp, bp, views, rec, first, rest, open_bits,
+                                             T_final, d_rgb, d_rec, d_tex, s);
+  }
   // One pixel per lane. Two pixels per lane (8 x 16 wave blocks) measured slower on the
   // 1M-splat 1080p workload (3.0 vs 2.3 ms): LDS limits such blocks to two waves per SIMD and
   // the per-wave cull is coarser.

@@ -27,6 +27,10 @@ struct BlendParams {
   // the backward's adjoint of it (nullable; xyz summed over the record's blended pixels)
   const float4* spec;
   float* d_spec;
+  // colour grids of several sides (nullable: every grid is N x N): per splat its side and the
+  // index of its first texel in the packed texture array
+  const int32_t* grid_n;
+  const int64_t* grid_at;
 };
 
 BlendParams make_blend_params(const Plan& pl, const gb_options& o, int n_views);
@@ -192,6 +196,48 @@ __device__ __forceinline__ void stage_texels(const void* __restrict__ textures,
   }
 }
 
+// Copies the texels of `nb` staged splats whose grids have sides of their own (at most N) into
+// the N x N LDS layout: splat j's n x n texels go to rows and columns [0, n). A one-texel grid
+// is also copied to (0, 1), (1, 0) and (1, 1), so that the bilinear lookup, which reads the four
+// corners of cell (0, 0) with weights (1, 0, 0, 0) there, reads finite values. As in
+// stage_texels, spec (nullable) adds each record's view-dependent colour.
+template <int N, bool BF16>
+__device__ __forceinline__ void stage_texels_mixed(const void* __restrict__ textures,
+                                                   const uint32_t* __restrict__ pairs,
+                                                   uint32_t rec_base, int nb, float4* s_tex,
+                                                   const float4* __restrict__ spec,
+                                                   const int32_t* __restrict__ side,
+                                                   const int64_t* __restrict__ toff) {
+  constexpr int per = 3 * N * N;
+  for (int e = threadIdx.x; e < nb * per; e += blockDim.x) {
+    const int j = e / per, r = e - j * per;
+    const int t = r / 3, c = r - 3 * t, iu = t / N, iv = t - iu * N;
+    const uint32_t k = pairs[j] - rec_base;
+    const int n = min(max(side[k], 1), N);
+    if (n == 1 ? (iu > 1 || iv > 1) : (iu >= n || iv >= n)) continue;
+    const int64_t src = 3 * (toff[k] + (n == 1 ? 0 : iu * n + iv)) + c;
+    float x = BF16 ? bf16_to_f32(reinterpret_cast<const uint16_t*>(textures)[src])
+                   : reinterpret_cast<const float*>(textures)[src];
+    if (spec) {
+      const float4 sc = spec[pairs[j]];
+      x += c == 0 ? sc.x : c == 1 ? sc.y : sc.z;
+    }
+    reinterpret_cast<float*>(s_tex + j * TexLayout<N>::kPerSplat + TexLayout<N>::at(iu, iv))[c] = x;
+  }
+}
+
+// Side of splat k's grid in a call with several sides, clamped to [1, N].
+template <int N>
+__device__ __forceinline__ int grid_side(const BlendParams& p, uint32_t k) {
+  return min(max(p.grid_n[k], 1), N);
+}
+
+// Slope of the uv -> grid map of an n-texel side, formed as the host forms it for a uniform
+// side (a call whose sides all equal N then matches the uniform path bit for bit).
+__device__ __forceinline__ float grid_scale(int n, float sigma) {
+  return (float)(n - 1) / (2.0f * sigma);
+}
+
 // Ray-splat solve and falloff of one splat at one pixel.
 struct PixelEval {
   float dx, dy;       // pixel centre minus projected centre (float32; low-pass and gradients)
@@ -265,6 +311,17 @@ __device__ __forceinline__ void grid_coord(float u, const BlendParams& p, int& i
   const float up = fminf(fmaxf(__builtin_fmaf(u, p.tex_scale, p.tex_offset), 0.0f), (float)(N - 1));
   const int fi = (int)up;  // up >= 0, so truncation is the floor
   i = fi < N - 2 ? fi : N - 2;
+  f = up - (float)i;
+}
+
+// The same for a grid of n texels per side with slope `scale` (grid_scale): one texel gives
+// cell 0 with f = 0.
+__device__ __forceinline__ void grid_coord_n(float u, float scale, int n, int& i, float& f) {
+  const float hi = (float)(n - 1);
+  const float up = fminf(fmaxf(__builtin_fmaf(u, scale, 0.5f * hi), 0.0f), hi);
+  const int fi = (int)up;
+  const int cmax = n > 2 ? n - 2 : 0;
+  i = fi < cmax ? fi : cmax;
   f = up - (float)i;
 }
 

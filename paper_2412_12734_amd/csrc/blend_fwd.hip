@@ -30,7 +30,8 @@ constexpr int fwd_min_waves() {
   return 160 * 1024 / lds < 8 ? 160 * 1024 / lds : 8;
 }
 
-template <int N, bool BF16, int B, bool STATS, bool REST>
+// MIXED: each splat has a grid side of its own (at most N), read from p.grid_n.
+template <int N, bool BF16, int B, bool STATS, bool REST, bool MIXED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fwd_min_waves<N, B>())))
 blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__ rec,
                  const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ ranges,
@@ -40,6 +41,9 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   __shared__ GeoLds<B> s_geo;
   __shared__ float4 s_tex[B * TexLayout<N>::kPerSplat];
   __shared__ uint8_t s_reach[4][B];  // [wave block][staged splat]: may reach the block
+  // MIXED: side and uv -> grid slope of each staged splat's grid
+  __shared__ int32_t s_gn[MIXED ? B : 1];
+  __shared__ float s_gscale[MIXED ? B : 1];
   static_assert((B & (B - 1)) == 0, "batch sizes are powers of two");
 
   const int tile = tile_of_block(p);
@@ -99,13 +103,22 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
         const int kbx = tile_x0 + (b % waves_x) * 8, kby = tile_y0 + (b / waves_x) * 8;
         const StagedGeo g = stage_geo(R, kbx + 4, kby + 4, tcx, tcy);
         s_geo.store(b, j, g);
+        if (MIXED && b == 0) {
+          const int n = grid_side<N>(p, r - rec_base);
+          s_gn[j] = n;
+          s_gscale[j] = grid_scale(n, p.sigma);
+        }
         s_reach[b][j] =
             block_may_contribute(g, (float)(kbx + 4 - tcx), (float)(kby + 4 - tcy), kbx, kby, p)
                 ? 1
                 : 0;
       }
     }
-    stage_texels<N, BF16>(textures, pair_vals + b0, rec_base, nb, s_tex, p.spec);
+    if constexpr (MIXED)
+      stage_texels_mixed<N, BF16>(textures, pair_vals + b0, rec_base, nb, s_tex, p.spec,
+                                  p.grid_n, p.grid_at);
+    else
+      stage_texels<N, BF16>(textures, pair_vals + b0, rec_base, nb, s_tex, p.spec);
     __syncthreads();
 
     if (!__all(done)) {
@@ -135,8 +148,15 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
             } else {
               int iu, iv;
               float fu, fv;
-              grid_coord<N>(e.u, p, iu, fu);
-              grid_coord<N>(e.v, p, iv, fv);
+              if constexpr (MIXED) {
+                const int n = s_gn[j];
+                const float sc = s_gscale[j];
+                grid_coord_n(e.u, sc, n, iu, fu);
+                grid_coord_n(e.v, sc, n, iv, fv);
+              } else {
+                grid_coord<N>(e.u, p, iu, fu);
+                grid_coord<N>(e.v, p, iv, fv);
+              }
               const int k00 = TexLayout<N>::at(iu, iv), kr = TexLayout<N>::kRow;
               const float4 t00 = tex[k00], t01 = tex[k00 + 1];
               const float4 t10 = tex[k00 + kr], t11 = tex[k00 + kr + 1];
@@ -207,7 +227,7 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   }
 }
 
-template <int N, bool BF16, bool STATS, bool REST>
+template <int N, bool BF16, bool STATS, bool REST, bool MIXED>
 hipError_t launch_n(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
                     const ViewDev* views, const SplatRec* rec, const uint32_t* pair_vals,
                     const uint32_t* ranges, float* rgb, float* T_final, uint32_t* n_last,
@@ -216,7 +236,8 @@ hipError_t launch_n(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
                                            : 8 * (int64_t)bp.tiles_per_xcd));
   const dim3 block((unsigned)(pl.tile_w * pl.tile_h));
 #define GBB_FWD_B(BB)                                                                        \
-  hipLaunchKernelGGL((blend_fwd_kernel<N, BF16, BB, STATS, REST>), grid, block, 0, s, views, \
+  hipLaunchKernelGGL((blend_fwd_kernel<N, BF16, BB, STATS, REST, MIXED>), grid, block, 0, s,   \
+                     views,                                                                   \
                      rec, pair_vals, ranges, sp.textures, bp, rgb, T_final, n_last, split,    \
                      stats)
   if constexpr (N >= 16) {
@@ -233,21 +254,24 @@ hipError_t launch_n(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
   return hipGetLastError();
 }
 
-template <int N, bool BF16>
+template <int N, bool BF16, bool MIXED = false>
 hipError_t launch_nb(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
                      const ViewDev* views, const SplatRec* rec, const uint32_t* pair_vals,
                      const uint32_t* ranges, float* rgb, float* T_final, uint32_t* n_last,
                      const SplitState& split, unsigned long long* stats, hipStream_t s) {
   const bool rest = split.mode == kRestPass;
   if (stats)
-    return rest ? launch_n<N, BF16, true, true>(pl, sp, bp, views, rec, pair_vals, ranges, rgb,
-                                                T_final, n_last, split, stats, s)
-                : launch_n<N, BF16, true, false>(pl, sp, bp, views, rec, pair_vals, ranges, rgb,
-                                                 T_final, n_last, split, stats, s);
-  return rest ? launch_n<N, BF16, false, true>(pl, sp, bp, views, rec, pair_vals, ranges, rgb,
-                                               T_final, n_last, split, stats, s)
-              : launch_n<N, BF16, false, false>(pl, sp, bp, views, rec, pair_vals, ranges, rgb,
-                                                T_final, n_last, split, stats, s);
+    return rest ? launch_n<N, BF16, true, true, MIXED>(pl, sp, bp, views, rec, pair_vals,
+                                                       ranges, rgb, T_final, n_last, split,
+                                                       stats, s)
+                : launch_n<N, BF16, true, false, MIXED>(pl, sp, bp, views, rec, pair_vals,
+                                                        ranges, rgb, T_final, n_last, split,
+                                                        stats, s);
+  return rest ? launch_n<N, BF16, false, true, MIXED>(pl, sp, bp, views, rec, pair_vals, ranges,
+                                                      rgb, T_final, n_last, split, stats, s)
+              : launch_n<N, BF16, false, false, MIXED>(pl, sp, bp, views, rec, pair_vals,
+                                                       ranges, rgb, T_final, n_last, split,
+                                                       stats, s);
 }
 
 }  // namespace
@@ -276,6 +300,8 @@ BlendParams make_blend_params(const Plan& pl, const gb_options& o, int n_views) 
   bp.tile_work = nullptr;
   bp.spec = nullptr;
   bp.d_spec = nullptr;
+  bp.grid_n = nullptr;
+  bp.grid_at = nullptr;
   return bp;
 }
 
@@ -291,6 +317,20 @@ hipError_t launch_blend_fwd(const Plan& pl, const gb_splats& sp, const gb_option
   bp.tile_work = tile_work;
   bp.spec = spec;
   const bool bf = sp.tex_dtype == GB_BF16;
+  if (sp.tex_side) {
+    // grids of several sides, staged into the N x N layout (N = 8 or 16, checked by the API)
+    bp.grid_n = sp.tex_side;
+    bp.grid_at = sp.tex_offset;
+    if (pl.N == 16)
+      return bf ? launch_nb<16, true, true>(pl, sp, bp, views, rec, pair_vals, ranges, rgb,
+                                            T_final, n_last, split, stats, s)
+                : launch_nb<16, false, true>(pl, sp, bp, views, rec, pair_vals, ranges, rgb,
+                                             T_final, n_last, split, stats, s);
+    return bf ? launch_nb<8, true, true>(pl, sp, bp, views, rec, pair_vals, ranges, rgb, T_final,
+                                         n_last, split, stats, s)
+              : launch_nb<8, false, true>(pl, sp, bp, views, rec, pair_vals, ranges, rgb,
+                                          T_final, n_last, split, stats, s);
+  }
 #define GBB_FWD(NN)                                                                          \
   return bf ? launch_nb<NN, true>(pl, sp, bp, views, rec, pair_vals, ranges, rgb, T_final,   \
                                   n_last, split, stats, s)                                   \

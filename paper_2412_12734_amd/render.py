@@ -9,6 +9,7 @@ import ctypes
 import dataclasses
 from typing import Optional, Sequence, Tuple
 
+import numpy as np
 import torch
 
 from . import _lib as L
@@ -50,20 +51,39 @@ def _stream(device) -> int:
 class Splats:
     """Device views of the per-splat arrays in the layout the library expects. ``sh``
     (optional, [P, (D+1)^2, 3] float32) holds the spherical-harmonic coefficients of the
-    view-dependent colour term."""
+    view-dependent colour term.
 
-    def __init__(self, means, tan_u, tan_v, scales, opacity, textures, sh=None):
+    Colour grids of several sides: with ``tex_side`` ([P] int32, each side in [1, layout_side])
+    and ``tex_offset`` ([P] int64, the first texel of each grid), ``textures`` is the packed
+    [n_texels, 3] array of all grids, each [n][n][3] row-major, and ``layout_side`` (8 or 16)
+    is the largest side allowed; texture gradients then come back in the same packed layout."""
+
+    def __init__(self, means, tan_u, tan_v, scales, opacity, textures, sh=None, tex_side=None,
+                 tex_offset=None, layout_side=None):
         self.means, self.tan_u, self.tan_v = means, tan_u, tan_v
         self.scales, self.opacity, self.textures = scales, opacity, textures
         self.sh = sh
+        self.tex_side, self.tex_offset = tex_side, tex_offset
         for name in ("means", "tan_u", "tan_v", "scales", "opacity"):
             t = getattr(self, name)
             if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
                 raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
         if textures.dtype not in (torch.float32, torch.bfloat16) or not textures.is_contiguous():
-            raise ValueError("textures must be contiguous float32 or bfloat16 [P,N,N,3]")
+            raise ValueError("textures must be contiguous float32 or bfloat16")
         self.P = int(means.shape[0])
-        self.N = int(textures.shape[1])
+        if tex_side is None:
+            self.N = int(textures.shape[1])
+            self.n_texels = self.P * self.N * self.N
+        else:
+            if (tex_side.dtype != torch.int32 or tex_offset is None
+                    or tex_offset.dtype != torch.int64 or not tex_side.is_contiguous()
+                    or not tex_offset.is_contiguous() or tex_side.shape[0] != self.P
+                    or tex_offset.shape[0] != self.P or layout_side not in (8, 16)
+                    or textures.dim() != 2 or textures.shape[1] != 3):
+                raise ValueError("mixed grids take tex_side int32 [P], tex_offset int64 [P], "
+                                 "layout_side 8 or 16 and packed textures [n_texels, 3]")
+            self.N = int(layout_side)
+            self.n_texels = int(textures.shape[0])
         self.sh_degree = -1
         if sh is not None:
             n = int(sh.shape[1])
@@ -73,21 +93,40 @@ class Splats:
                 raise ValueError("sh must be contiguous float32 [P, (D+1)^2, 3] with D <= 3")
             self.sh_degree = d
 
+    @property
+    def mixed(self) -> bool:
+        return self.tex_side is not None
+
     @staticmethod
     def from_numpy(scene, device="cuda", tex_bf16: bool = False) -> "Splats":
+        """From a scene whose textures are one [P,N,N,3] array, or a list of per-splat [n,n,3]
+        grids of several sides (packed here in splat order)."""
         f = lambda a: torch.from_numpy(a).to(device)
-        tex = torch.from_numpy(scene.textures).to(device)
+        sh = getattr(scene, "sh", None)
+        side = off = layout = None
+        if isinstance(scene.textures, np.ndarray):
+            tex = torch.from_numpy(scene.textures).to(device)
+        else:
+            sides = np.array([g.shape[0] for g in scene.textures], dtype=np.int32)
+            offsets = np.zeros(len(sides), dtype=np.int64)
+            offsets[1:] = np.cumsum(sides.astype(np.int64) ** 2)[:-1]
+            packed = np.concatenate([np.asarray(g, dtype=np.float32).reshape(-1, 3)
+                                     for g in scene.textures])
+            tex = torch.from_numpy(np.ascontiguousarray(packed)).to(device)
+            side, off = f(sides), f(offsets)
+            layout = 8 if int(sides.max()) <= 8 else 16
         if tex_bf16:
             tex = tex.to(torch.bfloat16)
-        sh = getattr(scene, "sh", None)
         return Splats(f(scene.means), f(scene.tan_u), f(scene.tan_v), f(scene.scales),
-                      f(scene.opacity), tex, None if sh is None else f(sh))
+                      f(scene.opacity), tex, None if sh is None else f(sh), side, off, layout)
 
     def c(self) -> L.GbSplats:
         dt = L.GB_BF16 if self.textures.dtype == torch.bfloat16 else L.GB_F32
         return L.GbSplats(self.P, self.N, dt, _ptr(self.means), _ptr(self.tan_u),
                           _ptr(self.tan_v), _ptr(self.scales), _ptr(self.opacity),
-                          _ptr(self.textures), max(self.sh_degree, 0), _ptr(self.sh))
+                          _ptr(self.textures), max(self.sh_degree, 0), _ptr(self.sh),
+                          _ptr(self.tex_side), _ptr(self.tex_offset),
+                          self.n_texels if self.mixed else 0)
 
 
 class Rasterizer:
@@ -199,7 +238,7 @@ class Rasterizer:
             z = lambda *s: torch.empty(s, dtype=torch.float32, device=self.device)
             grads = dict(means=z(sp.P, 3), tan_u=z(sp.P, 3), tan_v=z(sp.P, 3),
                          scales=z(sp.P, 2), opacity=z(sp.P),
-                         textures=z(sp.P, sp.N, sp.N, 3))
+                         textures=(z(sp.n_texels, 3) if sp.mixed else z(sp.P, sp.N, sp.N, 3)))
         if sp.sh is not None and grads.get("sh") is None:
             grads["sh"] = torch.empty_like(sp.sh)
         d_rgb = d_rgb.contiguous().float()

@@ -24,6 +24,7 @@ import numpy as np
 __all__ = [
     "Scene", "View", "make_scene", "look_at_view", "frontal_view", "orbit_views",
     "make_dl_drgb", "to_bf16_bits", "bf16_bits_to_f32", "CONFIGS", "config", "with_sh",
+    "with_mixed_sides",
 ]
 
 
@@ -35,7 +36,8 @@ class Scene:
     tan_v: np.ndarray      # [P,3]
     scales: np.ndarray     # [P,2]  (s_u, s_v) > 0
     opacity: np.ndarray    # [P]    in (0, 1)
-    textures: np.ndarray   # [P,N,N,3] indexed [k, i_u, i_v, c]
+    textures: np.ndarray   # [P,N,N,3] indexed [k, i_u, i_v, c], or a list of P grids
+                           # [n_k, n_k, 3] of several sides
     # optional per-splat spherical-harmonic coefficients of the view-dependent colour term,
     # [P, (degree + 1)^2, 3] (None: no such term)
     sh: Optional[np.ndarray] = None
@@ -46,7 +48,10 @@ class Scene:
 
     @property
     def N(self) -> int:
-        return int(self.textures.shape[1])
+        """Texture side (the largest side when the grids have several)."""
+        if isinstance(self.textures, np.ndarray):
+            return int(self.textures.shape[1])
+        return max(int(g.shape[0]) for g in self.textures)
 
     @property
     def sh_degree(self) -> int:
@@ -55,9 +60,12 @@ class Scene:
 
     def subset(self, idx) -> "Scene":
         sh = None if self.sh is None else np.ascontiguousarray(self.sh[idx])
+        if isinstance(self.textures, np.ndarray):
+            tex = np.ascontiguousarray(self.textures[idx])
+        else:
+            tex = [self.textures[int(i)] for i in np.arange(self.P)[idx]]
         return Scene(*(np.ascontiguousarray(a[idx]) for a in
-                       (self.means, self.tan_u, self.tan_v, self.scales, self.opacity,
-                        self.textures)), sh)
+                       (self.means, self.tan_u, self.tan_v, self.scales, self.opacity)), tex, sh)
 
 
 @dataclasses.dataclass
@@ -160,6 +168,16 @@ def make_scene(seed: int, P: int, lo: float, hi: float, s_lo: float, s_hi: float
             part[...] = bf16_bits_to_f32(to_bf16_bits(part)).reshape(part.shape)
     f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
     return Scene(f32(means), f32(tu), f32(tv), f32(scales), f32(opacity), tex)
+
+
+def with_mixed_sides(scene: Scene, seed: int, sides) -> Scene:
+    """The scene with colour grids of several sides: splat k gets a side drawn uniformly from
+    ``sides`` and a grid of that side U(0, 1), from their own stream (float32 values)."""
+    rng = np.random.default_rng(seed)
+    sides = np.asarray(sides, dtype=np.int64)
+    n = sides[rng.integers(0, sides.size, scene.P)]
+    grids = [rng.uniform(0.0, 1.0, (int(m), int(m), 3)).astype(np.float32) for m in n]
+    return dataclasses.replace(scene, textures=grids)
 
 
 def with_sh(scene: Scene, seed: int, degree: int, scale: float = 0.2) -> Scene:

@@ -41,9 +41,10 @@ def test_struct_sizes_match_header_layout():
     # gb_view: 2 ints + 4 floats + 9 + 3 + 1 floats
     assert ctypes.sizeof(L.GbView) == 4 * (2 + 4 + 9 + 3 + 1)
     assert ctypes.sizeof(L.GbOptions) == 4 * (5 + 3 + 6)
-    # P, N, tex_dtype, pad, six pointers, sh_degree, pad, one pointer
-    assert ctypes.sizeof(L.GbSplats) == 16 + 6 * 8 + 8 + 8
+    # P, N, tex_dtype, pad, six pointers, sh_degree, pad, sh, tex_side, tex_offset, n_texels
+    assert ctypes.sizeof(L.GbSplats) == 16 + 6 * 8 + 8 + 8 + 3 * 8
     assert L.GbSplats.sh.offset == 16 + 6 * 8 + 8
+    assert L.GbSplats.n_texels.offset == 16 + 6 * 8 + 8 + 8 + 2 * 8
     assert ctypes.sizeof(L.GbGrads) == 7 * 8
     assert ctypes.sizeof(L.GbLayout) == 8 * 20
 
@@ -136,6 +137,31 @@ def test_render_rejects_null_pointers_before_launching():
                            None, None)
     assert st == L.GB_ERR_ARG
     assert b"NULL" in lib.gb_last_error()
+
+
+def test_mixed_grid_sides_are_checked_before_launching():
+    """Grids of several sides need the layout side 8 or 16, a tex_offset array and n_texels;
+    each refusal comes before any device access."""
+    lib = _lib()
+    views = L.make_views([sg.look_at_view((0, 0, -3), 32, 32)])
+    opts = L.make_options()
+    buf = ctypes.create_string_buffer(256)
+    base = ctypes.addressof(buf)
+    p16 = base + (-base) % 16
+
+    def fwd(N, side, offset, n_texels):
+        sp = L.GbSplats(10, N, L.GB_F32, p16, p16, p16, p16, p16, p16, 0, None, side, offset,
+                        n_texels)
+        return lib.gb_render_fwd(ctypes.byref(sp), views, 1, ctypes.byref(opts), None, 0, 0,
+                                 None, None, None)
+
+    assert fwd(4, p16, p16, 100) == L.GB_ERR_UNSUPPORTED  # layout side must be 8 or 16
+    assert b"8 or 16" in lib.gb_last_error()
+    assert fwd(8, p16, None, 100) == L.GB_ERR_ARG  # offsets missing
+    assert fwd(16, p16, p16, 0) == L.GB_ERR_ARG  # no texels
+    assert fwd(8, p16 + 2, p16, 100) == L.GB_ERR_ARG  # misaligned sides
+    # the sides' checks passed: the next refusal is the missing workspace
+    assert fwd(8, p16, p16, 100) == L.GB_ERR_ARG and b"workspace" in lib.gb_last_error()
 
 
 def test_training_glue_rejects_invalid_arguments_before_any_launch():

@@ -246,6 +246,8 @@ def check_grads(gb, scene, view, opts, crop, seed=0, tex_bf16=False, batch=0, ba
     for name in names:
         got = grads[name].cpu().numpy().astype(np.float64)
         want = getattr(ref_g, name)
+        if isinstance(want, list):  # grids of several sides: packed in splat order
+            want = np.concatenate([np.asarray(w).reshape(-1, 3) for w in want])
         errs[name] = rel_l2(got, want)
         # element-wise error against the tensor's scale, 99.9th percentile (reported only)
         scale = np.abs(want) + np.sqrt(np.mean(want * want))
@@ -904,3 +906,52 @@ def test_specular_sh_full_size_crop(gb):
     """Degree-3 coefficients on the 1M-splat 1080p workload: a 64 x 64 crop against the oracle
     (image and every gradient, coefficients included)."""
     check_full_size_crop(gb, "T0", 0, sh_degree=3)
+
+
+# --- colour grids of several sides in one call -------------------------------------------------
+def _bf16_grids(scene):
+    r = lambda g: sg.bf16_bits_to_f32(sg.to_bf16_bits(g)).reshape(g.shape).astype(np.float32)
+    return sg.Scene(scene.means, scene.tan_u, scene.tan_v, scene.scales, scene.opacity,
+                    [r(g) for g in scene.textures], scene.sh)
+
+
+@pytest.mark.parametrize("layout,sides,bf16", [(8, (1, 2, 3, 5, 8), False),
+                                               (16, (1, 4, 7, 12, 16), False),
+                                               (8, (2, 4, 6, 8), True)])
+def test_mixed_sides_image_and_gradients(gb, layout, sides, bf16):
+    """Splats whose grids have sides of their own (any side up to the layout's 8 or 16, packed
+    in one array with per-splat offsets) against the oracle: images, and every gradient
+    including each splat's own grid."""
+    scene = sg.with_mixed_sides(sg.make_scene(90 + layout, 2500, -1.2, 1.2, 0.01, 0.3, layout),
+                                7 + layout, sides)
+    if bf16:
+        scene = _bf16_grids(scene)
+    view = sg.look_at_view((0.4, 0.2, -3.0), 88, 72)
+    opts = O.Options(bg=(0.2, 0.1, 0.3))
+    rast, sp, rgb, T = run_gpu(gb, scene, [view], opts, tex_bf16=bf16)
+    assert sp.mixed and sp.N == layout
+    ref = O.render(scene, view, opts)
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 88, 72, scene, view, opts)
+    check_grads(gb, scene, view, opts, (12, 8, 64, 56), seed=layout, tex_bf16=bf16)
+
+
+def test_mixed_sides_all_equal_match_the_uniform_path(gb):
+    """The same grids given once as a [P, N, N, 3] array and once through per-splat sides (all
+    N) render bit for bit alike, and their gradients agree to float32 summation order."""
+    base = sg.make_scene(95, 3000, -1.2, 1.2, 0.01, 0.3, 8)
+    mixed = sg.Scene(base.means, base.tan_u, base.tan_v, base.scales, base.opacity,
+                     [g for g in base.textures])
+    view = sg.look_at_view((-0.3, 0.5, -2.8), 96, 80)
+    opts = O.Options()
+    out = []
+    for scene in (base, mixed):
+        rast, sp, rgb, T = run_gpu(gb, scene, [view], opts)
+        g = torch.from_numpy(sg.make_dl_drgb(2, [view])).cuda()
+        grads = rast.backward(sp, T, g)
+        torch.cuda.synchronize()
+        out.append((rgb.cpu().numpy(), T.cpu().numpy(),
+                    {k: v.cpu().numpy().reshape(-1) for k, v in grads.items()}))
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    for k in out[0][2]:
+        assert rel_l2(out[1][2][k], out[0][2][k]) <= 1e-6, k

@@ -3,6 +3,7 @@
 Each test names the passage it pins. None of them re-types the oracle's own formula: they use
 closed forms of special geometries, invariants, symmetries, finite differences and brute force.
 """
+import dataclasses
 import json
 import math
 import os
@@ -682,3 +683,57 @@ def test_specular_gradients_match_central_differences(degree):
             assert a == pytest.approx(fd, rel=2e-5, abs=2e-6 * max(1.0, abs(fd))), (name, idx)
             checked += 1
     assert checked >= 14
+
+
+# --- colour grids of several sides in one scene ----------------------------------------------
+def _refine_weights(n, L):
+    """[L, n] weights of the exact refinement of a corner-aligned n-texel side to L texels,
+    where the coarse knots are fine knots ((L - 1) a multiple of (n - 1), or n = 1): fine texel
+    i lies at coarse coordinate x = i (n - 1) / (L - 1), between knots floor(x) and floor(x) + 1
+    with weights 1 - frac(x) and frac(x) (one knot of weight 1 for n = 1)."""
+    W = np.zeros((L, n))
+    if n == 1:
+        W[:, 0] = 1.0
+        return W
+    step = (L - 1) // (n - 1)
+    assert step * (n - 1) == L - 1
+    for i in range(L):
+        a, r = divmod(i, step)
+        if a == n - 1:
+            W[i, a] = 1.0
+        else:
+            W[i, a] = 1.0 - r / step
+            W[i, a + 1] = r / step
+    return W
+
+
+@pytest.mark.parametrize("layout,sides", [(8, (1, 2, 8)), (16, (1, 2, 4, 16))])
+def test_mixed_sides_equal_their_exact_refinement(layout, sides):
+    """A scene whose grids have several sides renders exactly as the same scene with every
+    coarse grid refined to the largest side (a bilinear field on a coarse grid is bilinear on
+    every cell of a refinement whose knots include the coarse knots), and the coarse grids'
+    gradients are the refinement's transpose applied to the refined grids' gradients; the
+    other gradients are equal."""
+    base = sg.make_scene(23 + layout, 40, -0.6, 0.6, 0.05, 0.35, layout)
+    scene = sg.with_mixed_sides(base, 5, sides)
+    assert {g.shape[0] for g in scene.textures} == set(sides)
+    fine = [np.einsum("ia,jb,abc->ijc", _refine_weights(g.shape[0], layout),
+                      _refine_weights(g.shape[0], layout), g.astype(np.float64))
+            for g in scene.textures]
+    refined = dataclasses.replace(scene, textures=np.stack(fine))
+    view = sg.look_at_view((0.3, -0.2, -2.4), 40, 36)
+    opts = O.Options(bg=(0.1, 0.3, 0.2))
+    a = O.render(scene, view, opts, keep_saved=True)
+    b = O.render(refined, view, opts, keep_saved=True)
+    np.testing.assert_allclose(a.rgb, b.rgb, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(a.T_final, b.T_final, rtol=0, atol=1e-12)
+    g = np.random.default_rng(3).standard_normal((40 * 36, 3))
+    ga = O.render_backward(scene, view, opts, a, g)
+    gb_ = O.render_backward(refined, view, opts, b, g)
+    for name in ("means", "tan_u", "tan_v", "scales", "opacity"):
+        np.testing.assert_allclose(getattr(ga, name), getattr(gb_, name), rtol=1e-9, atol=1e-12)
+    for k, gk in enumerate(ga.textures):
+        W = _refine_weights(gk.shape[0], layout)
+        want = np.einsum("ia,jb,ijc->abc", W, W, gb_.textures[k])
+        np.testing.assert_allclose(gk, want, rtol=1e-9, atol=1e-12)
+    assert sum(float(np.abs(gk).sum()) > 0 for gk in ga.textures) >= 10
