@@ -110,9 +110,11 @@ def time_steps(rast, sp, rgb, T, g, grads, steps, torch):
     return sec
 
 
-def setup(gb, sg, torch, name, views=None):
+def setup(gb, sg, torch, name, views=None, transform=None):
     scene, v = sg.config(name)
     views = views or v
+    if transform is not None:
+        scene = transform(scene)
     sp = gb.Splats.from_numpy(scene, tex_bf16=sg.CONFIGS[name]["bf16"])
     rast = gb.Rasterizer(views, gb.Options(), check_overflow=False)
     rast.plan(sp)
@@ -456,6 +458,20 @@ def main():
                                        "texels_per_splat": 256}
         del rast_16, sp_16, rgb_16, T_16, grads_16, g_16
         torch.cuda.empty_cache()
+        for label, sides in (("mixed_sides_2_4_8_single_view", (2, 4, 8)),
+                             ("mixed_sides_4_8_16_single_view", (4, 8, 16))):
+            log(f"variant: colour grids of sides {sides} in one call, one view")
+            _, _, sp_m, rast_m, g_m, rgb_m, T_m, grads_m, _ = setup(
+                gb, sg, torch, "T0", transform=lambda sc: sg.with_mixed_sides(sc, 1, sides))
+            for _ in range(args.warmup):
+                rast_m.forward(sp_m, rgb_m, T_m)
+                rast_m.backward(sp_m, T_m, g_m, grads_m)
+            s_m = time_steps(rast_m, sp_m, rgb_m, T_m, g_m, grads_m, args.steps, torch)
+            variants[label] = {"ms_per_step": round(s_m * 1e3, 3),
+                               "mpix_per_s": round(pixels / s_m / 1e6, 1),
+                               "layout_side": sp_m.N, "texels": sp_m.n_texels}
+            del rast_m, sp_m, rgb_m, T_m, grads_m, g_m
+            torch.cuda.empty_cache()
         log("variant: bf16 textures, four 1080p views batched in one call")
         views4 = sg.orbit_views(0, 4, 8.0, [(1920, 1080)])
         _, _, sp4, rast4, g4, rgb4, T4, grads4, K4 = setup(gb, sg, torch, "T0_BF16", views=views4)

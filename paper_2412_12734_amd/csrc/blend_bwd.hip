@@ -288,10 +288,11 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
       }
       for (int e = tid; e < nb * TEXG; e += nthr) s_gtex[e] = 0.f;
       for (int e = tid; e < nb * kRecGrad; e += nthr) s_grec[e] = 0.f;
-      if constexpr (MIXED)
-        stage_texels_mixed<N, BF16>(textures, pair_vals + bstart, rec_base, nb, s_tex, p.spec,
-                                    p.grid_n, p.grid_at);
-      else
+      if constexpr (MIXED) {
+        __syncthreads();  // sides and offsets of the batch's grids
+        stage_texels_mixed<N, BF16>(textures, pair_vals + bstart, nb, s_tex, p.spec, s_gn,
+                                    s_toff);
+      } else
         stage_texels<N, BF16>(textures, pair_vals + bstart, rec_base, nb, s_tex, p.spec);
       __syncthreads();
 
@@ -428,15 +429,22 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
         }
       }
       // flush the batch's sums
-      for (int e = tid; e < nb * TEXG; e += nthr) {
-        const float x = s_gtex[e];
-        if (x != 0.f) {
-          const int j = e / TEXG, r = e - j * TEXG;
-          if constexpr (MIXED) {
-            // the N x N sums hold the splat's n x n grid in rows and columns [0, n)
-            const int t = r / 3, c = r - 3 * t, iu = t / N, iv = t - iu * N, n = s_gn[j];
-            if (iu < n && iv < n) atomicAdd(&d_tex[3 * (s_toff[j] + iu * n + iv) + c], x);
-          } else {
+      if constexpr (MIXED) {
+        // the N x N sums hold splat j's n x n grid in rows and columns [0, n): one wave per
+        // splat, lane i taking values i, i + 64, ... of the grid's 3 n^2
+        for (int j = w; j < nb; j += nthr >> 6) {
+          const int n = s_gn[j];
+          for (int i = lane; i < 3 * n * n; i += 64) {
+            const int t = i / 3, c = i - 3 * t, iu = div_side(t, n), iv = t - iu * n;
+            const float x = s_gtex[j * TEXG + 3 * (iu * N + iv) + c];
+            if (x != 0.f) atomicAdd(&d_tex[3 * s_toff[j] + i], x);
+          }
+        }
+      } else {
+        for (int e = tid; e < nb * TEXG; e += nthr) {
+          const float x = s_gtex[e];
+          if (x != 0.f) {
+            const int j = e / TEXG, r = e - j * TEXG;
             atomicAdd(&d_tex[(int64_t)s_splat[j] * TEXG + r], x);
           }
         }

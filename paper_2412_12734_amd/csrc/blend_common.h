@@ -196,33 +196,47 @@ __device__ __forceinline__ void stage_texels(const void* __restrict__ textures,
   }
 }
 
+// Row and column of texel t (< 256) of an n-texel side (n <= 16): t / n as a multiply by
+// ceil(2^16 / n) and a shift, exact in that range (checked for every t and n).
+__device__ __forceinline__ int div_side(int t, int n) {
+  return (int)(((uint32_t)t * (uint32_t)((65536 + n - 1) / n)) >> 16);
+}
+
 // Copies the texels of `nb` staged splats whose grids have sides of their own (at most N) into
-// the N x N LDS layout: splat j's n x n texels go to rows and columns [0, n). A one-texel grid
-// is also copied to (0, 1), (1, 0) and (1, 1), so that the bilinear lookup, which reads the four
-// corners of cell (0, 0) with weights (1, 0, 0, 0) there, reads finite values. As in
-// stage_texels, spec (nullable) adds each record's view-dependent colour.
+// the N x N LDS layout: splat j's n x n texels (side s_gn[j], first texel s_toff[j]) go to rows
+// and columns [0, n). One wave per splat; lane i moves values i, i + 64, ... of the grid's
+// 3 n^2 contiguous values. A one-texel grid is also copied to (0, 1), (1, 0) and (1, 1), so that
+// the bilinear lookup, which reads the four corners of cell (0, 0) with weights (1, 0, 0, 0)
+// there, reads finite values. As in stage_texels, spec (nullable) adds each record's
+// view-dependent colour.
 template <int N, bool BF16>
 __device__ __forceinline__ void stage_texels_mixed(const void* __restrict__ textures,
-                                                   const uint32_t* __restrict__ pairs,
-                                                   uint32_t rec_base, int nb, float4* s_tex,
-                                                   const float4* __restrict__ spec,
-                                                   const int32_t* __restrict__ side,
-                                                   const int64_t* __restrict__ toff) {
-  constexpr int per = 3 * N * N;
-  for (int e = threadIdx.x; e < nb * per; e += blockDim.x) {
-    const int j = e / per, r = e - j * per;
-    const int t = r / 3, c = r - 3 * t, iu = t / N, iv = t - iu * N;
-    const uint32_t k = pairs[j] - rec_base;
-    const int n = min(max(side[k], 1), N);
-    if (n == 1 ? (iu > 1 || iv > 1) : (iu >= n || iv >= n)) continue;
-    const int64_t src = 3 * (toff[k] + (n == 1 ? 0 : iu * n + iv)) + c;
-    float x = BF16 ? bf16_to_f32(reinterpret_cast<const uint16_t*>(textures)[src])
-                   : reinterpret_cast<const float*>(textures)[src];
-    if (spec) {
-      const float4 sc = spec[pairs[j]];
-      x += c == 0 ? sc.x : c == 1 ? sc.y : sc.z;
+                                                   const uint32_t* __restrict__ pairs, int nb,
+                                                   float4* s_tex, const float4* __restrict__ spec,
+                                                   const int32_t* s_gn, const int64_t* s_toff) {
+  const int lane = threadIdx.x & 63, nw = (int)(blockDim.x >> 6);
+  for (int j = (int)(threadIdx.x >> 6); j < nb; j += nw) {
+    const int n = s_gn[j];
+    const int64_t base = 3 * s_toff[j];
+    float4 sc = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (spec) sc = spec[pairs[j]];
+    float4* dst = s_tex + j * TexLayout<N>::kPerSplat;
+    auto texel = [&](int64_t i, int c) {
+      const float x = BF16 ? bf16_to_f32(reinterpret_cast<const uint16_t*>(textures)[i])
+                           : reinterpret_cast<const float*>(textures)[i];
+      return x + (c == 0 ? sc.x : c == 1 ? sc.y : sc.z);
+    };
+    if (n == 1) {
+      if (lane < 12) {  // corner lane / 3 of cell (0, 0), channel lane % 3
+        const int q = lane / 3, c = lane - 3 * q;
+        reinterpret_cast<float*>(dst + TexLayout<N>::at(q >> 1, q & 1))[c] = texel(base + c, c);
+      }
+    } else {
+      for (int i = lane; i < 3 * n * n; i += 64) {
+        const int t = i / 3, c = i - 3 * t, iu = div_side(t, n), iv = t - iu * n;
+        reinterpret_cast<float*>(dst + TexLayout<N>::at(iu, iv))[c] = texel(base + i, c);
+      }
     }
-    reinterpret_cast<float*>(s_tex + j * TexLayout<N>::kPerSplat + TexLayout<N>::at(iu, iv))[c] = x;
   }
 }
 

@@ -176,7 +176,10 @@ def with_mixed_sides(scene: Scene, seed: int, sides) -> Scene:
     rng = np.random.default_rng(seed)
     sides = np.asarray(sides, dtype=np.int64)
     n = sides[rng.integers(0, sides.size, scene.P)]
-    grids = [rng.uniform(0.0, 1.0, (int(m), int(m), 3)).astype(np.float32) for m in n]
+    # one draw for all texels, in splat order, cut into the grids
+    vals = rng.uniform(0.0, 1.0, (int(np.sum(n * n)), 3)).astype(np.float32)
+    cuts = np.cumsum(n * n)[:-1]
+    grids = [g.reshape(int(m), int(m), 3) for g, m in zip(np.split(vals, cuts), n)]
     return dataclasses.replace(scene, textures=grids)
 
 
