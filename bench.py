@@ -102,7 +102,8 @@ def time_steps(rast, sp, rgb, T, g, grads, steps, torch):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        rast.forward(sp, rgb, T)
+        # the forward zeroes the texture gradients that the backward then accumulates into
+        rast.forward(sp, rgb, T, zero_grads=grads)
         rast.backward(sp, T, g, grads)
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / steps
@@ -247,7 +248,7 @@ def c3_variant(gb, sg, torch, warmup, steps):
 
     def single_step():
         for r, rgb_i, T_i, g_i in singles:
-            r.forward(sp, rgb_i, T_i)
+            r.forward(sp, rgb_i, T_i, zero_grads=grads)
             r.backward(sp, T_i, g_i, grads)
 
     for _ in range(warmup):
@@ -281,14 +282,14 @@ def config_times(gb, sg, torch, warmup, steps, only=None):
         scene, views, sp, rast, g, rgb, T, grads, K = setup(gb, sg, torch, name)
         px = sum(v.width * v.height for v in views)
         for _ in range(warmup):
-            rast.forward(sp, rgb, T)
+            rast.forward(sp, rgb, T, zero_grads=grads if bwd else None)
             if bwd:
                 rast.backward(sp, T, g, grads)
         rast.status_ex()  # clears the sticky overflow flag of the warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            rast.forward(sp, rgb, T)
+            rast.forward(sp, rgb, T, zero_grads=grads if bwd else None)
             if bwd:
                 rast.backward(sp, T, g, grads)
         torch.cuda.synchronize()
@@ -299,7 +300,7 @@ def config_times(gb, sg, torch, warmup, steps, only=None):
                      "pairs": K}
         if only is not None:
             rast.timing(True)
-            rast.forward(sp, rgb, T)
+            rast.forward(sp, rgb, T, zero_grads=grads if bwd else None)
             if bwd:
                 rast.backward(sp, T, g, grads)
             out[name]["stage_ms"] = {k: round(v, 4) for k, v in rast.stage_times().items()}
@@ -367,7 +368,7 @@ def main():
     scene, views, sp, rast, g, rgb, T, grads, K = setup(gb, sg, torch, "T0")
     pixels = sum(v.width * v.height for v in views)
     for _ in range(args.warmup):
-        rast.forward(sp, rgb, T)
+        rast.forward(sp, rgb, T, zero_grads=grads)
         rast.backward(sp, T, g, grads)
     sec = time_steps(rast, sp, rgb, T, g, grads, args.steps, torch)
     value = pixels / sec / 1e6
@@ -391,7 +392,7 @@ def main():
     stage_sum = {}
     rast.timing(True)
     for _ in range(args.steps):
-        rast.forward(sp, rgb, T)
+        rast.forward(sp, rgb, T, zero_grads=grads)
         rast.backward(sp, T, g, grads)
         for k, v in rast.stage_times().items():
             stage_sum[k] = stage_sum.get(k, 0.0) + v
@@ -432,7 +433,7 @@ def main():
         log("variant: bf16 textures, one view")
         _, views_b, sp_b, rast_b, g_b, rgb_b, T_b, grads_b, _ = setup(gb, sg, torch, "T0_BF16")
         for _ in range(args.warmup):
-            rast_b.forward(sp_b, rgb_b, T_b)
+            rast_b.forward(sp_b, rgb_b, T_b, zero_grads=grads_b)
             rast_b.backward(sp_b, T_b, g_b, grads_b)
         s_b = time_steps(rast_b, sp_b, rgb_b, T_b, g_b, grads_b, args.steps, torch)
         # storage error of bfloat16 textures: the same scene rendered from FP32 textures
@@ -450,7 +451,7 @@ def main():
         log("variant: 16 x 16 colour grids, one view")
         _, _, sp_16, rast_16, g_16, rgb_16, T_16, grads_16, _ = setup(gb, sg, torch, "T0_N16")
         for _ in range(args.warmup):
-            rast_16.forward(sp_16, rgb_16, T_16)
+            rast_16.forward(sp_16, rgb_16, T_16, zero_grads=grads_16)
             rast_16.backward(sp_16, T_16, g_16, grads_16)
         s_16 = time_steps(rast_16, sp_16, rgb_16, T_16, g_16, grads_16, args.steps, torch)
         variants["n16_single_view"] = {"ms_per_step": round(s_16 * 1e3, 3),
@@ -464,7 +465,7 @@ def main():
             _, _, sp_m, rast_m, g_m, rgb_m, T_m, grads_m, _ = setup(
                 gb, sg, torch, "T0", transform=lambda sc: sg.with_mixed_sides(sc, 1, sides))
             for _ in range(args.warmup):
-                rast_m.forward(sp_m, rgb_m, T_m)
+                rast_m.forward(sp_m, rgb_m, T_m, zero_grads=grads_m)
                 rast_m.backward(sp_m, T_m, g_m, grads_m)
             s_m = time_steps(rast_m, sp_m, rgb_m, T_m, g_m, grads_m, args.steps, torch)
             variants[label] = {"ms_per_step": round(s_m * 1e3, 3),
@@ -476,7 +477,7 @@ def main():
         views4 = sg.orbit_views(0, 4, 8.0, [(1920, 1080)])
         _, _, sp4, rast4, g4, rgb4, T4, grads4, K4 = setup(gb, sg, torch, "T0_BF16", views=views4)
         for _ in range(args.warmup):
-            rast4.forward(sp4, rgb4, T4)
+            rast4.forward(sp4, rgb4, T4, zero_grads=grads4)
             rast4.backward(sp4, T4, g4, grads4)
         s_4 = time_steps(rast4, sp4, rgb4, T4, g4, grads4, args.steps, torch)
         px4 = 4 * 1920 * 1080

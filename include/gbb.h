@@ -201,6 +201,18 @@ gb_status gb_render_fwd(const gb_splats* splats, const gb_view* views, int32_t n
                         const gb_options* opts, void* workspace, size_t ws_bytes,
                         int64_t pair_capacity, float* rgb, float* T_final, void* stream);
 
+/* gb_render_fwd that also zeroes d_textures, the texture-gradient array that the next
+ * gb_render_bwd on `workspace` will be given (its full size: [P][N][N][3], or [n_texels][3]
+ * with tex_side). The forward's blend workgroups store the zeros while they blend, which is
+ * bound by arithmetic and leaves HBM mostly idle, and that gb_render_bwd then skips its own
+ * clear of the array. The caller must not write d_textures between the two calls. The
+ * backward clears as usual when given another array, or after any other forward on the
+ * workspace. Errors as gb_render_fwd, and GB_ERR_ARG for a NULL or misaligned d_textures. */
+gb_status gb_render_fwd_zeroing(const gb_splats* splats, const gb_view* views, int32_t n_views,
+                                const gb_options* opts, void* workspace, size_t ws_bytes,
+                                int64_t pair_capacity, float* rgb, float* T_final,
+                                float* d_textures, void* stream);
+
 /* Backward of the last gb_render_fwd on `workspace` with the same splats, views, options and
  * capacity (Alg. 1 backward, Alg. 2 adj-bilinear). T_final is the forward's output;
  * d_rgb: [sum HW][3] float32 device adjoint of rgb. Writes every field of *grads (all must be

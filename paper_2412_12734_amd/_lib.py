@@ -24,7 +24,7 @@ EXPORTS = (
     "gb_activate_fwd", "gb_activate_bwd", "gb_l1_loss", "gb_adam_step", "gb_to_bf16",
     "gb_mse_loss", "gb_box_filter_textures", "gb_rotz_only",
     "gb_densify_stats", "gb_densify_work_bytes", "gb_densify_plan", "gb_densify_apply",
-    "gb_densify_noalloc",
+    "gb_densify_noalloc", "gb_render_fwd_zeroing",
 )
 
 # most splats gb_densify_noalloc takes (GB_DENSIFY_NOALLOC_MAX_P)
@@ -111,6 +111,9 @@ def load() -> ctypes.CDLL:
     lib.gb_render_fwd.argtypes = [POINTER(GbSplats), POINTER(GbView), c_int32,
                                   POINTER(GbOptions), c_void_p, c_size_t, c_int64, c_void_p,
                                   c_void_p, c_void_p]
+    lib.gb_render_fwd_zeroing.argtypes = [POINTER(GbSplats), POINTER(GbView), c_int32,
+                                          POINTER(GbOptions), c_void_p, c_size_t, c_int64,
+                                          c_void_p, c_void_p, c_void_p, c_void_p]
     lib.gb_render_bwd.argtypes = [POINTER(GbSplats), POINTER(GbView), c_int32,
                                   POINTER(GbOptions), c_void_p, c_size_t, c_int64, c_void_p,
                                   c_void_p, POINTER(GbGrads), c_void_p]
@@ -155,6 +158,7 @@ def load() -> ctypes.CDLL:
                                        POINTER(GbRawSplats), POINTER(GbRowState), c_int32,
                                        POINTER(c_int64), c_void_p]
     for name in ("gb_workspace_layout", "gb_count_pairs", "gb_render_fwd", "gb_render_bwd",
+                 "gb_render_fwd_zeroing",
                  "gb_read_status", "gb_blend_stats", "gb_timing_enable", "gb_timing_read",
                  "gb_activate_fwd", "gb_activate_bwd", "gb_l1_loss", "gb_adam_step",
                  "gb_to_bf16", "gb_mse_loss", "gb_box_filter_textures", "gb_rotz_only",

@@ -635,13 +635,59 @@ gb_status gb_count_pairs(const gb_splats* s, const gb_view* views, int32_t n_vie
   return GB_OK;
 }
 
+// Per workspace: the texture-gradient array that its last forward zeroed (null if none), so
+// that the backward of that forward can skip clearing the same array.
+struct ZeroedRecord {
+  std::mutex mu;
+  const void* key[kMirrorSlots] = {};
+  const float* ptr[kMirrorSlots] = {};
+  int64_t n[kMirrorSlots] = {};
+  int next = 0;
+} g_zeroed;
+
+void zeroed_set(const void* ws, const float* ptr, int64_t n) {
+  std::lock_guard<std::mutex> lock(g_zeroed.mu);
+  int i = 0;
+  while (i < kMirrorSlots && g_zeroed.key[i] != ws) ++i;
+  if (i == kMirrorSlots) {
+    if (!ptr) return;  // nothing recorded for this workspace
+    i = g_zeroed.next;
+    g_zeroed.next = (g_zeroed.next + 1) % kMirrorSlots;
+    g_zeroed.key[i] = ws;
+  }
+  g_zeroed.ptr[i] = ptr;
+  g_zeroed.n[i] = n;
+}
+
+// True (and forgets it) if the last forward on `ws` zeroed exactly `ptr` [n].
+bool zeroed_take(const void* ws, const float* ptr, int64_t n) {
+  std::lock_guard<std::mutex> lock(g_zeroed.mu);
+  for (int i = 0; i < kMirrorSlots; ++i) {
+    if (g_zeroed.key[i] != ws) continue;
+    const bool hit = g_zeroed.ptr[i] == ptr && g_zeroed.n[i] == n && ptr != nullptr;
+    g_zeroed.ptr[i] = nullptr;
+    return hit;
+  }
+  return false;
+}
+
+// Number of floats of the texture-gradient array of these splats.
+int64_t tex_grad_values(const gb_splats* s) {
+  return s->tex_side ? 3 * s->n_texels : (int64_t)s->P * 3 * s->N * s->N;
+}
+
 static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32_t n_views,
                                  const gb_options* o, void* ws, size_t ws_bytes, int64_t cap,
                                  float* rgb, float* T_final, bool stats, void* stream,
-                                 bool use_mirror = true, uint32_t* overflow_flag = nullptr) {
+                                 bool use_mirror = true, uint32_t* overflow_flag = nullptr,
+                                 float* zero_tex = nullptr) {
   Plan pl;
   gb_status st = check_common(s, views, n_views, o, ws, ws_bytes, cap, &pl);
   if (st != GB_OK) return st;
+  if (zero_tex && !aligned(zero_tex, 4)) return arg_fail("d_textures to zero misaligned");
+  // whatever happens below, the backward must not rely on an older forward's zeroing
+  zeroed_set(ws, nullptr, 0);
+  const int64_t zero_n = zero_tex ? tex_grad_values(s) : 0;
   if (!rgb || !T_final || !aligned(rgb, 4) || !aligned(T_final, 4))
     return arg_fail("rgb / T_final NULL or misaligned");
   // a completed earlier forward on this workspace that did not fit this capacity
@@ -739,9 +785,10 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   const float4* spec = s->sh ? at<float4>(ws, pl.off_spec) : nullptr;
   GBB_TRY(launch_blend_fwd(pl, *s, *o, d_views, n_views, rec, pv, ranges, rgb, T_final,
                            at<uint32_t>(ws, pl.off_n_last), split, tile_work, spec,
-                           stats ? d_stats : nullptr, hs),
+                           stats ? d_stats : nullptr, zero_tex, zero_n, hs),
           "blend forward");
   GBB_TRY(stage_mark(kStBlendFwd, 1, hs), "timing");
+  if (zero_tex) zeroed_set(ws, zero_tex, zero_n);
   if (!pl.split) return GB_OK;
 
   // rest pass: the remaining records, paired with the tiles the prefix left open
@@ -776,7 +823,7 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   GBB_TRY(stage_mark(kStBlendFwdRest, 0, hs), "timing");
   GBB_TRY(launch_blend_fwd(pl, *s, *o, d_views, n_views, rec, pv_r, ranges_rest, rgb, T_final,
                            at<uint32_t>(ws, pl.off_n_last_rest), split, tile_work, spec,
-                           stats ? d_stats : nullptr, hs),
+                           stats ? d_stats : nullptr, nullptr, 0, hs),
           "blend forward (rest)");
   GBB_TRY(stage_mark(kStBlendFwdRest, 1, hs), "timing");
   return GB_OK;
@@ -786,6 +833,14 @@ gb_status gb_render_fwd(const gb_splats* s, const gb_view* views, int32_t n_view
                         const gb_options* o, void* ws, size_t ws_bytes, int64_t cap, float* rgb,
                         float* T_final, void* stream) {
   return render_fwd_impl(s, views, n_views, o, ws, ws_bytes, cap, rgb, T_final, false, stream);
+}
+
+gb_status gb_render_fwd_zeroing(const gb_splats* s, const gb_view* views, int32_t n_views,
+                                const gb_options* o, void* ws, size_t ws_bytes, int64_t cap,
+                                float* rgb, float* T_final, float* d_textures, void* stream) {
+  if (!d_textures) return arg_fail("d_textures NULL");
+  return render_fwd_impl(s, views, n_views, o, ws, ws_bytes, cap, rgb, T_final, false, stream,
+                         true, nullptr, d_textures);
 }
 
 gb_status gb_blend_stats(const gb_splats* s, const gb_view* views, int32_t n_views,
@@ -852,9 +907,11 @@ gb_status gb_render_bwd(const gb_splats* s, const gb_view* views, int32_t n_view
   if (d_spec)
     GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_spec), 0u, 4 * pl.VP, hs),
             "clear d_spec");
-  const int64_t tex_values = s->tex_side ? 3 * s->n_texels : (int64_t)s->P * 3 * s->N * s->N;
-  GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(g->d_textures), 0u, tex_values, hs),
-          "clear d_textures");
+  const int64_t tex_values = tex_grad_values(s);
+  // skipped when this workspace's forward already zeroed this array while it blended
+  if (!zeroed_take(ws, g->d_textures, tex_values))
+    GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(g->d_textures), 0u, tex_values, hs),
+            "clear d_textures");
   // the backward takes the tiles with the longest blended spans (saved by the forward) first
   const uint32_t* tile_order = nullptr;
   if (pl.ordered) {

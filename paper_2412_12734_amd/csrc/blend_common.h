@@ -31,6 +31,12 @@ struct BlendParams {
   // index of its first texel in the packed texture array
   const int32_t* grid_n;
   const int64_t* grid_at;
+  // forward only (nullable): an array that the workgroups zero while they blend (the coming
+  // backward's texture gradients): zero_n4 float4s, then zero_tail_n trailing floats
+  float4* zero4;
+  int64_t zero_n4;
+  float* zero_tail;
+  int32_t zero_tail_n;
 };
 
 BlendParams make_blend_params(const Plan& pl, const gb_options& o, int n_views);

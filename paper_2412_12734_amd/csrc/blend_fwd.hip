@@ -30,6 +30,19 @@ constexpr int fwd_min_waves() {
   return 160 * 1024 / lds < 8 ? 160 * 1024 / lds : 8;
 }
 
+// With p.zero4: this workgroup's slice of the array to zero (the coming backward's texture
+// gradients). Called when the workgroup has finished blending, so that the stores drain
+// while other workgroups blend, and without holding registers during the blend.
+__device__ __forceinline__ void zero_slice(const BlendParams& p) {
+  if (!p.zero4) return;
+  const int64_t per = (p.zero_n4 + (int64_t)gridDim.x - 1) / (int64_t)gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * per;
+  const int64_t hi = lo + per < p.zero_n4 ? lo + per : p.zero_n4;
+  for (int64_t i = lo + (int64_t)threadIdx.x; i < hi; i += (int64_t)blockDim.x)
+    p.zero4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (blockIdx.x == 0 && (int)threadIdx.x < p.zero_tail_n) p.zero_tail[threadIdx.x] = 0.f;
+}
+
 // MIXED: each splat has a grid side of its own (at most N), read from p.grid_n.
 template <int N, bool BF16, int B, bool STATS, bool REST, bool MIXED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fwd_min_waves<N, B>())))
@@ -48,7 +61,10 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   static_assert((B & (B - 1)) == 0, "batch sizes are powers of two");
 
   const int tile = tile_of_block(p);
-  if (tile >= p.total_tiles) return;
+  if (tile >= p.total_tiles) {
+    if (!REST) zero_slice(p);
+    return;
+  }
   if (REST && !((split.open_bits[tile >> 5] >> (tile & 31)) & 1u)) return;
   const int vi = view_of_tile(views, p.n_views, tile);
   const ViewDev& V = views[vi];
@@ -227,6 +243,7 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
       if (REST) atomicAdd(&stats[4], (unsigned long long)red[0]);
     }
   }
+  if (!REST) zero_slice(p);
 }
 
 template <int N, bool BF16, bool STATS, bool REST, bool MIXED>
@@ -304,6 +321,10 @@ BlendParams make_blend_params(const Plan& pl, const gb_options& o, int n_views) 
   bp.d_spec = nullptr;
   bp.grid_n = nullptr;
   bp.grid_at = nullptr;
+  bp.zero4 = nullptr;
+  bp.zero_n4 = 0;
+  bp.zero_tail = nullptr;
+  bp.zero_tail_n = 0;
   return bp;
 }
 
@@ -312,12 +333,21 @@ hipError_t launch_blend_fwd(const Plan& pl, const gb_splats& sp, const gb_option
                             const uint32_t* pair_vals, const uint32_t* ranges, float* rgb,
                             float* T_final, uint32_t* n_last, const SplitState& split,
                             uint32_t* tile_work, const float4* spec, unsigned long long* stats,
-                            hipStream_t s) {
+                            float* zero, int64_t zero_n, hipStream_t s) {
   // the forward keeps the fixed tile bands: ranking its tiles by list length measured no
   // faster on the 1M-splat 1080p workload (0.50 ms either way)
   BlendParams bp = make_blend_params(pl, o, n_views);
   bp.tile_work = tile_work;
   bp.spec = spec;
+  if (zero && zero_n > 0 && split.mode != kRestPass) {
+    // 16-byte stores over the aligned part, single floats for the rest (at most 3 trailing,
+    // or all of a short array)
+    const int64_t head = (reinterpret_cast<uintptr_t>(zero) & 15) == 0 ? zero_n / 4 : 0;
+    bp.zero4 = reinterpret_cast<float4*>(zero);
+    bp.zero_n4 = head;
+    bp.zero_tail = zero + 4 * head;
+    bp.zero_tail_n = (int32_t)(zero_n - 4 * head);
+  }
   const bool bf = sp.tex_dtype == GB_BF16;
   if (sp.tex_side) {
     // grids of several sides, staged into the N x N layout (N = 8 or 16, checked by the API)

@@ -220,13 +220,14 @@ hipError_t launch_order_tiles(const uint32_t* work, int64_t n_tiles, uint32_t* o
                               hipStream_t s);
 // Forward blend of one pass (mode in split.mode). REST launches the open-tile kernel.
 // tile_work (nullable): per tile, the span of pairs (first pair to one past the last pair any
-// pixel blended) is written by the first pass and added to by the rest pass.
+// pixel blended) is written by the first pass and added to by the rest pass. zero (nullable):
+// zero_n floats that the first pass's workgroups set to zero while they blend.
 hipError_t launch_blend_fwd(const Plan& pl, const gb_splats& sp, const gb_options& o,
                             const ViewDev* views, int n_views, const SplatRec* rec,
                             const uint32_t* pair_vals, const uint32_t* ranges, float* rgb,
                             float* T_final, uint32_t* n_last, const SplitState& split,
                             uint32_t* tile_work, const float4* spec, unsigned long long* stats,
-                            hipStream_t s);
+                            float* zero, int64_t zero_n, hipStream_t s);
 // Backward blend over the prefix (or only) pass's pairs `first`; with open_bits != null the
 // tiles marked there first walk `rest` (the rest pass's pairs). tile_order (nullable):
 // workgroup b takes tile tile_order[b]. With spec != null the records' view-dependent colours

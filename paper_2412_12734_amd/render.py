@@ -207,7 +207,11 @@ class Rasterizer:
 
     # -- raw calls -------------------------------------------------------------------------
     def forward(self, sp: Splats, rgb: Optional[torch.Tensor] = None,
-                T_final: Optional[torch.Tensor] = None):
+                T_final: Optional[torch.Tensor] = None, zero_grads: Optional[dict] = None):
+        """Forward render. ``zero_grads`` (optional): the gradient dict that the next
+        ``backward`` will be given; the forward then zeroes its texture gradients while it
+        blends, and that backward skips its own clear (the dict must not be written in
+        between)."""
         if self.ws is None or getattr(self, "_plan_key", None) != (sp.P, sp.N) or self.capacity == 0:
             self.plan(sp)
         if rgb is None:
@@ -215,11 +219,22 @@ class Rasterizer:
         if T_final is None:
             T_final = torch.empty((self.total_pixels,), dtype=torch.float32, device=self.device)
         self.generation += 1
+        zt = None if zero_grads is None else zero_grads["textures"]
+        if zt is not None and (zt.dtype != torch.float32 or not zt.is_contiguous()
+                               or zt.numel() != 3 * sp.n_texels):
+            raise ValueError("zero_grads['textures'] must be the contiguous float32 texture "
+                             "gradient of these splats")
         for _ in range(3):
-            st = self.lib.gb_render_fwd(ctypes.byref(sp.c()), self.cviews, self.nv,
-                                        ctypes.byref(self.copts), self.ws.data_ptr(),
-                                        self.ws.numel(), self.capacity, rgb.data_ptr(),
-                                        T_final.data_ptr(), _stream(self.device))
+            if zt is None:
+                st = self.lib.gb_render_fwd(ctypes.byref(sp.c()), self.cviews, self.nv,
+                                            ctypes.byref(self.copts), self.ws.data_ptr(),
+                                            self.ws.numel(), self.capacity, rgb.data_ptr(),
+                                            T_final.data_ptr(), _stream(self.device))
+            else:
+                st = self.lib.gb_render_fwd_zeroing(
+                    ctypes.byref(sp.c()), self.cviews, self.nv, ctypes.byref(self.copts),
+                    self.ws.data_ptr(), self.ws.numel(), self.capacity, rgb.data_ptr(),
+                    T_final.data_ptr(), zt.data_ptr(), _stream(self.device))
             if st == L.GB_ERR_CAPACITY and self.check_overflow:
                 # an earlier forward on this workspace overflowed: count again and re-size
                 self.plan(sp)
@@ -283,12 +298,12 @@ class Rasterizer:
             side = torch.cuda.Stream(self.device)
             side.wait_stream(torch.cuda.current_stream(self.device))
             with torch.cuda.stream(side):  # warm-up outside the capture
-                self.forward(sp, rgb, T_final)
+                self.forward(sp, rgb, T_final, zero_grads=grads)
                 self.backward(sp, T_final, d_rgb, grads)
             torch.cuda.current_stream(self.device).wait_stream(side)
             graph = torch.cuda.CUDAGraph()
             with torch.cuda.graph(graph):
-                self.forward(sp, rgb, T_final)
+                self.forward(sp, rgb, T_final, zero_grads=grads)
                 self.backward(sp, T_final, d_rgb, grads)
         finally:
             self.check_overflow = keep

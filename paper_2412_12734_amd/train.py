@@ -274,14 +274,17 @@ class Trainer:
             z = lambda *s: torch.empty(s, dtype=torch.float32, device=st.device)
             self.bufs = (z(n_px, 3), z(n_px), z(n_px, 3), z(n_px, 3))
         rgb, T, target, d_rgb = self.bufs
+        # the forward zeroes the texture gradients of the backward below while it blends
+        zg = self.grads if (self.grads is not None
+                            and self.grads["textures"].numel() == 3 * sp.n_texels) else None
         try:
-            rgb, T = self.rast.forward(sp, rgb, T)
+            rgb, T = self.rast.forward(sp, rgb, T, zero_grads=zg)
         except GbbError as e:
             if e.status != L.GB_ERR_CAPACITY:
                 raise
             # a completed earlier step overflowed: re-size for this batch and render again
             self.rast.plan(sp, int(self.rast.count_pairs(sp) * 1.5) + 4096)
-            rgb, T = self.rast.forward(sp, rgb, T)
+            rgb, T = self.rast.forward(sp, rgb, T, zero_grads=zg)
         at = 0
         for i in batch:  # device-to-device copies of the batch's target images
             hw = self.views[i].width * self.views[i].height

@@ -955,3 +955,48 @@ def test_mixed_sides_all_equal_match_the_uniform_path(gb):
     np.testing.assert_array_equal(out[0][1], out[1][1])
     for k in out[0][2]:
         assert rel_l2(out[1][2][k], out[0][2][k]) <= 1e-6, k
+
+
+# --- texture gradients zeroed by the forward ----------------------------------------------------
+def test_forward_zeroing_replaces_the_backward_clear(gb):
+    """A forward given the coming backward's gradient arrays zeroes the texture gradients while
+    it blends and the backward skips its clear: gradients equal those of the plain path even
+    from arrays full of NaN. After a plain forward, or with another array, the backward clears
+    again. The images are those of the plain forward, bit for bit."""
+    scene = sg.make_scene(97, 3000, -1.2, 1.2, 0.01, 0.3, 8)
+    view = sg.look_at_view((0.2, -0.4, -2.9), 96, 72)
+    sp = gb.Splats.from_numpy(scene)
+    rast = gb.Rasterizer([view], gpu_opts(O.Options()))
+    rast.plan(sp)
+    g = torch.from_numpy(sg.make_dl_drgb(5, [view])).cuda()
+    rgb0, T0 = rast.forward(sp)
+    ref = {k: v.clone() for k, v in rast.backward(sp, T0, g).items()}
+    rgb0, T0 = rgb0.clone(), T0.clone()
+    nan_like = lambda d: {k: torch.full_like(v, float("nan")) for k, v in d.items()}
+
+    def check(grads):
+        torch.cuda.synchronize()
+        for k, v in ref.items():
+            got = grads[k]
+            assert bool(torch.isfinite(got).all()), k
+            assert rel_l2(got.cpu().numpy().astype(np.float64),
+                          v.cpu().numpy().astype(np.float64)) <= 1e-6, k
+
+    grads = nan_like(ref)
+    rgb, T = rast.forward(sp, zero_grads=grads)
+    torch.cuda.synchronize()
+    assert torch.equal(rgb, rgb0) and torch.equal(T, T0)
+    rast.backward(sp, T, g, grads)
+    check(grads)
+    # a plain forward in between: the backward clears by itself
+    grads = nan_like(ref)
+    rast.forward(sp, zero_grads=grads)
+    grads["textures"].fill_(float("nan"))
+    rgb, T = rast.forward(sp)
+    rast.backward(sp, T, g, grads)
+    check(grads)
+    # the backward given another array than the one the forward zeroed
+    other = nan_like(ref)
+    rgb, T = rast.forward(sp, zero_grads=nan_like(ref))
+    rast.backward(sp, T, g, other)
+    check(other)
