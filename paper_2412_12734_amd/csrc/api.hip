@@ -196,6 +196,7 @@ gb_status make_plan(int32_t P, int32_t N, const gb_view* views, int32_t n_views,
   pl->off_partials = take(4 * (size_t)pl->partials_len);
   pl->off_partials64 = take(8 * (size_t)pl->partials_len);
   pl->off_hist = take(4 * (size_t)pl->hist_len);
+  pl->off_digit_tot = take(4 * (size_t)kDigitTotWords);
   // pairs: the prefix pass's [0, prefix_cap), then the capacity (the only pass, or the rest)
   const size_t slots = (size_t)(pl->prefix_cap + capacity);
   pl->off_pair_keys = take(4 * slots);
@@ -734,8 +735,12 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   // depth order of all records: sort the key copy written by the preprocess, carrying
   // record indices (the offsets array is free until the scan and serves as ping-pong space)
   GBB_TRY(stage_mark(kStDepthSort, 0, hs), "timing");
-  GBB_TRY(launch_iota_u32(order, pl.VP, hs), "iota");
-  GBB_TRY(launch_radix_sort(dk_a, order, offsets, order_alt, nullptr, pl.VP, 32, hist, partials, hs),
+  // (the radix sorts' digit totals start from zero in every forward and each sort leaves
+  // them zero)
+  uint32_t* digit_tot = at<uint32_t>(ws, pl.off_digit_tot);
+  GBB_TRY(launch_iota_u32(order, pl.VP, digit_tot, kDigitTotWords, hs), "iota");
+  GBB_TRY(launch_radix_sort(dk_a, order, offsets, order_alt, nullptr, pl.VP, 32, hist, digit_tot,
+                            hs),
           "depth sort");
   GBB_TRY(stage_mark(kStDepthSort, 1, hs), "timing");
   // tile counts in depth order -> pair offsets and K; with the split, the prefix cut
@@ -762,7 +767,7 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   GBB_TRY(stage_mark(kStDuplicate, 1, hs), "timing");
   GBB_TRY(stage_mark(kStTileSort, 0, hs), "timing");
   GBB_TRY(launch_radix_sort(pk, pv, pk_a, pv_a, &d_st->n_sorted, cap_a, pl.tile_bits, hist,
-                            partials, hs),
+                            digit_tot, hs),
           "tile sort");
   GBB_TRY(stage_mark(kStTileSort, 1, hs), "timing");
   GBB_TRY(stage_mark(kStRanges, 0, hs), "timing");
@@ -814,7 +819,7 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
                                 pk_r, pv_r, hs),
           "rest duplicate");
   GBB_TRY(launch_radix_sort(pk_r, pv_r, pk_ra, pv_ra, &d_st->n_rest, pl.capacity, pl.tile_bits,
-                            hist, partials, hs),
+                            hist, at<uint32_t>(ws, pl.off_digit_tot), hs),
           "rest tile sort");
   GBB_TRY(launch_fill_u32(ranges_rest, 0u, 2 * pl.total_tiles, hs), "clear rest ranges");
   GBB_TRY(launch_ranges(pk_r, &d_st->n_rest, pl.capacity, ranges_rest, hs), "rest ranges");

@@ -105,7 +105,7 @@ struct Plan {
   int64_t nb_pairs;   // radix blocks over the pair capacity
   // byte offsets
   size_t off_status, off_views, off_depth_key, off_depth_key_alt, off_order, off_order_alt,
-      off_count, off_offsets, off_rec, off_partials, off_hist, off_pair_keys, off_pair_vals,
+      off_count, off_offsets, off_rec, off_partials, off_hist, off_digit_tot, off_pair_keys, off_pair_vals,
       off_pair_keys_alt, off_pair_vals_alt, off_ranges, off_n_last, off_drec, off_stats,
       off_partials64, off_view_pairs, off_spec, off_dspec,
       off_ranges_rest, off_n_last_rest, off_fwd_state, off_open_bits,
@@ -120,6 +120,9 @@ constexpr int kRadixItems = 16;
 constexpr int kRadixThreads = 256;
 constexpr int kRadixTile = kRadixItems * kRadixThreads;  // 4096 elements per block
 constexpr int kScanTile = 4096;
+// copies of a radix pass's 256 digit totals, and the words of the four passes' totals
+constexpr int kTotCopies = 64;
+constexpr int64_t kDigitTotWords = 4 * kTotCopies * 256;
 
 // Key-stage radius (px) of the screen-space low-pass disk: 2.36 for variances up to 1/2, else
 // 3.34 sqrt(var) (>= sqrt(2 var ln 255)), computed in double and rounded once to float32.
@@ -135,7 +138,9 @@ hipError_t launch_preprocess(const gb_splats& sp, const ViewDev* d_views, int n_
                              uint32_t* sort_key, uint32_t* count, SplatRec* rec, float4* spec,
                              hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
-hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t s);
+// p[i] = i for i < n, and zero[i] = 0 for i < n_zero, in one launch.
+hipError_t launch_iota_u32(uint32_t* p, int64_t n, uint32_t* zero, int64_t n_zero,
+                           hipStream_t s);
 // Pair slots per chunk of the duplicate kernels (one workgroup round).
 constexpr int kChunkSlots = 1024;
 
@@ -160,10 +165,11 @@ hipError_t launch_scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t*
 // Stable LSD radix sort of (key, value) pairs on bits [0, bits). The element count is
 // read from *d_n on the device (at most n_cap); the work of every kernel follows that count,
 // the launch sizes follow n_cap. Buffers ping-pong; the result is written back to keys/vals.
-// hist needs 256 * ceil(n_cap / kRadixTile) entries.
+// hist needs 256 * ceil(n_cap / kRadixTile) entries. digit_tot (kDigitTotWords entries) must
+// be zero on entry and is zero again on return.
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                              uint32_t* vals_alt, const uint32_t* d_n, int64_t n_cap, int bits,
-                             uint32_t* hist, uint32_t* partials, hipStream_t s);
+                             uint32_t* hist, uint32_t* digit_tot, hipStream_t s);
 // Overflow decision of a forward: st->overflow from the exact pair count against the capacity,
 // ORed into st->sticky_overflow; records the plan echo (views, splats, section offsets) for
 // gb_read_status. With mirror != null (host-mapped memory) it also stores

@@ -2,8 +2,12 @@
 //
 // Scan: reduce per 4096-element tile -> scan of tile sums in one workgroup -> per-tile scan.
 // Radix pass (a digit of at most 8 bits; a key of b bits takes ceil(b/8) passes with the bits
-// spread evenly over them): per-tile digit histogram -> exclusive scan of the digit-major
-// [digit][tile] counts -> scatter. The scatter ranks each element stably among equal digits
+// spread evenly over them), three launches: per-tile digit histogram, which also adds each
+// digit's count to the pass's digit totals -> one workgroup per digit turns its row of the
+// digit-major [digit][tile] counts into output offsets (the totals of the smaller digits
+// give the row's base) -> scatter. The totals are kept in kTotCopies copies (workgroup b adds
+// to copy b mod kTotCopies): device-wide atomics on one address are served one at a time,
+// about 55 ns each, so 2048 workgroups adding to a single copy took 35 us. The scatter ranks each element stably among equal digits
 // of its tile: each wave takes a contiguous quarter of the tile in rounds of 64; lanes with
 // the same digit are found with one ballot per digit bit and counted against the wave's
 // running per-digit counters in LDS. Wave offsets and digit starts then place every element
@@ -224,7 +228,8 @@ __device__ __forceinline__ int64_t sort_count(const uint32_t* d_n, int64_t n_cap
 template <int NBITS>
 __global__ void __launch_bounds__(kRadixThreads)
 radix_hist_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ d_n,
-                  int64_t n_cap, int shift, uint32_t* __restrict__ hist) {
+                  int64_t n_cap, int shift, uint32_t* __restrict__ hist,
+                  uint32_t* __restrict__ digit_tot) {
   constexpr int kBins = 1 << NBITS;
   constexpr uint32_t kMask = (uint32_t)kBins - 1u;
   constexpr int kWaves = kRadixThreads / 64;
@@ -232,6 +237,8 @@ radix_hist_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict_
   const int64_t n = sort_count(d_n, n_cap);
   const int64_t nb = (n + kRadixTile - 1) / kRadixTile;
   const int w = threadIdx.x >> 6;
+  static_assert(kBins <= kRadixThreads, "one digit per thread");
+  uint32_t acc = 0;  // this thread's digit, summed over the workgroup's tiles
   for (int64_t tile = blockIdx.x; tile < nb; tile += gridDim.x) {
     for (int i = threadIdx.x; i < kWaves * kBins; i += kRadixThreads) (&h[0][0])[i] = 0;
     __syncthreads();
@@ -262,13 +269,56 @@ radix_hist_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict_
       }
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < kBins; d += kRadixThreads) {
+    const int d = threadIdx.x;
+    if (d < kBins) {
       uint32_t c = 0;
 #pragma unroll
       for (int ww = 0; ww < kWaves; ++ww) c += h[ww][d];
       hist[(int64_t)d * nb + tile] = c;
+      acc += c;
     }
     __syncthreads();  // the next tile reuses the LDS histograms
+  }
+  if (threadIdx.x < kBins && acc != 0)
+    atomicAdd(&digit_tot[(blockIdx.x % kTotCopies) * 256 + threadIdx.x], acc);
+}
+
+// Output offsets of one digit (the workgroup's): its row of the [digit][tile] counts becomes
+// the exclusive prefix over tiles plus the number of elements with a smaller digit. Each
+// thread takes kItems consecutive entries of a chunk.
+template <int NBITS>
+__global__ void __launch_bounds__(kThreads)
+radix_offsets_kernel(const uint32_t* __restrict__ d_n, int64_t n_cap,
+                     const uint32_t* __restrict__ digit_tot, uint32_t* __restrict__ hist) {
+  static_assert((1 << NBITS) <= kThreads, "one smaller digit per thread");
+  __shared__ uint32_t wave_tot[kThreads / 64];
+  const int64_t n = sort_count(d_n, n_cap);
+  const int64_t nb = (n + kRadixTile - 1) / kRadixTile;
+  const int d = blockIdx.x, tid = threadIdx.x;
+  uint32_t smaller = 0;  // elements whose digit is tid (< d)
+  if (tid < d) {
+#pragma unroll 16
+    for (int c = 0; c < kTotCopies; ++c) smaller += digit_tot[c * 256 + tid];
+  }
+  uint32_t base;
+  block_inclusive_scan(smaller, wave_tot, &base);
+  uint32_t* __restrict__ row = hist + (int64_t)d * nb;
+  for (int64_t c0 = 0; c0 < nb; c0 += (int64_t)kThreads * kItems) {
+    const int64_t i0 = c0 + (int64_t)tid * kItems;
+    uint32_t v[kItems], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      v[k] = i0 + k < nb ? row[i0 + k] : 0u;
+      sum += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = base + block_inclusive_scan(sum, wave_tot, &tot) - sum;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      if (i0 + k < nb) row[i0 + k] = run;
+      run += v[k];
+    }
+    base += tot;
   }
 }
 
@@ -277,7 +327,7 @@ __global__ void __launch_bounds__(kRadixThreads)
 radix_scatter_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
                      uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
                      const uint32_t* __restrict__ d_n, int64_t n_cap, int shift,
-                     const uint32_t* __restrict__ hist_scanned) {
+                     const uint32_t* __restrict__ hist_scanned, uint32_t* __restrict__ digit_tot) {
   constexpr int kBins = 1 << NBITS;
   constexpr uint32_t kMask = (uint32_t)kBins - 1u;
   constexpr int kWaves = kRadixThreads / 64;
@@ -291,6 +341,8 @@ radix_scatter_kernel(const uint32_t* __restrict__ keys_in, const uint32_t* __res
   const int64_t n = sort_count(d_n, n_cap);
   const int64_t nb = (n + kRadixTile - 1) / kRadixTile;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  // the offsets launch has read this pass's digit totals: leave them zero for the next sort
+  for (int c = blockIdx.x; c < kTotCopies; c += gridDim.x) digit_tot[c * 256 + tid] = 0u;
   for (int64_t tile = blockIdx.x; tile < nb; tile += gridDim.x) {
     const int64_t base = tile * kRadixTile;
     const int nvalid = (int)((n - base) < kRadixTile ? (n - base) : kRadixTile);
@@ -394,10 +446,14 @@ __global__ void fill_u32x4_kernel(uint32_t* __restrict__ p, uint32_t value, int6
   if (first < (n & 3)) p[4 * n4 + first] = value;
 }
 
-__global__ void iota_u32_kernel(uint32_t* __restrict__ p, int64_t n) {
+__global__ void iota_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t* __restrict__ z,
+                                int64_t n_zero) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     p[i] = (uint32_t)i;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_zero;
+       i += (int64_t)gridDim.x * blockDim.x)
+    z[i] = 0u;
 }
 
 unsigned grid_for(int64_t n, int threads) {
@@ -420,9 +476,12 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(iota_u32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n);
+hipError_t launch_iota_u32(uint32_t* p, int64_t n, uint32_t* zero, int64_t n_zero,
+                           hipStream_t s) {
+  const int64_t m = n > n_zero ? n : n_zero;
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(iota_u32_kernel, dim3(grid_for(m, 256)), dim3(256), 0, s, p, n, zero,
+                     n_zero);
   return hipGetLastError();
 }
 
@@ -454,42 +513,40 @@ hipError_t launch_scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t*
 template <int NBITS>
 hipError_t radix_pass(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo,
                       const uint32_t* d_n, int64_t n_cap, int shift, int64_t nb, uint32_t* hist,
-                      uint32_t* partials, hipStream_t s) {
+                      uint32_t* digit_tot, hipStream_t s) {
   const unsigned grid = (unsigned)(nb < kRadixGrid ? nb : kRadixGrid);
   hipLaunchKernelGGL(radix_hist_kernel<NBITS>, dim3(grid), dim3(kRadixThreads), 0, s, ki, d_n,
-                     n_cap, shift, hist);
-  ScanLen len;
-  if (d_n) len = ScanLen{d_n, kRadixTile, (int64_t)1 << NBITS};
-  hipError_t e = launch_scan_u32(hist, nullptr, hist, ((int64_t)1 << NBITS) * nb, partials,
-                                 nullptr, nullptr, nullptr, s, nullptr, 0, len);
-  if (e != hipSuccess) return e;
+                     n_cap, shift, hist, digit_tot);
+  hipLaunchKernelGGL(radix_offsets_kernel<NBITS>, dim3(1u << NBITS), dim3(kThreads), 0, s, d_n,
+                     n_cap, digit_tot, hist);
   hipLaunchKernelGGL(radix_scatter_kernel<NBITS>, dim3(grid), dim3(kRadixThreads), 0, s, ki, vi,
-                     ko, vo, d_n, n_cap, shift, hist);
+                     ko, vo, d_n, n_cap, shift, hist, digit_tot);
   return hipGetLastError();
 }
 
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                              uint32_t* vals_alt, const uint32_t* d_n, int64_t n_cap, int bits,
-                             uint32_t* hist, uint32_t* partials, hipStream_t s) {
+                             uint32_t* hist, uint32_t* digit_tot, hipStream_t s) {
   const int64_t nb = (n_cap + kRadixTile - 1) / kRadixTile;
   if (nb == 0 || bits <= 0) return hipSuccess;
   if (bits > 32) return hipErrorInvalidValue;
   // the fewest 8-bit-or-narrower passes, with the key bits spread evenly over them
   const int passes = (bits + 7) / 8;
+  hipError_t e = hipSuccess;
   uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
   int shift = 0;
   for (int p = 0; p < passes; ++p) {
     const int nbits = bits / passes + (p < bits % passes ? 1 : 0);
-    hipError_t e;
+    uint32_t* const tot = digit_tot + (int64_t)kTotCopies * 256 * p;
     switch (nbits) {
-      case 1: e = radix_pass<1>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, partials, s); break;
-      case 2: e = radix_pass<2>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, partials, s); break;
-      case 3: e = radix_pass<3>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, partials, s); break;
-      case 4: e = radix_pass<4>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, partials, s); break;
-      case 5: e = radix_pass<5>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, partials, s); break;
-      case 6: e = radix_pass<6>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, partials, s); break;
-      case 7: e = radix_pass<7>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, partials, s); break;
-      default: e = radix_pass<8>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, partials, s); break;
+      case 1: e = radix_pass<1>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, tot, s); break;
+      case 2: e = radix_pass<2>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, tot, s); break;
+      case 3: e = radix_pass<3>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, tot, s); break;
+      case 4: e = radix_pass<4>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, tot, s); break;
+      case 5: e = radix_pass<5>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, tot, s); break;
+      case 6: e = radix_pass<6>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, tot, s); break;
+      case 7: e = radix_pass<7>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, tot, s); break;
+      default: e = radix_pass<8>(ki, vi, ko, vo, d_n, n_cap, shift, nb, hist, tot, s); break;
     }
     if (e != hipSuccess) return e;
     shift += nbits;
