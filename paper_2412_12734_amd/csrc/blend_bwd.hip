@@ -138,8 +138,9 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
 
 // With batches of 8 the LDS would allow more than 6 waves per SIMD, but the register
 // allocation (75 VGPRs unconstrained) stops there; asking for 7 (at most 72 VGPRs; the
-// compiler's resource report gives 71 and no VGPR spills for 8 x 8 grids) measured 4 % faster
-// on the 1M-splat 1080p workload, 8 (64 VGPRs) slower.
+// compiler's resource report gives 72, with 3 dwords spilled in the prologue and the list
+// loop's header, none inside the batch loop, for 8 x 8 grids) measured 4 % faster on the
+// 1M-splat 1080p workload, 8 (64 VGPRs) slower.
 // (N = 16 blocks hold 61 KB of LDS, two per CU, so no register target applies there.)
 // Wave steps that blended at most this many pixels skip the cell grouping (measured at 1M
 // splats and 1080p: unchanged time; 100k splats at 800x800 and 3M splats at 4 x 1080p, where
@@ -169,7 +170,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   __shared__ int32_t s_splat[B];
   __shared__ uint32_t s_recid[B];
   __shared__ float4 s_tex[B * TexLayout<N>::kPerSplat];
-  __shared__ float s_gtex[B * TEXG];
+  __shared__ __attribute__((aligned(16))) float s_gtex[B * TEXG];
   __shared__ float s_grec[B * kRecGrad];  // per splat
   __shared__ uint32_t s_tile_last;
   __shared__ int32_t s_gn[MIXED ? B : 1];
@@ -286,7 +287,13 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
           }
         }
       }
-      for (int e = tid; e < nb * TEXG; e += nthr) s_gtex[e] = 0.f;
+      if constexpr (TEXG % 4 == 0) {
+        // 16-byte stores: a batch's sums are a whole number of float4s
+        float4* g4 = reinterpret_cast<float4*>(s_gtex);
+        for (int e = tid; e < nb * (TEXG / 4); e += nthr) g4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+      } else {
+        for (int e = tid; e < nb * TEXG; e += nthr) s_gtex[e] = 0.f;
+      }
       for (int e = tid; e < nb * kRecGrad; e += nthr) s_grec[e] = 0.f;
       if constexpr (MIXED) {
         __syncthreads();  // sides and offsets of the batch's grids
@@ -438,6 +445,21 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
             const int t = i / 3, c = i - 3 * t, iu = div_side(t, n), iv = t - iu * n;
             const float x = s_gtex[j * TEXG + 3 * (iu * N + iv) + c];
             if (x != 0.f) atomicAdd(&d_tex[3 * s_toff[j] + i], x);
+          }
+        }
+      } else if constexpr (TEXG % 4 == 0) {
+        // four sums per 16-byte LDS read; one global atomic per non-zero sum
+        constexpr int TEXG4 = TEXG / 4;
+        const float4* g4 = reinterpret_cast<const float4*>(s_gtex);
+        for (int e = tid; e < nb * TEXG4; e += nthr) {
+          const float4 x = g4[e];
+          if (x.x != 0.f || x.y != 0.f || x.z != 0.f || x.w != 0.f) {
+            const int j = e / TEXG4, r = 4 * (e - j * TEXG4);
+            float* dst = d_tex + (int64_t)s_splat[j] * TEXG + r;
+            if (x.x != 0.f) atomicAdd(dst + 0, x.x);
+            if (x.y != 0.f) atomicAdd(dst + 1, x.y);
+            if (x.z != 0.f) atomicAdd(dst + 2, x.z);
+            if (x.w != 0.f) atomicAdd(dst + 3, x.w);
           }
         }
       } else {
