@@ -495,7 +495,7 @@ def main():
         rgb_t, T_t = rast_t.forward(sp4)
         grads_t = rast_t.backward(sp4, T_t, g4)
         for _ in range(args.warmup):
-            rast_t.forward(sp4, rgb_t, T_t)
+            rast_t.forward(sp4, rgb_t, T_t, zero_grads=grads_t)
             rast_t.backward(sp4, T_t, g4, grads_t)
         s_t = time_steps(rast_t, sp4, rgb_t, T_t, g4, grads_t, args.steps, torch)
         variants["bf16_batched_4x1080p_autotuned"] = {

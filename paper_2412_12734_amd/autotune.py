@@ -104,13 +104,15 @@ def gpu_cost(splats, views, steps: int = 3, warmup: int = 1) -> Callable[[object
         rgb, T = rast.forward(splats)
         g = torch.ones((rast.total_pixels, 3), dtype=torch.float32, device=rgb.device)
         grads = rast.backward(splats, T, g)
+        # the forward zeroes the texture gradients the backward accumulates into, as in a
+        # training step
         for _ in range(warmup):
-            rast.forward(splats, rgb, T)
+            rast.forward(splats, rgb, T, zero_grads=grads)
             rast.backward(splats, T, g, grads)
         times = []
         rast.timing(True)
         for _ in range(steps):
-            rast.forward(splats, rgb, T)
+            rast.forward(splats, rgb, T, zero_grads=grads)
             rast.backward(splats, T, g, grads)
             times.append(sum(rast.stage_times().values()))
         rast.timing(False)
