@@ -753,16 +753,22 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   const StatusEcho echo{(uint32_t)n_views, (uint32_t)pl.P, (unsigned long long)pl.off_count,
                         (unsigned long long)pl.off_view_pairs};
   GBB_TRY(launch_finalize_count(offsets, pl.VP, d_st, pl.capacity, echo, m_dev, overflow_flag,
-                                hs),
+                                pl.split ? pl.prefix_cap : 0, hs),
           "finalize count");
-  if (pl.split)
-    GBB_TRY(launch_prefix_cut(offsets, pl.VP, pl.prefix_cap, d_st, hs), "prefix cut");
   GBB_TRY(stage_mark(kStPairScan, 1, hs), "timing");
   // first (or only) pass: pairs of the depth prefix, sorted by tile, ranges, blend
   const int64_t cap_a = pl.split ? pl.prefix_cap : pl.capacity;
   GBB_TRY(stage_mark(kStDuplicate, 0, hs), "timing");
+  // the duplicate launch also zeroes the tile ranges and, with the split, the open-tile bitmap
+  ClearList clear_a;
+  clear_a.p[0] = ranges;
+  clear_a.n[0] = 2 * pl.total_tiles;
+  if (pl.split) {
+    clear_a.p[1] = at<uint32_t>(ws, pl.off_open_bits);
+    clear_a.n[1] = (pl.total_tiles + 31) / 32;
+  }
   GBB_TRY(launch_duplicate(order, count, offsets, chunk_owner, rec, d_views, pl.tile_w, pl.tile_h,
-                           d_st, cap_a, pk, pv, hs),
+                           d_st, cap_a, pk, pv, clear_a, hs),
           "duplicate");
   GBB_TRY(stage_mark(kStDuplicate, 1, hs), "timing");
   GBB_TRY(stage_mark(kStTileSort, 0, hs), "timing");
@@ -771,7 +777,6 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
           "tile sort");
   GBB_TRY(stage_mark(kStTileSort, 1, hs), "timing");
   GBB_TRY(stage_mark(kStRanges, 0, hs), "timing");
-  GBB_TRY(launch_fill_u32(ranges, 0u, 2 * pl.total_tiles, hs), "clear ranges");
   GBB_TRY(launch_ranges(pk, &d_st->n_sorted, cap_a, ranges, hs), "ranges");
   GBB_TRY(stage_mark(kStRanges, 1, hs), "timing");
   // per-tile blended spans for the backward's work order
@@ -784,7 +789,6 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
     split.open_bits = at<uint32_t>(ws, pl.off_open_bits);
     split.fwd_state = at<float4>(ws, pl.off_fwd_state);
     split.any_open = &d_st->any_open;  // cleared by the count's finalisation
-    GBB_TRY(launch_fill_u32(split.open_bits, 0u, (pl.total_tiles + 31) / 32, hs), "clear bits");
   }
   GBB_TRY(stage_mark(kStBlendFwd, 0, hs), "timing");
   const float4* spec = s->sh ? at<float4>(ws, pl.off_spec) : nullptr;
@@ -814,14 +818,16 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
                           &d_st->K_rest64, partials64, hs, chunk_owner, pl.n_chunks),
           "rest scan");
   GBB_TRY(launch_finalize_rest(offsets_rest, pl.VP, d_st, hs), "rest finalize");
+  ClearList clear_r;  // the rest pass's tile ranges
+  clear_r.p[0] = ranges_rest;
+  clear_r.n[0] = 2 * pl.total_tiles;
   GBB_TRY(launch_duplicate_rest(order, count_rest, offsets_rest, chunk_owner, rec, d_views,
                                 pl.tile_w, pl.tile_h, d_st, split.open_bits, sat, pl.capacity,
-                                pk_r, pv_r, hs),
+                                pk_r, pv_r, clear_r, hs),
           "rest duplicate");
   GBB_TRY(launch_radix_sort(pk_r, pv_r, pk_ra, pv_ra, &d_st->n_rest, pl.capacity, pl.tile_bits,
                             hist, at<uint32_t>(ws, pl.off_digit_tot), hs),
           "rest tile sort");
-  GBB_TRY(launch_fill_u32(ranges_rest, 0u, 2 * pl.total_tiles, hs), "clear rest ranges");
   GBB_TRY(launch_ranges(pk_r, &d_st->n_rest, pl.capacity, ranges_rest, hs), "rest ranges");
   GBB_TRY(stage_mark(kStRestTiles, 1, hs), "timing");
   split.mode = kRestPass;

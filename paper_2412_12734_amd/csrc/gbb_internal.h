@@ -179,24 +179,28 @@ struct StatusEcho {
   uint32_t n_views, P;
   unsigned long long off_count, off_view_pairs;
 };
+// With budget > 0 (the depth-prefix split) it also takes the prefix cut: the largest record
+// count (in depth order) whose pairs fit the budget, in st->cut, with st->n_sorted the
+// prefix's pairs (both zero on overflow); otherwise st->cut = VP and st->n_sorted = K.
 hipError_t launch_finalize_count(const uint32_t* offsets, int64_t VP, Status* st,
                                  int64_t capacity, StatusEcho echo,
                                  unsigned long long* mirror, uint32_t* overflow_flag,
-                                 hipStream_t s);
+                                 int64_t budget, hipStream_t s);
 // Per-view pair totals: out[v] = sum of count[v P .. (v + 1) P) (one workgroup per view).
 hipError_t launch_view_pairs(const uint32_t* count, int64_t P, int n_views,
                              unsigned long long* out, hipStream_t s);
-// Depth-prefix cut: the largest record count (in depth order) whose pairs fit `budget`.
-// Writes st->cut and st->n_sorted (the prefix's pairs); nothing on overflow.
-hipError_t launch_prefix_cut(const uint32_t* offsets, int64_t VP, int64_t budget, Status* st,
-                             hipStream_t s);
 // Pairs of the first pass: the st->n_sorted slots of the depth order's offsets, expanded in
 // chunks of kChunkSlots (chunk_owner from the offset scan); cap bounds the slot count.
+// Up to two u32 arrays that a duplicate launch also zeroes (p[k] may be null when n[k] = 0).
+struct ClearList {
+  uint32_t* p[2] = {nullptr, nullptr};
+  int64_t n[2] = {0, 0};
+};
 hipError_t launch_duplicate(const uint32_t* order, const uint32_t* count,
                             const uint32_t* offsets, const uint32_t* chunk_owner,
                             const SplatRec* rec, const ViewDev* views, int tile_w, int tile_h,
                             const Status* st, int64_t cap, uint32_t* pair_keys,
-                            uint32_t* pair_vals, hipStream_t s);
+                            uint32_t* pair_vals, ClearList clear, hipStream_t s);
 // Second pass: count_rest[r] = open tiles covered by the record at depth rank r >= st->cut.
 hipError_t launch_count_rest(const uint32_t* order, const uint32_t* count, const SplatRec* rec,
                              const ViewDev* views, int64_t VP, int tile_w, int tile_h,
@@ -214,7 +218,7 @@ hipError_t launch_duplicate_rest(const uint32_t* order, const uint32_t* count_re
                                  const SplatRec* rec, const ViewDev* views, int tile_w,
                                  int tile_h, const Status* st, const uint32_t* open_bits,
                                  const uint32_t* sat, int64_t cap, uint32_t* pair_keys,
-                                 uint32_t* pair_vals, hipStream_t s);
+                                 uint32_t* pair_vals, ClearList clear, hipStream_t s);
 // Tile ranges of the first *d_n sorted keys.
 hipError_t launch_ranges(const uint32_t* pair_keys, const uint32_t* d_n, int64_t n_cap,
                          uint32_t* ranges, hipStream_t s);

@@ -33,7 +33,8 @@ __device__ __forceinline__ int64_t last_at_or_below(const uint32_t* __restrict__
 
 __global__ void finalize_count_kernel(const uint32_t* __restrict__ offsets, int64_t VP,
                                       Status* st, int64_t capacity, StatusEcho echo,
-                                      unsigned long long* mirror, uint32_t* overflow_flag) {
+                                      unsigned long long* mirror, uint32_t* overflow_flag,
+                                      int64_t budget) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     // the exact 64-bit total decides: the 32-bit offsets wrap only when it exceeds 2^32,
     // and the capacity is below that
@@ -48,10 +49,20 @@ __global__ void finalize_count_kernel(const uint32_t* __restrict__ offsets, int6
     // one aligned 8-byte store, so that the host never reads a torn value
     if (mirror) *reinterpret_cast<volatile unsigned long long*>(mirror) = (over ? 1ull << 63 : 0ull) | K;
     if (overflow_flag && over) *overflow_flag = 1u;
-    st->n_sorted = over ? 0u : (uint32_t)K;
-    st->cut = (uint32_t)VP;
-    st->last_first = (!over && K > 0) ? (uint32_t)last_at_or_below(offsets, VP, K - 1) : 0u;
     st->any_open = 0u;
+    uint32_t n = over ? 0u : (uint32_t)K, cut = (uint32_t)VP;
+    if (budget > 0) {
+      // depth-prefix cut: the largest record count (in depth order) whose pairs fit the budget
+      if (over) {
+        cut = 0u;
+      } else if (K > (unsigned long long)budget) {
+        cut = (uint32_t)last_at_or_below(offsets, VP, (uint64_t)budget);
+        n = offsets[cut];
+      }
+    }
+    st->cut = cut;
+    st->n_sorted = n;
+    st->last_first = n > 0 ? (uint32_t)last_at_or_below(offsets, VP, n - 1) : 0u;
   }
 }
 
@@ -76,27 +87,6 @@ static_assert(kChunkSlots == 4 * kDupThreads, "four slots per thread and round")
 
 // Prefix pass: the largest record count (in depth order) whose pairs fit the budget; single
 // thread, binary search over the exclusive offsets (offsets[VP] = K).
-__global__ void prefix_cut_kernel(const uint32_t* __restrict__ offsets, int64_t VP,
-                                  int64_t budget, Status* st) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (st->overflow) {
-    st->cut = 0;
-    st->n_sorted = 0;
-    return;
-  }
-  const unsigned long long K = st->K64;
-  if (K <= (unsigned long long)budget) {
-    st->cut = (uint32_t)VP;
-    st->n_sorted = (uint32_t)K;
-  } else {
-    const int64_t cut = last_at_or_below(offsets, VP, (uint64_t)budget);
-    st->cut = (uint32_t)cut;
-    st->n_sorted = offsets[cut];
-  }
-  st->last_first = st->n_sorted > 0 ? (uint32_t)last_at_or_below(offsets, VP, st->n_sorted - 1)
-                                     : 0u;
-}
-
 // Inclusive max-scan over the 64 lanes of a wave.
 __device__ __forceinline__ int wave_max_scan(int v) {
   const int lane = threadIdx.x & 63;
@@ -165,7 +155,7 @@ expand_kernel(const uint32_t* __restrict__ order, const uint32_t* __restrict__ c
               const SplatRec* __restrict__ rec, const ViewDev* __restrict__ views, int tile_w,
               int tile_h, const Status* __restrict__ st, const uint32_t* __restrict__ open_bits,
               const uint32_t* __restrict__ sat, int64_t cap, uint32_t* __restrict__ pair_keys,
-              uint32_t* __restrict__ pair_vals) {
+              uint32_t* __restrict__ pair_vals, ClearList clear) {
   constexpr int C = kChunkSlots;
   __shared__ int s_own[C];
   __shared__ uint32_t s_start[C];   // first slot of the record
@@ -177,6 +167,13 @@ expand_kernel(const uint32_t* __restrict__ order, const uint32_t* __restrict__ c
   __shared__ uint32_t s_h[REST ? C : 1];    // rectangle height in tiles
   __shared__ uint32_t s_sat[REST ? C : 1];  // open-tile table entry of the top-left tile
   __shared__ int s_wave_max[kDupThreads / 64];
+  // arrays the later stages of the pass expect zeroed (the pass's tile ranges, the open-tile
+  // bitmap), whatever the pair count, so that they need no launches of their own
+  for (int k = 0; k < 2; ++k) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < clear.n[k];
+         i += (int64_t)gridDim.x * blockDim.x)
+      clear.p[k][i] = 0u;
+  }
   if (st->overflow) return;
   const int64_t total = (int64_t)(REST ? st->n_rest : st->n_sorted);
   const int64_t last = (int64_t)(REST ? st->last_rest : st->last_first);
@@ -523,21 +520,15 @@ hipError_t launch_order_tiles(const uint32_t* work, int64_t n_tiles, uint32_t* o
 hipError_t launch_finalize_count(const uint32_t* offsets, int64_t VP, Status* st,
                                  int64_t capacity, StatusEcho echo,
                                  unsigned long long* mirror, uint32_t* overflow_flag,
-                                 hipStream_t s) {
+                                 int64_t budget, hipStream_t s) {
   hipLaunchKernelGGL(finalize_count_kernel, dim3(1), dim3(64), 0, s, offsets, VP, st, capacity,
-                     echo, mirror, overflow_flag);
+                     echo, mirror, overflow_flag, budget);
   return hipGetLastError();
 }
 
 hipError_t launch_view_pairs(const uint32_t* count, int64_t P, int n_views,
                              unsigned long long* out, hipStream_t s) {
   hipLaunchKernelGGL(view_pairs_kernel, dim3((unsigned)n_views), dim3(256), 0, s, count, P, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_prefix_cut(const uint32_t* offsets, int64_t VP, int64_t budget, Status* st,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(prefix_cut_kernel, dim3(1), dim3(64), 0, s, offsets, VP, budget, st);
   return hipGetLastError();
 }
 
@@ -550,10 +541,10 @@ hipError_t launch_duplicate(const uint32_t* order, const uint32_t* count,
                             const uint32_t* offsets, const uint32_t* chunk_owner,
                             const SplatRec* rec, const ViewDev* views, int tile_w, int tile_h,
                             const Status* st, int64_t cap, uint32_t* pair_keys,
-                            uint32_t* pair_vals, hipStream_t s) {
+                            uint32_t* pair_vals, ClearList clear, hipStream_t s) {
   hipLaunchKernelGGL(expand_kernel<false>, dim3(dup_grid(cap)), dim3(kDupThreads), 0, s, order,
                      count, offsets, chunk_owner, rec, views, tile_w, tile_h, st, nullptr, nullptr,
-                     cap, pair_keys, pair_vals);
+                     cap, pair_keys, pair_vals, clear);
   return hipGetLastError();
 }
 
@@ -586,10 +577,10 @@ hipError_t launch_duplicate_rest(const uint32_t* order, const uint32_t* count_re
                                  const SplatRec* rec, const ViewDev* views, int tile_w,
                                  int tile_h, const Status* st, const uint32_t* open_bits,
                                  const uint32_t* sat, int64_t cap, uint32_t* pair_keys,
-                                 uint32_t* pair_vals, hipStream_t s) {
+                                 uint32_t* pair_vals, ClearList clear, hipStream_t s) {
   hipLaunchKernelGGL(expand_kernel<true>, dim3(dup_grid(cap)), dim3(kDupThreads), 0, s, order,
                      count_rest, offsets_rest, chunk_owner, rec, views, tile_w, tile_h, st,
-                     open_bits, sat, cap, pair_keys, pair_vals);
+                     open_bits, sat, cap, pair_keys, pair_vals, clear);
   return hipGetLastError();
 }
 
