@@ -22,6 +22,7 @@
 // global memory with one float atomic each.
 #include "blend_common.h"
 
+
 namespace gbb {
 
 namespace {
@@ -136,12 +137,13 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
   o.gc2y = -ddy;
 }
 
-// With batches of 8 the LDS would allow more than 6 waves per SIMD, but the register
-// allocation (75 VGPRs unconstrained) stops there; asking for 7 (at most 72 VGPRs; the
-// compiler's resource report gives 72, with 3 dwords spilled in the prologue and the list
-// loop's header, none inside the batch loop, for 8 x 8 grids) measured 4 % faster on the
-// 1M-splat 1080p workload, 8 (64 VGPRs) slower.
-// (N = 16 blocks hold 61 KB of LDS, two per CU, so no register target applies there.)
+// With batches of 8 the LDS allows 7 workgroups per CU (22.6 KB each for 8 x 8 grids, with
+// the geometry of 8 batches), but the register allocation (75 VGPRs unconstrained) stops at
+// 6 waves per SIMD; asking for 7 (at most 72 VGPRs; the compiler's resource report gives 72,
+// with 4 dwords spilled: in the prologue, the list loop's header and one reload per batch,
+// none inside the splat loop) measured 4 % faster on the 1M-splat 1080p workload, 8
+// (64 VGPRs) slower.
+// (N = 16 blocks hold 67 KB of LDS, two per CU, so no register target applies there.)
 // Wave steps that blended at most this many pixels skip the cell grouping (measured at 1M
 // splats and 1080p: unchanged time; 100k splats at 800x800 and 3M splats at 4 x 1080p, where
 // fewer lanes blend per step: 5 and 6 % faster; 32 lanes gained more there but cost the 1M
@@ -150,6 +152,16 @@ constexpr int kLaneAddMax = 16;
 
 template <int N, int B>
 constexpr int bwd_min_waves() { return (B <= 8 && N <= 8) ? 7 : 1; }
+
+// Batches whose geometry one staging pass prepares: as many as the workgroup's threads can
+// stage at once. A workgroup has 64 threads per wave block and a batch needs B per block, so
+// that is 64 / B whatever the tile shape. The staging pass is on every wave's path (the waves
+// wait for it at the barrier), so fewer, fuller passes shorten the walk: at 1M splats and
+// 1080p the backward took 1.540 ms staging every batch on its own (32 of one wave's 64 lanes
+// busy), 1.473 / 1.448 / 1.420 ms staging 2 / 4 / 8 batches at once; at 3M splats on four
+// 1080p views 16.82 / 15.95 / 15.60 / 15.50 ms.
+template <int B>
+constexpr int bwd_stage_ahead() { return 64 / B; }
 
 // Depth-prefix split: on a tile that the prefix left open the block first walks the rest
 // pass's list (the later splats) and then, with each pixel's T and S carried over in
@@ -165,17 +177,21 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
                  float* __restrict__ d_rec, float* __restrict__ d_tex) {
   constexpr int TEXG = 3 * N * N;
   constexpr int BH = 8 * PIX;  // wave block: 8 columns x BH rows
-  __shared__ GeoLds<B> s_geo;
-  __shared__ uint8_t s_reach[4][B];  // [wave block][staged splat]: may reach the block
-  __shared__ int32_t s_splat[B];
-  __shared__ uint32_t s_recid[B];
+  // Per-splat geometry and indices of AHEAD batches (slot k holds [k B, (k + 1) B)): every
+  // AHEAD-th batch stages its own and the next AHEAD - 1 batches' geometry in one pass of the
+  // staging threads.
+  constexpr int AHEAD = bwd_stage_ahead<B>();
+  __shared__ GeoLds<AHEAD * B> s_geo;
+  __shared__ uint8_t s_reach[4][AHEAD * B];  // [wave block][staged splat]: may reach the block
+  __shared__ int32_t s_splat[AHEAD * B];
+  __shared__ uint32_t s_recid[AHEAD * B];
   __shared__ float4 s_tex[B * TexLayout<N>::kPerSplat];
   __shared__ __attribute__((aligned(16))) float s_gtex[B * TEXG];
   __shared__ float s_grec[B * kRecGrad];  // per splat
   __shared__ uint32_t s_tile_last;
-  __shared__ int32_t s_gn[MIXED ? B : 1];
-  __shared__ float s_gscale[MIXED ? B : 1];
-  __shared__ int64_t s_toff[MIXED ? B : 1];
+  __shared__ int32_t s_gn[MIXED ? AHEAD * B : 1];
+  __shared__ float s_gscale[MIXED ? AHEAD * B : 1];
+  __shared__ int64_t s_toff[MIXED ? AHEAD * B : 1];
 
   const int tile = tile_of_block(p);
   if (tile >= p.total_tiles) return;
@@ -254,35 +270,47 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
     __syncthreads();
     const uint32_t tile_last = s_tile_last;
 
-    for (uint32_t bend = tile_last; bend > start;) {
+    int slot = 0;  // slot of the batch's geometry: the batch's index in the list mod AHEAD
+    for (uint32_t bend = tile_last; bend > start; slot = slot + 1 < AHEAD ? slot + 1 : 0) {
       const uint32_t bstart = (bend - start) > (uint32_t)B ? bend - (uint32_t)B : start;
       const int nb = (int)(bend - bstart);
-      {
-        // thread c stages splat c mod B for wave block c / B (geometry centred on that block)
-        // and tests whether it can reach the block
+      const int so = slot * B;
+      if (slot == 0) {
+        // thread c stages splat c mod B of batch h = c / (B n_waves) from this one (h = 0 is
+        // this batch; h < AHEAD since the workgroup has 64 n_waves threads) for wave block
+        // (c / B) mod n_waves (n_waves is 1, 2 or 4), geometry centred on that block, and tests
+        // whether it can reach the block
         // (recomputed per batch from an opaque copy of the thread index: hoisted out of the
         // loop, these indices would hold registers across the reverse walk)
         int t = tid;
         __asm__ volatile("" : "+v"(t));
-        const int j = t & (B - 1), b = t / B;
-        if (b < n_waves && j < nb) {
-          const uint32_t r = pair_vals[bstart + j];
+        const int j = t & (B - 1), b = (t / B) & (n_waves - 1),
+                  h = (t / B) >> __builtin_ctz((unsigned)n_waves);
+        // batch h is [bend - min(rem, (h + 1) B), bend - min(rem, h B))
+        const uint32_t rem = bend - start;
+        const uint32_t o0 = (uint32_t)(h * B) < rem ? (uint32_t)(h * B) : rem;
+        const uint32_t o1 = (uint32_t)((h + 1) * B) < rem ? (uint32_t)((h + 1) * B) : rem;
+        const uint32_t hstart = bend - o1;
+        const int hnb = (int)(o1 - o0);
+        if (h < AHEAD && j < hnb) {
+          const int jj = h * B + j;
+          const uint32_t r = pair_vals[hstart + j];
           const SplatRec R = rec[r];
           const int kbx = tile_x0 + (b % waves_x) * 8, kby = tile_y0 + (b / waves_x) * BH;
           const StagedGeo g = stage_geo(R, kbx + 4, kby + BH / 2, tcx, tcy);
-          s_geo.store(b, j, g);
-          s_reach[b][j] = block_may_contribute(g, (float)(kbx + 4 - tcx),
-                                               (float)(kby + BH / 2 - tcy), kbx, kby, p, 8, BH)
-                              ? 1
-                              : 0;
+          s_geo.store(b, jj, g);
+          s_reach[b][jj] = block_may_contribute(g, (float)(kbx + 4 - tcx),
+                                                (float)(kby + BH / 2 - tcy), kbx, kby, p, 8, BH)
+                               ? 1
+                               : 0;
           if (b == 0) {
-            s_splat[j] = R.splat;
-            s_recid[j] = r;
+            s_splat[jj] = R.splat;
+            s_recid[jj] = r;
             if (MIXED) {
               const int n = grid_side<N>(p, r - rec_base);
-              s_gn[j] = n;
-              s_gscale[j] = grid_scale(n, p.sigma);
-              s_toff[j] = p.grid_at[r - rec_base];
+              s_gn[jj] = n;
+              s_gscale[jj] = grid_scale(n, p.sigma);
+              s_toff[jj] = p.grid_at[r - rec_base];
             }
           }
         }
@@ -297,21 +325,21 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
       for (int e = tid; e < nb * kRecGrad; e += nthr) s_grec[e] = 0.f;
       if constexpr (MIXED) {
         __syncthreads();  // sides and offsets of the batch's grids
-        stage_texels_mixed<N, BF16>(textures, pair_vals + bstart, nb, s_tex, p.spec, s_gn,
-                                    s_toff);
+        stage_texels_mixed<N, BF16>(textures, pair_vals + bstart, nb, s_tex, p.spec, s_gn + so,
+                                    s_toff + so);
       } else
         stage_texels<N, BF16>(textures, pair_vals + bstart, rec_base, nb, s_tex, p.spec);
       __syncthreads();
 
       // splats of this batch that can reach the wave's block, walked back to front
-      const bool may = lane < nb && s_reach[w][lane] != 0;
+      const bool may = lane < nb && s_reach[w][so + lane] != 0;
       uint64_t todo = ballot(may);
       while (todo != 0) {
         const int j = 63 - (int)__builtin_clzll(todo);
         todo &= ~(1ull << j);
         const uint32_t jg = bstart + (uint32_t)j;
         if (!__any(jg < lane_last)) continue;
-        const StagedGeo g = s_geo.load(w, j);
+        const StagedGeo g = s_geo.load(w, so + j);
         const float4* tex = s_tex + j * TexLayout<N>::kPerSplat;
         PixelEval e[PIX];
         bool act[PIX], wave_act = false;
@@ -324,8 +352,8 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
         if (!__any(wave_act)) continue;  // no pixel of the wave blended this splat
         PixOut po[PIX];
         if constexpr (MIXED) {
-          const int gn = s_gn[j];
-          const float gscale = s_gscale[j];
+          const int gn = s_gn[so + j];
+          const float gscale = s_gscale[so + j];
 #pragma unroll
           for (int s = 0; s < PIX; ++s)
             pixel_step<N, true>(g, tex, e[s], act[s], ps[s], p, po[s], gn, gscale);
@@ -432,7 +460,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
           float x = 0.f;
           for (int t = lane; t < N * N; t += 64) x += s_gtex[j * TEXG + 3 * t + c];
           x = wave_sum(x);
-          if (lane == 0 && x != 0.f) atomicAdd(&p.d_spec[4 * (int64_t)s_recid[j] + c], x);
+          if (lane == 0 && x != 0.f) atomicAdd(&p.d_spec[4 * (int64_t)s_recid[so + j] + c], x);
         }
       }
       // flush the batch's sums
@@ -440,11 +468,11 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
         // the N x N sums hold splat j's n x n grid in rows and columns [0, n): one wave per
         // splat, lane i taking values i, i + 64, ... of the grid's 3 n^2
         for (int j = w; j < nb; j += nthr >> 6) {
-          const int n = s_gn[j];
+          const int n = s_gn[so + j];
           for (int i = lane; i < 3 * n * n; i += 64) {
             const int t = i / 3, c = i - 3 * t, iu = div_side(t, n), iv = t - iu * n;
             const float x = s_gtex[j * TEXG + 3 * (iu * N + iv) + c];
-            if (x != 0.f) atomicAdd(&d_tex[3 * s_toff[j] + i], x);
+            if (x != 0.f) atomicAdd(&d_tex[3 * s_toff[so + j] + i], x);
           }
         }
       } else if constexpr (TEXG % 4 == 0) {
@@ -455,7 +483,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
           const float4 x = g4[e];
           if (x.x != 0.f || x.y != 0.f || x.z != 0.f || x.w != 0.f) {
             const int j = e / TEXG4, r = 4 * (e - j * TEXG4);
-            float* dst = d_tex + (int64_t)s_splat[j] * TEXG + r;
+            float* dst = d_tex + (int64_t)s_splat[so + j] * TEXG + r;
             if (x.x != 0.f) atomicAdd(dst + 0, x.x);
             if (x.y != 0.f) atomicAdd(dst + 1, x.y);
             if (x.z != 0.f) atomicAdd(dst + 2, x.z);
@@ -467,14 +495,14 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
           const float x = s_gtex[e];
           if (x != 0.f) {
             const int j = e / TEXG, r = e - j * TEXG;
-            atomicAdd(&d_tex[(int64_t)s_splat[j] * TEXG + r], x);
+            atomicAdd(&d_tex[(int64_t)s_splat[so + j] * TEXG + r], x);
           }
         }
       }
       for (int e = tid; e < nb * kRecGrad; e += nthr) {
         const int j = e / kRecGrad, r = e - j * kRecGrad;
         const float x = s_grec[e];
-        if (x != 0.f) atomicAdd(&d_rec[(int64_t)s_recid[j] * kRecGrad + r], x);
+        if (x != 0.f) atomicAdd(&d_rec[(int64_t)s_recid[so + j] * kRecGrad + r], x);
       }
       __syncthreads();
       bend = bstart;

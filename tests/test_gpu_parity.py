@@ -454,6 +454,18 @@ def test_batch_sizes(gb, batch, batch_bwd):
                 batch_bwd=batch_bwd)
 
 
+# --- backward batch sizes on every wave count: one, two and four 8 x 8 wave blocks per tile ----
+# (the backward stages the geometry of several batches at once, 64 / batch of them, with the
+# staging threads spread over the workgroup's waves; each tile here walks tens of batches)
+@pytest.mark.parametrize("tile", [(8, 8), (16, 8), (8, 16), (16, 16)])
+@pytest.mark.parametrize("batch_bwd", [8, 16, 32])
+def test_backward_batches_on_every_tile_shape(gb, tile, batch_bwd):
+    scene = sg.make_scene(23, 3000, -1.5, 1.5, 0.02, 0.25, 4)
+    view = sg.look_at_view((0.2, -0.1, -4.0), 88, 72)
+    opts = O.Options(tile_w=tile[0], tile_h=tile[1])
+    check_grads(gb, scene, view, opts, (8, 8, 64, 56), seed=17, batch_bwd=batch_bwd)
+
+
 # --- depth-prefix split: same images as one pass, exact pair sets ---------------------------
 def dense_scene(N=4):
     scene = sg.make_scene(31, 20000, -1.0, 1.0, 0.03, 0.3, N)
