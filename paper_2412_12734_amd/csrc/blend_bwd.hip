@@ -249,6 +249,11 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   wave_scatter_slot<KT>(sides, tex_slot, tex_owner);
   const int tex_off = 3 * ((tex_slot / 3 & 1) + (tex_slot / 6) * N) + tex_slot % 3;
 
+  // the per-batch LDS sums start at zero; each batch's flush clears what it read
+  // (the first barrier of the list loop orders these stores before any add)
+  for (int e = tid; e < B * TEXG; e += nthr) s_gtex[e] = 0.f;
+  for (int e = tid; e < B * kRecGrad; e += nthr) s_grec[e] = 0.f;
+
 #pragma unroll 1
   for (int li = tile_open ? 0 : 1; li < 2; ++li) {
     const PairList L = li == 0 ? rest : first;
@@ -270,66 +275,70 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
     __syncthreads();
     const uint32_t tile_last = s_tile_last;
 
-    int slot = 0;  // slot of the batch's geometry: the batch's index in the list mod AHEAD
-    for (uint32_t bend = tile_last; bend > start; slot = slot + 1 < AHEAD ? slot + 1 : 0) {
-      const uint32_t bstart = (bend - start) > (uint32_t)B ? bend - (uint32_t)B : start;
-      const int nb = (int)(bend - bstart);
-      const int so = slot * B;
-      if (slot == 0) {
-        // thread c stages splat c mod B of batch h = c / (B n_waves) from this one (h = 0 is
-        // this batch; h < AHEAD since the workgroup has 64 n_waves threads) for wave block
-        // (c / B) mod n_waves (n_waves is 1, 2 or 4), geometry centred on that block, and tests
-        // whether it can reach the block
-        // (recomputed per batch from an opaque copy of the thread index: hoisted out of the
-        // loop, these indices would hold registers across the reverse walk)
-        int t = tid;
-        __asm__ volatile("" : "+v"(t));
-        const int j = t & (B - 1), b = (t / B) & (n_waves - 1),
-                  h = (t / B) >> __builtin_ctz((unsigned)n_waves);
-        // batch h is [bend - min(rem, (h + 1) B), bend - min(rem, h B))
-        const uint32_t rem = bend - start;
-        const uint32_t o0 = (uint32_t)(h * B) < rem ? (uint32_t)(h * B) : rem;
-        const uint32_t o1 = (uint32_t)((h + 1) * B) < rem ? (uint32_t)((h + 1) * B) : rem;
-        const uint32_t hstart = bend - o1;
-        const int hnb = (int)(o1 - o0);
-        if (h < AHEAD && j < hnb) {
-          const int jj = h * B + j;
-          const uint32_t r = pair_vals[hstart + j];
-          const SplatRec R = rec[r];
-          const int kbx = tile_x0 + (b % waves_x) * 8, kby = tile_y0 + (b / waves_x) * BH;
-          const StagedGeo g = stage_geo(R, kbx + 4, kby + BH / 2, tcx, tcy);
-          s_geo.store(b, jj, g);
-          s_reach[b][jj] = block_may_contribute(g, (float)(kbx + 4 - tcx),
-                                                (float)(kby + BH / 2 - tcy), kbx, kby, p, 8, BH)
-                               ? 1
-                               : 0;
-          if (b == 0) {
-            s_splat[jj] = R.splat;
-            s_recid[jj] = r;
-            if (MIXED) {
-              const int n = grid_side<N>(p, r - rec_base);
-              s_gn[jj] = n;
-              s_gscale[jj] = grid_scale(n, p.sigma);
-              s_toff[jj] = p.grid_at[r - rec_base];
-            }
+    // One staging pass: the geometry of the AHEAD batches that end at pend, into slots
+    // [0, AHEAD B).
+    auto stage_geometry = [&](uint32_t pend) {
+      // thread c stages splat c mod B of batch h = c / (B n_waves) from this one (h = 0 is
+      // this batch; h < AHEAD since the workgroup has 64 n_waves threads) for wave block
+      // (c / B) mod n_waves (n_waves is 1, 2 or 4), geometry centred on that block, and tests
+      // whether it can reach the block
+      // (recomputed per batch from an opaque copy of the thread index: hoisted out of the
+      // loop, these indices would hold registers across the reverse walk)
+      int t = tid;
+      __asm__ volatile("" : "+v"(t));
+      const int j = t & (B - 1), b = (t / B) & (n_waves - 1),
+                h = (t / B) >> __builtin_ctz((unsigned)n_waves);
+      // batch h is [pend - min(rem, (h + 1) B), pend - min(rem, h B))
+      const uint32_t rem = pend - start;
+      const uint32_t o0 = (uint32_t)(h * B) < rem ? (uint32_t)(h * B) : rem;
+      const uint32_t o1 = (uint32_t)((h + 1) * B) < rem ? (uint32_t)((h + 1) * B) : rem;
+      const uint32_t hstart = pend - o1;
+      const int hnb = (int)(o1 - o0);
+      if (h < AHEAD && j < hnb) {
+        const int jj = h * B + j;
+        const uint32_t r = pair_vals[hstart + j];
+        const SplatRec R = rec[r];
+        const int kbx = tile_x0 + (b % waves_x) * 8, kby = tile_y0 + (b / waves_x) * BH;
+        const StagedGeo g = stage_geo(R, kbx + 4, kby + BH / 2, tcx, tcy);
+        s_geo.store(b, jj, g);
+        s_reach[b][jj] = block_may_contribute(g, (float)(kbx + 4 - tcx),
+                                              (float)(kby + BH / 2 - tcy), kbx, kby, p, 8, BH)
+                             ? 1
+                             : 0;
+        if (b == 0) {
+          s_splat[jj] = R.splat;
+          s_recid[jj] = r;
+          if (MIXED) {
+            const int n = grid_side<N>(p, r - rec_base);
+            s_gn[jj] = n;
+            s_gscale[jj] = grid_scale(n, p.sigma);
+            s_toff[jj] = p.grid_at[r - rec_base];
           }
         }
       }
-      if constexpr (TEXG % 4 == 0) {
-        // 16-byte stores: a batch's sums are a whole number of float4s
-        float4* g4 = reinterpret_cast<float4*>(s_gtex);
-        for (int e = tid; e < nb * (TEXG / 4); e += nthr) g4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
-      } else {
-        for (int e = tid; e < nb * TEXG; e += nthr) s_gtex[e] = 0.f;
-      }
-      for (int e = tid; e < nb * kRecGrad; e += nthr) s_grec[e] = 0.f;
-      if constexpr (MIXED) {
-        __syncthreads();  // sides and offsets of the batch's grids
-        stage_texels_mixed<N, BF16>(textures, pair_vals + bstart, nb, s_tex, p.spec, s_gn + so,
-                                    s_toff + so);
-      } else
-        stage_texels<N, BF16>(textures, pair_vals + bstart, rec_base, nb, s_tex, p.spec);
+    };
+    // Texels of the batch [bs, bs + n), whose geometry is in slot offset sof.
+    auto stage_batch_texels = [&](uint32_t bs, int n, int sof) {
+      if constexpr (MIXED)
+        stage_texels_mixed<N, BF16>(textures, pair_vals + bs, n, s_tex, p.spec, s_gn + sof,
+                                    s_toff + sof);
+      else
+        stage_texels<N, BF16>(textures, pair_vals + bs, rec_base, n, s_tex, p.spec);
+    };
+    // The first batch's geometry pass and texels; later batches stage theirs while the batch
+    // before them flushes its sums (below).
+    if (tile_last > start) {
+      stage_geometry(tile_last);
+      if constexpr (MIXED) __syncthreads();  // sides and offsets of the batch's grids
+      const uint32_t bs = (tile_last - start) > (uint32_t)B ? tile_last - (uint32_t)B : start;
+      stage_batch_texels(bs, (int)(tile_last - bs), 0);
       __syncthreads();
+    }
+    int slot = 0;  // slot of the batch's geometry: the batch's index in the list mod AHEAD
+    for (uint32_t bend = tile_last; bend > start;) {
+      const uint32_t bstart = (bend - start) > (uint32_t)B ? bend - (uint32_t)B : start;
+      const int nb = (int)(bend - bstart);
+      const int so = slot * B;
 
       // splats of this batch that can reach the wave's block, walked back to front
       const bool may = lane < nb && s_reach[w][so + lane] != 0;
@@ -462,8 +471,9 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
           x = wave_sum(x);
           if (lane == 0 && x != 0.f) atomicAdd(&p.d_spec[4 * (int64_t)s_recid[so + j] + c], x);
         }
+        __syncthreads();  // every texel sum has been read before the flush clears it
       }
-      // flush the batch's sums
+      // flush the batch's sums, leaving them zero for the next batch
       if constexpr (MIXED) {
         // the N x N sums hold splat j's n x n grid in rows and columns [0, n): one wave per
         // splat, lane i taking values i, i + 64, ... of the grid's 3 n^2
@@ -471,16 +481,19 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
           const int n = s_gn[so + j];
           for (int i = lane; i < 3 * n * n; i += 64) {
             const int t = i / 3, c = i - 3 * t, iu = div_side(t, n), iv = t - iu * n;
-            const float x = s_gtex[j * TEXG + 3 * (iu * N + iv) + c];
+            float* const sum = &s_gtex[j * TEXG + 3 * (iu * N + iv) + c];
+            const float x = *sum;
+            *sum = 0.f;
             if (x != 0.f) atomicAdd(&d_tex[3 * s_toff[so + j] + i], x);
           }
         }
       } else if constexpr (TEXG % 4 == 0) {
         // four sums per 16-byte LDS read; one global atomic per non-zero sum
         constexpr int TEXG4 = TEXG / 4;
-        const float4* g4 = reinterpret_cast<const float4*>(s_gtex);
+        float4* g4 = reinterpret_cast<float4*>(s_gtex);
         for (int e = tid; e < nb * TEXG4; e += nthr) {
           const float4 x = g4[e];
+          g4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
           if (x.x != 0.f || x.y != 0.f || x.z != 0.f || x.w != 0.f) {
             const int j = e / TEXG4, r = 4 * (e - j * TEXG4);
             float* dst = d_tex + (int64_t)s_splat[so + j] * TEXG + r;
@@ -493,6 +506,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
       } else {
         for (int e = tid; e < nb * TEXG; e += nthr) {
           const float x = s_gtex[e];
+          s_gtex[e] = 0.f;
           if (x != 0.f) {
             const int j = e / TEXG, r = e - j * TEXG;
             atomicAdd(&d_tex[(int64_t)s_splat[so + j] * TEXG + r], x);
@@ -502,10 +516,24 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
       for (int e = tid; e < nb * kRecGrad; e += nthr) {
         const int j = e / kRecGrad, r = e - j * kRecGrad;
         const float x = s_grec[e];
+        s_grec[e] = 0.f;
         if (x != 0.f) atomicAdd(&d_rec[(int64_t)s_recid[so + j] * kRecGrad + r], x);
+      }
+      // the next batch: its texels (and, when it starts a staging pass, the pass's geometry)
+      // load while the atomics above drain
+      const int nslot = slot + 1 < AHEAD ? slot + 1 : 0;
+      if (bstart > start) {
+        const uint32_t nbs = (bstart - start) > (uint32_t)B ? bstart - (uint32_t)B : start;
+        if (nslot == 0) {
+          __syncthreads();  // the flush above has read the pass's splat and record indices
+          stage_geometry(bstart);
+          if constexpr (MIXED) __syncthreads();  // sides and offsets of the batch's grids
+        }
+        stage_batch_texels(nbs, (int)(bstart - nbs), nslot * B);
       }
       __syncthreads();
       bend = bstart;
+      slot = nslot;
     }
   }  // lists
 }
