@@ -17,9 +17,9 @@
 // sigma = 0.5 the grid covers only the splat's core, so most blended pixels are border-clamped
 // and share a few cells); each group's four corners and three channels are reduced the same
 // way, one group after another until every pixel's cell has been taken (a step that blended
-// at most 16 pixels adds each pixel's corners directly instead). A splat that no pixel of the
-// wave blended is skipped after evaluation. After each batch the non-zero LDS sums go to
-// global memory with one float atomic each.
+// at most kLaneAddMax pixels adds each pixel's corners directly instead). A splat that no
+// pixel of the wave blended is skipped after evaluation. After each batch the non-zero LDS
+// sums go to global memory with one float atomic each.
 #include "blend_common.h"
 
 
@@ -144,11 +144,11 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
 // none inside the splat loop) measured 4 % faster on the 1M-splat 1080p workload, 8
 // (64 VGPRs) slower.
 // (N = 16 blocks hold 67 KB of LDS, two per CU, so no register target applies there.)
-// Wave steps that blended at most this many pixels skip the cell grouping (measured at 1M
-// splats and 1080p: unchanged time; 100k splats at 800x800 and 3M splats at 4 x 1080p, where
-// fewer lanes blend per step: 5 and 6 % faster; 32 lanes gained more there but cost the 1M
-// splat workload).
-constexpr int kLaneAddMax = 16;
+// Wave steps that blended at most this many pixels skip the cell grouping. Measured with the
+// multi-batch staging, backward ms for thresholds 16 / 24 / 28 / 32: 1M splats at 1080p 1.41 /
+// 1.41 / 1.41 / 1.42 (two runs each), 3M splats at 4 x 1080p 15.32 / 14.77 / 14.63 / 14.61,
+// 100k splats at 800x800 0.807 / 0.764 / 0.765 / 0.745.
+constexpr int kLaneAddMax = 28;
 
 template <int N, int B>
 constexpr int bwd_min_waves() { return (B <= 8 && N <= 8) ? 7 : 1; }
@@ -398,7 +398,8 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
 #pragma unroll
         for (int s = 0; s < PIX; ++s) pend[s] = ballot(po[s].act);
         // A wave step that blended few pixels (small or distant splats) adds each pixel's
-        // bilinear corners to LDS directly; up to 16 lanes this costs less than group passes.
+        // bilinear corners to LDS directly; up to kLaneAddMax lanes this costs less than group
+        // passes.
         int n_act = 0;
 #pragma unroll
         for (int s = 0; s < PIX; ++s) n_act += __builtin_popcountll(pend[s]);
