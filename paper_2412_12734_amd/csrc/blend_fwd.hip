@@ -32,14 +32,19 @@ constexpr int fwd_min_waves() {
 
 // With p.zero4: this workgroup's slice of the array to zero (the coming backward's texture
 // gradients). Called when the workgroup has finished blending, so that the stores drain
-// while other workgroups blend, and without holding registers during the blend.
+// while other workgroups blend, and without holding registers during the blend. The stores
+// are non-temporal: the zeros are not read again before the backward's atomics, and kept out
+// of the caches they do not evict the records and texels other workgroups are reading (at 1M
+// splats and 1080p the forward took 0.533 ms with ordinary stores, 0.507 with these).
 __device__ __forceinline__ void zero_slice(const BlendParams& p) {
   if (!p.zero4) return;
+  typedef float v4f __attribute__((ext_vector_type(4)));
   const int64_t per = (p.zero_n4 + (int64_t)gridDim.x - 1) / (int64_t)gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * per;
   const int64_t hi = lo + per < p.zero_n4 ? lo + per : p.zero_n4;
+  v4f* const z = reinterpret_cast<v4f*>(p.zero4);
   for (int64_t i = lo + (int64_t)threadIdx.x; i < hi; i += (int64_t)blockDim.x)
-    p.zero4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    __builtin_nontemporal_store((v4f){0.f, 0.f, 0.f, 0.f}, z + i);
   if (blockIdx.x == 0 && (int)threadIdx.x < p.zero_tail_n) p.zero_tail[threadIdx.x] = 0.f;
 }
 
