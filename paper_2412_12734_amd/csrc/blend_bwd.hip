@@ -317,11 +317,12 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
         }
       }
     };
-    // Texels of the batch [bs, bs + n), whose geometry is in slot offset sof.
+    // Texels of the batch [bs, bs + n), whose geometry is in slot offset sof (staged by the
+    // pass's geometry launch, with a barrier between them).
     auto stage_batch_texels = [&](uint32_t bs, int n, int sof) {
       if constexpr (MIXED)
-        stage_texels_mixed<N, BF16>(textures, pair_vals + bs, n, s_tex, p.spec, s_gn + sof,
-                                    s_toff + sof);
+        stage_texels_mixed<N, BF16, true>(textures, pair_vals + bs, rec_base, n, s_tex, p,
+                                          s_gn + sof, s_toff + sof);
       else
         stage_texels<N, BF16>(textures, pair_vals + bs, rec_base, n, s_tex, p.spec);
     };

@@ -208,24 +208,43 @@ __device__ __forceinline__ int div_side(int t, int n) {
   return (int)(((uint32_t)t * (uint32_t)((65536 + n - 1) / n)) >> 16);
 }
 
+// Side of splat k's grid in a call with several sides, clamped to [1, N].
+template <int N>
+__device__ __forceinline__ int grid_side(const BlendParams& p, uint32_t k) {
+  return min(max(p.grid_n[k], 1), N);
+}
+
 // Copies the texels of `nb` staged splats whose grids have sides of their own (at most N) into
-// the N x N LDS layout: splat j's n x n texels (side s_gn[j], first texel s_toff[j]) go to rows
-// and columns [0, n). One wave per splat; lane i moves values i, i + 64, ... of the grid's
-// 3 n^2 contiguous values. A one-texel grid is also copied to (0, 1), (1, 0) and (1, 1), so that
-// the bilinear lookup, which reads the four corners of cell (0, 0) with weights (1, 0, 0, 0)
-// there, reads finite values. As in stage_texels, spec (nullable) adds each record's
-// view-dependent colour.
-template <int N, bool BF16>
+// the N x N LDS layout: splat j's n x n texels go to rows and columns [0, n). One wave per
+// splat; lane i moves values i, i + 64, ... of the grid's 3 n^2 contiguous values. A one-texel
+// grid is also copied to (0, 1), (1, 0) and (1, 1), so that the bilinear lookup, which reads the
+// four corners of cell (0, 0) with weights (1, 0, 0, 0) there, reads finite values. As in
+// stage_texels, spec (nullable) adds each record's view-dependent colour.
+// FROM_LDS: each grid's side and first texel come from the staged copies s_gn / s_toff (the
+// backward, whose geometry pass staged them well before); otherwise they are read from
+// p.grid_n / p.grid_at for record pairs[j] - rec_base, so that the forward need not wait at a
+// barrier for the copies staged in the same phase.
+template <int N, bool BF16, bool FROM_LDS>
 __device__ __forceinline__ void stage_texels_mixed(const void* __restrict__ textures,
-                                                   const uint32_t* __restrict__ pairs, int nb,
-                                                   float4* s_tex, const float4* __restrict__ spec,
-                                                   const int32_t* s_gn, const int64_t* s_toff) {
+                                                   const uint32_t* __restrict__ pairs,
+                                                   uint32_t rec_base, int nb, float4* s_tex,
+                                                   const BlendParams& p, const int32_t* s_gn,
+                                                   const int64_t* s_toff) {
   const int lane = threadIdx.x & 63, nw = (int)(blockDim.x >> 6);
+  const float4* __restrict__ spec = p.spec;
   for (int j = (int)(threadIdx.x >> 6); j < nb; j += nw) {
-    const int n = s_gn[j];
-    const int64_t base = 3 * s_toff[j];
+    const uint32_t r = pairs[j];
+    int n;
+    int64_t base;
+    if constexpr (FROM_LDS) {
+      n = s_gn[j];
+      base = 3 * s_toff[j];
+    } else {
+      n = grid_side<N>(p, r - rec_base);
+      base = 3 * p.grid_at[r - rec_base];
+    }
     float4 sc = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (spec) sc = spec[pairs[j]];
+    if (spec) sc = spec[r];
     float4* dst = s_tex + j * TexLayout<N>::kPerSplat;
     auto texel = [&](int64_t i, int c) {
       const float x = BF16 ? bf16_to_f32(reinterpret_cast<const uint16_t*>(textures)[i])
@@ -244,12 +263,6 @@ __device__ __forceinline__ void stage_texels_mixed(const void* __restrict__ text
       }
     }
   }
-}
-
-// Side of splat k's grid in a call with several sides, clamped to [1, N].
-template <int N>
-__device__ __forceinline__ int grid_side(const BlendParams& p, uint32_t k) {
-  return min(max(p.grid_n[k], 1), N);
 }
 
 // Slope of the uv -> grid map of an n-texel side, formed as the host forms it for a uniform

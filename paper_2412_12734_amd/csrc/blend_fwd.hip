@@ -62,7 +62,6 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   // MIXED: side and uv -> grid slope of each staged splat's grid
   __shared__ int32_t s_gn[MIXED ? B : 1];
   __shared__ float s_gscale[MIXED ? B : 1];
-  __shared__ int64_t s_toff[MIXED ? B : 1];
   static_assert((B & (B - 1)) == 0, "batch sizes are powers of two");
 
   const int tile = tile_of_block(p);
@@ -129,7 +128,6 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
           const int n = grid_side<N>(p, r - rec_base);
           s_gn[j] = n;
           s_gscale[j] = grid_scale(n, p.sigma);
-          s_toff[j] = p.grid_at[r - rec_base];
         }
         s_reach[b][j] =
             block_may_contribute(g, (float)(kbx + 4 - tcx), (float)(kby + 4 - tcy), kbx, kby, p)
@@ -137,10 +135,10 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
                 : 0;
       }
     }
-    if constexpr (MIXED) {
-      __syncthreads();  // sides and offsets of the batch's grids
-      stage_texels_mixed<N, BF16>(textures, pair_vals + b0, nb, s_tex, p.spec, s_gn, s_toff);
-    } else
+    if constexpr (MIXED)
+      stage_texels_mixed<N, BF16, false>(textures, pair_vals + b0, rec_base, nb, s_tex, p,
+                                         nullptr, nullptr);
+    else
       stage_texels<N, BF16>(textures, pair_vals + b0, rec_base, nb, s_tex, p.spec);
     __syncthreads();
 
