@@ -101,8 +101,8 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
     const float fv2 = (t01.z - t00.z) * (1.f - fu) + (t11.z - t10.z) * fu;
     const float dfv = o.dc0 * fv0 + o.dc1 * fv1 + o.dc2 * fv2;
     const float tsc = MIXED ? gscale : p.tex_scale;
-    du = (u > -p.sigma && u < p.sigma) ? tsc * dfu : 0.f;
-    dv = (v > -p.sigma && v < p.sigma) ? tsc * dfv : 0.f;
+    du = fabsf(u) < p.sigma ? tsc * dfu : 0.f;  // (-sigma, sigma): one compare with |u|
+    dv = fabsf(v) < p.sigma ? tsc * dfv : 0.f;
   }
   const float dalpha_act = ps.g0 * (c0 * ps.T - ps.S0 * inv1m) +
                            ps.g1 * (c1 * ps.T - ps.S1 * inv1m) + ps.g2 * (c2 * ps.T - ps.S2 * inv1m);
@@ -113,14 +113,11 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
   const bool unclamped = g.g0.w * e.G <= p.alpha_max;
   o.go = unclamped ? dalpha * e.G : 0.f;
   const float dq = unclamped ? -e.G * g.g0.w * dalpha : 0.f;
-  float ddx = 0.f, ddy = 0.f;
-  if (e.uv_branch) {
-    du += dq * u;
-    dv += dq * v;
-  } else {
-    ddx = dq * 2.f * p.lp_scale * e.dx;
-    ddy = dq * 2.f * p.lp_scale * e.dy;
-  }
+  // the falloff's adjoint goes to (u, v) or to the low-pass offset, selected without a branch
+  const float dq_uv = e.uv_branch ? dq : 0.f;
+  const float dq_lp = e.uv_branch ? 0.f : dq * 2.f * p.lp_scale;
+  du += dq_uv * u;
+  dv += dq_uv * v;
   const float dr0 = du * inv, dr1 = dv * inv;
   const float dr2 = -(du * u + dv * v) * inv;
   o.gh[0] = dr0 * e.dx;
@@ -131,10 +128,10 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
   o.gh[5] = dr2 * e.dy;
   o.gh[6] = dr2;
   // d c2 collects the low-pass term and the uv term through rho's dependence on the offset
-  ddx += dr0 * g.g1.x + dr1 * g.g1.z + dr2 * g.g2.x;
-  ddy += dr0 * g.g1.y + dr1 * g.g1.w + dr2 * g.g2.y;
-  o.gc2x = -ddx;
-  o.gc2y = -ddy;
+  // (c2 enters both with a minus sign; written as negated products, which fold into the
+  // multiply-adds)
+  o.gc2x = -(dq_lp * e.dx) - dr0 * g.g1.x - dr1 * g.g1.z - dr2 * g.g2.x;
+  o.gc2y = -(dq_lp * e.dy) - dr0 * g.g1.y - dr1 * g.g1.w - dr2 * g.g2.y;
 }
 
 // With batches of 8 the LDS allows 7 workgroups per CU (22.6 KB each for 8 x 8 grids, with
@@ -352,14 +349,18 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
         const StagedGeo g = s_geo.load(w, so + j);
         const float4* tex = s_tex + j * TexLayout<N>::kPerSplat;
         PixelEval e[PIX];
-        bool act[PIX], wave_act = false;
+        bool act[PIX];
+        // lanes that blended this splat (one mask per pixel slot); the masks serve the skip test
+        // below and the texel scatter
+        uint64_t pend[PIX], any_act = 0;
 #pragma unroll
         for (int s = 0; s < PIX; ++s) {
           e[s] = eval_splat(g, lx, ly[s], lx + bcx, ly[s] + bcy, p);
           act[s] = (jg < ps[s].last) && e[s].hit;
-          wave_act = wave_act || act[s];
+          pend[s] = ballot(act[s]);
+          any_act |= pend[s];
         }
-        if (!__any(wave_act)) continue;  // no pixel of the wave blended this splat
+        if (any_act == 0) continue;  // no pixel of the wave blended this splat
         PixOut po[PIX];
         if constexpr (MIXED) {
           const int gn = s_gn[so + j];
@@ -395,9 +396,6 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
 
         // Texel gradients, grouped by cell over all pixels of the wave.
         float* gt = s_gtex + j * TEXG + tex_off;  // this lane's value in cell 0
-        uint64_t pend[PIX];
-#pragma unroll
-        for (int s = 0; s < PIX; ++s) pend[s] = ballot(po[s].act);
         // A wave step that blended few pixels (small or distant splats) adds each pixel's
         // bilinear corners to LDS directly; up to kLaneAddMax lanes this costs less than group
         // passes.
