@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 # without packed FP32 (this build never emits packed FP32), i.e. 78.6 TFLOP/s counting an
 # FMA as two flops; HBM3E 8 TB/s.
 PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+PEAK_LANE_SLOTS_T = 256 * 4 * 16 * 2.4e9 / 1e12  # FP32 VALU issue slots, T lane-ops/s
 PEAK_HBM_GBS = 8000.0
 
 # Algorithmic FP32 flops of the blend kernels per unit of work, counted from the formulas
@@ -44,6 +45,13 @@ PEAK_HBM_GBS = 8000.0
 FLOPS_FWD_EVAL = 30
 FLOPS_FWD_BLEND = 48
 FLOPS_BWD_BLEND = 177
+
+# The roofline unit of the blend backward: VALU issue slots the method needs per contributing
+# (pixel, splat) pair (blended pairs plus the pair that stops each terminated pixel), about
+# 200 full-rate lane-ops and 3 quarter-rate ones (4 slots each). The adjoint of Alg. 1's
+# per-pixel blend and of the bilinear fetch of Alg. 2 take that many, before any reduction
+# of the per-splat gradients over pixels.
+SLOTS_BWD_CONTRIB = 212
 
 # Size of the plain device-to-device copy issued once at start-up. Its FETCH_SIZE and
 # WRITE_SIZE readings under rocprofv3 --pmc calibrate those counters to bytes.
@@ -415,15 +423,22 @@ def main():
     fwd_ms = stages["blend_fwd"] + stages.get("blend_fwd_rest", 0.0)
     bwd_flops = e_blend_bwd * FLOPS_BWD_BLEND
     fwd_flops = e_eval * FLOPS_FWD_EVAL + e_blend * FLOPS_FWD_BLEND
-    achieved = bwd_flops / (bwd_ms * 1e-3) / 1e12
+    achieved_tf = bwd_flops / (bwd_ms * 1e-3) / 1e12
+    # issue slots the method needs over the launch's contributing pairs, per second
+    achieved = st["e_contrib"] * SLOTS_BWD_CONTRIB / (bwd_ms * 1e-3) / 1e12
     traffic = None
     if BWD_TRAFFIC and BWD_TRAFFIC["sources_sha1"] == sources_sha1(BWD_SOURCES):
         traffic = BWD_TRAFFIC["fetch_bytes"] + BWD_TRAFFIC["write_bytes"]
     roofline = {"bound": "alu", "kernel": "blend_bwd", "achieved": round(achieved, 3),
-                "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
-                "units_per_launch": {"blended_pairs": e_blend_bwd},
-                "flops_per_unit": FLOPS_BWD_BLEND, "avg_ms": round(bwd_ms, 4)}
+                "peak": round(PEAK_LANE_SLOTS_T, 2), "unit": "T VALU lane-slots/s",
+                "frac": round(achieved / PEAK_LANE_SLOTS_T, 4), "traffic": traffic,
+                "units_per_launch": {"contributing_pairs": st["e_contrib"]},
+                "slots_per_unit": SLOTS_BWD_CONTRIB, "avg_ms": round(bwd_ms, 4),
+                "flops": {"achieved_tflops": round(achieved_tf, 3),
+                          "peak_tflops": round(PEAK_FP32_TFLOPS, 1),
+                          "frac": round(achieved_tf / PEAK_FP32_TFLOPS, 4),
+                          "flops_per_blended_pair": FLOPS_BWD_BLEND,
+                          "blended_pairs": e_blend_bwd}}
     fwd_tf = fwd_flops / (fwd_ms * 1e-3) / 1e12
 
     variants = {}
