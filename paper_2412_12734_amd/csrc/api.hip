@@ -333,15 +333,20 @@ T* at(void* ws, size_t off) {
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
 
+// With order != null the preprocess launch also writes the depth sort's initial order and
+// clears n_zero words at `zero`.
 gb_status run_preprocess(const gb_splats* s, const gb_view* views, int32_t n_views,
-                         const gb_options* o, void* ws, const Plan& pl, hipStream_t st) {
+                         const gb_options* o, void* ws, const Plan& pl, hipStream_t st,
+                         uint32_t* order = nullptr, uint32_t* zero = nullptr,
+                         int64_t n_zero = 0) {
   GBB_TRY(stage_mark(kStPreprocess, 0, st), "timing");
   ViewDev* d_views = at<ViewDev>(ws, pl.off_views);
   GBB_TRY(launch_upload_views(views, n_views, pl.tile_w, pl.tile_h, d_views, st), "upload views");
   GBB_TRY(launch_preprocess(*s, d_views, n_views, *o, pl.tile_w, pl.tile_h,
                             at<uint32_t>(ws, pl.off_depth_key),
                             at<uint32_t>(ws, pl.off_depth_key_alt), at<uint32_t>(ws, pl.off_count),
-                            at<SplatRec>(ws, pl.off_rec), at<float4>(ws, pl.off_spec), st),
+                            at<SplatRec>(ws, pl.off_rec), at<float4>(ws, pl.off_spec), order,
+                            zero, n_zero, st),
           "preprocess");
   GBB_TRY(stage_mark(kStPreprocess, 1, st), "timing");
   return GB_OK;
@@ -636,17 +641,20 @@ gb_status gb_count_pairs(const gb_splats* s, const gb_view* views, int32_t n_vie
   return GB_OK;
 }
 
-// Per workspace: the texture-gradient array that its last forward zeroed (null if none), so
-// that the backward of that forward can skip clearing the same array.
+// Per workspace: the gradient arrays that its last forward zeroed (kZeroTex: the texture
+// gradients, kZeroRec: the per-record gradient accumulators; null if none), so that the
+// backward of that forward can skip clearing the same array.
+enum { kZeroTex = 0, kZeroRec = 1, kZeroKinds = 2 };
 struct ZeroedRecord {
   std::mutex mu;
   const void* key[kMirrorSlots] = {};
-  const float* ptr[kMirrorSlots] = {};
-  int64_t n[kMirrorSlots] = {};
+  const float* ptr[kMirrorSlots][kZeroKinds] = {};
+  int64_t n[kMirrorSlots][kZeroKinds] = {};
   int next = 0;
 } g_zeroed;
 
-void zeroed_set(const void* ws, const float* ptr, int64_t n) {
+// Records that the forward on `ws` zeroed ptr [n] (ptr == null: forgets the kind).
+void zeroed_set(const void* ws, int kind, const float* ptr, int64_t n) {
   std::lock_guard<std::mutex> lock(g_zeroed.mu);
   int i = 0;
   while (i < kMirrorSlots && g_zeroed.key[i] != ws) ++i;
@@ -655,18 +663,20 @@ void zeroed_set(const void* ws, const float* ptr, int64_t n) {
     i = g_zeroed.next;
     g_zeroed.next = (g_zeroed.next + 1) % kMirrorSlots;
     g_zeroed.key[i] = ws;
+    for (int k = 0; k < kZeroKinds; ++k) g_zeroed.ptr[i][k] = nullptr;
   }
-  g_zeroed.ptr[i] = ptr;
-  g_zeroed.n[i] = n;
+  g_zeroed.ptr[i][kind] = ptr;
+  g_zeroed.n[i][kind] = n;
 }
 
-// True (and forgets it) if the last forward on `ws` zeroed exactly `ptr` [n].
-bool zeroed_take(const void* ws, const float* ptr, int64_t n) {
+// True (and forgets it) if the last forward on `ws` zeroed exactly `ptr` [n] of this kind.
+bool zeroed_take(const void* ws, int kind, const float* ptr, int64_t n) {
   std::lock_guard<std::mutex> lock(g_zeroed.mu);
   for (int i = 0; i < kMirrorSlots; ++i) {
     if (g_zeroed.key[i] != ws) continue;
-    const bool hit = g_zeroed.ptr[i] == ptr && g_zeroed.n[i] == n && ptr != nullptr;
-    g_zeroed.ptr[i] = nullptr;
+    const bool hit =
+        g_zeroed.ptr[i][kind] == ptr && g_zeroed.n[i][kind] == n && ptr != nullptr;
+    g_zeroed.ptr[i][kind] = nullptr;
     return hit;
   }
   return false;
@@ -687,7 +697,7 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   if (st != GB_OK) return st;
   if (zero_tex && !aligned(zero_tex, 4)) return arg_fail("d_textures to zero misaligned");
   // whatever happens below, the backward must not rely on an older forward's zeroing
-  zeroed_set(ws, nullptr, 0);
+  for (int k = 0; k < kZeroKinds; ++k) zeroed_set(ws, k, nullptr, 0);
   const int64_t zero_n = zero_tex ? tex_grad_values(s) : 0;
   if (!rgb || !T_final || !aligned(rgb, 4) || !aligned(T_final, 4))
     return arg_fail("rgb / T_final NULL or misaligned");
@@ -714,10 +724,16 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   // overflow word starts at zero
   if (fresh)
     GBB_TRY(launch_fill_u32(&d_st->sticky_overflow, 0u, 1, hs), "clear sticky overflow");
-  if ((st = run_preprocess(s, views, n_views, o, ws, pl, hs)) != GB_OK) return st;
+  uint32_t* order = at<uint32_t>(ws, pl.off_order);
+  uint32_t* digit_tot = at<uint32_t>(ws, pl.off_digit_tot);
+  // the preprocess launch also writes the depth sort's initial order (record indices) and
+  // clears the radix sorts' digit totals: they start from zero in every forward, and each
+  // sort leaves them zero
+  if ((st = run_preprocess(s, views, n_views, o, ws, pl, hs, order, digit_tot,
+                           kDigitTotWords)) != GB_OK)
+    return st;
 
   uint32_t* dk_a = at<uint32_t>(ws, pl.off_depth_key_alt);
-  uint32_t* order = at<uint32_t>(ws, pl.off_order);
   uint32_t* order_alt = at<uint32_t>(ws, pl.off_order_alt);
   uint32_t* count = at<uint32_t>(ws, pl.off_count);
   uint32_t* offsets = at<uint32_t>(ws, pl.off_offsets);
@@ -735,10 +751,6 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   // depth order of all records: sort the key copy written by the preprocess, carrying
   // record indices (the offsets array is free until the scan and serves as ping-pong space)
   GBB_TRY(stage_mark(kStDepthSort, 0, hs), "timing");
-  // (the radix sorts' digit totals start from zero in every forward and each sort leaves
-  // them zero)
-  uint32_t* digit_tot = at<uint32_t>(ws, pl.off_digit_tot);
-  GBB_TRY(launch_iota_u32(order, pl.VP, digit_tot, kDigitTotWords, hs), "iota");
   GBB_TRY(launch_radix_sort(dk_a, order, offsets, order_alt, nullptr, pl.VP, 32, hist, digit_tot,
                             hs),
           "depth sort");
@@ -792,12 +804,17 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   }
   GBB_TRY(stage_mark(kStBlendFwd, 0, hs), "timing");
   const float4* spec = s->sh ? at<float4>(ws, pl.off_spec) : nullptr;
+  // the workgroups also zero the coming backward's per-record gradient accumulators (and,
+  // with zero_tex, its texture gradients) while they blend
+  float* d_rec = at<float>(ws, pl.off_drec);
+  const int64_t rec_n = (int64_t)kRecGrad * pl.VP;
   GBB_TRY(launch_blend_fwd(pl, *s, *o, d_views, n_views, rec, pv, ranges, rgb, T_final,
                            at<uint32_t>(ws, pl.off_n_last), split, tile_work, spec,
-                           stats ? d_stats : nullptr, zero_tex, zero_n, hs),
+                           stats ? d_stats : nullptr, zero_tex, zero_n, d_rec, rec_n, hs),
           "blend forward");
   GBB_TRY(stage_mark(kStBlendFwd, 1, hs), "timing");
-  if (zero_tex) zeroed_set(ws, zero_tex, zero_n);
+  if (zero_tex) zeroed_set(ws, kZeroTex, zero_tex, zero_n);
+  zeroed_set(ws, kZeroRec, d_rec, rec_n);
   if (!pl.split) return GB_OK;
 
   // rest pass: the remaining records, paired with the tiles the prefix left open
@@ -810,7 +827,7 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   uint32_t* pv_ra = pv_a + pl.prefix_cap;
   uint32_t* sat = at<uint32_t>(ws, pl.off_sat);
   GBB_TRY(stage_mark(kStRestTiles, 0, hs), "timing");
-  GBB_TRY(launch_open_sat(d_views, n_views, split.open_bits, sat, hs), "open-tile table");
+  GBB_TRY(launch_open_sat(d_views, n_views, split.open_bits, d_st, sat, hs), "open-tile table");
   GBB_TRY(launch_count_rest(order, count, rec, d_views, pl.VP, pl.tile_w, pl.tile_h, d_st, sat,
                             count_rest, hs),
           "rest count");
@@ -834,7 +851,7 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   GBB_TRY(stage_mark(kStBlendFwdRest, 0, hs), "timing");
   GBB_TRY(launch_blend_fwd(pl, *s, *o, d_views, n_views, rec, pv_r, ranges_rest, rgb, T_final,
                            at<uint32_t>(ws, pl.off_n_last_rest), split, tile_work, spec,
-                           stats ? d_stats : nullptr, nullptr, 0, hs),
+                           stats ? d_stats : nullptr, nullptr, 0, nullptr, 0, hs),
           "blend forward (rest)");
   GBB_TRY(stage_mark(kStBlendFwdRest, 1, hs), "timing");
   return GB_OK;
@@ -914,13 +931,16 @@ gb_status gb_render_bwd(const gb_splats* s, const gb_view* views, int32_t n_view
   const float4* spec = s->sh ? at<float4>(ws, pl.off_spec) : nullptr;
   float4* d_spec = s->sh ? at<float4>(ws, pl.off_dspec) : nullptr;
   GBB_TRY(stage_mark(kStBwdClear, 0, hs), "timing");
-  GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_rec), 0u, kRecGrad * pl.VP, hs), "clear d_rec");
+  // skipped when this workspace's forward already zeroed it while it blended
+  if (!zeroed_take(ws, kZeroRec, d_rec, (int64_t)kRecGrad * pl.VP))
+    GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_rec), 0u, kRecGrad * pl.VP, hs),
+            "clear d_rec");
   if (d_spec)
     GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_spec), 0u, 4 * pl.VP, hs),
             "clear d_spec");
   const int64_t tex_values = tex_grad_values(s);
   // skipped when this workspace's forward already zeroed this array while it blended
-  if (!zeroed_take(ws, g->d_textures, tex_values))
+  if (!zeroed_take(ws, kZeroTex, g->d_textures, tex_values))
     GBB_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(g->d_textures), 0u, tex_values, hs),
             "clear d_textures");
   // the backward takes the tiles with the longest blended spans (saved by the forward) first

@@ -8,6 +8,16 @@
 
 namespace gbb {
 
+// A float array zeroed by the forward's workgroups: n_head single floats up to the first
+// 16-byte boundary, n_body float4s, then n_tail (at most 3) trailing floats.
+struct ZeroRange {
+  float* head;
+  float4* body;
+  float* tail;
+  int64_t n_body;
+  int32_t n_head, n_tail;
+};
+
 struct BlendParams {
   float tex_scale;    // (N - 1) / (2 sigma): uv -> grid coordinate slope
   float tex_offset;   // (N - 1) / 2
@@ -31,12 +41,9 @@ struct BlendParams {
   // index of its first texel in the packed texture array
   const int32_t* grid_n;
   const int64_t* grid_at;
-  // forward only (nullable): an array that the workgroups zero while they blend (the coming
-  // backward's texture gradients): zero_n4 float4s, then zero_tail_n trailing floats
-  float4* zero4;
-  int64_t zero_n4;
-  float* zero_tail;
-  int32_t zero_tail_n;
+  // forward only: arrays that the workgroups zero while they blend (the coming backward's
+  // texture and record gradients); an empty range zeroes nothing
+  ZeroRange zero[2];
 };
 
 BlendParams make_blend_params(const Plan& pl, const gb_options& o, int n_views);

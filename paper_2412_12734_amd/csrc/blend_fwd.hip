@@ -30,22 +30,29 @@ constexpr int fwd_min_waves() {
   return 160 * 1024 / lds < 8 ? 160 * 1024 / lds : 8;
 }
 
-// With p.zero4: this workgroup's slice of the array to zero (the coming backward's texture
+// This workgroup's slices of the arrays to zero (the coming backward's texture and record
 // gradients). Called when the workgroup has finished blending, so that the stores drain
 // while other workgroups blend, and without holding registers during the blend. The stores
 // are non-temporal: the zeros are not read again before the backward's atomics, and kept out
 // of the caches they do not evict the records and texels other workgroups are reading (at 1M
 // splats and 1080p the forward took 0.533 ms with ordinary stores, 0.507 with these).
-__device__ __forceinline__ void zero_slice(const BlendParams& p) {
-  if (!p.zero4) return;
+__device__ __forceinline__ void zero_range(const ZeroRange& z) {
   typedef float v4f __attribute__((ext_vector_type(4)));
-  const int64_t per = (p.zero_n4 + (int64_t)gridDim.x - 1) / (int64_t)gridDim.x;
+  const int64_t per = (z.n_body + (int64_t)gridDim.x - 1) / (int64_t)gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * per;
-  const int64_t hi = lo + per < p.zero_n4 ? lo + per : p.zero_n4;
-  v4f* const z = reinterpret_cast<v4f*>(p.zero4);
+  const int64_t hi = lo + per < z.n_body ? lo + per : z.n_body;
+  v4f* const q = reinterpret_cast<v4f*>(z.body);
   for (int64_t i = lo + (int64_t)threadIdx.x; i < hi; i += (int64_t)blockDim.x)
-    __builtin_nontemporal_store((v4f){0.f, 0.f, 0.f, 0.f}, z + i);
-  if (blockIdx.x == 0 && (int)threadIdx.x < p.zero_tail_n) p.zero_tail[threadIdx.x] = 0.f;
+    __builtin_nontemporal_store((v4f){0.f, 0.f, 0.f, 0.f}, q + i);
+  if (blockIdx.x == 0) {
+    if ((int)threadIdx.x < z.n_head) z.head[threadIdx.x] = 0.f;
+    if ((int)threadIdx.x < z.n_tail) z.tail[threadIdx.x] = 0.f;
+  }
+}
+
+__device__ __forceinline__ void zero_slice(const BlendParams& p) {
+  zero_range(p.zero[0]);
+  zero_range(p.zero[1]);
 }
 
 // MIXED: each splat has a grid side of its own (at most N), read from p.grid_n.
@@ -298,6 +305,23 @@ hipError_t launch_nb(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
 
 }  // namespace
 
+// Split of a 4-byte aligned float array into single floats up to its first 16-byte boundary,
+// 16-byte stores, and at most 3 trailing floats.
+static ZeroRange zero_range_of(float* p, int64_t n) {
+  ZeroRange z{nullptr, nullptr, nullptr, 0, 0, 0};
+  if (!p || n <= 0) return z;
+  int64_t head = (int64_t)((16 - (reinterpret_cast<uintptr_t>(p) & 15)) & 15) / 4;
+  if (head > n) head = n;
+  const int64_t body = (n - head) / 4;
+  z.head = p;
+  z.n_head = (int32_t)head;
+  z.body = reinterpret_cast<float4*>(p + head);
+  z.n_body = body;
+  z.tail = p + head + 4 * body;
+  z.n_tail = (int32_t)(n - head - 4 * body);
+  return z;
+}
+
 BlendParams make_blend_params(const Plan& pl, const gb_options& o, int n_views) {
   BlendParams bp;
   const int N = pl.N;
@@ -324,10 +348,8 @@ BlendParams make_blend_params(const Plan& pl, const gb_options& o, int n_views) 
   bp.d_spec = nullptr;
   bp.grid_n = nullptr;
   bp.grid_at = nullptr;
-  bp.zero4 = nullptr;
-  bp.zero_n4 = 0;
-  bp.zero_tail = nullptr;
-  bp.zero_tail_n = 0;
+  bp.zero[0] = ZeroRange{nullptr, nullptr, nullptr, 0, 0, 0};
+  bp.zero[1] = ZeroRange{nullptr, nullptr, nullptr, 0, 0, 0};
   return bp;
 }
 
@@ -336,20 +358,16 @@ hipError_t launch_blend_fwd(const Plan& pl, const gb_splats& sp, const gb_option
                             const uint32_t* pair_vals, const uint32_t* ranges, float* rgb,
                             float* T_final, uint32_t* n_last, const SplitState& split,
                             uint32_t* tile_work, const float4* spec, unsigned long long* stats,
-                            float* zero, int64_t zero_n, hipStream_t s) {
+                            float* zero, int64_t zero_n, float* zero2, int64_t zero2_n,
+                            hipStream_t s) {
   // the forward keeps the fixed tile bands: ranking its tiles by list length measured no
   // faster on the 1M-splat 1080p workload (0.50 ms either way)
   BlendParams bp = make_blend_params(pl, o, n_views);
   bp.tile_work = tile_work;
   bp.spec = spec;
-  if (zero && zero_n > 0 && split.mode != kRestPass) {
-    // 16-byte stores over the aligned part, single floats for the rest (at most 3 trailing,
-    // or all of a short array)
-    const int64_t head = (reinterpret_cast<uintptr_t>(zero) & 15) == 0 ? zero_n / 4 : 0;
-    bp.zero4 = reinterpret_cast<float4*>(zero);
-    bp.zero_n4 = head;
-    bp.zero_tail = zero + 4 * head;
-    bp.zero_tail_n = (int32_t)(zero_n - 4 * head);
+  if (split.mode != kRestPass) {
+    bp.zero[0] = zero_range_of(zero, zero_n);
+    bp.zero[1] = zero_range_of(zero2, zero2_n);
   }
   const bool bf = sp.tex_dtype == GB_BF16;
   if (sp.tex_side) {

@@ -132,15 +132,13 @@ float lowpass_radius(float lowpass_var);
 hipError_t launch_upload_views(const gb_view* views, int n_views, int tile_w, int tile_h,
                                ViewDev* d_views, hipStream_t s);
 // With sp.sh != null it also writes spec[v P + k] = (view-dependent colour of splat k seen
-// from view v, 0) for every visible record.
+// from view v, 0) for every visible record. With order != null it also writes order[r] = r
+// for every record r and zero[i] = 0 for i < n_zero.
 hipError_t launch_preprocess(const gb_splats& sp, const ViewDev* d_views, int n_views,
                              const gb_options& o, int tile_w, int tile_h, uint32_t* depth_key,
                              uint32_t* sort_key, uint32_t* count, SplatRec* rec, float4* spec,
-                             hipStream_t s);
+                             uint32_t* order, uint32_t* zero, int64_t n_zero, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
-// p[i] = i for i < n, and zero[i] = 0 for i < n_zero, in one launch.
-hipError_t launch_iota_u32(uint32_t* p, int64_t n, uint32_t* zero, int64_t n_zero,
-                           hipStream_t s);
 // Pair slots per chunk of the duplicate kernels (one workgroup round).
 constexpr int kChunkSlots = 1024;
 
@@ -209,9 +207,10 @@ hipError_t launch_count_rest(const uint32_t* order, const uint32_t* count, const
 hipError_t launch_finalize_rest(const uint32_t* offsets_rest, int64_t VP, Status* st,
                                 hipStream_t s);
 // Summed-area tables of the open-tile bitmap, one per view: sat[y][x] = open tiles in rows
-// below y and columns below x (row stride tiles_x + 1).
+// below y and columns below x (row stride tiles_x + 1). Left unwritten when st reports an
+// overflow or no open tile.
 hipError_t launch_open_sat(const ViewDev* views, int n_views, const uint32_t* open_bits,
-                           uint32_t* sat, hipStream_t s);
+                           const Status* st, uint32_t* sat, hipStream_t s);
 // Second pass pairs: (open tile, record) for every record at rank >= st->cut, in depth order.
 hipError_t launch_duplicate_rest(const uint32_t* order, const uint32_t* count_rest,
                                  const uint32_t* offsets_rest, const uint32_t* chunk_owner,
@@ -237,7 +236,8 @@ hipError_t launch_blend_fwd(const Plan& pl, const gb_splats& sp, const gb_option
                             const uint32_t* pair_vals, const uint32_t* ranges, float* rgb,
                             float* T_final, uint32_t* n_last, const SplitState& split,
                             uint32_t* tile_work, const float4* spec, unsigned long long* stats,
-                            float* zero, int64_t zero_n, hipStream_t s);
+                            float* zero, int64_t zero_n, float* zero2, int64_t zero2_n,
+                            hipStream_t s);
 // Backward blend over the prefix (or only) pass's pairs `first`; with open_bits != null the
 // tiles marked there first walk `rest` (the rest pass's pairs). tile_order (nullable):
 // workgroup b takes tile tile_order[b]. With spec != null the records' view-dependent colours

@@ -87,8 +87,15 @@ preprocess_kernel(const float* __restrict__ means, const float* __restrict__ tan
                   uint32_t* __restrict__ depth_key, uint32_t* __restrict__ sort_key,
                   uint32_t* __restrict__ count,
                   SplatRec* __restrict__ rec, const float* __restrict__ sh,
-                  float4* __restrict__ spec) {
+                  float4* __restrict__ spec, uint32_t* __restrict__ order,
+                  uint32_t* __restrict__ zero, int64_t n_zero) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (order) {
+    // the depth sort's initial order (record indices), and words to clear, in the same launch
+    if (idx < VP) order[idx] = (uint32_t)idx;
+    const int64_t n_threads = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = idx; i < n_zero; i += n_threads) zero[i] = 0u;
+  }
   if (idx >= VP) return;
   const int v = (int)(idx / P);
   const int64_t k = idx - (int64_t)v * P;
@@ -282,7 +289,7 @@ hipError_t launch_upload_views(const gb_view* views, int n_views, int tile_w, in
 hipError_t launch_preprocess(const gb_splats& sp, const ViewDev* d_views, int n_views,
                              const gb_options& o, int tile_w, int tile_h, uint32_t* depth_key,
                              uint32_t* sort_key, uint32_t* count, SplatRec* rec, float4* spec,
-                             hipStream_t s) {
+                             uint32_t* order, uint32_t* zero, int64_t n_zero, hipStream_t s) {
   const int64_t VP = (int64_t)sp.P * n_views;
   const int threads = 256;
   const int64_t blocks = (VP + threads - 1) / threads;
@@ -292,7 +299,7 @@ hipError_t launch_preprocess(const gb_splats& sp, const ViewDev* d_views, int n_
   hipLaunchKernelGGL(preprocess_kernel<D>, dim3((unsigned)blocks), dim3(threads), 0, s,        \
                      sp.means, sp.tan_u, sp.tan_v, sp.scales, sp.opacity, d_views,            \
                      (int64_t)sp.P, VP, o.alpha_min, r_lp, tile_w, tile_h, depth_key, sort_key, \
-                     count, rec, sp.sh, spec)
+                     count, rec, sp.sh, spec, order, zero, n_zero)
   switch (shd) {
     case 0: GBB_PRE(0); break;
     case 1: GBB_PRE(1); break;

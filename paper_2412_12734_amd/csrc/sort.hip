@@ -446,16 +446,6 @@ __global__ void fill_u32x4_kernel(uint32_t* __restrict__ p, uint32_t value, int6
   if (first < (n & 3)) p[4 * n4 + first] = value;
 }
 
-__global__ void iota_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t* __restrict__ z,
-                                int64_t n_zero) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = (uint32_t)i;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_zero;
-       i += (int64_t)gridDim.x * blockDim.x)
-    z[i] = 0u;
-}
-
 unsigned grid_for(int64_t n, int threads) {
   int64_t b = (n + threads - 1) / threads;
   if (b > 65536) b = 65536;
@@ -473,15 +463,6 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s
     return hipGetLastError();
   }
   hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, value, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_iota_u32(uint32_t* p, int64_t n, uint32_t* zero, int64_t n_zero,
-                           hipStream_t s) {
-  const int64_t m = n > n_zero ? n : n_zero;
-  if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(iota_u32_kernel, dim3(grid_for(m, 256)), dim3(256), 0, s, p, n, zero,
-                     n_zero);
   return hipGetLastError();
 }
 

@@ -343,14 +343,16 @@ count_rest_kernel(const uint32_t* __restrict__ order, const uint32_t* __restrict
 
 // One workgroup per view: row prefix sums of the open bits (a wave per row, 64 tiles per
 // step), then column prefix sums (a thread per column). The table is built in LDS and copied
-// out when it fits (any 1080p-class view does), else directly in global memory.
+// out when it fits (any 1080p-class view does), else directly in global memory. With no open
+// tile (or an overflow) nothing reads the table, and the kernel returns at once.
 constexpr int kSatThreads = 1024;
 constexpr int kSatLds = 12288;  // table entries held in LDS (48 KB)
 
 __global__ void __launch_bounds__(kSatThreads)
 open_sat_kernel(const ViewDev* __restrict__ views, const uint32_t* __restrict__ open_bits,
-                uint32_t* __restrict__ sat) {
+                const Status* __restrict__ st, uint32_t* __restrict__ sat) {
   __shared__ uint32_t lds[kSatLds];
+  if (st->overflow || st->any_open == 0u) return;
   const ViewDev& V = views[blockIdx.x];
   const int tx = V.tiles_x, ty = V.tiles_y, stride = tx + 1;
   const int64_t entries = (int64_t)stride * (ty + 1);
@@ -560,9 +562,9 @@ hipError_t launch_count_rest(const uint32_t* order, const uint32_t* count, const
 }
 
 hipError_t launch_open_sat(const ViewDev* views, int n_views, const uint32_t* open_bits,
-                           uint32_t* sat, hipStream_t s) {
+                           const Status* st, uint32_t* sat, hipStream_t s) {
   hipLaunchKernelGGL(open_sat_kernel, dim3((unsigned)n_views), dim3(kSatThreads), 0, s, views,
-                     open_bits, sat);
+                     open_bits, st, sat);
   return hipGetLastError();
 }
 
