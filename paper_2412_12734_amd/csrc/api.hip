@@ -765,7 +765,7 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   const StatusEcho echo{(uint32_t)n_views, (uint32_t)pl.P, (unsigned long long)pl.off_count,
                         (unsigned long long)pl.off_view_pairs};
   GBB_TRY(launch_finalize_count(offsets, pl.VP, d_st, pl.capacity, echo, m_dev, overflow_flag,
-                                pl.split ? pl.prefix_cap : 0, hs),
+                                pl.split ? pl.prefix_cap : 0, chunk_owner, hs),
           "finalize count");
   GBB_TRY(stage_mark(kStPairScan, 1, hs), "timing");
   // first (or only) pass: pairs of the depth prefix, sorted by tile, ranges, blend
@@ -834,7 +834,7 @@ static gb_status render_fwd_impl(const gb_splats* s, const gb_view* views, int32
   GBB_TRY(launch_scan_u32(count_rest, nullptr, offsets_rest, pl.VP, partials, &d_st->K_rest,
                           &d_st->K_rest64, partials64, hs, chunk_owner, pl.n_chunks),
           "rest scan");
-  GBB_TRY(launch_finalize_rest(offsets_rest, pl.VP, d_st, hs), "rest finalize");
+  GBB_TRY(launch_finalize_rest(offsets_rest, pl.VP, d_st, chunk_owner, hs), "rest finalize");
   ClearList clear_r;  // the rest pass's tile ranges
   clear_r.p[0] = ranges_rest;
   clear_r.n[0] = 2 * pl.total_tiles;

@@ -180,10 +180,11 @@ struct StatusEcho {
 // With budget > 0 (the depth-prefix split) it also takes the prefix cut: the largest record
 // count (in depth order) whose pairs fit the budget, in st->cut, with st->n_sorted the
 // prefix's pairs (both zero on overflow); otherwise st->cut = VP and st->n_sorted = K.
+// chunk_owner: the table written by the scan that produced `offsets` (searches start there).
 hipError_t launch_finalize_count(const uint32_t* offsets, int64_t VP, Status* st,
                                  int64_t capacity, StatusEcho echo,
                                  unsigned long long* mirror, uint32_t* overflow_flag,
-                                 int64_t budget, hipStream_t s);
+                                 int64_t budget, const uint32_t* chunk_owner, hipStream_t s);
 // Per-view pair totals: out[v] = sum of count[v P .. (v + 1) P) (one workgroup per view).
 hipError_t launch_view_pairs(const uint32_t* count, int64_t P, int n_views,
                              unsigned long long* out, hipStream_t s);
@@ -205,7 +206,7 @@ hipError_t launch_count_rest(const uint32_t* order, const uint32_t* count, const
                              const Status* st, const uint32_t* sat, uint32_t* count_rest,
                              hipStream_t s);
 hipError_t launch_finalize_rest(const uint32_t* offsets_rest, int64_t VP, Status* st,
-                                hipStream_t s);
+                                const uint32_t* chunk_owner, hipStream_t s);
 // Summed-area tables of the open-tile bitmap, one per view: sat[y][x] = open tiles in rows
 // below y and columns below x (row stride tiles_x + 1). Left unwritten when st reports an
 // overflow or no open tile.

@@ -31,15 +31,57 @@ __device__ __forceinline__ int64_t last_at_or_below(const uint32_t* __restrict__
   return lo;
 }
 
+// The element whose run [offsets[r], offsets[r] + count) holds slot s (< total, the scan's
+// total, with no zero-count element owning a slot): the largest r with offsets[r] <= s. The
+// chunk-owner table of the same scan brackets it: the owner of the chunk start at or below s
+// is at most r, the owner of the next chunk start (if below total) at least r. One wave
+// narrows the bracket by sampling 64 evenly spaced offsets per round (a range of n elements
+// takes about log(n) / log(63) dependent loads, against log2(n) for a binary search); all 64
+// lanes take part and return the same r.
+__device__ int64_t wave_slot_owner(const uint32_t* __restrict__ offsets, int64_t n,
+                                   const uint32_t* __restrict__ chunk_owner, uint64_t total,
+                                   uint64_t s) {
+  const uint64_t c = s / kChunkSlots;
+  int64_t lo = chunk_owner[c];
+  if (s % kChunkSlots == 0) return lo;
+  int64_t hi = (c + 1) * kChunkSlots < total ? (int64_t)chunk_owner[c + 1] : n - 1;
+  const int lane = threadIdx.x & 63;
+  while (lo < hi) {
+    const int64_t span = hi - lo;
+    const int64_t pos = lo + span * lane / 63;  // lane 0 samples lo, lane 63 hi
+    // offsets do not decrease, so the lanes at or below s form a prefix (lane 0 is in it)
+    const uint64_t m = ballot((uint64_t)offsets[pos] <= s);
+    const int j = 63 - __builtin_clzll(m);
+    const int64_t next = j < 63 ? lo + span * (j + 1) / 63 - 1 : hi;
+    lo = lo + span * j / 63;
+    hi = next;
+  }
+  return lo;
+}
+
+// One wave.
 __global__ void finalize_count_kernel(const uint32_t* __restrict__ offsets, int64_t VP,
                                       Status* st, int64_t capacity, StatusEcho echo,
                                       unsigned long long* mirror, uint32_t* overflow_flag,
-                                      int64_t budget) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    // the exact 64-bit total decides: the 32-bit offsets wrap only when it exceeds 2^32,
-    // and the capacity is below that
-    const unsigned long long K = st->K64;
-    const bool over = K > (unsigned long long)capacity;
+                                      int64_t budget, const uint32_t* __restrict__ chunk_owner) {
+  // the exact 64-bit total decides: the 32-bit offsets wrap only when it exceeds 2^32,
+  // and the capacity is below that
+  const unsigned long long K = st->K64;
+  const bool over = K > (unsigned long long)capacity;
+  uint32_t n = over ? 0u : (uint32_t)K, cut = (uint32_t)VP;
+  if (budget > 0) {
+    // depth-prefix cut: the largest record count (in depth order) whose pairs fit the budget,
+    // i.e. the owner of pair slot `budget`
+    if (over) {
+      cut = 0u;
+    } else if (K > (unsigned long long)budget) {
+      cut = (uint32_t)wave_slot_owner(offsets, VP, chunk_owner, K, (uint64_t)budget);
+      n = offsets[cut];
+    }
+  }
+  const uint32_t last = n > 0 ? (uint32_t)wave_slot_owner(offsets, VP, chunk_owner, K, n - 1)
+                              : 0u;
+  if (threadIdx.x == 0) {
     st->overflow = over ? 1u : 0u;
     st->sticky_overflow |= over ? 1u : 0u;
     st->n_views = echo.n_views;
@@ -50,19 +92,9 @@ __global__ void finalize_count_kernel(const uint32_t* __restrict__ offsets, int6
     if (mirror) *reinterpret_cast<volatile unsigned long long*>(mirror) = (over ? 1ull << 63 : 0ull) | K;
     if (overflow_flag && over) *overflow_flag = 1u;
     st->any_open = 0u;
-    uint32_t n = over ? 0u : (uint32_t)K, cut = (uint32_t)VP;
-    if (budget > 0) {
-      // depth-prefix cut: the largest record count (in depth order) whose pairs fit the budget
-      if (over) {
-        cut = 0u;
-      } else if (K > (unsigned long long)budget) {
-        cut = (uint32_t)last_at_or_below(offsets, VP, (uint64_t)budget);
-        n = offsets[cut];
-      }
-    }
     st->cut = cut;
     st->n_sorted = n;
-    st->last_first = n > 0 ? (uint32_t)last_at_or_below(offsets, VP, n - 1) : 0u;
+    st->last_first = last;
   }
 }
 
@@ -396,12 +428,16 @@ open_sat_kernel(const ViewDev* __restrict__ views, const uint32_t* __restrict__ 
   }
 }
 
+// One wave.
 __global__ void finalize_rest_kernel(const uint32_t* __restrict__ offsets_rest, int64_t VP,
-                                     Status* st) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const uint32_t n = st->overflow ? 0u : (uint32_t)st->K_rest64;  // <= K64 <= capacity
+                                     Status* st, const uint32_t* __restrict__ chunk_owner) {
+  const uint64_t K = st->K_rest64;
+  const uint32_t n = st->overflow ? 0u : (uint32_t)K;  // <= K64 <= capacity
+  const uint32_t last =
+      n > 0 ? (uint32_t)wave_slot_owner(offsets_rest, VP, chunk_owner, K, n - 1) : 0u;
+  if (threadIdx.x == 0) {
     st->n_rest = n;
-    st->last_rest = n > 0 ? (uint32_t)last_at_or_below(offsets_rest, VP, n - 1) : 0u;
+    st->last_rest = last;
   }
 }
 
@@ -522,9 +558,9 @@ hipError_t launch_order_tiles(const uint32_t* work, int64_t n_tiles, uint32_t* o
 hipError_t launch_finalize_count(const uint32_t* offsets, int64_t VP, Status* st,
                                  int64_t capacity, StatusEcho echo,
                                  unsigned long long* mirror, uint32_t* overflow_flag,
-                                 int64_t budget, hipStream_t s) {
+                                 int64_t budget, const uint32_t* chunk_owner, hipStream_t s) {
   hipLaunchKernelGGL(finalize_count_kernel, dim3(1), dim3(64), 0, s, offsets, VP, st, capacity,
-                     echo, mirror, overflow_flag, budget);
+                     echo, mirror, overflow_flag, budget, chunk_owner);
   return hipGetLastError();
 }
 
@@ -569,8 +605,9 @@ hipError_t launch_open_sat(const ViewDev* views, int n_views, const uint32_t* op
 }
 
 hipError_t launch_finalize_rest(const uint32_t* offsets_rest, int64_t VP, Status* st,
-                                hipStream_t s) {
-  hipLaunchKernelGGL(finalize_rest_kernel, dim3(1), dim3(64), 0, s, offsets_rest, VP, st);
+                                const uint32_t* chunk_owner, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_rest_kernel, dim3(1), dim3(64), 0, s, offsets_rest, VP, st,
+                     chunk_owner);
   return hipGetLastError();
 }
 
