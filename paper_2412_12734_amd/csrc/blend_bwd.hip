@@ -346,7 +346,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
         const int j = 63 - (int)__builtin_clzll(todo);
         todo &= ~(1ull << j);
         const uint32_t jg = bstart + (uint32_t)j;
-        if (!__any(jg < lane_last)) continue;
+        if (ballot(jg < lane_last) == 0) continue;
         const StagedGeo g = s_geo.load(w, so + j);
         const float4* tex = s_tex + j * TexLayout<N>::kPerSplat;
         PixelEval e[PIX];
@@ -407,7 +407,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
           float* gb = s_gtex + j * TEXG;
 #pragma unroll
           for (int s = 0; s < PIX; ++s) {
-            if ((pend[s] >> lane) & 1ull) {
+            if (act[s]) {  // this lane's bit of pend[s]
 #pragma unroll
               for (int q = 0; q < KT / 3; ++q) {
                 const float wq = po[s].w[q];
@@ -430,7 +430,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
           // four VALU instructions fewer than testing the pending mask bit and selecting the
           // four corner weights; backward 1.41 -> 1.39 ms at 1M splats and 1080p.)
           static_assert(PIX == 1, "one pixel per lane");
-          int key = ((pend[0] >> lane) & 1ull) ? po[0].k00 : -1;
+          int key = act[0] ? po[0].k00 : -1;  // act[0]: this lane's bit of pend[0]
   #pragma unroll 1
           for (uint64_t left = pend[0]; left != 0;) {
             const int lead_cell = __builtin_amdgcn_readlane(key, (int)__builtin_ctzll(left));

@@ -149,7 +149,7 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
       stage_texels<N, BF16>(textures, pair_vals + b0, rec_base, nb, s_tex, p.spec);
     __syncthreads();
 
-    if (!__all(done)) {
+    if (ballot(!done) != 0) {
       // splats of this batch that can reach the wave's 8 x 8 block (one lane per splat)
       const bool may = lane < nb && s_reach[w][lane] != 0;
       uint64_t todo = ballot(may);
@@ -203,7 +203,7 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
             last = b0 + (uint32_t)j + 1u;
           }
         }
-        if (__all(done)) break;
+        if (ballot(!done) == 0) break;
       }
     }
     if (__syncthreads_and(done)) break;

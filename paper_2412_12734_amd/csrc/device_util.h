@@ -83,7 +83,10 @@ __device__ __forceinline__ f2 f2_div(f2 a, f2 b) {
 }
 
 // ---- wave64 helpers ------------------------------------------------------------------
-__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+// The lanes (of the active ones) where p holds. The compiler builtin takes the condition as
+// a lane mask in scalar registers; HIP's __ballot(int) widened it to an integer first and
+// compared that again (two vector instructions per vote in the blend loops).
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ __forceinline__ uint32_t lane_id() {
   return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
