@@ -137,10 +137,9 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
 
 // With batches of 8 the LDS allows 7 workgroups per CU (22.6 KB each for 8 x 8 grids, with
 // the geometry of 8 batches), but the register allocation (75 VGPRs unconstrained) stops at
-// 6 waves per SIMD; asking for 7 (at most 72 VGPRs; the compiler's resource report gives 72,
-// with 4 dwords spilled: in the prologue, the list loop's header and one reload per batch,
-// none inside the splat loop) measured 4 % faster on the 1M-splat 1080p workload, 8
-// (64 VGPRs) slower.
+// 6 waves per SIMD; asking for 7 (at most 72 VGPRs; the compiler's resource report for
+// 8 x 8 FP32 grids gives 71 and no scratch) measured 4 % faster on the 1M-splat 1080p
+// workload, 8 (64 VGPRs) slower.
 // (N = 16 blocks hold 67 KB of LDS, two per CU, so no register target applies there.)
 // Wave steps that blended at most this many pixels skip the cell grouping. Measured with the
 // multi-batch staging, backward ms for thresholds 16 / 24 / 28 / 32: 1M splats at 1080p 1.41 /
