@@ -1012,3 +1012,34 @@ def test_forward_zeroing_replaces_the_backward_clear(gb):
     rgb, T = rast.forward(sp, zero_grads=nan_like(ref))
     rast.backward(sp, T, g, other)
     check(other)
+
+
+def test_forward_zeroing_of_a_texture_gradient_off_a_16_byte_boundary(gb):
+    """The forward's zeroing splits its array into single floats up to the first 16-byte
+    boundary, 16-byte stores and a tail: a texture-gradient array that starts 4, 8 or 12 bytes
+    past a boundary (and so also ends off one) is zeroed whole, so the backward that skips its
+    clear still gives the gradients of the plain path from arrays full of NaN."""
+    scene = sg.make_scene(98, 2001, -1.2, 1.2, 0.01, 0.3, 8)
+    view = sg.look_at_view((0.1, -0.3, -2.9), 80, 64)
+    sp = gb.Splats.from_numpy(scene)
+    rast = gb.Rasterizer([view], gpu_opts(O.Options()))
+    rast.plan(sp)
+    g = torch.from_numpy(sg.make_dl_drgb(6, [view])).cuda()
+    rgb0, T0 = rast.forward(sp)
+    ref = {k: v.clone() for k, v in rast.backward(sp, T0, g).items()}
+    for shift in (1, 2, 3):
+        grads = {k: torch.full_like(v, float("nan")) for k, v in ref.items()}
+        n = ref["textures"].numel()
+        big = torch.full((n + 8,), float("nan"), dtype=torch.float32, device="cuda")
+        grads["textures"] = big[shift:shift + n].view(ref["textures"].shape)
+        assert grads["textures"].data_ptr() % 16 == 4 * shift
+        rgb, T = rast.forward(sp, zero_grads=grads)
+        rast.backward(sp, T, g, grads)
+        torch.cuda.synchronize()
+        for k, v in ref.items():
+            got = grads[k]
+            assert bool(torch.isfinite(got).all()), (shift, k)
+            assert rel_l2(got.cpu().numpy().astype(np.float64),
+                          v.cpu().numpy().astype(np.float64)) <= 1e-6, (shift, k)
+        # the words around the array are not touched
+        assert bool(torch.isnan(big[:shift]).all()) and bool(torch.isnan(big[shift + n:]).all())
