@@ -188,7 +188,9 @@ gb_status gb_count_pairs(const gb_splats* splats, const gb_view* views, int32_t 
 /* Forward render of all views (Alg. 1 forward):
  *   rgb     [sum HW][3] float32 (device)  composited colour, background included;
  *   T_final [sum HW]    float32 (device)  transmittance after the last blended splat.
- * The workspace keeps what gb_render_bwd needs until the next forward on it.
+ * The workspace keeps what gb_render_bwd needs until the next forward on it (the blend
+ * workgroups also clear the workspace's per-record gradient sums for that backward, which then
+ * skips the clear; a second backward of the same forward clears them itself).
  * Capacity: if the pair count exceeds `pair_capacity`, the overflow flag is set on the device,
  * every later stage of this call does nothing and the images are background; gb_read_status
  * reports it. The count and flag of every forward are also stored, without synchronising,
