@@ -222,11 +222,15 @@ __device__ __forceinline__ int grid_side(const BlendParams& p, uint32_t k) {
 }
 
 // Copies the texels of `nb` staged splats whose grids have sides of their own (at most N) into
-// the N x N LDS layout: splat j's n x n texels go to rows and columns [0, n). One wave per
-// splat; lane i moves values i, i + 64, ... of the grid's 3 n^2 contiguous values. A one-texel
-// grid is also copied to (0, 1), (1, 0) and (1, 1), so that the bilinear lookup, which reads the
-// four corners of cell (0, 0) with weights (1, 0, 0, 0) there, reads finite values. As in
-// stage_texels, spec (nullable) adds each record's view-dependent colour.
+// the N x N LDS layout: splat j's n x n texels go to rows and columns [0, n). Wave w takes
+// splats w, w + nw, ...; lane q of the wave first loads the side, first value and
+// view-dependent colour (spec, nullable, added to each texel as in stage_texels) of the wave's
+// q-th splat, so that these loads of all the wave's splats are in flight together; then, splat
+// by splat, lane i moves texels i, i + 64, ... of the grid (three channel values in, one
+// 16-byte LDS store out: a third of the index arithmetic of moving single values). A
+// one-texel grid is also copied to (0, 1), (1, 0) and (1, 1), so that the bilinear lookup,
+// which reads the four corners of cell (0, 0) with weights (1, 0, 0, 0) there, reads finite
+// values.
 // FROM_LDS: each grid's side and first texel come from the staged copies s_gn / s_toff (the
 // backward, whose geometry pass staged them well before); otherwise they are read from
 // p.grid_n / p.grid_at for record pairs[j] - rec_base, so that the forward need not wait at a
@@ -237,36 +241,60 @@ __device__ __forceinline__ void stage_texels_mixed(const void* __restrict__ text
                                                    uint32_t rec_base, int nb, float4* s_tex,
                                                    const BlendParams& p, const int32_t* s_gn,
                                                    const int64_t* s_toff) {
-  const int lane = threadIdx.x & 63, nw = (int)(blockDim.x >> 6);
+  const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6), nw = (int)(blockDim.x >> 6);
   const float4* __restrict__ spec = p.spec;
-  for (int j = (int)(threadIdx.x >> 6); j < nb; j += nw) {
-    const uint32_t r = pairs[j];
-    int n;
-    int64_t base;
+  // lane q: the wave's q-th splat (nb <= 64 nw, so one lane per splat suffices)
+  int my_n = 1;
+  int64_t my_base = 0;
+  float4 my_sc = make_float4(0.f, 0.f, 0.f, 0.f);
+  const int jq = w + lane * nw;
+  if (jq < nb) {
+    const uint32_t r = pairs[jq];
     if constexpr (FROM_LDS) {
-      n = s_gn[j];
-      base = 3 * s_toff[j];
+      my_n = s_gn[jq];
+      my_base = 3 * s_toff[jq];
     } else {
-      n = grid_side<N>(p, r - rec_base);
-      base = 3 * p.grid_at[r - rec_base];
+      my_n = grid_side<N>(p, r - rec_base);
+      my_base = 3 * p.grid_at[r - rec_base];
     }
+    if (spec) my_sc = spec[r];
+  }
+  for (int q = 0; w + q * nw < nb; ++q) {
+    const int j = w + q * nw;
+    const int n = __builtin_amdgcn_readlane(my_n, q);
+    const int64_t base =
+        (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(my_base >> 32), q) << 32) |
+                  (uint32_t)__builtin_amdgcn_readlane((int)my_base, q));
     float4 sc = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (spec) sc = spec[r];
+    if (spec)
+      sc = make_float4(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_sc.x), q)),
+                       __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_sc.y), q)),
+                       __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_sc.z), q)),
+                       0.f);
     float4* dst = s_tex + j * TexLayout<N>::kPerSplat;
-    auto texel = [&](int64_t i, int c) {
-      const float x = BF16 ? bf16_to_f32(reinterpret_cast<const uint16_t*>(textures)[i])
-                           : reinterpret_cast<const float*>(textures)[i];
-      return x + (c == 0 ? sc.x : c == 1 ? sc.y : sc.z);
+    // texel at value index i (its three channels), with the view-dependent colour added
+    auto texel = [&](int64_t i) {
+      float x0, x1, x2;
+      if constexpr (BF16) {
+        const uint16_t* t = reinterpret_cast<const uint16_t*>(textures) + i;
+        x0 = bf16_to_f32(t[0]);
+        x1 = bf16_to_f32(t[1]);
+        x2 = bf16_to_f32(t[2]);
+      } else {
+        const float* t = reinterpret_cast<const float*>(textures) + i;
+        x0 = t[0];
+        x1 = t[1];
+        x2 = t[2];
+      }
+      return make_float4(x0 + sc.x, x1 + sc.y, x2 + sc.z, 0.f);
     };
     if (n == 1) {
-      if (lane < 12) {  // corner lane / 3 of cell (0, 0), channel lane % 3
-        const int q = lane / 3, c = lane - 3 * q;
-        reinterpret_cast<float*>(dst + TexLayout<N>::at(q >> 1, q & 1))[c] = texel(base + c, c);
-      }
+      if (lane < 4) dst[TexLayout<N>::at(lane >> 1, lane & 1)] = texel(base);  // corner lane
     } else {
-      for (int i = lane; i < 3 * n * n; i += 64) {
-        const int t = i / 3, c = i - 3 * t, iu = div_side(t, n), iv = t - iu * n;
-        reinterpret_cast<float*>(dst + TexLayout<N>::at(iu, iv))[c] = texel(base + i, c);
+      // one texel per lane and pass: its three channels in, one 16-byte LDS store out
+      for (int t = lane; t < n * n; t += 64) {
+        const int iu = div_side(t, n), iv = t - iu * n;
+        dst[TexLayout<N>::at(iu, iv)] = texel(base + 3 * t);
       }
     }
   }
