@@ -140,7 +140,8 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
 // 6 waves per SIMD; asking for 7 (at most 72 VGPRs; the compiler's resource report for
 // 8 x 8 FP32 grids gives 71 and no scratch) measured 4 % faster on the 1M-splat 1080p
 // workload, 8 (64 VGPRs) slower.
-// (N = 16 blocks hold 67 KB of LDS, two per CU, so no register target applies there.)
+// (N = 16 blocks, at a batch of 4, hold 37 KB of LDS, four per CU, so no register target
+// applies there.)
 // Wave steps that blended at most this many pixels skip the cell grouping. Measured with the
 // multi-batch staging, backward ms for thresholds 16 / 24 / 28 / 32: 1M splats at 1080p 1.41 /
 // 1.41 / 1.41 / 1.42 (two runs each), 3M splats at 4 x 1080p 15.32 / 14.77 / 14.63 / 14.61,
@@ -543,7 +544,11 @@ hipError_t launch_np(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
   hipLaunchKernelGGL((blend_bwd_kernel<N, BF16, BB, PIX, MIXED>), grid, block, 0, s, views, rec, \
                      first, rest, open_bits, sp.textures, bp, T_final, d_rgb, d_rec, d_tex)
   if constexpr (N >= 16) {
-    GBB_BWD_B(8);  // the only batch built for N = 16 (LDS)
+    // the only batch built for N = 16: at 8 splats of 16 x 16 texels (texels and their
+    // gradient sums) a workgroup held 67 KB of LDS, two per CU; at 4 the backward at 1M
+    // splats and 1080p took 2.58 ms against 3.87 (grids of sides {4, 8, 16}: 2.84 against
+    // 4.48); a batch of 2 took 2.47 and 3.25
+    GBB_BWD_B(4);
   } else {
     switch (pl.batch_bwd) {
       case 8: GBB_BWD_B(8); break;

@@ -270,7 +270,10 @@ hipError_t launch_n(const Plan& pl, const gb_splats& sp, const BlendParams& bp,
                      rec, pair_vals, ranges, sp.textures, bp, rgb, T_final, n_last, split,    \
                      stats)
   if constexpr (N >= 16) {
-    GBB_FWD_B(8);  // the only batch built for N = 16 (LDS)
+    // the only batch built for N = 16: 8 splats of 16 x 16 texels hold 36 KB of LDS (4
+    // workgroups per CU); 4 double that, and the forward at 1M splats and 1080p took 1.24 ms
+    // against 1.33 (a batch of 2: 1.85 ms)
+    GBB_FWD_B(4);
   } else {
     switch (pl.batch_fwd) {
       case 8: GBB_FWD_B(8); break;
