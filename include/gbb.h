@@ -47,8 +47,8 @@ typedef enum {
   GB_ERR_ARG = 1,          /* invalid argument; nothing was launched */
   GB_ERR_HIP = 2,          /* a HIP runtime call failed */
   GB_ERR_CAPACITY = 3,     /* the (tile, splat) pair count exceeded the workspace capacity */
-  GB_ERR_UNSUPPORTED = 4   /* valid but not built (e.g. texture side N outside {1,2,4,8,16}, or
-                              N = 16 with a batch other than 8) */
+  GB_ERR_UNSUPPORTED = 4   /* valid but not built (e.g. texture side N outside {1,2,4,8,16},
+                              N = 16 with a batch other than 4, or a batch of 4 with N < 16) */
 } gb_status;
 
 typedef enum { GB_F32 = 0, GB_BF16 = 1 } gb_dtype;
@@ -65,7 +65,7 @@ typedef struct {
 
 typedef struct {
   int32_t P;               /* number of splats, >= 1 */
-  int32_t N;               /* texture side, one of 1, 2, 4, 8, 16 (16: batch and batch_bwd 8);
+  int32_t N;               /* texture side, one of 1, 2, 4, 8, 16 (16: batch and batch_bwd 4);
                               with tex_side: the largest side any splat may have, 8 or 16 */
   int32_t tex_dtype;       /* gb_dtype of `textures` */
   const float* means;      /* [P][3] */
@@ -106,11 +106,12 @@ typedef struct {
   float bg[3];        /* background colour composited with the final transmittance */
   int32_t tile_w;     /* tile width in px: 8, 16 or 32 */
   int32_t tile_h;     /* tile height in px: 8, 16 or 32; tile_w * tile_h <= 256 */
-  int32_t batch;      /* splats staged in LDS per forward batch: 0 = default (8 for N = 16,
-                         16 for N = 8, 32 for N = 4, else 64), or 8, 16, 32, 64 (N = 16: 8
-                         only) */
-  int32_t batch_bwd;  /* splats staged in LDS per backward batch: 0 = default (8 for N >= 8,
-                         else 32), or 8, 16, 32 (N = 16: 8 only) */
+  int32_t batch;      /* splats staged in LDS per forward batch: 0 = default (4 for N = 16,
+                         16 for N = 8, 32 for N = 4, else 64), or 8, 16, 32, 64 (N < 16), 4
+                         (N = 16, its only batch) */
+  int32_t batch_bwd;  /* splats staged in LDS per backward batch: 0 = default (4 for N = 16,
+                         8 for N = 8, else 32), or 8, 16, 32 (N < 16), 4 (N = 16, its only
+                         batch) */
   int32_t prefix_pairs_per_tile;
                       /* depth-prefix split. The first pass renders the longest prefix of the
                          depth order whose pairs fit this many pairs per tile (0 = default 1024);

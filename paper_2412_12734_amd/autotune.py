@@ -36,8 +36,8 @@ def resolve_defaults(opts, N: int):
     search results are explicit."""
     return dataclasses.replace(
         opts,
-        batch=opts.batch or (8 if N >= 16 else 16 if N >= 8 else 32 if N >= 4 else 64),
-        batch_bwd=opts.batch_bwd or (8 if N >= 8 else 32),
+        batch=opts.batch or (4 if N >= 16 else 16 if N >= 8 else 32 if N >= 4 else 64),
+        batch_bwd=opts.batch_bwd or (4 if N >= 16 else 8 if N >= 8 else 32),
         prefix_pairs_per_tile=opts.prefix_pairs_per_tile or 1024,
         tile_order=opts.tile_order or 1)
 
@@ -143,8 +143,8 @@ def autotune(splats, views, base=None, cache_path: Optional[str] = None,
         fields["bg"] = tuple(fields["bg"])  # JSON keeps tuples as lists
         return Options(**fields), cache[key]
     cost = cost or gpu_cost(splats, views, steps=steps)
-    if knobs is None and splats.N >= 16:  # the library builds only batches of 8 for N = 16
-        knobs = dict(KNOBS, batch=[8], batch_bwd=[8])
+    if knobs is None and splats.N >= 16:  # the library builds only batches of 4 for N = 16
+        knobs = dict(KNOBS, batch=[4], batch_bwd=[4])
     best, best_cost, log = search(base, cost, knobs)
     record = {"options": dataclasses.asdict(best), "ms": best_cost,
               "default_ms": log[0][1], "candidates": log}

@@ -52,10 +52,12 @@ gb_status validate_options(const gb_options* o) {
   const int tw = o->tile_w == 0 ? 16 : o->tile_w, th = o->tile_h == 0 ? 16 : o->tile_h;
   const bool ok_w = tw == 8 || tw == 16 || tw == 32, ok_h = th == 8 || th == 16 || th == 32;
   if (!ok_w || !ok_h || tw * th > 256) return arg_fail("tile must be 8/16/32 per side, <= 256 px");
-  if (o->batch != 0 && o->batch != 8 && o->batch != 16 && o->batch != 32 && o->batch != 64)
-    return arg_fail("batch must be 0, 8, 16, 32 or 64");
-  if (o->batch_bwd != 0 && o->batch_bwd != 8 && o->batch_bwd != 16 && o->batch_bwd != 32)
-    return arg_fail("batch_bwd must be 0, 8, 16 or 32");
+  if (o->batch != 0 && o->batch != 4 && o->batch != 8 && o->batch != 16 && o->batch != 32 &&
+      o->batch != 64)
+    return arg_fail("batch must be 0, 4, 8, 16, 32 or 64");
+  if (o->batch_bwd != 0 && o->batch_bwd != 4 && o->batch_bwd != 8 && o->batch_bwd != 16 &&
+      o->batch_bwd != 32)
+    return arg_fail("batch_bwd must be 0, 4, 8, 16 or 32");
   if (o->prefix_pairs_per_tile < -1 || o->prefix_pairs_per_tile > (1 << 20))
     return arg_fail("prefix_pairs_per_tile must be -1, 0 or in [1, 2^20]");
   if (o->tile_order < -1 || o->tile_order > 1) return arg_fail("tile_order must be -1, 0 or 1");
@@ -132,12 +134,17 @@ gb_status make_plan(int32_t P, int32_t N, const gb_view* views, int32_t n_views,
   // per block lets more blocks share a CU; at N = 4 a forward batch of 32 beat 64 and 16 (1M
   // splats at 1080p, forward + backward: 2.06 vs 2.13 ms) and a backward batch of 32 beat
   // 16 and 8 (2.13 vs 2.19 and 2.28 ms)
-  pl->batch_fwd = o->batch != 0 ? o->batch : (N >= 16 ? 8 : N >= 8 ? 16 : N >= 4 ? 32 : 64);
-  pl->batch_bwd = o->batch_bwd != 0 ? o->batch_bwd : (N >= 8 ? 8 : 32);
-  // N = 16: 4.3 KB of staged texels per splat; batches of 8 keep the backward's LDS (texels
-  // plus their gradient sums) near 61 KB per workgroup
-  if (N >= 16 && (pl->batch_fwd != 8 || pl->batch_bwd != 8)) {
-    g_last_error = "N = 16 takes batch and batch_bwd 8 (or 0)";
+  pl->batch_fwd = o->batch != 0 ? o->batch : (N >= 16 ? 4 : N >= 8 ? 16 : N >= 4 ? 32 : 64);
+  pl->batch_bwd = o->batch_bwd != 0 ? o->batch_bwd : (N >= 16 ? 4 : N >= 8 ? 8 : 32);
+  // N = 16: 4.3 KB of staged texels per splat; batches of 4 keep the backward's LDS (texels
+  // plus their gradient sums) near 37 KB per workgroup, four per CU. Batches of 4 are built
+  // for N = 16 only, and N = 16 only with them.
+  if (N >= 16 && (pl->batch_fwd != 4 || pl->batch_bwd != 4)) {
+    g_last_error = "N = 16 takes batch and batch_bwd 4 (or 0)";
+    return GB_ERR_UNSUPPORTED;
+  }
+  if (N < 16 && (pl->batch_fwd == 4 || pl->batch_bwd == 4)) {
+    g_last_error = "batches of 4 are built for N = 16 only";
     return GB_ERR_UNSUPPORTED;
   }
   int64_t tiles = 0, pixels = 0, sat = 0;

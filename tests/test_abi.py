@@ -118,11 +118,15 @@ def test_invalid_sizes_are_rejected():
     assert _layout(P=0)[0] == L.GB_ERR_ARG
     assert _layout(N=3)[0] == L.GB_ERR_UNSUPPORTED
     assert _layout(N=32)[0] == L.GB_ERR_UNSUPPORTED
-    # N = 16 is built with batches of 8 only
+    # N = 16 is built with batches of 4 only, and batches of 4 for N = 16 only
     assert _layout(N=16)[0] == L.GB_OK
-    assert _layout(N=16, opts=L.make_options(batch=8, batch_bwd=8))[0] == L.GB_OK
+    assert _layout(N=16, opts=L.make_options(batch=4, batch_bwd=4))[0] == L.GB_OK
+    assert _layout(N=16, opts=L.make_options(batch=8))[0] == L.GB_ERR_UNSUPPORTED
+    assert _layout(N=16, opts=L.make_options(batch_bwd=8))[0] == L.GB_ERR_UNSUPPORTED
     assert _layout(N=16, opts=L.make_options(batch=16))[0] == L.GB_ERR_UNSUPPORTED
-    assert _layout(N=16, opts=L.make_options(batch_bwd=16))[0] == L.GB_ERR_UNSUPPORTED
+    assert _layout(N=8, opts=L.make_options(batch=4))[0] == L.GB_ERR_UNSUPPORTED
+    assert _layout(N=8, opts=L.make_options(batch_bwd=4))[0] == L.GB_ERR_UNSUPPORTED
+    assert _layout(N=8, opts=L.make_options(batch=2))[0] == L.GB_ERR_ARG
     assert _layout(cap=-1)[0] == L.GB_ERR_ARG
     bad = sg.look_at_view((0, 0, -3), 0, 48)
     assert _layout(views=[bad])[0] == L.GB_ERR_ARG

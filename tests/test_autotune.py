@@ -35,9 +35,9 @@ def test_search_finds_the_separable_minimum():
     assert len(set(keys)) == len(keys)
 
 
-def test_n16_defaults_and_search_space_use_batches_of_8(tmp_path):
-    assert at.resolve_defaults(Options(), 16).batch == 8
-    assert at.resolve_defaults(Options(), 16).batch_bwd == 8
+def test_n16_defaults_and_search_space_use_batches_of_4(tmp_path):
+    assert at.resolve_defaults(Options(), 16).batch == 4
+    assert at.resolve_defaults(Options(), 16).batch_bwd == 4
     splats = types.SimpleNamespace(P=100, N=16, textures=torch.zeros(1))
     views = [types.SimpleNamespace(width=32, height=32)]
     seen = []
@@ -47,7 +47,7 @@ def test_n16_defaults_and_search_space_use_batches_of_8(tmp_path):
         return 1.0
 
     at.autotune(splats, views, cost=cost)
-    assert set(seen) == {(8, 8)}
+    assert set(seen) == {(4, 4)}
 
 
 def test_search_keeps_the_base_when_it_is_best():

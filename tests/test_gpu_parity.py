@@ -466,6 +466,19 @@ def test_backward_batches_on_every_tile_shape(gb, tile, batch_bwd):
     check_grads(gb, scene, view, opts, (8, 8, 64, 56), seed=17, batch_bwd=batch_bwd)
 
 
+# --- 16 x 16 colour grids (batches of 4) on every wave count: the backward stages 16 batches'
+#     geometry per pass, the forward 4 splats per wave block --------------------------------------
+@pytest.mark.parametrize("tile", [(8, 8), (16, 8), (8, 16), (16, 16)])
+def test_n16_on_every_tile_shape(gb, tile):
+    scene = sg.make_scene(29, 1500, -1.5, 1.5, 0.03, 0.3, 16)
+    view = sg.look_at_view((0.1, -0.2, -4.0), 80, 64)
+    opts = O.Options(tile_w=tile[0], tile_h=tile[1])
+    rast, sp, rgb, T = run_gpu(gb, scene, [view], opts)
+    ref = O.render(scene, view, opts, crop=(8, 8, 48, 40))
+    assert_image_parity(rgb.cpu().numpy(), T.cpu().numpy(), ref, 0, 80, 64, scene, view, opts)
+    check_grads(gb, scene, view, opts, (8, 8, 48, 40), seed=19)
+
+
 # --- depth-prefix split: same images as one pass, exact pair sets ---------------------------
 def dense_scene(N=4):
     scene = sg.make_scene(31, 20000, -1.0, 1.0, 0.03, 0.3, N)
