@@ -140,8 +140,8 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
 // 6 waves per SIMD; asking for 7 (at most 72 VGPRs; the compiler's resource report for
 // 8 x 8 FP32 grids gives 71 and no scratch) measured 4 % faster on the 1M-splat 1080p
 // workload, 8 (64 VGPRs) slower.
-// (N = 16 blocks, at a batch of 4, hold 37 KB of LDS, four per CU, so no register target
-// applies there.)
+// (N = 16 blocks, at a batch of 4 with a ring of 4 batches' geometry, hold 32 KB of LDS, five
+// per CU, so no register target applies there.)
 // Wave steps that blended at most this many pixels skip the cell grouping. Measured with the
 // multi-batch staging, backward ms for thresholds 16 / 24 / 28 / 32: 1M splats at 1080p 1.41 /
 // 1.41 / 1.41 / 1.42 (two runs each), 3M splats at 4 x 1080p 15.32 / 14.77 / 14.63 / 14.61,
@@ -157,9 +157,12 @@ constexpr int bwd_min_waves() { return (B <= 8 && N <= 8) ? 7 : 1; }
 // wait for it at the barrier), so fewer, fuller passes shorten the walk: at 1M splats and
 // 1080p the backward took 1.540 ms staging every batch on its own (32 of one wave's 64 lanes
 // busy), 1.473 / 1.448 / 1.420 ms staging 2 / 4 / 8 batches at once; at 3M splats on four
-// 1080p views 16.82 / 15.95 / 15.60 / 15.50 ms.
-template <int B>
-constexpr int bwd_stage_ahead() { return 64 / B; }
+// 1080p views 16.82 / 15.95 / 15.60 / 15.50 ms. For 16 x 16 grids LDS decides instead: a ring
+// of 4 batches (16 splats) rather than 16 takes the workgroup from 37 to 32 KB, five per CU
+// rather than four; backward at 1M splats and 1080p 2.59 -> 2.36 ms (sides {4, 8, 16}:
+// 2.83 -> 2.62; a ring of 8 batches: 2.65 and 2.91).
+template <int N, int B>
+constexpr int bwd_stage_ahead() { return N >= 16 ? 4 : 64 / B; }
 
 // Depth-prefix split: on a tile that the prefix left open the block first walks the rest
 // pass's list (the later splats) and then, with each pixel's T and S carried over in
@@ -178,7 +181,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   // Per-splat geometry and indices of AHEAD batches (slot k holds [k B, (k + 1) B)): every
   // AHEAD-th batch stages its own and the next AHEAD - 1 batches' geometry in one pass of the
   // staging threads.
-  constexpr int AHEAD = bwd_stage_ahead<B>();
+  constexpr int AHEAD = bwd_stage_ahead<N, B>();
   __shared__ GeoLds<AHEAD * B> s_geo;
   __shared__ uint8_t s_reach[4][AHEAD * B];  // [wave block][staged splat]: may reach the block
   __shared__ int32_t s_splat[AHEAD * B];
