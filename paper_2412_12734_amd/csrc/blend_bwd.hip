@@ -148,8 +148,11 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
 // 100k splats at 800x800 0.807 / 0.764 / 0.765 / 0.745.
 constexpr int kLaneAddMax = 28;
 
-template <int N, int B>
-constexpr int bwd_min_waves() { return (B <= 8 && N <= 8) ? 7 : 1; }
+// Grids of several sides (MIXED) need a few more registers: at 7 waves they spilled 28-40
+// bytes, and 6 waves measured faster (sides {2, 4, 8} at 1M splats and 1080p: backward 1.567
+// against 1.605 ms).
+template <int N, int B, bool MIXED>
+constexpr int bwd_min_waves() { return (B <= 8 && N <= 8) ? (MIXED ? 6 : 7) : 1; }
 
 // Batches whose geometry one staging pass prepares: as many as the workgroup's threads can
 // stage at once. A workgroup has 64 threads per wave block and a batch needs B per block, so
@@ -170,7 +173,7 @@ constexpr int bwd_stage_ahead() { return N >= 16 ? 4 : 64 / B; }
 // MIXED: each splat has a grid side of its own (at most N), read from p.grid_n; its texel
 // gradients go to its own n x n grid at p.grid_at.
 template <int N, bool BF16, int B, int PIX, bool MIXED>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(bwd_min_waves<N, B>())))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(bwd_min_waves<N, B, MIXED>())))
 blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__ rec,
                  PairList first, PairList rest, const uint32_t* __restrict__ open_bits,
                  const void* __restrict__ textures, BlendParams p,
