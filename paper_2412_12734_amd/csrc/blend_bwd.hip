@@ -47,12 +47,12 @@ struct PixOut {
 // transmittance factor, so that all of its outputs are zero and its state is unchanged
 // without a branch or zeroed outputs; its u, v and 1 / rho2 are replaced by 0 (they are
 // infinite where rho2 = 0). Its cell and corner weights are left unspecified.
-// MIXED: the splat's grid has gn texels per side (at most N) and uv -> grid slope gscale.
+// MIXED: gc holds the grid-coordinate constants of the splat's grid (grid_consts).
 template <int N, bool MIXED = false>
 __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex,
                                            const PixelEval& e, bool act, PixState& ps,
-                                           const BlendParams& p, PixOut& o, int gn = N,
-                                           float gscale = 0.f) {
+                                           const BlendParams& p, PixOut& o,
+                                           float4 gc = make_float4(0.f, 0.f, 0.f, 0.f)) {
   o.act = act;
   const float inv = act ? e.inv : 0.f;
   const float u = act ? e.u : 0.f, v = act ? e.v : 0.f;
@@ -76,8 +76,8 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
     int iu, iv;
     float fu, fv;
     if constexpr (MIXED) {
-      grid_coord_n(u, gscale, gn, iu, fu);
-      grid_coord_n(v, gscale, gn, iv, fv);
+      grid_coord_c(u, gc, iu, fu);
+      grid_coord_c(v, gc, iv, fv);
     } else {
       grid_coord<N>(u, p, iu, fu);
       grid_coord<N>(v, p, iv, fv);
@@ -101,7 +101,7 @@ __device__ __forceinline__ void pixel_step(const StagedGeo& g, const float4* tex
     const float fv1 = (t01.y - t00.y) * (1.f - fu) + (t11.y - t10.y) * fu;
     const float fv2 = (t01.z - t00.z) * (1.f - fu) + (t11.z - t10.z) * fu;
     const float dfv = o.dc0 * fv0 + o.dc1 * fv1 + o.dc2 * fv2;
-    const float tsc = MIXED ? gscale : p.tex_scale;
+    const float tsc = MIXED ? gc.x : p.tex_scale;
     du = fabsf(u) < p.sigma ? tsc * dfu : 0.f;  // (-sigma, sigma): one compare with |u|
     dv = fabsf(v) < p.sigma ? tsc * dfv : 0.f;
   }
@@ -194,7 +194,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   __shared__ float s_grec[B * kRecGrad];  // per splat
   __shared__ uint32_t s_tile_last;
   __shared__ int32_t s_gn[MIXED ? AHEAD * B : 1];
-  __shared__ float s_gscale[MIXED ? AHEAD * B : 1];
+  __shared__ float4 s_gc[MIXED ? AHEAD * B : 1];
   __shared__ int64_t s_toff[MIXED ? AHEAD * B : 1];
 
   const int tile = tile_of_block(p);
@@ -315,7 +315,7 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
           if (MIXED) {
             const int n = grid_side<N>(p, r - rec_base);
             s_gn[jj] = n;
-            s_gscale[jj] = grid_scale(n, p.sigma);
+            s_gc[jj] = grid_consts(n, p.sigma);
             s_toff[jj] = p.grid_at[r - rec_base];
           }
         }
@@ -370,11 +370,10 @@ blend_bwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
         if (any_act == 0) continue;  // no pixel of the wave blended this splat
         PixOut po[PIX];
         if constexpr (MIXED) {
-          const int gn = s_gn[so + j];
-          const float gscale = s_gscale[so + j];
+          const float4 gc = s_gc[so + j];
 #pragma unroll
           for (int s = 0; s < PIX; ++s)
-            pixel_step<N, true>(g, tex, e[s], act[s], ps[s], p, po[s], gn, gscale);
+            pixel_step<N, true>(g, tex, e[s], act[s], ps[s], p, po[s], gc);
         } else {
 #pragma unroll
           for (int s = 0; s < PIX; ++s) pixel_step<N>(g, tex, e[s], act[s], ps[s], p, po[s]);

@@ -382,13 +382,33 @@ __device__ __forceinline__ void grid_coord(float u, const BlendParams& p, int& i
   f = up - (float)i;
 }
 
-// The same for a grid of n texels per side with slope `scale` (grid_scale): one texel gives
-// cell 0 with f = 0.
+// Grid coordinate of u on a corner-aligned grid of n texels per side with slope `scale`
+// (grid_scale): as grid_coord<N> with n in place of N (a uniform call's grids give the same
+// results); one texel gives cell 0 with f = 0.
 __device__ __forceinline__ void grid_coord_n(float u, float scale, int n, int& i, float& f) {
   const float hi = (float)(n - 1);
   const float up = fminf(fmaxf(__builtin_fmaf(u, scale, 0.5f * hi), 0.0f), hi);
   const int fi = (int)up;
   const int cmax = n > 2 ? n - 2 : 0;
+  i = fi < cmax ? fi : cmax;
+  f = up - (float)i;
+}
+
+// Constants of grid_coord_c for an n-texel side: slope (grid_scale), offset (n - 1) / 2,
+// upper clamp n - 1 and the largest cell index (its int bits in w), staged once per splat so
+// that the per-pixel coordinate costs what the uniform grid's does.
+__device__ __forceinline__ float4 grid_consts(int n, float sigma) {
+  const float hi = (float)(n - 1);
+  const int cmax = n > 2 ? n - 2 : 0;
+  return make_float4(grid_scale(n, sigma), 0.5f * hi, hi, __int_as_float(cmax));
+}
+
+// grid_coord_n from the side's staged constants (the same operations in the same order, so
+// the same results).
+__device__ __forceinline__ void grid_coord_c(float u, const float4& gc, int& i, float& f) {
+  const float up = fminf(fmaxf(__builtin_fmaf(u, gc.x, gc.y), 0.0f), gc.z);
+  const int fi = (int)up;
+  const int cmax = __float_as_int(gc.w);
   i = fi < cmax ? fi : cmax;
   f = up - (float)i;
 }

@@ -66,7 +66,8 @@ blend_fwd_kernel(const ViewDev* __restrict__ views, const SplatRec* __restrict__
   __shared__ GeoLds<B> s_geo;
   __shared__ float4 s_tex[B * TexLayout<N>::kPerSplat];
   __shared__ uint8_t s_reach[4][B];  // [wave block][staged splat]: may reach the block
-  // MIXED: side and uv -> grid slope of each staged splat's grid
+  // MIXED: side and uv -> grid slope of each staged splat's grid (two words per splat: the 16
+  // of grid_consts would take the LDS of a batch of 16 8 x 8 grids past an eighth of the CU's)
   __shared__ int32_t s_gn[MIXED ? B : 1];
   __shared__ float s_gscale[MIXED ? B : 1];
   static_assert((B & (B - 1)) == 0, "batch sizes are powers of two");
