@@ -136,9 +136,9 @@ gb_status make_plan(int32_t P, int32_t N, const gb_view* views, int32_t n_views,
   // 16 and 8 (2.13 vs 2.19 and 2.28 ms)
   pl->batch_fwd = o->batch != 0 ? o->batch : (N >= 16 ? 4 : N >= 8 ? 16 : N >= 4 ? 32 : 64);
   pl->batch_bwd = o->batch_bwd != 0 ? o->batch_bwd : (N >= 16 ? 4 : N >= 8 ? 8 : 32);
-  // N = 16: 4.3 KB of staged texels per splat; batches of 4 keep the backward's LDS (texels
-  // plus their gradient sums) near 37 KB per workgroup, four per CU. Batches of 4 are built
-  // for N = 16 only, and N = 16 only with them.
+  // N = 16: 4.3 KB of staged texels per splat; batches of 4 keep the backward's LDS (texels,
+  // their gradient sums and a ring of 4 batches' geometry) near 32 KB per workgroup, five per
+  // CU. Batches of 4 are built for N = 16 only, and N = 16 only with them.
   if (N >= 16 && (pl->batch_fwd != 4 || pl->batch_bwd != 4)) {
     g_last_error = "N = 16 takes batch and batch_bwd 4 (or 0)";
     return GB_ERR_UNSUPPORTED;
